@@ -1,0 +1,491 @@
+/*
+ * Oracle for the permutation flow-shop lower bound and branch-and-bound.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library and is written to be read
+ * against the paper (Melab, Chakroun, Mezmaz, Tuyttens, "A GPU-accelerated
+ * Branch-and-Bound Algorithm for the Flow-Shop Scheduling Problem"), not to be
+ * fast.  All arithmetic is integer; sums are carried in int64 so that no
+ * intermediate can wrap.
+ *
+ * Indexing: jobs 0..n-1, machines 0..m-1, processing time of job j on machine
+ * k is p[j*m + k] (row-major n x m, the PTM matrix of Table I).
+ *
+ * Readings of the paper taken here (each is also listed with its reason in the
+ * design notes of the repository):
+ *   - Machine releases (RM) are the completion times of the scheduled prefix
+ *     on each machine; the root has all releases 0.
+ *   - The tail of machine l (QM) is the minimum over unscheduled jobs of the
+ *     job's total time on machines after l; 0 when no job is unscheduled.
+ *   - The lag of job j on pair (k,l) (LM) is its total time on the machines
+ *     strictly between k and l.
+ *   - Johnson's rule with lags for pair (k,l): with a = p[j][k], b = p[j][l],
+ *     L = lag, jobs with a <= b come first by increasing a+L, then jobs with
+ *     a > b by decreasing b+L; ties by increasing job id (Johnson 1954;
+ *     Mitten 1959 for the lags, as used by Lageweg, Lenstra and Rinnooy Kan).
+ *   - The bound starts from 0: Fig. 2 initialises it to the largest integer
+ *     and then takes a maximum, which can only be a typo.
+ *   - Elimination prunes a node whose bound is >= the upper bound; the
+ *     paper's strict ">" is available for the brute-force pins (strict_gt).
+ *
+ * Parity pins live in tests/test_oracle_pins.py (brute force, closed forms,
+ * invariants).  Nothing here is "parity unpinned".
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_INVALID (-1)
+
+/* Counters of accesses to the data structures of Table I, filled by
+ * orc_bound_counted() so a test can check the access pattern against the
+ * table's "number of accesses" column. */
+typedef struct {
+    int64_t ptm;  /* reads of processing times inside the pair scans */
+    int64_t lm;   /* reads of lags inside the pair scans */
+    int64_t rm;   /* reads of machine releases by the pair loop */
+    int64_t qm;   /* reads of machine tails by the pair loop */
+    int64_t mm;   /* reads of the machine-pair list */
+} orc_counts;
+
+/* ---------------------------------------------------------------------------
+ * Makespan of a (partial) permutation: completion time of its last job on the
+ * last machine (Sec. II-B/II-C: jobs visit machines 1..m in order, one job at
+ * a time per machine, same job order on every machine).
+ * ------------------------------------------------------------------------- */
+static void completion_times(const int32_t *p, int m, const int32_t *seq, int len,
+                             int64_t *C /* m, in: start state, out: after seq */)
+{
+    for (int i = 0; i < len; ++i) {
+        const int32_t *row = p + (int64_t)seq[i] * m;
+        C[0] += row[0];
+        for (int k = 1; k < m; ++k) {
+            int64_t ready = C[k] > C[k - 1] ? C[k] : C[k - 1];
+            C[k] = ready + row[k];
+        }
+    }
+}
+
+int32_t orc_makespan(const int32_t *p, int n, int m, const int32_t *seq, int len)
+{
+    (void)n;
+    int64_t *C = (int64_t *)calloc((size_t)m, sizeof(int64_t));
+    completion_times(p, m, seq, len, C);
+    int64_t v = C[m - 1];
+    free(C);
+    return (int32_t)v;
+}
+
+/* Checks a node: 0 <= d <= n, prefix jobs in range and pairwise distinct.
+ * Fills scheduled[] (1 = in the prefix).  Returns 1 when valid. */
+static int decode_node(int n, const int32_t *prefix, int d, unsigned char *scheduled)
+{
+    if (d < 0 || d > n) return 0;
+    memset(scheduled, 0, (size_t)n);
+    for (int i = 0; i < d; ++i) {
+        int32_t j = prefix[i];
+        if (j < 0 || j >= n || scheduled[j]) return 0;
+        scheduled[j] = 1;
+    }
+    return 1;
+}
+
+/* A job with its Johnson-with-lags sort fields for one pair (k,l):
+ * group 0 holds the jobs with a <= b, ordered by increasing a+L; group 1 the
+ * jobs with a > b, ordered by decreasing b+L; ties by increasing tie key.
+ * eq_in_s2 moves the a == b jobs to group 1 and tiekey replaces the job id as
+ * tie key; both exist only so a test can show the bound does not depend on
+ * these choices. */
+typedef struct { int group; int64_t primary; int64_t tie; int32_t job; } keyed_job;
+
+static int cmp_keyed(const void *x, const void *y)
+{
+    const keyed_job *a = (const keyed_job *)x, *b = (const keyed_job *)y;
+    if (a->group != b->group) return a->group < b->group ? -1 : 1;
+    if (a->group == 0) {                       /* a+L ascending */
+        if (a->primary != b->primary) return a->primary < b->primary ? -1 : 1;
+    } else {                                   /* b+L descending */
+        if (a->primary != b->primary) return a->primary > b->primary ? -1 : 1;
+    }
+    if (a->tie != b->tie) return a->tie < b->tie ? -1 : 1;
+    return (a->job > b->job) - (a->job < b->job);
+}
+
+static int64_t lag(const int32_t *p, int m, int j, int k, int l)
+{
+    int64_t s = 0;
+    for (int h = k + 1; h < l; ++h) s += p[(int64_t)j * m + h];
+    return s;
+}
+
+static keyed_job johnson_fields(int32_t j, int64_t a, int64_t b, int64_t L, int64_t tie,
+                                int eq_in_s2)
+{
+    keyed_job kj;
+    int first = eq_in_s2 ? (a < b) : (a <= b);
+    kj.group = first ? 0 : 1;
+    kj.primary = first ? (a + L) : (b + L);
+    kj.tie = tie;
+    kj.job = j;
+    return kj;
+}
+
+/* The lower bound of Sec. II-D / Fig. 2 for the node (prefix[0..d-1]).
+ *
+ * For every machine pair (k,l), k<l (the MM list, lexicographic):
+ *   timeOnM1 = release of k, timeOnM2 = release of l (RM);
+ *   for the unscheduled jobs in Johnson-with-lags order for (k,l) (JM
+ *   restricted to the unscheduled set, here obtained by sorting that set):
+ *     timeOnM1 += p[j][k];
+ *     if timeOnM2 > timeOnM1 + lag  then timeOnM2 += p[j][l]
+ *     else                               timeOnM2 = timeOnM1 + lag + p[j][l];
+ *   timeOnM2 += tail of l (QM);  LB = max(LB, timeOnM2).
+ * Returns ORC_INVALID for an invalid node. */
+static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix, int d,
+                          const int32_t *tiekey, int eq_in_s2, orc_counts *cnt,
+                          int only_k, int only_l, int64_t *pair_t2, int64_t *pair_q)
+{
+    unsigned char *scheduled = (unsigned char *)malloc((size_t)n + 1);
+    if (!decode_node(n, prefix, d, scheduled)) { free(scheduled); return ORC_INVALID; }
+
+    /* RM: completion times of the prefix on each machine. */
+    int64_t *r = (int64_t *)calloc((size_t)m, sizeof(int64_t));
+    completion_times(p, m, prefix, d, r);
+
+    /* QM: min over unscheduled jobs of the time left after machine l. */
+    int64_t *q = (int64_t *)calloc((size_t)m, sizeof(int64_t));
+    for (int l = 0; l < m; ++l) {
+        int64_t best = -1;
+        for (int j = 0; j < n; ++j) {
+            if (scheduled[j]) continue;
+            int64_t t = 0;
+            for (int h = l + 1; h < m; ++h) t += p[(int64_t)j * m + h];
+            if (best < 0 || t < best) best = t;
+        }
+        q[l] = best < 0 ? 0 : best;
+    }
+
+    keyed_job *order = (keyed_job *)malloc(sizeof(keyed_job) * (size_t)(n + 1));
+    int64_t LB = 0;
+    for (int k = 0; k < m; ++k) {
+        for (int l = k + 1; l < m; ++l) {
+            if (only_k >= 0 && (k != only_k || l != only_l)) continue;
+            if (cnt) cnt->mm += 2;
+            /* Johnson-with-lags order of the unscheduled jobs for (k,l). */
+            int cnt_u = 0;
+            for (int j = 0; j < n; ++j) {
+                if (scheduled[j]) continue;
+                int64_t a = p[(int64_t)j * m + k], b = p[(int64_t)j * m + l];
+                int64_t tie = tiekey ? tiekey[j] : j;
+                order[cnt_u++] = johnson_fields(j, a, b, lag(p, m, j, k, l), tie, eq_in_s2);
+            }
+            qsort(order, (size_t)cnt_u, sizeof(keyed_job), cmp_keyed);
+
+            int64_t timeOnM1 = r[k], timeOnM2 = r[l];
+            if (cnt) cnt->rm += 2;
+            for (int i = 0; i < cnt_u; ++i) {
+                int j = order[i].job;
+                int64_t L = lag(p, m, j, k, l);
+                timeOnM1 += p[(int64_t)j * m + k];
+                if (timeOnM2 > timeOnM1 + L)
+                    timeOnM2 += p[(int64_t)j * m + l];
+                else
+                    timeOnM2 = timeOnM1 + L + p[(int64_t)j * m + l];
+                if (cnt) { cnt->ptm += 2; cnt->lm += 1; }
+            }
+            if (pair_t2) *pair_t2 = timeOnM2;
+            if (pair_q) *pair_q = q[l];
+            timeOnM2 += q[l];
+            if (cnt) cnt->qm += 1;
+            if (timeOnM2 > LB) LB = timeOnM2;
+        }
+    }
+    free(order); free(q); free(r); free(scheduled);
+    return (int32_t)LB;
+}
+
+int32_t orc_bound(const int32_t *p, int n, int m, const int32_t *prefix, int d)
+{
+    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL);
+}
+
+/* Same bound with a custom tie-break key per job and a choice of group for
+ * the a == b jobs. */
+int32_t orc_bound_tie(const int32_t *p, int n, int m, const int32_t *prefix, int d,
+                      const int32_t *tiekey, int eq_in_s2)
+{
+    return bound_impl(p, n, m, prefix, d, tiekey, eq_in_s2, NULL, -1, -1, NULL, NULL);
+}
+
+/* Same bound, counting accesses to the Table I structures. */
+int32_t orc_bound_counted(const int32_t *p, int n, int m, const int32_t *prefix, int d,
+                          orc_counts *cnt)
+{
+    memset(cnt, 0, sizeof(*cnt));
+    return bound_impl(p, n, m, prefix, d, NULL, 0, cnt, -1, -1, NULL, NULL);
+}
+
+/* One pair only: *t2 = timeOnM2 after the scan (before the tail), *q = tail
+ * of machine l.  Returns ORC_INVALID for an invalid node, else 0. */
+int32_t orc_pair_scan(const int32_t *p, int n, int m, const int32_t *prefix, int d,
+                      int k, int l, int64_t *t2, int64_t *q)
+{
+    if (k < 0 || l <= k || l >= m) return ORC_INVALID;
+    int32_t v = bound_impl(p, n, m, prefix, d, NULL, 0, NULL, k, l, t2, q);
+    return v == ORC_INVALID ? ORC_INVALID : 0;
+}
+
+/* Bounds of a pool: prefixes is count x n (row i holds depths[i] scheduled
+ * jobs first), out[i] = bound or ORC_INVALID.  Returns the number of invalid
+ * rows. */
+int64_t orc_bound_pool(const int32_t *p, int n, int m, const int32_t *prefixes,
+                       const int32_t *depths, int64_t count, int32_t *out)
+{
+    int64_t bad = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        out[i] = orc_bound(p, n, m, prefixes + i * (int64_t)n, depths[i]);
+        if (out[i] == ORC_INVALID) ++bad;
+    }
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
+ * Brute force: minimum makespan over all completions of a prefix (n small).
+ * ------------------------------------------------------------------------- */
+static void brute_rec(const int32_t *p, int n, int m, unsigned char *used, int left,
+                      const int64_t *C, int64_t *best)
+{
+    if (left == 0) {
+        if (*best < 0 || C[m - 1] < *best) *best = C[m - 1];
+        return;
+    }
+    int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    for (int j = 0; j < n; ++j) {
+        if (used[j]) continue;
+        memcpy(D, C, sizeof(int64_t) * (size_t)m);
+        int32_t seq = j;
+        completion_times(p, m, &seq, 1, D);
+        used[j] = 1;
+        brute_rec(p, n, m, used, left - 1, D, best);
+        used[j] = 0;
+    }
+    free(D);
+}
+
+int32_t orc_brute(const int32_t *p, int n, int m, const int32_t *prefix, int d)
+{
+    unsigned char *used = (unsigned char *)malloc((size_t)n + 1);
+    if (!decode_node(n, prefix, d, used)) { free(used); return ORC_INVALID; }
+    int64_t *C = (int64_t *)calloc((size_t)m, sizeof(int64_t));
+    completion_times(p, m, prefix, d, C);
+    int64_t best = -1;
+    brute_rec(p, n, m, used, n - d, C, &best);
+    free(C); free(used);
+    return (int32_t)best;
+}
+
+/* ---------------------------------------------------------------------------
+ * NEH constructive heuristic (Nawaz, Enscore and Ham, 1983) for the initial
+ * upper bound: order jobs by decreasing total processing time (ties: smaller
+ * id first); insert each job, in that order, at the position of the partial
+ * sequence that gives the smallest partial makespan (ties: earliest
+ * position).  Returns the makespan; perm_out receives the sequence.
+ * ------------------------------------------------------------------------- */
+int32_t orc_neh(const int32_t *p, int n, int m, int32_t *perm_out)
+{
+    int32_t *jobs = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *tot = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int j = 0; j < n; ++j) {
+        jobs[j] = j;
+        tot[j] = 0;
+        for (int k = 0; k < m; ++k) tot[j] += p[(int64_t)j * m + k];
+    }
+    /* insertion sort by (total desc, id asc): plain and stable */
+    for (int i = 1; i < n; ++i) {
+        int32_t x = jobs[i];
+        int t = i - 1;
+        while (t >= 0 && (tot[jobs[t]] < tot[x] || (tot[jobs[t]] == tot[x] && jobs[t] > x))) {
+            jobs[t + 1] = jobs[t];
+            --t;
+        }
+        jobs[t + 1] = x;
+    }
+    int32_t *seq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *trial = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int len = 0;
+    for (int i = 0; i < n; ++i) {
+        int32_t x = jobs[i];
+        int best_pos = 0;
+        int32_t best_val = 0;
+        for (int pos = 0; pos <= len; ++pos) {
+            int t = 0;
+            for (int a = 0; a < pos; ++a) trial[t++] = seq[a];
+            trial[t++] = x;
+            for (int a = pos; a < len; ++a) trial[t++] = seq[a];
+            int32_t v = orc_makespan(p, n, m, trial, len + 1);
+            if (pos == 0 || v < best_val) { best_val = v; best_pos = pos; }
+        }
+        for (int a = len; a > best_pos; --a) seq[a] = seq[a - 1];
+        seq[best_pos] = x;
+        ++len;
+    }
+    int32_t ms = orc_makespan(p, n, m, seq, n);
+    if (perm_out) memcpy(perm_out, seq, sizeof(int32_t) * (size_t)n);
+    free(trial); free(seq); free(tot); free(jobs);
+    return ms;
+}
+
+/* ---------------------------------------------------------------------------
+ * Branch-and-bound, pool-synchronous depth-first (Sec. II-A operators; the
+ * pool of Sec. III-A).  The paper does not fix the order semantics of a pool,
+ * so they are fixed here so that node counts are a function of
+ * (instance, ub0, pool_cap):
+ *   1. The root is bounded (1 node).  If it is eliminated, stop.
+ *   2. Selection: pop parents from the top of the stack while the stack is
+ *      not empty and the children gathered so far plus the next parent's
+ *      (n - depth) children fit in pool_cap (the first parent is always
+ *      taken).
+ *   3. Branching: for each parent in pop order, one child per unscheduled
+ *      job in increasing job id; the child appends that job to the prefix
+ *      (forward branching, Sec. II-B).
+ *   4. Bounding: every child is bounded; nodes_bounded counts them.
+ *   5. Complete children (depth n) are scanned in child order; a bound below
+ *      the upper bound replaces it and its permutation becomes the incumbent.
+ *   6. Elimination: the remaining children whose bound is below the upper
+ *      bound after step 5 (not eliminated) are pushed in reverse child order,
+ *      so the first child is on top.
+ *   7. Stop when the stack is empty (proven) or nodes_bounded has reached
+ *      node_budget (not proven).
+ * strict_gt = 1 eliminates only bound > UB (the paper's wording); the default
+ * eliminates bound >= UB.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t ub;
+    int32_t proven;
+    int64_t nodes_bounded;
+    int64_t steps;
+    int64_t improvements;
+    int64_t max_stack;
+} orc_bnb_result;
+
+/* steplog, when non-NULL, receives per step (up to steplog_cap steps):
+ *   [0] parents popped, [1] children bounded, [2] UB after the step,
+ *   [3] children pushed, [4] stack size after the step,
+ *   [5] sum over pushed children of (position in push order + 1) * (job
+ *       appended + 1), a cheap order-sensitive fingerprint of the frontier. */
+int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+            int64_t pool_cap, int64_t node_budget, int strict_gt,
+            orc_bnb_result *res, int32_t *incumbent_out,
+            int64_t *steplog, int64_t steplog_cap)
+{
+    memset(res, 0, sizeof(*res));
+    if (n < 1 || m < 2 || pool_cap < 1) return -1;
+    int32_t UB = ub0;
+    int32_t *inc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int have_inc = 0;
+    if (inc0) { memcpy(inc, inc0, sizeof(int32_t) * (size_t)n); have_inc = 1; }
+
+    int64_t cap_nodes = 1024, top = 0;
+    int32_t *stack = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1) * (size_t)cap_nodes);
+    /* node layout: [depth, job_0 .. job_{n-1}] */
+#define NODE(i) (stack + (int64_t)(i) * (n + 1))
+
+    int64_t nodes = 1;
+    int32_t root_lb = orc_bound(p, n, m, NULL, 0);
+    int pruned_root = strict_gt ? (root_lb > UB) : (root_lb >= UB);
+    if (!pruned_root) {
+        NODE(0)[0] = 0;
+        top = 1;
+    }
+    int64_t steps = 0, improvements = 0, max_stack = top;
+    int32_t *children = NULL, *lbs = NULL;
+    int64_t child_cap = 0;
+    unsigned char *sched = (unsigned char *)malloc((size_t)n);
+
+    while (top > 0 && nodes < node_budget) {
+        /* 2. selection */
+        int64_t first = top, nchild = 0;
+        while (first > 0) {
+            int32_t dtop = NODE(first - 1)[0];
+            int64_t c = n - dtop;
+            if (first < top && nchild + c > pool_cap) break;
+            nchild += c;
+            --first;
+        }
+        int64_t npar = top - first;
+        if (nchild > child_cap) {
+            child_cap = nchild;
+            children = (int32_t *)realloc(children, sizeof(int32_t) * (size_t)(n + 1) * (size_t)child_cap);
+            lbs = (int32_t *)realloc(lbs, sizeof(int32_t) * (size_t)child_cap);
+        }
+        /* 3. branching, parents in pop order (top of stack first) */
+        int64_t c = 0;
+        for (int64_t t = top - 1; t >= first; --t) {
+            int32_t *par = NODE(t);
+            int32_t d = par[0];
+            memset(sched, 0, (size_t)n);
+            for (int i = 0; i < d; ++i) sched[par[1 + i]] = 1;
+            for (int j = 0; j < n; ++j) {
+                if (sched[j]) continue;
+                int32_t *ch = children + c * (n + 1);
+                ch[0] = d + 1;
+                memcpy(ch + 1, par + 1, sizeof(int32_t) * (size_t)d);
+                ch[1 + d] = j;
+                ++c;
+            }
+        }
+        top = first;
+        /* 4. bounding */
+        for (int64_t i = 0; i < nchild; ++i) {
+            int32_t *ch = children + i * (n + 1);
+            lbs[i] = orc_bound(p, n, m, ch + 1, ch[0]);
+        }
+        nodes += nchild;
+        /* 5. complete children update the upper bound */
+        for (int64_t i = 0; i < nchild; ++i) {
+            int32_t *ch = children + i * (n + 1);
+            if (ch[0] == n && lbs[i] < UB) {
+                UB = lbs[i];
+                memcpy(inc, ch + 1, sizeof(int32_t) * (size_t)n);
+                have_inc = 1;
+                ++improvements;
+            }
+        }
+        /* 6. elimination and push in reverse child order */
+        int64_t pushed = 0, fp = 0;
+        for (int64_t i = nchild - 1; i >= 0; --i) {
+            int32_t *ch = children + i * (n + 1);
+            if (ch[0] == n) continue;
+            int keep = strict_gt ? !(lbs[i] > UB) : (lbs[i] < UB);
+            if (!keep) continue;
+            if (top >= cap_nodes) {
+                cap_nodes *= 2;
+                stack = (int32_t *)realloc(stack, sizeof(int32_t) * (size_t)(n + 1) * (size_t)cap_nodes);
+            }
+            memcpy(NODE(top), ch, sizeof(int32_t) * (size_t)(n + 1));
+            ++top;
+            ++pushed;
+            fp += pushed * (int64_t)(ch[ch[0]] + 1);
+        }
+        if (top > max_stack) max_stack = top;
+        if (steplog && steps < steplog_cap) {
+            int64_t *s = steplog + steps * 6;
+            s[0] = npar; s[1] = nchild; s[2] = UB; s[3] = pushed; s[4] = top; s[5] = fp;
+        }
+        ++steps;
+    }
+#undef NODE
+    res->ub = UB;
+    res->proven = (top == 0);
+    res->nodes_bounded = nodes;
+    res->steps = steps;
+    res->improvements = improvements;
+    res->max_stack = max_stack;
+    if (incumbent_out) {
+        if (have_inc) memcpy(incumbent_out, inc, sizeof(int32_t) * (size_t)n);
+        else for (int j = 0; j < n; ++j) incumbent_out[j] = -1;
+    }
+    free(sched); free(children); free(lbs); free(stack); free(inc);
+    return 0;
+}

@@ -1,0 +1,353 @@
+"""Pins of the oracle against facts fixed by the paper and by the mathematics.
+
+Each test ties the oracle to something other than itself: brute-force
+enumeration over completions, an independent path formulation of the
+makespan, closed forms, a hand-worked example and invariants.  A plausible
+slip in the oracle (a dropped lag, a wrong release, a swapped Johnson group,
+a wrong tail, an off-by-one in the pair list) fails at least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_3933_amd import gen
+
+
+def inst(n, m, seed, lo=1, hi=99):
+    return gen.processing_times(n, m, gen.make_seed(90, seed, 0), lo, hi)
+
+
+def path_makespan(p, seq, last_machine=None):
+    """Completion of seq on a machine as the longest monotone path through the
+    (position, machine) grid: independent of the recurrence used by the oracle."""
+    p = np.asarray(p)
+    m = p.shape[1] if last_machine is None else last_machine + 1
+    L = len(seq)
+    if L == 0:
+        return 0
+    best = 0
+    # a path is fixed by the positions where it steps down a machine
+    for cuts in itertools.combinations_with_replacement(range(L), m - 1):
+        tot = 0
+        pos = 0
+        for k in range(m):
+            end = cuts[k] if k < m - 1 else L - 1
+            tot += sum(int(p[seq[i], k]) for i in range(pos, end + 1))
+            pos = end
+        best = max(best, tot)
+    return best
+
+
+def brute_opt_python(p, prefix):
+    n = p.shape[0]
+    rest = [j for j in range(n) if j not in prefix]
+    return min(path_makespan(p, list(prefix) + list(t)) for t in itertools.permutations(rest))
+
+
+# --- makespan and brute force ------------------------------------------------
+
+@pytest.mark.parametrize("n,m,seed", [(4, 3, 1), (5, 4, 2), (3, 5, 3), (6, 2, 4)])
+def test_makespan_equals_longest_path(n, m, seed):
+    p = inst(n, m, seed)
+    for t, perm in enumerate(itertools.permutations(range(n))):
+        if t > 40:
+            break
+        for L in range(n + 1):
+            assert oracle.makespan(p, perm[:L]) == path_makespan(p, perm[:L])
+
+
+@pytest.mark.parametrize("n,m,seed", [(4, 3, 5), (5, 3, 6), (4, 4, 7)])
+def test_brute_force_matches_python_enumeration(n, m, seed):
+    p = inst(n, m, seed)
+    for prefix in [(), (0,), (2, 1), (n - 1,)]:
+        assert oracle.brute(p, prefix) == brute_opt_python(p, prefix)
+
+
+# --- hand-worked example -------------------------------------------------------
+
+def test_hand_worked_example():
+    # n = 2 jobs, m = 3 machines.
+    p = np.array([[3, 2, 4], [1, 5, 2]], np.int32)
+    # Root: releases 0, tails q = (min(6,7), min(4,2), 0) = (6, 2, 0).
+    # Pair (0,1), no lag: job1 (a=1<=b=5) first, then job0 (a=3>b=2):
+    #   t1=1, t2=max(0,1)+5=6; t1=4, t2=max(6,4)+2=8; +q1=2 -> 10.
+    # Pair (0,2), lags (2,5): both a<=b, keys a+L = 5 (job0), 6 (job1):
+    #   t1=3, t2=max(0,3+2)+4=9; t1=4, t2=max(9,4+5)+2=11; +0 -> 11.
+    # Pair (1,2), no lag: job0 (2<=4) then job1 (5>2):
+    #   t1=2, t2=6; t1=7, t2=max(6,7)+2=9 -> 9.
+    # LB = max(10, 11, 9) = 11; both permutations have makespan 12.
+    assert oracle.bound(p, []) == 11
+    assert oracle.pair_scan(p, [], 0, 1) == (8, 2)
+    assert oracle.pair_scan(p, [], 0, 2) == (11, 0)
+    assert oracle.pair_scan(p, [], 1, 2) == (9, 0)
+    assert oracle.bound(p, [0]) == 12
+    assert oracle.bound(p, [1]) == 12
+    assert oracle.makespan(p, [0, 1]) == 12 and oracle.makespan(p, [1, 0]) == 12
+    assert oracle.brute(p) == 12
+
+
+# --- closed forms --------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 11), (7, 4, 12), (30, 6, 13), (200, 20, 14), (500, 20, 15)])
+def test_leaf_bound_is_makespan(n, m, seed):
+    """Depth n: releases are the completion times, no pair scans anything, tails
+    are 0, so the bound is the makespan of the permutation."""
+    p = inst(n, m, seed)
+    prefixes, _ = gen.random_pool(n, 6, gen.make_seed(90, seed, 1))
+    for row in prefixes:
+        v = oracle.bound(p, row)
+        if n <= 7:
+            assert v == path_makespan(p, list(row))
+        assert v == oracle.makespan(p, row)
+
+
+@pytest.mark.parametrize("n,m,c", [(1, 2, 7), (4, 3, 5), (9, 5, 1), (20, 20, 99), (200, 20, 13)])
+def test_constant_times_closed_form(n, m, c):
+    """All times equal to c: every permutation has makespan (n+m-1)c and the
+    bound reaches it at every node (pair (0, m-1) alone gives (n+m-1)c)."""
+    p = np.full((n, m), c, np.int32)
+    prefixes, depths = gen.random_pool(n, 12, gen.make_seed(91, n, 1), 0, n)
+    for row, d in zip(prefixes, depths):
+        assert oracle.bound(p, row[:d]) == (n + m - 1) * c
+
+
+@pytest.mark.parametrize("n,m,b,B", [(5, 3, 1, 99), (12, 5, 2, 40), (30, 6, 3, 7), (200, 20, 9, 99)])
+def test_middle_bottleneck_closed_form(n, m, b, B):
+    """Machine b takes B for every job, every other machine takes 1.  Any
+    permutation then has makespan b + n*B + (m-1-b) (machine b is busy without
+    a gap from time b on), and the bound reaches it at every node through pair
+    (b-1, b) plus the tail m-1-b of machine b."""
+    p = np.ones((n, m), np.int32)
+    p[:, b] = B
+    want = b + n * B + (m - 1 - b)
+    prefixes, depths = gen.random_pool(n, 10, gen.make_seed(97, n, 1), 0, n)
+    for row, d in zip(prefixes, depths):
+        assert oracle.bound(p, row[:d]) == want
+    if n <= 6:
+        assert oracle.brute(p) == want
+
+
+@pytest.mark.parametrize("m", [2, 3, 7])
+def test_single_job(m):
+    p = inst(1, m, 20 + m)
+    assert oracle.bound(p, []) == int(p.sum())
+    assert oracle.bound(p, [0]) == int(p.sum())
+
+
+# --- brute force: validity and exactness --------------------------------------
+
+def all_prefixes(n, maxd):
+    for d in range(maxd + 1):
+        for pre in itertools.permutations(range(n), d):
+            yield pre
+
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 31), (6, 4, 32), (7, 5, 33), (8, 3, 34), (8, 6, 35)])
+def test_bound_never_exceeds_optimum(n, m, seed):
+    p = inst(n, m, seed)
+    checked = 0
+    for pre in all_prefixes(n, 2):
+        lb = oracle.bound(p, pre)
+        opt = oracle.brute(p, pre)
+        assert 0 < lb <= opt, (pre, lb, opt)
+        checked += 1
+    assert checked > 10
+
+
+@pytest.mark.parametrize("n,seed", [(3, 41), (5, 42), (6, 43), (7, 44), (8, 45)])
+def test_two_machines_bound_is_exact(n, seed):
+    """m = 2: one pair, no lag, and Johnson's rule is optimal with machine
+    availabilities r0 <= r1, so the bound equals the optimum of every node."""
+    p = inst(n, 2, seed)
+    for pre in all_prefixes(n, min(n, 3)):
+        assert oracle.bound(p, pre) == oracle.brute(p, pre), pre
+
+
+def test_two_machines_exact_with_ties():
+    p = inst(7, 2, 46, lo=1, hi=3)
+    for pre in all_prefixes(7, 2):
+        assert oracle.bound(p, pre) == oracle.brute(p, pre), pre
+
+
+# --- per-pair closed form: Johnson with lags is optimal for the relaxation ----
+
+def release_path(p, prefix, k):
+    return path_makespan(p, list(prefix), last_machine=k) if prefix else 0
+
+
+def two_machine_lag_value(a, b, L, rk, rl, order):
+    """Longest path of the two-machine relaxation with lags for one order: the
+    path either stays on machine l throughout, or switches from k to l at
+    some job u (passing through u's lag)."""
+    best = rl + sum(b[j] for j in order)
+    for u in range(len(order)):
+        v = rk + sum(a[order[i]] for i in range(u + 1)) + L[order[u]] \
+            + sum(b[order[i]] for i in range(u, len(order)))
+        best = max(best, v)
+    return best
+
+
+@pytest.mark.parametrize("n,m,seed,lo,hi", [(6, 4, 51, 1, 99), (7, 5, 52, 1, 99), (6, 6, 53, 1, 4)])
+def test_pair_scan_is_optimal_two_machine_relaxation(n, m, seed, lo, hi):
+    p = inst(n, m, seed, lo, hi)
+    for pre in [(), (1,), (0, 3), (n - 1, 2)]:
+        U = [j for j in range(n) if j not in pre]
+        for k in range(m):
+            for l in range(k + 1, m):
+                a = {j: int(p[j, k]) for j in U}
+                b = {j: int(p[j, l]) for j in U}
+                L = {j: int(p[j, k + 1:l].sum()) for j in U}
+                rk, rl = release_path(p, pre, k), release_path(p, pre, l)
+                best = min(two_machine_lag_value(a, b, L, rk, rl, o) for o in itertools.permutations(U))
+                t2, q = oracle.pair_scan(p, pre, k, l)
+                assert t2 == best, (pre, k, l)
+                assert q == min(int(p[j, l + 1:].sum()) for j in U)
+
+
+def test_bound_is_max_over_pairs():
+    p = inst(9, 5, 54)
+    for pre in [(), (4,), (3, 8, 0)]:
+        vals = [sum(oracle.pair_scan(p, pre, k, l)) for k in range(5) for l in range(k + 1, 5)]
+        assert oracle.bound(p, pre) == max(vals)
+
+
+# --- invariants ------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,seed", [(10, 5, 61), (25, 8, 62), (40, 10, 63)])
+def test_tie_breaks_do_not_change_the_bound(n, m, seed):
+    """Johnson's order is not unique under ties; the bound must not depend on
+    which optimal order is scanned (nor on the group of a == b jobs)."""
+    p = inst(n, m, seed, lo=1, hi=4)
+    prefixes, depths = gen.random_pool(n, 20, gen.make_seed(92, seed, 1))
+    for t, (row, d) in enumerate(zip(prefixes, depths)):
+        keys = gen.random_pool(n, 1, gen.make_seed(93, seed, t))[0][0]
+        ref = oracle.bound(p, row[:d])
+        assert oracle.bound_tie(p, row[:d], keys, False) == ref
+        assert oracle.bound_tie(p, row[:d], keys, True) == ref
+
+
+@pytest.mark.parametrize("n,m,seed", [(8, 4, 71), (20, 5, 72), (50, 10, 73)])
+def test_child_bound_not_below_parent(n, m, seed):
+    p = inst(n, m, seed)
+    prefixes, depths = gen.random_pool(n, 30, gen.make_seed(94, seed, 1), 0, n - 1)
+    for row, d in zip(prefixes, depths):
+        parent = oracle.bound(p, row[:d])
+        for j in row[d:]:
+            assert oracle.bound(p, list(row[:d]) + [j]) >= parent
+
+
+@pytest.mark.parametrize("n,m,seed", [(10, 4, 81), (30, 7, 82)])
+def test_table1_access_counts(n, m, seed):
+    """Table I: PTM n'm(m-1), LM n'm(m-1)/2, RM m(m-1), QM m(m-1)/2, MM m(m-1)."""
+    p = inst(n, m, seed)
+    P = m * (m - 1) // 2
+    prefixes, depths = gen.random_pool(n, 8, gen.make_seed(95, seed, 1), 0, n)
+    for row, d in zip(prefixes, depths):
+        _, c = oracle.bound_counted(p, row[:d])
+        nu = n - d
+        assert c == {"ptm": nu * m * (m - 1), "lm": nu * P, "rm": m * (m - 1), "qm": P, "mm": m * (m - 1)}
+
+
+def test_invalid_nodes():
+    p = inst(6, 3, 99)
+    assert oracle.bound(p, [0, 0]) == oracle.INVALID
+    assert oracle.bound(p, [6]) == oracle.INVALID
+    assert oracle.bound(p, [-1]) == oracle.INVALID
+    pre = np.zeros((2, 6), np.int32)
+    out = oracle.bound_pool(p, pre, np.array([7, -1], np.int32))
+    assert list(out) == [oracle.INVALID, oracle.INVALID]
+
+
+def test_pool_matches_single_calls():
+    p = inst(20, 5, 100)
+    prefixes, depths = gen.random_pool(20, 64, gen.make_seed(96, 0, 1))
+    out = oracle.bound_pool(p, prefixes, depths)
+    for i in range(64):
+        assert out[i] == oracle.bound(p, prefixes[i, :depths[i]])
+
+
+# --- NEH -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 111), (7, 4, 112), (8, 5, 113), (60, 10, 114)])
+def test_neh_is_a_valid_upper_bound(n, m, seed):
+    p = inst(n, m, seed)
+    ms, perm = oracle.neh(p)
+    assert sorted(perm.tolist()) == list(range(n))
+    assert oracle.makespan(p, perm) == ms
+    if n <= 8:
+        assert ms >= oracle.brute(p)
+    # the last job NEH inserts (smallest total, largest id among ties) sits at
+    # a best position: moving it anywhere else cannot shorten the schedule
+    tot = p.sum(axis=1)
+    last = sorted(range(n), key=lambda j: (-int(tot[j]), j))[-1]
+    rest = [j for j in perm.tolist() if j != last]
+    for pos in range(n):
+        assert oracle.makespan(p, rest[:pos] + [last] + rest[pos:]) >= ms
+
+
+# --- branch-and-bound -----------------------------------------------------------
+
+def expanded_count(p, ub):
+    """Nodes bounded by any pool-synchronous B&B started with UB0 = ub equal to
+    the optimum: the root plus all children of every node whose bound, and
+    the bound of each ancestor, is below ub (no leaf can improve ub)."""
+    n = p.shape[0]
+    total = 1
+    stack = [()] if oracle.bound(p, ()) < ub else []
+    while stack:
+        pre = stack.pop()
+        kids = [pre + (j,) for j in range(n) if j not in pre]
+        total += len(kids)
+        for c in kids:
+            if len(c) < n and oracle.bound(p, c) < ub:
+                stack.append(c)
+    return total
+
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 121), (6, 4, 122), (7, 3, 123), (8, 4, 124), (8, 2, 125)])
+def test_bnb_finds_the_optimum(n, m, seed):
+    p = inst(n, m, seed)
+    opt = oracle.brute(p)
+    neh_ms, neh_perm = oracle.neh(p)
+    for cap in [1, 3, 16, 1 << 20]:
+        r = oracle.bnb(p, neh_ms, neh_perm, pool_cap=cap)
+        assert r["proven"] and r["ub"] == opt
+        assert oracle.makespan(p, r["incumbent"]) == opt
+        r2 = oracle.bnb(p, 1 << 30, None, pool_cap=cap)
+        assert r2["proven"] and r2["ub"] == opt
+        assert oracle.makespan(p, r2["incumbent"]) == opt
+        r3 = oracle.bnb(p, 1 << 30, None, pool_cap=cap, strict_gt=True)
+        assert r3["proven"] and r3["ub"] == opt
+
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 131), (6, 4, 132), (7, 5, 133), (8, 3, 134)])
+def test_bnb_node_count_closed_form(n, m, seed):
+    """With UB0 = optimum the explored set does not depend on pool size or order."""
+    p = inst(n, m, seed)
+    opt = oracle.brute(p)
+    want = expanded_count(p, opt)
+    for cap in [1, 2, 7, 50, 1 << 20]:
+        r = oracle.bnb(p, opt, None, pool_cap=cap)
+        assert r["nodes_bounded"] == want and r["proven"] and r["ub"] == opt
+
+
+def test_bnb_budget_and_root_prune():
+    p = inst(10, 5, 141)
+    lb0 = oracle.bound(p, ())
+    r = oracle.bnb(p, lb0, None)
+    assert r["nodes_bounded"] == 1 and r["proven"] and r["steps"] == 0
+    r = oracle.bnb(p, 1 << 30, None, pool_cap=4, node_budget=30)
+    assert not r["proven"] and r["nodes_bounded"] >= 30
+
+
+def test_bnb_steplog_consistency():
+    p = inst(9, 4, 142)
+    ms, perm = oracle.neh(p)
+    r = oracle.bnb(p, ms, perm, pool_cap=20, steplog_cap=1 << 20)
+    log = r["steplog"]
+    assert log.shape[0] == r["steps"]
+    assert 1 + int(log[:, 1].sum()) == r["nodes_bounded"]
+    assert (log[:, 1] <= 20).all() or (log[:, 0] == 1).all()
+    assert int(log[-1, 4]) == 0
