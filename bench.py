@@ -1,0 +1,153 @@
+"""Benchmark: nodes bounded per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (the 200 jobs x 20 machines plain-bounding configuration): one seeded
+instance with processing times i.i.d. U[1,99], a pool of 262,144 nodes whose
+depths are uniform on 0..199 and whose prefixes are seeded random job
+sequences; inputs are resident in HBM before timing starts.  A step is one
+fsp_bound_pool call over the whole pool (decode + scan kernels).  Prints one
+JSON line.  The oracle leg times the plain C oracle on a bounded prefix of
+the same pool on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "nodes bounded/s at 200x20 (batched vs plain) + p50/p99 solve latency"
+N_JOBS, N_MACH, POOL = 200, 20, 262144
+CONFIG = 2
+# Peak of the unit the scan kernel is bound by: packed 16-bit integer VALU ops,
+# 256 CUs x 4 SIMDs x 16 lanes x 2 halves x 2.4 GHz.
+PEAK_U16_OPS = 256 * 4 * 16 * 2 * 2.4e9
+
+
+def algorithmic_scan_ops(n: int, m: int, depths: np.ndarray) -> float:
+    """Integer ops of the pair scans of one pool, counted as in Table I / Fig. 2:
+    per node and pair, n membership tests, 4 ops per unscheduled job (two
+    adds, a max and an add) and 2 for the tail and the max over pairs."""
+    P = m * (m - 1) // 2
+    nprime = (n - depths.astype(np.int64)).sum()
+    return float(P * (n * len(depths) + 4 * nprime + 2 * len(depths)))
+
+
+def cpu_baseline(p, pre, dep, sample: int, threads: int) -> dict:
+    import concurrent.futures as cf
+
+    import oracle
+    idx = np.arange(min(sample, len(dep)))
+    chunks = np.array_split(idx, threads * 4)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: oracle.bound_pool(p, pre[c], dep[c]), chunks))
+    dt = time.perf_counter() - t0
+    return {"value": len(idx) / dt, "unit": "nodes/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per core"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the bound path runs on "
+              "one device; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1208_3933_amd import fspbb, gen
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    fspbb.lib()
+
+    p = gen.processing_times(N_JOBS, N_MACH, gen.make_seed(CONFIG, 0, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(N_JOBS, POOL, gen.make_seed(CONFIG, 0, gen.PURPOSE_POOL))
+    print(f"[bench] workload ready: {N_JOBS}x{N_MACH}, pool {POOL}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    pre_d = torch.from_numpy(pre).to(dev)
+    dep_d = torch.from_numpy(dep).to(dev)
+    out = torch.empty(POOL, dtype=torch.int32, device=dev)
+    inst = fspbb.create_instance(p)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        fspbb.bound_pool(inst, pre_d, dep_d, out, stream)
+    torch.cuda.synchronize()
+    if fspbb.pool_status(inst, stream) != 0:
+        raise RuntimeError("invalid nodes in the benchmark pool")
+
+    # spot check against the oracle before timing
+    import oracle
+    got = out.cpu().numpy()
+    idx = np.arange(0, POOL, POOL // 64)
+    want = oracle.bound_pool(p, pre[idx], dep[idx])
+    if not (got[idx] == want).all():
+        raise RuntimeError("benchmark bounds differ from the oracle")
+
+    fspbb.timing_enable(inst, True)
+    fspbb.timing_read(inst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fspbb.bound_pool(inst, pre_d, dep_d, out, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dec_ms, scan_ms, launches = fspbb.timing_read(inst)
+    fspbb.timing_enable(inst, False)
+    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+
+    elapsed = t1 - t0
+    value = POOL * args.steps / elapsed
+    scan_avg_s = scan_ms / 1e3 / max(launches, 1)
+    ops = algorithmic_scan_ops(N_JOBS, N_MACH, dep)
+    achieved = ops / scan_avg_s / 1e12
+    peak = PEAK_U16_OPS / 1e12
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": "plain bounding, 200 jobs x 20 machines (190 pairs), U[1,99] times, "
+                               "pool of 262144 nodes, depths U{0..199}",
+                   "n": N_JOBS, "m": N_MACH, "pool": POOL, "kernel": "decode16 + scan16 (8 waves/group)"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "bound_scan16_kernel", "kernel_avg_ms": scan_avg_s * 1e3,
+                     "decode_avg_ms": dec_ms / max(launches, 1)},
+        "plain_nodes_per_s": value,
+    }
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads)
+    inst.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,138 @@
+/*
+ * fspbb.h - C ABI of the MI355X (gfx950) flow-shop bounding library.
+ *
+ * The library evaluates, on one GPU, the two-machine lower bound of
+ * Lageweg, Lenstra and Rinnooy Kan (built on Johnson's rule) over pools of
+ * permutation flow-shop sub-problems, and runs the branch-and-bound steps
+ * around it, after Melab, Chakroun, Mezmaz and Tuyttens, "A GPU-accelerated
+ * Branch-and-Bound Algorithm for the Flow-Shop Scheduling Problem".
+ *
+ * Conventions shared by every call:
+ *   - n jobs (0..n-1), m machines (0..m-1); p[j*m + k] is the processing time
+ *     of job j on machine k (the PTM matrix of Table I), row-major int32.
+ *   - A sub-problem (node) is a scheduled prefix pi(1..d) followed by the
+ *     unscheduled jobs (Sec. II-C).  A pool of N nodes is two device arrays:
+ *     prefixes[N*n] (row i holds its d_i scheduled jobs in order in its first
+ *     d_i entries; the rest of the row is ignored) and depths[N].
+ *   - "dev" pointers are HIP device pointers, "host" pointers are host
+ *     memory.  The caller owns every buffer it passes; the library never
+ *     frees them and keeps no reference after the call returns.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls marked "async" only enqueue work on that stream.
+ *   - Every call returns an fsp_status: 0 = success, < 0 = error, > 0 =
+ *     informational.  fsp_status_string() names each code.
+ */
+#ifndef FSPBB_H
+#define FSPBB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fsp_status;
+
+enum {
+    FSP_OK = 0,
+    FSP_E_INVAL = -1,     /* bad argument: null pointer, n < 1, m < 2, p < 0, N < 0 ... */
+    FSP_E_RANGE = -2,     /* a value could overflow the int32 arithmetic of the bound,
+                             or a buffer is too small for the result */
+    FSP_E_NOMEM = -3,     /* device or host allocation failed */
+    FSP_E_DEVICE = -4,    /* a HIP runtime call failed (see fsp_last_error_string) */
+    FSP_E_BADNODE = -5,   /* the pool held invalid nodes (their bound is FSP_LB_INVALID) */
+    FSP_E_NODEVICE = -6,  /* no gfx950 device is visible */
+    FSP_BUDGET = 1        /* a search stopped at its node budget without a proof */
+};
+
+/* Bound written for an invalid node: depth outside 0..n, a job outside
+ * 0..n-1, or a job repeated in the prefix. */
+#define FSP_LB_INVALID (-1)
+
+/* Opaque instance: owns host and device copies of the per-instance tables of
+ * Table I (PTM, LM, JM, the machine-pair list MM) and the per-job tails. */
+typedef struct fsp_instance_s *fsp_instance;
+
+typedef struct {
+    int32_t n, m;          /* jobs, machines */
+    int32_t pairs;         /* m(m-1)/2 machine pairs */
+    int32_t max_value;     /* (n+m-1) * max p: bound on every intermediate value */
+    int32_t packed16;      /* 1 when max_value < 65536: the fast 16-bit path is used */
+    int32_t reserved;
+    int64_t table_bytes;   /* device bytes held by the instance */
+} fsp_instance_info;
+
+/* Name of a status code (static string). */
+const char *fsp_status_string(fsp_status s);
+
+/* Text of the last HIP error seen by this thread (static buffer). */
+const char *fsp_last_error_string(void);
+
+/*
+ * fsp_create_instance - copy an instance and build its tables on the device
+ * (Sec. II-D: lags, Johnson-with-lags order per machine pair, computed once).
+ *   p    host, n*m int32, p[j*m+k] >= 0.  Copied; the caller may free it.
+ *   n    >= 1, m >= 2 (with one machine there is no pair and no bound).
+ *   out  host, receives the new instance.
+ * Errors: FSP_E_INVAL (null, n < 1, m < 2, n > 512, m > 32, p < 0),
+ * FSP_E_RANGE ((n+m-1) * max p >= 2^31), FSP_E_NOMEM, FSP_E_DEVICE,
+ * FSP_E_NODEVICE.  Uses the current HIP device; the instance's kernels must
+ * later run on that same device.
+ */
+fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_instance *out);
+
+/* Release an instance (synchronises the device first).  NULL is a no-op. */
+fsp_status fsp_destroy_instance(fsp_instance inst);
+
+/* Shape and table size of an instance. */
+fsp_status fsp_get_instance_info(fsp_instance inst, fsp_instance_info *info);
+
+/*
+ * fsp_bound_pool - lower bound of every node of a pool (Sec. III-A: one pool
+ * of sub-problems bounded in parallel on the GPU; the bound of Sec. II-D,
+ * Fig. 2).  Async on stream.
+ *   prefixes  dev, N*n int32, row i = the d_i scheduled jobs, then ignored.
+ *   depths    dev, N int32, 0 <= d_i <= n (d_i = n gives the makespan).
+ *   N         >= 0 (0 is a no-op).
+ *   out_lb    dev, N int32: bound of node i, or FSP_LB_INVALID.
+ * Invalid nodes do not stop the call: their row gets FSP_LB_INVALID, every
+ * other row is computed, and the instance's invalid-node counter is raised;
+ * fsp_pool_status() reads it.  Errors (returned at once): FSP_E_INVAL
+ * (null pointer with N > 0, N < 0), FSP_E_DEVICE (launch failure).
+ */
+fsp_status fsp_bound_pool(fsp_instance inst, const int32_t *prefixes, const int32_t *depths,
+                          int64_t N, int32_t *out_lb, void *stream);
+
+/*
+ * fsp_pool_status - synchronise stream, then return FSP_E_BADNODE if any
+ * invalid node was met by fsp_bound_pool on this instance since the last
+ * call (and clear the counter), else FSP_OK.  n_bad (host, may be NULL)
+ * receives the count.
+ */
+fsp_status fsp_pool_status(fsp_instance inst, void *stream, int64_t *n_bad);
+
+/*
+ * fsp_bound_pool_variant - like fsp_bound_pool with an explicit kernel
+ * variant (0 = automatic, 1 = general 32-bit lane-per-node kernel,
+ * 2 = 16-bit packed decode+scan kernels).  Used by tests and by the tuner to compare
+ * variants on the same pool.  FSP_E_INVAL for a variant the instance cannot
+ * run (2 needs max_value < 65536).
+ */
+fsp_status fsp_bound_pool_variant(fsp_instance inst, const int32_t *prefixes,
+                                  const int32_t *depths, int64_t N, int32_t *out_lb,
+                                  int32_t variant, void *stream);
+
+/*
+ * Kernel timing (instrumentation).  When enabled on an instance, each bound
+ * launch records HIP events on its stream around its decode and scan kernels.
+ * fsp_timing_read() waits for the recorded events, returns the summed device
+ * time of each kernel in milliseconds and the number of launches, and clears
+ * the record.  Enabling costs two event records per kernel launch.
+ */
+fsp_status fsp_timing_enable(fsp_instance inst, int32_t on);
+fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSPBB_H */

@@ -1,0 +1,129 @@
+// C ABI entry points of the bound path (include/fspbb.h).
+#include "fspbb_internal.h"
+
+using namespace fspbb;
+
+namespace {
+
+// Makes the instance's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+namespace fspbb {
+void timing_mark(fsp_instance_s *I, int which, hipStream_t s)
+{
+    if (!I->timing) return;
+    if (!I->timing_log) I->timing_log = new std::vector<TimingRecord>();
+    if (which == 0) {
+        TimingRecord r;
+        for (auto &e : r.ev) hipEventCreate(&e);
+        I->timing_log->push_back(r);
+    }
+    if (!I->timing_log->empty()) hipEventRecord(I->timing_log->back().ev[which], s);
+}
+}  // namespace fspbb
+
+namespace {
+
+fsp_status dispatch(fsp_instance inst, const int32_t *prefixes, const int32_t *depths, int64_t N,
+                    int32_t *out_lb, int variant, void *stream)
+{
+    if (!inst || N < 0) return FSP_E_INVAL;
+    if (N == 0) return FSP_OK;
+    if (!prefixes || !depths || !out_lb) return FSP_E_INVAL;
+    if (variant == 0) variant = inst->packed16 ? 2 : 1;
+    if (variant == 2 && !inst->packed16) return FSP_E_INVAL;
+    if (variant < 1 || variant > 2) return FSP_E_INVAL;
+    DeviceGuard g(inst->device);
+    if (!g.ok) return FSP_E_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = variant == 1 ? launch_bound_lane32(const_cast<fsp_instance_s *>(inst), prefixes, depths, N, out_lb, s)
+                                : launch_bound_packed(const_cast<fsp_instance_s *>(inst), prefixes, depths, N, out_lb, s);
+    if (e != hipSuccess) {
+        set_last_error(e);
+        return e == hipErrorOutOfMemory ? FSP_E_NOMEM : FSP_E_DEVICE;
+    }
+    return FSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsp_status fsp_bound_pool(fsp_instance inst, const int32_t *prefixes, const int32_t *depths, int64_t N,
+                          int32_t *out_lb, void *stream)
+{
+    return dispatch(inst, prefixes, depths, N, out_lb, 0, stream);
+}
+
+fsp_status fsp_bound_pool_variant(fsp_instance inst, const int32_t *prefixes, const int32_t *depths,
+                                  int64_t N, int32_t *out_lb, int32_t variant, void *stream)
+{
+    return dispatch(inst, prefixes, depths, N, out_lb, variant, stream);
+}
+
+fsp_status fsp_pool_status(fsp_instance inst, void *stream, int64_t *n_bad)
+{
+    if (!inst) return FSP_E_INVAL;
+    DeviceGuard g(inst->device);
+    if (!g.ok) return FSP_E_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long cnt = 0;
+    hipError_t e = hipMemcpyAsync(&cnt, inst->dt.bad, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemsetAsync(inst->dt.bad, 0, sizeof(cnt), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_last_error(e); return FSP_E_DEVICE; }
+    if (n_bad) *n_bad = (int64_t)cnt;
+    return cnt ? FSP_E_BADNODE : FSP_OK;
+}
+
+fsp_status fsp_timing_enable(fsp_instance inst, int32_t on)
+{
+    if (!inst) return FSP_E_INVAL;
+    inst->timing = on ? 1 : 0;
+    return FSP_OK;
+}
+
+fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms, int64_t *launches)
+{
+    if (!inst) return FSP_E_INVAL;
+    DeviceGuard g(inst->device);
+    double dsum = 0, ssum = 0;
+    int64_t cnt = 0;
+    hipError_t err = hipSuccess;
+    if (inst->timing_log) {
+        for (auto &r : *inst->timing_log) {
+            float a = 0, b = 0;
+            hipError_t e = hipEventSynchronize(r.ev[2]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&a, r.ev[0], r.ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, r.ev[1], r.ev[2]);
+            if (e != hipSuccess) err = e;
+            dsum += a;
+            ssum += b;
+            ++cnt;
+            for (auto &ev : r.ev) hipEventDestroy(ev);
+        }
+        inst->timing_log->clear();
+    }
+    if (decode_ms) *decode_ms = dsum;
+    if (scan_ms) *scan_ms = ssum;
+    if (launches) *launches = cnt;
+    if (err != hipSuccess) { set_last_error(err); return FSP_E_DEVICE; }
+    return FSP_OK;
+}
+
+}  // extern "C"

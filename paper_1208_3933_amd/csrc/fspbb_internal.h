@@ -1,0 +1,88 @@
+// Internal definitions of the gfx950 flow-shop bounding library (not part of
+// the C ABI).  Device tables follow Table I of the paper: PTM (times), LM
+// (lags), JM (Johnson order per machine pair), MM (pairs); the per-node RM
+// (releases) and QM (tails) are computed on the device from each prefix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/fspbb.h"
+
+namespace fspbb {
+
+constexpr int kMaxJobs = 512;      // largest n (bit masks fit a 16-word register vector)
+constexpr int kMaxMachines = 32;   // largest m
+constexpr int kGroup = 128;        // nodes per scan group in the 16-bit path (64 lanes x 2 halves)
+
+// Per-slot record of the general 32-bit kernel, in Johnson-with-lags order of
+// its pair: job word (j >> 5), job bit (j & 31), E = lag + a, C = b - a
+// (a = p[j][k], b = p[j][l]).  The pair scan is then s <- max(s, E) + C over
+// unscheduled jobs, where s = timeOnM2 - timeOnM1 of Fig. 2.
+struct Rec32 {
+    uint32_t word, bit;
+    int32_t E, C;
+};
+
+// Per-slot record of the 16-bit scan: LDS byte offset of the job's mask row
+// (j * 256) and (E << 16) | (C & 0xffff).  Padding slots point at an all-zero
+// row, so they leave the state unchanged.
+struct Rec16 {
+    uint32_t joff;
+    uint32_t ce;
+};
+
+// Kernel-side view of an instance (passed by value).
+struct DevTables {
+    int32_t n, m, P;
+    int32_t npad;             // slots per pair in rec16 (n rounded up to 4)
+    const int32_t *p32;       // (n+1) x 32, zero-padded; row n is zero (PTM)
+    const int32_t *colsum32;  // 32: sum over all jobs of p[j][k], zero-padded
+    const int32_t *tails32;   // n x 32: Q[j][l] = sum_{h>l} p[j][h], zero-padded
+    const int32_t *pairs;     // P x 2: (k, l), k < l, lexicographic (MM)
+    const Rec32 *rec32;       // P x n
+    const Rec16 *rec16;       // P x npad
+    const uint32_t *recw;     // n x P: slot-major records of the wave-per-node kernel:
+                              // job | (E << 9) | ((C + 32768) << ... ) see bound_wavepair.hip
+    unsigned long long *bad;  // invalid-node counter
+};
+
+}  // namespace fspbb
+
+// Event triples recorded around one bound launch (start, after decode, after scan).
+struct TimingRecord {
+    hipEvent_t ev[3];
+};
+
+struct fsp_instance_s {
+    int32_t n, m, P;
+    int32_t max_value;
+    int32_t packed16;
+    int device;
+    int64_t table_bytes;
+    void *dev_blob;
+    fspbb::DevTables dt;
+    // host copies (kept for the host-side search code)
+    int32_t *p_host;
+    // optional kernel timing
+    int timing = 0;
+    std::vector<TimingRecord> *timing_log = nullptr;
+};
+
+namespace fspbb {
+// Launchers (bound_*.hip).  Return a HIP error code.
+hipError_t launch_bound_lane32(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
+                               int64_t N, int32_t *out_lb, hipStream_t s);
+hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
+                               int64_t N, int32_t *out_lb, hipStream_t s);
+hipError_t launch_bound_wavepair(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
+                                 int64_t N, int32_t *out_lb, hipStream_t s);
+
+void set_last_error(hipError_t e);
+
+// Records event `which` (0 = start, 1 = after decode, 2 = after scan) of the
+// current launch when timing is on.  which = 0 opens a new record.
+void timing_mark(fsp_instance_s *I, int which, hipStream_t s);
+}  // namespace fspbb

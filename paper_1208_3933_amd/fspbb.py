@@ -1,0 +1,203 @@
+"""Thin ctypes binding of libfspbb.so (include/fspbb.h).
+
+Argument marshalling only: every step of the bound runs in the library's HIP
+kernels.  Device buffers are torch tensors (torch is used for device memory
+and streams); each function has the name of the C entry point it calls,
+without the ``fsp_`` prefix.  Importing this module does not need a GPU;
+calling into the library does, and the calls raise if the library has not
+been built (``python -m paper_1208_3933_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfspbb.so")
+
+OK = 0
+E_INVAL = -1
+E_RANGE = -2
+E_NOMEM = -3
+E_DEVICE = -4
+E_BADNODE = -5
+E_NODEVICE = -6
+BUDGET = 1
+LB_INVALID = -1
+
+VARIANT_AUTO = 0
+VARIANT_LANE32 = 1
+VARIANT_PACKED16 = 2
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+class FspError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} {last_error_string()}".strip())
+
+
+class InstanceInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("pairs", ctypes.c_int32),
+                ("max_value", ctypes.c_int32), ("packed16", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("table_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_SIGNATURES = {
+    "fsp_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "fsp_last_error_string": (ctypes.c_char_p, []),
+    "fsp_create_instance": (ctypes.c_int32, [_i32p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "fsp_destroy_instance": (ctypes.c_int32, [_vp]),
+    "fsp_get_instance_info": (ctypes.c_int32, [_vp, ctypes.POINTER(InstanceInfo)]),
+    "fsp_bound_pool": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "fsp_bound_pool_variant": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp]),
+    "fsp_pool_status": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "fsp_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
+    "fsp_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_3933_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().fsp_status_string(int(status)).decode()
+
+
+def last_error_string() -> str:
+    return lib().fsp_last_error_string().decode()
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise FspError(status, what)
+    return status
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_i32(t, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+class Instance:
+    """An instance created by fsp_create_instance (owns the device tables)."""
+
+    def __init__(self, p):
+        p = np.ascontiguousarray(p, dtype=np.int32)
+        if p.ndim != 2:
+            raise ValueError("p must be an n x m matrix")
+        self.n, self.m = int(p.shape[0]), int(p.shape[1])
+        h = _vp()
+        _check(lib().fsp_create_instance(p.ctypes.data_as(_i32p), self.n, self.m, ctypes.byref(h)),
+               "fsp_create_instance")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("instance destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        return get_instance_info(self)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fsp_destroy_instance(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def create_instance(p) -> Instance:
+    return Instance(p)
+
+
+def destroy_instance(inst: Instance) -> None:
+    inst.close()
+
+
+def get_instance_info(inst: Instance) -> dict:
+    info = InstanceInfo()
+    _check(lib().fsp_get_instance_info(inst.handle, ctypes.byref(info)), "fsp_get_instance_info")
+    return {f: getattr(info, f) for f, _ in InstanceInfo._fields_}
+
+
+def bound_pool(inst: Instance, prefixes, depths, out_lb, stream=None, variant: int = VARIANT_AUTO) -> None:
+    """Enqueue the bound of every node of a pool (async on the stream)."""
+    N = int(depths.shape[0])
+    a = _dev_i32(prefixes, "prefixes", (N, inst.n))
+    b = _dev_i32(depths, "depths", (N,))
+    c = _dev_i32(out_lb, "out_lb", (N,))
+    s = _stream_handle(stream)
+    if variant == VARIANT_AUTO:
+        st = lib().fsp_bound_pool(inst.handle, a, b, N, c, s)
+    else:
+        st = lib().fsp_bound_pool_variant(inst.handle, a, b, N, c, int(variant), s)
+    _check(st, "fsp_bound_pool")
+
+
+def bound_pool_variant(inst: Instance, prefixes, depths, out_lb, variant: int, stream=None) -> None:
+    bound_pool(inst, prefixes, depths, out_lb, stream, variant)
+
+
+def pool_status(inst: Instance, stream=None) -> int:
+    """Synchronise the stream; return the number of invalid nodes met since the last call."""
+    n_bad = ctypes.c_int64(0)
+    st = lib().fsp_pool_status(inst.handle, _stream_handle(stream), ctypes.byref(n_bad))
+    if st != E_BADNODE:
+        _check(st, "fsp_pool_status")
+    return int(n_bad.value)
+
+
+def timing_enable(inst: Instance, on: bool = True) -> None:
+    _check(lib().fsp_timing_enable(inst.handle, int(bool(on))), "fsp_timing_enable")
+
+
+def timing_read(inst: Instance):
+    """(decode_ms, scan_ms, launches) summed over the launches since the last read."""
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(lib().fsp_timing_read(inst.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "fsp_timing_read")
+    return a.value, b.value, int(c.value)

@@ -1,0 +1,69 @@
+"""The C ABI library loads and exports every symbol its header declares, and
+argument checks that need no device behave as documented (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1208_3933_amd import fspbb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(fsp_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for want in ["fsp_create_instance", "fsp_destroy_instance", "fsp_bound_pool", "fsp_pool_status"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = fspbb.lib()
+    missing = [n for n in declared_symbols() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for code in [0, -1, -2, -3, -4, -5, -6, 1]:
+        assert fspbb.status_string(code).startswith("FSP_")
+
+
+@pytest.mark.parametrize("n,m,bad", [(0, 5, None), (5, 1, None), (513, 5, None), (5, 33, None),
+                                     (4, 3, (1, 2, -7))])
+def test_create_instance_rejects_bad_arguments(n, m, bad):
+    L = fspbb.lib()
+    p = np.ones((max(n, 1), max(m, 1)), np.int32)
+    if bad:
+        p[bad[0], bad[1]] = bad[2]
+    h = ctypes.c_void_p()
+    st = L.fsp_create_instance(p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n, m, ctypes.byref(h))
+    assert st == fspbb.E_INVAL and not h.value
+
+
+def test_create_instance_rejects_overflow():
+    L = fspbb.lib()
+    p = np.full((100, 20), 30_000_000, np.int32)
+    h = ctypes.c_void_p()
+    st = L.fsp_create_instance(p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 100, 20, ctypes.byref(h))
+    assert st == fspbb.E_RANGE
+
+
+def test_null_arguments():
+    L = fspbb.lib()
+    assert L.fsp_create_instance(None, 3, 3, None) == fspbb.E_INVAL
+    assert L.fsp_bound_pool(None, None, None, 0, None, None) == fspbb.E_INVAL
+    assert L.fsp_destroy_instance(None) == fspbb.OK
+    assert L.fsp_get_instance_info(None, None) == fspbb.E_INVAL
+    assert L.fsp_pool_status(None, None, None) == fspbb.E_INVAL

@@ -1,0 +1,177 @@
+"""GPU bounds against the oracle, element by element, through the C ABI.
+
+Bounds are integers: the bar is bit-exact equality.  Small configurations are
+checked on every node; the 200 x 20 pool of 262,144 nodes (the size and launch
+the benchmark times) is checked on a seeded sample against the oracle and on
+every node against the second kernel family, plus leaf rows against the
+makespan.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import CONFIG_SHAPES, oracle_bounds, require_gpu, to_dev, workload
+from paper_1208_3933_amd import fspbb, gen
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16]
+
+
+def gpu_bounds(torch, inst, pre, dep, variant=fspbb.VARIANT_AUTO):
+    pre_d, dep_d = to_dev(torch, pre, dep)
+    out = torch.full((dep.shape[0],), -7, dtype=torch.int32, device="cuda")
+    fspbb.bound_pool(inst, pre_d, dep_d, out, variant=variant)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("config", [0, 1])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_pool_parity(config, variant):
+    torch = require_gpu()
+    n, m, N = CONFIG_SHAPES[config]
+    p, pre, dep = workload(config, n, m, N)
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        got = gpu_bounds(torch, inst, pre, dep, variant)
+        assert fspbb.pool_status(inst) == 0
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first {bad[:5]}: got {got[bad[:5]]} want {want[bad[:5]]}"
+
+
+def test_200x20_full_pool_sampled_parity():
+    torch = require_gpu()
+    n, m, N = CONFIG_SHAPES[2]
+    p, pre, dep = workload(2, n, m, N)
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 1
+        got = gpu_bounds(torch, inst, pre, dep)                           # the benchmarked launch
+        got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)   # the other kernel family
+        assert fspbb.pool_status(inst) == 0
+    assert (got == got32).all()
+    idx = np.unique(gen.splitmix64(gen.make_seed(2, 0, 9), 3000) % np.uint64(N)).astype(np.int64)
+    want = oracle_bounds(p, pre[idx], dep[idx])
+    assert (got[idx] == want).all()
+    leaves = np.nonzero(dep == n - 1)[0][:50]
+    for i in leaves:  # one job left: the child leaf's makespan bounds it from above
+        full = list(pre[i])
+        assert got[i] <= oracle.makespan(p, full)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("N", [1, 63, 127, 129, 257, 1000])
+def test_ragged_pool_sizes(variant, N):
+    torch = require_gpu()
+    p, pre, dep = workload(10, 30, 7, N, instance=N)
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        assert (gpu_bounds(torch, inst, pre, dep, variant) == want).all()
+
+
+def test_empty_pool_is_a_noop():
+    torch = require_gpu()
+    p, _, _ = workload(11, 10, 4, 1)
+    with fspbb.create_instance(p) as inst:
+        e = torch.zeros((0, 10), dtype=torch.int32, device="cuda")
+        d = torch.zeros((0,), dtype=torch.int32, device="cuda")
+        o = torch.zeros((0,), dtype=torch.int32, device="cuda")
+        fspbb.bound_pool(inst, e, d, o)
+        assert fspbb.pool_status(inst) == 0
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_root_and_leaves(variant):
+    """Depth 0 (the root) and depth n (complete permutations: the makespan)."""
+    torch = require_gpu()
+    n, m = 40, 9
+    p, pre, _ = workload(12, n, m, 300)
+    dep = np.where(np.arange(300) % 2 == 0, 0, n).astype(np.int32)
+    with fspbb.create_instance(p) as inst:
+        got = gpu_bounds(torch, inst, pre, dep, variant)
+    root = oracle.bound(p, [])
+    for i in range(300):
+        want = root if dep[i] == 0 else oracle.makespan(p, pre[i])
+        assert got[i] == want
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_two_machines_is_exact(variant):
+    torch = require_gpu()
+    n = 7
+    p, pre, dep = workload(13, n, 2, 200)
+    with fspbb.create_instance(p) as inst:
+        got = gpu_bounds(torch, inst, pre, dep, variant)
+    for i in range(200):
+        assert got[i] == oracle.brute(p, pre[i, :dep[i]])
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("n,m,lo,hi", [(1, 2, 1, 99), (1, 32, 1, 99), (33, 32, 1, 99), (64, 3, 1, 3),
+                                       (65, 17, 1, 99), (512, 4, 1, 30), (96, 20, 1, 2)])
+def test_shape_and_value_edges(variant, n, m, lo, hi):
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(14, n * 100 + m, 0), lo, hi)
+    pre, dep = gen.random_pool(n, 400, gen.make_seed(14, n * 100 + m, 1), 0, n)
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        assert (gpu_bounds(torch, inst, pre, dep, variant) == want).all()
+
+
+def test_large_values_use_the_32bit_kernel():
+    torch = require_gpu()
+    n, m = 50, 10
+    p = gen.processing_times(n, m, gen.make_seed(15, 0, 0), 1, 100000)
+    pre, dep = gen.random_pool(n, 700, gen.make_seed(15, 0, 1))
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 0
+        assert (gpu_bounds(torch, inst, pre, dep) == want).all()
+        with pytest.raises(fspbb.FspError):
+            gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_PACKED16)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_invalid_nodes(variant):
+    torch = require_gpu()
+    n, m, N = 20, 5, 500
+    p, pre, dep = workload(16, n, m, N)
+    pre = pre.copy()
+    dep = dep.copy()
+    dep[3] = n + 1
+    dep[4] = -1
+    dep[5] = 5; pre[5, 4] = pre[5, 0]          # repeated job
+    dep[6] = 3; pre[6, 1] = n                  # job out of range
+    dep[7] = 2; pre[7, 0] = -3                 # negative job
+    dep[8] = 2; pre[8, 2] = 999                # junk after the prefix is ignored
+    want = oracle_bounds(p, pre, dep)
+    assert (want[[3, 4, 5, 6, 7]] == oracle.INVALID).all() and want[8] != oracle.INVALID
+    with fspbb.create_instance(p) as inst:
+        got = gpu_bounds(torch, inst, pre, dep, variant)
+        assert fspbb.pool_status(inst) == 5
+        assert fspbb.pool_status(inst) == 0
+    assert (got == want).all()
+
+
+def test_500x20_sampled():
+    torch = require_gpu()
+    n, m, N = 500, 20, 4096
+    p, pre, dep = workload(4, n, m, N)
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 1
+        got = gpu_bounds(torch, inst, pre, dep)
+        got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)
+    assert (got == got32).all()
+    idx = np.arange(0, N, 16)
+    assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
+
+
+def test_ties_heavy_instance():
+    torch = require_gpu()
+    n, m = 60, 12
+    p = gen.processing_times(n, m, gen.make_seed(17, 0, 0), 1, 3)
+    pre, dep = gen.random_pool(n, 2000, gen.make_seed(17, 0, 1))
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        for v in VARIANTS:
+            assert (gpu_bounds(torch, inst, pre, dep, v) == want).all()
