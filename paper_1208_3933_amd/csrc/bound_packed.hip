@@ -16,6 +16,9 @@
 // per-slot records (mask-row offset, lag + a, b - a) are wave-uniform scalar
 // loads; only the mask is per lane.  Per slot and wave: one address add, one
 // LDS read, one packed max, one packed add and one bitwise select.
+#include <algorithm>
+#include <cstdlib>
+
 #include "bound_common.h"
 
 namespace fspbb {
@@ -25,46 +28,178 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u16x2 as16(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t as32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
 
-// Workspace of one pool, G = ceil(N / 128) groups.
+// Workspace of one pool, G = ceil(N / 128) groups.  Nodes are decoded and
+// scanned in depth order (order[i] = original index of the i-th node), so the
+// lanes of a wave walk prefixes of nearly equal length.
 struct Workspace16 {
-    uint32_t *dec;  // G x 3 x m x 64 dwords: releases R, closing sums Tk, tails Q
-    uint32_t *flg;  // G x NW x 128 dwords: unscheduled-job bits per node
-    uint32_t *st;   // G*128: 1 = valid node
+    uint32_t *dec;    // G x 3 x m x 64 dwords: releases R, closing sums Tk, tails Q
+    uint32_t *flg;    // G x NW x 128 dwords: unscheduled-job bits per node
+    uint32_t *st;     // G*128: 1 = valid node
+    int32_t *order;   // N: node index at each depth-sorted position
+    uint32_t *cnt;    // (n + 2) x B: per-block depth counts, then scatter offsets
 };
 
+// ---- counting sort of node indices by depth (bucket n+1 holds invalid depths)
+
+__device__ __forceinline__ int depth_bucket(int d, int n) { return (d >= 0 && d <= n) ? d : n + 1; }
+
+__global__ __launch_bounds__(256) void depth_count_kernel(const int32_t *__restrict__ depths, int64_t N, int n,
+                                                          int64_t chunk, int B, uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t h[];
+    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(N, lo + chunk);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[depth_bucket(depths[i], n)], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cnt[(int64_t)b * B + blockIdx.x] = h[b];
+}
+
+// Exclusive prefix sum of cnt[0..total) in place, one block of 1024 threads.
+__global__ __launch_bounds__(1024) void depth_scan_kernel(uint32_t *__restrict__ cnt, int64_t total)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (total + 1023) / 1024, lo = t * per, hi = min(total, lo + per);
+    uint32_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(256) void depth_scatter_kernel(const int32_t *__restrict__ depths, int64_t N, int n,
+                                                            int64_t chunk, int B, const uint32_t *__restrict__ cnt,
+                                                            int32_t *__restrict__ order)
+{
+    extern __shared__ uint32_t cur[];
+    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cur[b] = cnt[(int64_t)b * B + blockIdx.x];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(N, lo + chunk);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint32_t pos = atomicAdd(&cur[depth_bucket(depths[i], n)], 1u);
+        order[pos] = (int32_t)i;
+    }
+}
+
+// ---- decode: one lane per node, nodes taken in depth order
+//
+// Computes for each node its scheduled set (rejecting out-of-range and
+// repeated jobs), the completion times of its prefix on every machine (the
+// releases, RM of Table I), the time of the unscheduled jobs on each machine,
+// and the tails (QM of Table I: least time left after machine l over the
+// unscheduled jobs).  MV = m rounded up to a multiple of 4.  The processing
+// times are staged in LDS; the tails are taken two machines at a time with
+// packed 16-bit minima over a scalar-loaded table.
 template <int MV>
 __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const int32_t *__restrict__ prefixes,
                                                              const int32_t *__restrict__ depths, int64_t N,
                                                              int64_t Npad, Workspace16 W,
                                                              int32_t *__restrict__ out_lb)
 {
-    __shared__ uint32_t bits[kMaskWords * 256];
-    const int tid = threadIdx.x;
-    const int64_t node = (int64_t)blockIdx.x * 256 + tid;
-    if (node >= Npad) return;
-    const bool live = node < N;
+    extern __shared__ uint32_t sm[];
+    uint32_t *bits = sm;                                      // 16 words x 256 lanes
+    int32_t *ptab = reinterpret_cast<int32_t *>(sm + kMaskWords * 256);  // (n+1) x MV
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
-    const int d = live ? depths[node] : 0;
-    Decoded<MV> D;
-    decode_node<MV>(T, prefixes + (live ? node : 0) * (int64_t)n, d, bits + tid, 256, D);
-    const bool ok = live && D.ok;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < (n + 1) * MV; e += 256) ptab[e] = T.p32[(e / MV) * kMaxMachines + (e % MV)];
+    __syncthreads();
 
-    const int64_t G = node >> 7;
-    const int g = (int)(node & 127), lane = g & 63, half = g >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    if (i >= Npad) return;
+    const bool live = i < N;
+    const int64_t node = live ? W.order[i] : 0;
+    int d = live ? depths[node] : 0;
+    bool ok = live && d >= 0 && d <= n;
+    if (!ok) d = 0;
+
+    uint32_t *mybits = bits + tid;
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) mybits[w * 256] = 0u;
+    int32_t C[MV], S[MV];
+#pragma unroll
+    for (int k = 0; k < MV; ++k) { C[k] = 0; S[k] = 0; }
+    const int32_t *row = prefixes + node * (int64_t)n;
+    for (int t = 0; t < d; t += 4) {
+        int32_t jj[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) jj[c] = row[min(t + c, n - 1)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (t + c < d && ok) {
+                const int j = jj[c];
+                if ((unsigned)j >= (unsigned)n) { ok = false; continue; }
+                const uint32_t bit = 1u << (j & 31);
+                const uint32_t old = atomicOr(&mybits[(j >> 5) * 256], bit);
+                if (old & bit) { ok = false; continue; }
+                const int4 *pr = reinterpret_cast<const int4 *>(ptab + j * MV);
+                int32_t prev = 0;
+#pragma unroll
+                for (int q = 0; q < MV / 4; ++q) {
+                    const int4 v = pr[q];
+                    const int32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) {
+                        const int k = 4 * q + cc;
+                        const int32_t ck = max(C[k], prev) + x[cc];
+                        C[k] = ck;
+                        prev = ck;
+                        S[k] += x[cc];
+                    }
+                }
+            }
+        }
+    }
+
+    u32v<kMaskWords> act;
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) {
+        const int lo = w * 32;
+        const uint32_t valid = n >= lo + 32 ? 0xffffffffu : (n <= lo ? 0u : ((1u << (n - lo)) - 1u));
+        act[w] = ok ? (~mybits[w * 256] & valid) : 0u;
+    }
+    // tails, two machines per register: q = min over jobs of (Q | inactive mask)
+    uint32_t q2[MV / 2];
+#pragma unroll
+    for (int c = 0; c < MV / 2; ++c) q2[c] = 0xffffffffu;
+    for (int j = 0; j < n; ++j) {
+        const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)act[j >> 5], j & 31, 1);
+        cptr<uint32_t> qr = as_const(T.tails16 + (size_t)j * (kMaxMachines / 2));
+#pragma unroll
+        for (int c = 0; c < MV / 2; ++c)
+            q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
+    }
+
+    const bool empty = d == n;  // no unscheduled job: every tail is 0
+    const int64_t G = i >> 7;
+    const int g = (int)(i & 127), lane = g & 63, half = g >> 6;
     uint16_t *d16 = reinterpret_cast<uint16_t *>(W.dec);
+    cptr<int32_t> cs = as_const(T.colsum32);
 #pragma unroll
     for (int k = 0; k < MV; ++k) {
         if (k < m) {
-            d16[((G * 3 + 0) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? D.R[k] : 0);
-            d16[((G * 3 + 1) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? D.Tk[k] : 0);
-            d16[((G * 3 + 2) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? D.Qv[k] : 0);
+            const uint32_t qk = (q2[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+            d16[((G * 3 + 0) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[k] : 0);
+            d16[((G * 3 + 1) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[k] + (cs[k] - S[k]) : 0);
+            d16[((G * 3 + 2) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok && !empty ? qk : 0u);
         }
     }
 #pragma unroll
     for (int w = 0; w < kMaskWords; ++w)
-        if (w < NW) W.flg[(G * NW + w) * 128 + g] = ok ? D.act[w] : 0u;
-    W.st[node] = ok ? 1u : 0u;
-    if (live && !D.ok) {
+        if (w < NW) W.flg[(G * NW + w) * 128 + g] = act[w];
+    W.st[i] = ok ? 1u : 0u;
+    if (live && !ok) {
         out_lb[node] = FSP_LB_INVALID;
         atomicAdd(T.bad, 1ull);
     }
@@ -80,7 +215,71 @@ __device__ __forceinline__ void scan_step(u16x2 &s, const unsigned char *lds_lan
     s = as16((msk & as32(t)) | (~msk & as32(s)));
 }
 
-template <int WAVES>
+// Mask rows of UNR slots through the LDS "add thread id" read: for each slot
+// M0 = row offset, and every lane reads the dword at M0 + 4 * lane, so no
+// vector instruction is spent on addresses.  M0 is saved and restored; the
+// block waits for its own reads (scalar loads are then complete as well).
+// A write of M0 by a scalar instruction needs one wait state before the read.
+// The scalar adds write SCC, which the block declares clobbered.
+template <int UNR>
+__device__ __forceinline__ void gather_rows_addtid(uint32_t (&x)[UNR], const uint32_t (&joff)[UNR], uint32_t base);
+
+#define FSP_ADDTID_1(i) "s_add_u32 m0, %[j" #i "], %[base]\n\ts_nop 0\n\tds_read_addtid_b32 %[x" #i "]\n\t"
+
+template <>
+__device__ __forceinline__ void gather_rows_addtid<8>(uint32_t (&x)[8], const uint32_t (&joff)[8], uint32_t base)
+{
+    uint32_t save;
+    asm volatile("s_mov_b32 %[sv], m0\n\t"
+                 FSP_ADDTID_1(0) FSP_ADDTID_1(1) FSP_ADDTID_1(2) FSP_ADDTID_1(3)
+                 FSP_ADDTID_1(4) FSP_ADDTID_1(5) FSP_ADDTID_1(6) FSP_ADDTID_1(7)
+                 "s_waitcnt lgkmcnt(0)\n\t"
+                 "s_mov_b32 m0, %[sv]"
+                 : [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [x3] "=&v"(x[3]),
+                   [x4] "=&v"(x[4]), [x5] "=&v"(x[5]), [x6] "=&v"(x[6]), [x7] "=&v"(x[7]), [sv] "=&s"(save)
+                 : [j0] "s"(joff[0]), [j1] "s"(joff[1]), [j2] "s"(joff[2]), [j3] "s"(joff[3]),
+                   [j4] "s"(joff[4]), [j5] "s"(joff[5]), [j6] "s"(joff[6]), [j7] "s"(joff[7]),
+                   [base] "s"(base)
+                 : "scc");
+}
+
+template <>
+__device__ __forceinline__ void gather_rows_addtid<4>(uint32_t (&x)[4], const uint32_t (&joff)[4], uint32_t base)
+{
+    uint32_t save;
+    asm volatile("s_mov_b32 %[sv], m0\n\t"
+                 FSP_ADDTID_1(0) FSP_ADDTID_1(1) FSP_ADDTID_1(2) FSP_ADDTID_1(3)
+                 "s_waitcnt lgkmcnt(0)\n\t"
+                 "s_mov_b32 m0, %[sv]"
+                 : [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [x3] "=&v"(x[3]), [sv] "=&s"(save)
+                 : [j0] "s"(joff[0]), [j1] "s"(joff[1]), [j2] "s"(joff[2]), [j3] "s"(joff[3]),
+                   [base] "s"(base)
+                 : "scc");
+}
+
+template <>
+__device__ __forceinline__ void gather_rows_addtid<16>(uint32_t (&x)[16], const uint32_t (&joff)[16], uint32_t base)
+{
+    uint32_t lo[8], hi[8];
+    const uint32_t jl[8] = {joff[0], joff[1], joff[2], joff[3], joff[4], joff[5], joff[6], joff[7]};
+    const uint32_t jh[8] = {joff[8], joff[9], joff[10], joff[11], joff[12], joff[13], joff[14], joff[15]};
+    gather_rows_addtid<8>(lo, jl, base);
+    gather_rows_addtid<8>(hi, jh, base);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) { x[c] = lo[c]; x[8 + c] = hi[c]; }
+}
+#undef FSP_ADDTID_1
+
+__device__ __forceinline__ void scan_update(u16x2 &s, uint32_t msk, uint32_t ce)
+{
+    const unsigned short e = (unsigned short)(ce >> 16), c = (unsigned short)ce;
+    const u16x2 E = {e, e};
+    const u16x2 C = {c, c};
+    const u16x2 t = __builtin_elementwise_max(s, E) + C;
+    s = as16((msk & as32(t)) | (~msk & as32(s)));
+}
+
+template <int WAVES, int UNR, bool ADDTID>
 __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, Workspace16 W, int64_t N,
                                                                   int32_t *__restrict__ out_lb)
 {
@@ -102,6 +301,9 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
     __syncthreads();
 
     const unsigned char *lds_lane = reinterpret_cast<const unsigned char *>(lds) + lane * 4;
+    // LDS byte address of the mask rows (M0-relative reads add it to each row offset)
+    const uint32_t lds_base = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t *)lds);
     const uint32_t *dR = W.dec + (G * 3 + 0) * m * 64 + lane;
     const uint32_t *dT = dR + m * 64;
     const uint32_t *dQ = dT + m * 64;
@@ -111,10 +313,28 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
         u16x2 s = as16(dR[l * 64]) - as16(dR[k * 64]);
         const uint32_t tk = dT[k * 64], ql = dQ[l * 64];
         cptr<uint32_t> rec = as_const(reinterpret_cast<const uint32_t *>(T.rec16 + (size_t)pr * T.npad));
-        for (int i = 0; i < 2 * T.npad; i += 8) {
+        const int nslots = T.npad;  // multiple of 4; padding slots read the zero row
+        int i = 0;
+        for (; i + UNR <= nslots; i += UNR) {
+            uint32_t r[2 * UNR];
+#pragma unroll
+            for (int c = 0; c < 2 * UNR; ++c) r[c] = rec[2 * i + c];
+            if constexpr (ADDTID) {
+                uint32_t jo[UNR], x[UNR];
+#pragma unroll
+                for (int c = 0; c < UNR; ++c) jo[c] = r[2 * c];
+                gather_rows_addtid<UNR>(x, jo, lds_base);
+#pragma unroll
+                for (int c = 0; c < UNR; ++c) scan_update(s, x[c], r[2 * c + 1]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 2 * UNR; c += 2) scan_step(s, lds_lane, r[c], r[c + 1]);
+            }
+        }
+        for (; i < nslots; i += 4) {
             uint32_t r[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) r[c] = rec[i + c];
+            for (int c = 0; c < 8; ++c) r[c] = rec[2 * i + c];
 #pragma unroll
             for (int c = 0; c < 8; c += 2) scan_step(s, lds_lane, r[c], r[c + 1]);
         }
@@ -129,17 +349,60 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
 #pragma unroll
         for (int w = 1; w < WAVES; ++w) best = __builtin_elementwise_max(best, as16(lds[w * 64 + lane]));
         const int64_t a = G * 128 + lane, b = a + 64;
-        if (a < N && W.st[a]) out_lb[a] = (int32_t)best.x;
-        if (b < N && W.st[b]) out_lb[b] = (int32_t)best.y;
+        if (a < N && W.st[a]) out_lb[W.order[a]] = (int32_t)best.x;
+        if (b < N && W.st[b]) out_lb[W.order[b]] = (int32_t)best.y;
     }
 }
 
 static int scan_waves(int P)
 {
+    if (const char *e = getenv("FSPBB_SCAN_WAVES")) {
+        const int w = atoi(e);
+        if (w == 1 || w == 2 || w == 4 || w == 8 || w == 16) return w;
+    }
+    if (P >= 128) return 16;
     if (P >= 64) return 8;
     if (P >= 16) return 4;
     if (P >= 4) return 2;
     return 1;
+}
+
+static int scan_unroll()
+{
+    if (const char *e = getenv("FSPBB_SCAN_UNROLL")) {
+        const int u = atoi(e);
+        if (u == 4 || u == 8 || u == 16) return u;
+    }
+    return 16;
+}
+
+static bool scan_addtid()
+{
+    if (const char *e = getenv("FSPBB_SCAN_ADDTID")) return atoi(e) != 0;
+    return true;
+}
+
+template <int WAVES, bool ADDTID>
+static void launch_scan_u(int unr, dim3 grid, size_t lds_b, hipStream_t s, const DevTables &dt,
+                          const Workspace16 &W, int64_t N, int32_t *out_lb)
+{
+    const dim3 block(64 * WAVES);
+    if (unr == 4)
+        bound_scan16_kernel<WAVES, 4, ADDTID><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+    else if (unr == 16)
+        bound_scan16_kernel<WAVES, 16, ADDTID><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+    else
+        bound_scan16_kernel<WAVES, 8, ADDTID><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+}
+
+template <int WAVES>
+static void launch_scan(int unr, dim3 grid, size_t lds_b, hipStream_t s, const DevTables &dt, const Workspace16 &W,
+                        int64_t N, int32_t *out_lb)
+{
+    if (scan_addtid())
+        launch_scan_u<WAVES, true>(unr, grid, lds_b, s, dt, W, N, out_lb);
+    else
+        launch_scan_u<WAVES, false>(unr, grid, lds_b, s, dt, W, N, out_lb);
 }
 
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
@@ -148,34 +411,51 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
     if (N <= 0) return hipSuccess;
     const int n = I->n, m = I->m, NW = (n + 31) >> 5;
     const int64_t G = (N + kGroup - 1) / kGroup, Npad = G * kGroup;
-    const size_t dec_b = (size_t)G * 3 * m * 64 * 4, flg_b = (size_t)G * NW * 128 * 4, st_b = (size_t)Npad * 4;
+    const int B = (int)std::min<int64_t>(1024, (N + 4095) / 4096);
+    const int64_t chunk = (N + B - 1) / B;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t dec_b = al((size_t)G * 3 * m * 64 * 4), flg_b = al((size_t)G * NW * 128 * 4),
+                 st_b = al((size_t)Npad * 4), ord_b = al((size_t)N * 4), cnt_b = al((size_t)(n + 2) * B * 4);
     void *ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, dec_b + flg_b + st_b, s);
+    hipError_t e = hipMallocAsync(&ws, dec_b + flg_b + st_b + ord_b + cnt_b, s);
     if (e != hipSuccess) return e;
+    char *w = (char *)ws;
     Workspace16 W;
-    W.dec = (uint32_t *)ws;
-    W.flg = (uint32_t *)((char *)ws + dec_b);
-    W.st = (uint32_t *)((char *)ws + dec_b + flg_b);
+    W.dec = (uint32_t *)w;
+    W.flg = (uint32_t *)(w + dec_b);
+    W.st = (uint32_t *)(w + dec_b + flg_b);
+    W.order = (int32_t *)(w + dec_b + flg_b + st_b);
+    W.cnt = (uint32_t *)(w + dec_b + flg_b + st_b + ord_b);
+
+    timing_mark(I, 0, s);
+    const size_t hb = (size_t)(n + 2) * 4;
+    depth_count_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt);
+    depth_scan_kernel<<<1, 1024, 0, s>>>(W.cnt, (int64_t)(n + 2) * B);
+    depth_scatter_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt, W.order);
 
     const dim3 dgrid((unsigned)((Npad + 255) / 256)), dblock(256);
-    timing_mark(I, 0, s);
-    if (m <= 8)
-        bound_decode16_kernel<8><<<dgrid, dblock, 0, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb);
-    else if (m <= 16)
-        bound_decode16_kernel<16><<<dgrid, dblock, 0, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb);
-    else
-        bound_decode16_kernel<32><<<dgrid, dblock, 0, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb);
+    const int MV = (m + 3) & ~3;
+    const size_t dlds = (size_t)kMaskWords * 256 * 4 + (size_t)(n + 1) * MV * 4;
+#define FSP_DECODE(MVV) \
+    case MVV: bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb); break;
+    switch (MV) {
+        FSP_DECODE(4) FSP_DECODE(8) FSP_DECODE(12) FSP_DECODE(16)
+        FSP_DECODE(20) FSP_DECODE(24) FSP_DECODE(28) FSP_DECODE(32)
+    }
+#undef FSP_DECODE
     e = hipGetLastError();
     timing_mark(I, 1, s);
     if (e == hipSuccess) {
         const int waves = scan_waves(I->P);
         const size_t lds_b = (size_t)((n + 1) > waves ? (n + 1) : waves) * 256;
-        const dim3 grid((unsigned)G), block(64 * waves);
+        const dim3 grid((unsigned)G);
+        const int unr = scan_unroll();
         switch (waves) {
-        case 8: bound_scan16_kernel<8><<<grid, block, lds_b, s>>>(I->dt, W, N, out_lb); break;
-        case 4: bound_scan16_kernel<4><<<grid, block, lds_b, s>>>(I->dt, W, N, out_lb); break;
-        case 2: bound_scan16_kernel<2><<<grid, block, lds_b, s>>>(I->dt, W, N, out_lb); break;
-        default: bound_scan16_kernel<1><<<grid, block, lds_b, s>>>(I->dt, W, N, out_lb); break;
+        case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+        case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+        case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+        case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+        default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
         }
         e = hipGetLastError();
     }

@@ -41,6 +41,7 @@ struct DevTables {
     const int32_t *p32;       // (n+1) x 32, zero-padded; row n is zero (PTM)
     const int32_t *colsum32;  // 32: sum over all jobs of p[j][k], zero-padded
     const int32_t *tails32;   // n x 32: Q[j][l] = sum_{h>l} p[j][h], zero-padded
+    const uint32_t *tails16;  // n x 16: (Q[j][2c], Q[j][2c+1]) as 16-bit halves (16-bit path)
     const int32_t *pairs;     // P x 2: (k, l), k < l, lexicographic (MM)
     const Rec32 *rec32;       // P x n
     const Rec16 *rec16;       // P x npad

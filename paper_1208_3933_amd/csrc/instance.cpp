@@ -107,6 +107,11 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     for (int j = 0; j < n; ++j)
         for (int l = 0; l < m; ++l)
             for (int h = l + 1; h < m; ++h) tails[(size_t)j * S + l] += p[j * m + h];
+    std::vector<uint32_t> tails16((size_t)n * (S / 2), 0);
+    for (int j = 0; j < n; ++j)
+        for (int c = 0; c < S / 2; ++c)
+            tails16[(size_t)j * (S / 2) + c] = ((uint32_t)tails[(size_t)j * S + 2 * c] & 0xffffu) |
+                                               ((uint32_t)tails[(size_t)j * S + 2 * c + 1] << 16);
     std::vector<int> order;
     std::vector<int32_t> lagv;
     int pr = 0;
@@ -138,7 +143,8 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     size_t off_p = 0;
     size_t off_cs = align(off_p + hp.size() * 4);
     size_t off_t = align(off_cs + colsum.size() * 4);
-    size_t off_pr = align(off_t + tails.size() * 4);
+    size_t off_t16 = align(off_t + tails.size() * 4);
+    size_t off_pr = align(off_t16 + tails16.size() * 4);
     size_t off_r32 = align(off_pr + pairs.size() * 4);
     size_t off_r16 = align(off_r32 + rec32.size() * sizeof(Rec32));
     size_t off_rw = align(off_r16 + rec16.size() * sizeof(Rec16));
@@ -148,6 +154,7 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     std::memcpy(blob.data() + off_p, hp.data(), hp.size() * 4);
     std::memcpy(blob.data() + off_cs, colsum.data(), colsum.size() * 4);
     std::memcpy(blob.data() + off_t, tails.data(), tails.size() * 4);
+    std::memcpy(blob.data() + off_t16, tails16.data(), tails16.size() * 4);
     std::memcpy(blob.data() + off_pr, pairs.data(), pairs.size() * 4);
     std::memcpy(blob.data() + off_r32, rec32.data(), rec32.size() * sizeof(Rec32));
     std::memcpy(blob.data() + off_r16, rec16.data(), rec16.size() * sizeof(Rec16));
@@ -174,6 +181,7 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     I->dt.p32 = (const int32_t *)(b + off_p);
     I->dt.colsum32 = (const int32_t *)(b + off_cs);
     I->dt.tails32 = (const int32_t *)(b + off_t);
+    I->dt.tails16 = (const uint32_t *)(b + off_t16);
     I->dt.pairs = (const int32_t *)(b + off_pr);
     I->dt.rec32 = (const Rec32 *)(b + off_r32);
     I->dt.rec16 = (const Rec16 *)(b + off_r16);
