@@ -260,13 +260,37 @@ __device__ __forceinline__ void gather_rows_addtid<4>(uint32_t (&x)[4], const ui
 template <>
 __device__ __forceinline__ void gather_rows_addtid<16>(uint32_t (&x)[16], const uint32_t (&joff)[16], uint32_t base)
 {
-    uint32_t lo[8], hi[8];
-    const uint32_t jl[8] = {joff[0], joff[1], joff[2], joff[3], joff[4], joff[5], joff[6], joff[7]};
-    const uint32_t jh[8] = {joff[8], joff[9], joff[10], joff[11], joff[12], joff[13], joff[14], joff[15]};
-    gather_rows_addtid<8>(lo, jl, base);
-    gather_rows_addtid<8>(hi, jh, base);
+    uint32_t save;
+    asm volatile("s_mov_b32 %[sv], m0\n\t"
+                 FSP_ADDTID_1(0) FSP_ADDTID_1(1) FSP_ADDTID_1(2) FSP_ADDTID_1(3)
+                 FSP_ADDTID_1(4) FSP_ADDTID_1(5) FSP_ADDTID_1(6) FSP_ADDTID_1(7)
+                 FSP_ADDTID_1(8) FSP_ADDTID_1(9) FSP_ADDTID_1(10) FSP_ADDTID_1(11)
+                 FSP_ADDTID_1(12) FSP_ADDTID_1(13) FSP_ADDTID_1(14) FSP_ADDTID_1(15)
+                 "s_waitcnt lgkmcnt(0)\n\t"
+                 "s_mov_b32 m0, %[sv]"
+                 : [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [x3] "=&v"(x[3]),
+                   [x4] "=&v"(x[4]), [x5] "=&v"(x[5]), [x6] "=&v"(x[6]), [x7] "=&v"(x[7]),
+                   [x8] "=&v"(x[8]), [x9] "=&v"(x[9]), [x10] "=&v"(x[10]), [x11] "=&v"(x[11]),
+                   [x12] "=&v"(x[12]), [x13] "=&v"(x[13]), [x14] "=&v"(x[14]), [x15] "=&v"(x[15]),
+                   [sv] "=&s"(save)
+                 : [j0] "s"(joff[0]), [j1] "s"(joff[1]), [j2] "s"(joff[2]), [j3] "s"(joff[3]),
+                   [j4] "s"(joff[4]), [j5] "s"(joff[5]), [j6] "s"(joff[6]), [j7] "s"(joff[7]),
+                   [j8] "s"(joff[8]), [j9] "s"(joff[9]), [j10] "s"(joff[10]), [j11] "s"(joff[11]),
+                   [j12] "s"(joff[12]), [j13] "s"(joff[13]), [j14] "s"(joff[14]), [j15] "s"(joff[15]),
+                   [base] "s"(base)
+                 : "scc");
+}
+
+template <>
+__device__ __forceinline__ void gather_rows_addtid<32>(uint32_t (&x)[32], const uint32_t (&joff)[32], uint32_t base)
+{
+    uint32_t lo[16], hi[16], jl[16], jh[16];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) { x[c] = lo[c]; x[8 + c] = hi[c]; }
+    for (int c = 0; c < 16; ++c) { jl[c] = joff[c]; jh[c] = joff[16 + c]; }
+    gather_rows_addtid<16>(lo, jl, base);
+    gather_rows_addtid<16>(hi, jh, base);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) { x[c] = lo[c]; x[16 + c] = hi[c]; }
 }
 #undef FSP_ADDTID_1
 
@@ -279,7 +303,55 @@ __device__ __forceinline__ void scan_update(u16x2 &s, uint32_t msk, uint32_t ce)
     s = as16((msk & as32(t)) | (~msk & as32(s)));
 }
 
-template <int WAVES, int UNR, bool ADDTID>
+// Scans NCH machine pairs in lockstep over their Johnson-order slots.  The
+// chains are independent, so their dependent packed operations interleave.
+template <int UNR, int NCH, bool ADDTID>
+__device__ __forceinline__ void scan_pairs(const DevTables &T, const int (&prs)[NCH], u16x2 (&s)[NCH],
+                                           const unsigned char *lds_lane, uint32_t lds_base)
+{
+    const int npad = T.npad;  // multiple of 4; padding slots read the zero row
+    cptr<uint32_t> rec[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+        rec[ch] = as_const(reinterpret_cast<const uint32_t *>(T.rec16 + (size_t)prs[ch] * npad));
+    int i = 0;
+    for (; i + UNR <= npad; i += UNR) {
+        uint32_t r[NCH][2 * UNR];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int c = 0; c < 2 * UNR; ++c) r[ch][c] = rec[ch][2 * i + c];
+        if constexpr (ADDTID) {
+            uint32_t jo[NCH * UNR], x[NCH * UNR];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int c = 0; c < UNR; ++c) jo[ch * UNR + c] = r[ch][2 * c];
+            gather_rows_addtid<NCH * UNR>(x, jo, lds_base);
+#pragma unroll
+            for (int c = 0; c < UNR; ++c)
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) scan_update(s[ch], x[ch * UNR + c], r[ch][2 * c + 1]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < UNR; ++c)
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) scan_step(s[ch], lds_lane, r[ch][2 * c], r[ch][2 * c + 1]);
+        }
+    }
+    for (; i < npad; i += 4) {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            uint32_t r[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) r[c] = rec[ch][2 * i + c];
+#pragma unroll
+            for (int c = 0; c < 8; c += 2) scan_step(s[ch], lds_lane, r[c], r[c + 1]);
+        }
+    }
+}
+
+template <int WAVES, int UNR, bool ADDTID, int NCH>
 __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, Workspace16 W, int64_t N,
                                                                   int32_t *__restrict__ out_lb)
 {
@@ -307,39 +379,32 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
     const uint32_t *dR = W.dec + (G * 3 + 0) * m * 64 + lane;
     const uint32_t *dT = dR + m * 64;
     const uint32_t *dQ = dT + m * 64;
+    cptr<int32_t> pairs = as_const(T.pairs);
     u16x2 lb = {0, 0};
-    for (int pr = wave; pr < T.P; pr += WAVES) {
-        const int k = as_const(T.pairs)[2 * pr], l = as_const(T.pairs)[2 * pr + 1];
-        u16x2 s = as16(dR[l * 64]) - as16(dR[k * 64]);
+    int pr = wave;
+    for (; pr + (NCH - 1) * WAVES < T.P; pr += NCH * WAVES) {
+        int prs[NCH];
+        u16x2 s[NCH];
+        uint32_t tk[NCH], ql[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            prs[ch] = pr + ch * WAVES;
+            const int k = pairs[2 * prs[ch]], l = pairs[2 * prs[ch] + 1];
+            s[ch] = as16(dR[l * 64]) - as16(dR[k * 64]);
+            tk[ch] = dT[k * 64];
+            ql[ch] = dQ[l * 64];
+        }
+        scan_pairs<UNR, NCH, ADDTID>(T, prs, s, lds_lane, lds_base);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) lb = __builtin_elementwise_max(lb, as16(tk[ch]) + s[ch] + as16(ql[ch]));
+    }
+    for (; pr < T.P; pr += WAVES) {  // fewer than NCH pairs left for this wave
+        const int prs[1] = {pr};
+        const int k = pairs[2 * pr], l = pairs[2 * pr + 1];
+        u16x2 s[1] = {as16(dR[l * 64]) - as16(dR[k * 64])};
         const uint32_t tk = dT[k * 64], ql = dQ[l * 64];
-        cptr<uint32_t> rec = as_const(reinterpret_cast<const uint32_t *>(T.rec16 + (size_t)pr * T.npad));
-        const int nslots = T.npad;  // multiple of 4; padding slots read the zero row
-        int i = 0;
-        for (; i + UNR <= nslots; i += UNR) {
-            uint32_t r[2 * UNR];
-#pragma unroll
-            for (int c = 0; c < 2 * UNR; ++c) r[c] = rec[2 * i + c];
-            if constexpr (ADDTID) {
-                uint32_t jo[UNR], x[UNR];
-#pragma unroll
-                for (int c = 0; c < UNR; ++c) jo[c] = r[2 * c];
-                gather_rows_addtid<UNR>(x, jo, lds_base);
-#pragma unroll
-                for (int c = 0; c < UNR; ++c) scan_update(s, x[c], r[2 * c + 1]);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 2 * UNR; c += 2) scan_step(s, lds_lane, r[c], r[c + 1]);
-            }
-        }
-        for (; i < nslots; i += 4) {
-            uint32_t r[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) r[c] = rec[2 * i + c];
-#pragma unroll
-            for (int c = 0; c < 8; c += 2) scan_step(s, lds_lane, r[c], r[c + 1]);
-        }
-        const u16x2 v = as16(tk) + s + as16(ql);
-        lb = __builtin_elementwise_max(lb, v);
+        scan_pairs<UNR, 1, ADDTID>(T, prs, s, lds_lane, lds_base);
+        lb = __builtin_elementwise_max(lb, as16(tk) + s[0] + as16(ql));
     }
     __syncthreads();
     lds[wave * 64 + lane] = as32(lb);
@@ -371,9 +436,18 @@ static int scan_unroll()
 {
     if (const char *e = getenv("FSPBB_SCAN_UNROLL")) {
         const int u = atoi(e);
-        if (u == 4 || u == 8 || u == 16) return u;
+        if (u == 8 || u == 16) return u;
     }
-    return 16;
+    return 8;
+}
+
+static int scan_chains()
+{
+    if (const char *e = getenv("FSPBB_SCAN_CHAINS")) {
+        const int c = atoi(e);
+        if (c == 1 || c == 2) return c;
+    }
+    return 2;
 }
 
 static bool scan_addtid()
@@ -387,12 +461,15 @@ static void launch_scan_u(int unr, dim3 grid, size_t lds_b, hipStream_t s, const
                           const Workspace16 &W, int64_t N, int32_t *out_lb)
 {
     const dim3 block(64 * WAVES);
-    if (unr == 4)
-        bound_scan16_kernel<WAVES, 4, ADDTID><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+    const int nch = scan_chains();
+    if (unr == 16 && nch == 2)
+        bound_scan16_kernel<WAVES, 16, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
     else if (unr == 16)
-        bound_scan16_kernel<WAVES, 16, ADDTID><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+        bound_scan16_kernel<WAVES, 16, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+    else if (nch == 2)
+        bound_scan16_kernel<WAVES, 8, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
     else
-        bound_scan16_kernel<WAVES, 8, ADDTID><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+        bound_scan16_kernel<WAVES, 8, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
 }
 
 template <int WAVES>
