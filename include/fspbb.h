@@ -122,6 +122,81 @@ fsp_status fsp_bound_pool_variant(fsp_instance inst, const int32_t *prefixes,
                                   const int32_t *depths, int64_t N, int32_t *out_lb,
                                   int32_t variant, void *stream);
 
+/* ---- branch-and-bound ---------------------------------------------------- */
+
+/* ub0 value of fsp_solve: start from the NEH heuristic's schedule. */
+#define FSP_UB_NEH (-1)
+/* An upper bound that eliminates nothing. */
+#define FSP_UB_NONE 0x7fffffff
+
+typedef struct {
+    int64_t n_children;   /* children generated and bounded */
+    int64_t n_survivors;  /* children kept (not complete, bound < ub_out) */
+    int32_t ub_out;       /* min(ub_in, bound of the best complete child) */
+    int32_t improved;     /* 1 when a complete child lowered the upper bound */
+    int64_t fingerprint;  /* sum over survivors of (S - rank) * (appended job + 1), S survivors,
+                             rank in child order: a check of the survivor order */
+} fsp_step_result;
+
+/*
+ * fsp_branch_and_prune - one pool step of the branch-and-bound (Sec. II-A:
+ * branching, bounding, elimination; Sec. III-A: the pool is bounded on the
+ * GPU).  Synchronous on stream.
+ *   parents, parent_depths  dev, K rows of n int32 and K depths, in pop order.
+ *   ub_in       current upper bound (>= 0; FSP_UB_NONE for none).
+ *   Each parent of depth d < n gets n - d children, in parent order and, per
+ *   parent, in increasing appended job id (forward branching, Sec. II-B).
+ *   Every child is bounded.  ub_out = min(ub_in, best complete child); when
+ *   it improves, incumbent (dev, n int32, may be NULL) receives the first
+ *   complete child in child order that attains it.  The children that are
+ *   not complete and whose bound is below ub_out survive and are written in
+ *   child order to children (dev cap x n), child_depths (dev cap) and
+ *   child_lb (dev cap, may be NULL).
+ * Errors: FSP_E_INVAL, FSP_E_BADNODE (an invalid parent: it gets no
+ * children), FSP_E_RANGE (more survivors than cap: the first cap are
+ * written, res still counts all), FSP_E_NOMEM, FSP_E_DEVICE.
+ */
+fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const int32_t *parent_depths,
+                                int64_t K, int32_t ub_in, int32_t *children, int32_t *child_depths,
+                                int32_t *child_lb, int64_t cap, int32_t *incumbent, fsp_step_result *res,
+                                void *stream);
+
+typedef struct {
+    int32_t opt;           /* best makespan found (the optimum when proven) */
+    int32_t proven;        /* 1 when the search completed */
+    int64_t nodes_bounded; /* the root plus every child bounded */
+    int64_t steps;         /* pool steps */
+    int32_t ub0;           /* initial upper bound used */
+    int32_t improvements;  /* steps that lowered the upper bound */
+    int64_t max_stack;     /* largest device stack, in nodes */
+} fsp_solve_result;
+
+/*
+ * fsp_solve - depth-first branch-and-bound from the root, pool-synchronous,
+ * with the search stack resident on the device.  Each step pops parents from
+ * the top of the stack while their children fit in pool_cap (the first is
+ * always taken), runs one fsp_branch_and_prune step on them, and pushes the
+ * survivors in reverse child order.  The root is bounded first and
+ * eliminated when its bound is >= ub0.  Elimination is bound >= upper bound.
+ *   ub0         FSP_UB_NEH (start from NEH), FSP_UB_NONE, or a makespan >= 0.
+ *   pool_cap    >= 1, children per step.
+ *   node_budget >= 1: stop (FSP_BUDGET, proven = 0) once this many nodes
+ *               have been bounded.
+ *   perm_out    host, n int32: best schedule found (NEH's when nothing
+ *               better was found; -1s when ub0 was given and never beaten).
+ *   steplog     host, steplog_cap x 6 int64, may be NULL: per step the
+ *               parents popped, children bounded, upper bound after the step,
+ *               children pushed, stack size after, and the step fingerprint.
+ * Returns FSP_OK (proven), FSP_BUDGET, or an error.
+ */
+fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t node_budget,
+                     fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
+                     void *stream);
+
+/* fsp_neh - NEH heuristic schedule (host computation): perm_out (host n, may
+ * be NULL) and its makespan. */
+fsp_status fsp_neh(fsp_instance inst, int32_t *perm_out, int32_t *makespan);
+
 /*
  * Kernel timing (instrumentation).  When enabled on an instance, each bound
  * launch records HIP events on its stream around its decode and scan kernels.

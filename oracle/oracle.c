@@ -443,15 +443,17 @@ int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
         }
         nodes += nchild;
         /* 5. complete children update the upper bound */
+        int improved = 0;
         for (int64_t i = 0; i < nchild; ++i) {
             int32_t *ch = children + i * (n + 1);
             if (ch[0] == n && lbs[i] < UB) {
                 UB = lbs[i];
                 memcpy(inc, ch + 1, sizeof(int32_t) * (size_t)n);
                 have_inc = 1;
-                ++improvements;
+                improved = 1;
             }
         }
+        improvements += improved;  /* steps that lowered the upper bound */
         /* 6. elimination and push in reverse child order */
         int64_t pushed = 0, fp = 0;
         for (int64_t i = nchild - 1; i >= 0; --i) {

@@ -27,6 +27,9 @@ E_NODEVICE = -6
 BUDGET = 1
 LB_INVALID = -1
 
+UB_NEH = -1
+UB_NONE = 0x7FFFFFFF
+
 VARIANT_AUTO = 0
 VARIANT_LANE32 = 1
 VARIANT_PACKED16 = 2
@@ -47,6 +50,17 @@ class InstanceInfo(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("table_bytes", ctypes.c_int64)]
 
 
+class StepResult(ctypes.Structure):
+    _fields_ = [("n_children", ctypes.c_int64), ("n_survivors", ctypes.c_int64), ("ub_out", ctypes.c_int32),
+                ("improved", ctypes.c_int32), ("fingerprint", ctypes.c_int64)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("opt", ctypes.c_int32), ("proven", ctypes.c_int32), ("nodes_bounded", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("ub0", ctypes.c_int32), ("improvements", ctypes.c_int32),
+                ("max_stack", ctypes.c_int64)]
+
+
 _lib = None
 _SIGNATURES = {
     "fsp_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -57,6 +71,11 @@ _SIGNATURES = {
     "fsp_bound_pool": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
     "fsp_bound_pool_variant": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp]),
     "fsp_pool_status": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "fsp_neh": (ctypes.c_int32, [_vp, _i32p, ctypes.POINTER(ctypes.c_int32)]),
+    "fsp_branch_and_prune": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp,
+                                              ctypes.c_int64, _vp, ctypes.POINTER(StepResult), _vp]),
+    "fsp_solve": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(SolveResult),
+                                   _i32p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, _vp]),
     "fsp_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
     "fsp_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -201,3 +220,51 @@ def timing_read(inst: Instance):
     _check(lib().fsp_timing_read(inst.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "fsp_timing_read")
     return a.value, b.value, int(c.value)
+
+
+def neh(inst: Instance):
+    """(makespan, permutation) of the NEH heuristic."""
+    perm = np.empty(inst.n, np.int32)
+    ms = ctypes.c_int32()
+    _check(lib().fsp_neh(inst.handle, perm.ctypes.data_as(_i32p), ctypes.byref(ms)), "fsp_neh")
+    return int(ms.value), perm
+
+
+def branch_and_prune(inst: Instance, parents, parent_depths, ub_in: int, children, child_depths,
+                     child_lb=None, incumbent=None, stream=None) -> dict:
+    """One branch-and-bound step (synchronous).  Survivors land in children /
+    child_depths (/ child_lb) in child order.  Returns the step result."""
+    K = int(parent_depths.shape[0])
+    a = _dev_i32(parents, "parents", (K, inst.n))
+    b = _dev_i32(parent_depths, "parent_depths", (K,))
+    cap = int(child_depths.shape[0])
+    c = _dev_i32(children, "children", (cap, inst.n))
+    d = _dev_i32(child_depths, "child_depths", (cap,))
+    e = _dev_i32(child_lb, "child_lb", (cap,)) if child_lb is not None else None
+    f = _dev_i32(incumbent, "incumbent", (inst.n,)) if incumbent is not None else None
+    res = StepResult()
+    st = lib().fsp_branch_and_prune(inst.handle, a, b, K, int(ub_in), c, d, e, cap, f, ctypes.byref(res),
+                                    _stream_handle(stream))
+    out = {fn: getattr(res, fn) for fn, _ in StepResult._fields_}
+    out["status"] = st
+    if st not in (OK, E_RANGE, E_BADNODE):
+        _check(st, "fsp_branch_and_prune")
+    return out
+
+
+def solve(inst: Instance, ub0: int = UB_NEH, pool_cap: int = 1 << 18, node_budget: int = 1 << 62,
+          steplog_cap: int = 0, stream=None) -> dict:
+    """Depth-first branch-and-bound with the stack on the device."""
+    res = SolveResult()
+    perm = np.empty(inst.n, np.int32)
+    log = np.zeros((max(steplog_cap, 1), 6), np.int64)
+    st = lib().fsp_solve(inst.handle, int(ub0), int(pool_cap), int(node_budget), ctypes.byref(res),
+                         perm.ctypes.data_as(_i32p), log.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         int(steplog_cap), _stream_handle(stream))
+    if st not in (OK, BUDGET):
+        _check(st, "fsp_solve")
+    out = {fn: getattr(res, fn) for fn, _ in SolveResult._fields_}
+    out["status"] = st
+    out["perm"] = perm
+    out["steplog"] = log[:min(res.steps, steplog_cap)] if steplog_cap else None
+    return out

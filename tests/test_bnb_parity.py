@@ -1,0 +1,172 @@
+"""Branch-and-bound on the GPU against the oracle's pool-synchronous DFS.
+
+Node counts, upper-bound trajectories, survivor order fingerprints, the final
+makespan and the incumbent permutation are integers and must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import oracle_bounds, require_gpu, to_dev
+from paper_1208_3933_amd import fspbb, gen
+
+pytestmark = pytest.mark.gpu
+
+
+def inst_times(n, m, seed, lo=1, hi=99):
+    return gen.processing_times(n, m, gen.make_seed(40, seed, 0), lo, hi)
+
+
+# --- NEH ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 1), (12, 5, 2), (20, 20, 3), (50, 10, 4), (100, 20, 5), (200, 20, 6)])
+def test_neh_matches_oracle(n, m, seed):
+    require_gpu()
+    p = inst_times(n, m, seed)
+    want_ms, want_perm = oracle.neh(p)
+    with fspbb.create_instance(p) as inst:
+        ms, perm = fspbb.neh(inst)
+    assert ms == want_ms
+    assert (perm == want_perm).all()
+
+
+# --- one step -----------------------------------------------------------------
+
+def expected_step(p, parents, depths, ub_in):
+    n = p.shape[0]
+    kids = []
+    for i in range(len(depths)):
+        d = int(depths[i])
+        if d >= n:
+            continue
+        pre = [int(x) for x in parents[i, :d]]
+        for j in sorted(set(range(n)) - set(pre)):
+            kids.append((pre + [j], j))
+    rows = np.zeros((max(len(kids), 1), n), np.int32)
+    dep = np.zeros(max(len(kids), 1), np.int32)
+    for c, (row, _) in enumerate(kids):
+        rows[c, :len(row)] = row
+        dep[c] = len(row)
+    lbs = oracle_bounds(p, rows[:len(kids)], dep[:len(kids)]) if kids else np.zeros(0, np.int32)
+    ub, inc = ub_in, None
+    for (row, _), lb in zip(kids, lbs):
+        if len(row) == n and lb < ub:
+            ub, inc = int(lb), row
+    surv = [(row, j, int(lb)) for (row, j), lb in zip(kids, lbs) if len(row) < n and lb < ub]
+    S = len(surv)
+    fp = sum((S - s) * (j + 1) for s, (_, j, _) in enumerate(surv))
+    return {"n_children": len(kids), "n_survivors": S, "ub_out": ub, "improved": int(inc is not None),
+            "fingerprint": fp, "survivors": surv, "incumbent": inc}
+
+
+@pytest.mark.parametrize("n,m,K,seed,ub_mode", [(8, 4, 9, 1, "none"), (8, 4, 30, 2, "tight"),
+                                                (20, 5, 64, 3, "neh"), (50, 10, 40, 4, "neh"),
+                                                (12, 6, 50, 5, "deep")])
+def test_branch_and_prune_step(n, m, K, seed, ub_mode):
+    torch = require_gpu()
+    p = inst_times(n, m, seed)
+    if ub_mode == "deep":
+        pre, dep = gen.random_pool(n, K, gen.make_seed(41, seed, 1), n - 2, n)
+    else:
+        pre, dep = gen.random_pool(n, K, gen.make_seed(41, seed, 1))
+    neh_ms, _ = oracle.neh(p)
+    ub_in = {"none": fspbb.UB_NONE, "neh": neh_ms, "deep": neh_ms + 50,
+             "tight": int(np.median(oracle_bounds(p, pre, dep)))}[ub_mode]
+    want = expected_step(p, pre, dep, ub_in)
+    cap = max(want["n_children"], 1)
+    with fspbb.create_instance(p) as inst:
+        pre_d, dep_d = to_dev(torch, pre, dep)
+        rows = torch.full((cap, n), -9, dtype=torch.int32, device="cuda")
+        cdep = torch.full((cap,), -9, dtype=torch.int32, device="cuda")
+        clb = torch.full((cap,), -9, dtype=torch.int32, device="cuda")
+        inc = torch.full((n,), -9, dtype=torch.int32, device="cuda")
+        res = fspbb.branch_and_prune(inst, pre_d, dep_d, ub_in, rows, cdep, clb, inc)
+    assert res["status"] == fspbb.OK
+    for key in ["n_children", "n_survivors", "ub_out", "improved", "fingerprint"]:
+        assert res[key] == want[key], key
+    rows, cdep, clb = rows.cpu().numpy(), cdep.cpu().numpy(), clb.cpu().numpy()
+    for s, (row, _, lb) in enumerate(want["survivors"]):
+        assert cdep[s] == len(row) and clb[s] == lb
+        assert list(rows[s, :len(row)]) == row
+    if want["incumbent"] is not None:
+        assert list(inc.cpu().numpy()) == want["incumbent"]
+
+
+def test_branch_and_prune_errors():
+    torch = require_gpu()
+    n, m = 6, 3
+    p = inst_times(n, m, 9)
+    with fspbb.create_instance(p) as inst:
+        pre = torch.tensor([[0, 1, 2, 3, 4, 5], [0, 0, 1, 2, 3, 4]], dtype=torch.int32, device="cuda")
+        dep = torch.tensor([2, 3], dtype=torch.int32, device="cuda")  # second parent repeats job 0
+        rows = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+        cdep = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        res = fspbb.branch_and_prune(inst, pre, dep, fspbb.UB_NONE, rows, cdep)
+        assert res["status"] == fspbb.E_BADNODE
+        dep = torch.tensor([2, 2], dtype=torch.int32, device="cuda")
+        pre[1, 1] = 5
+        res = fspbb.branch_and_prune(inst, pre, dep, fspbb.UB_NONE, rows, cdep)
+        assert res["status"] == fspbb.E_RANGE and res["n_survivors"] == 8 and res["n_children"] == 8
+
+
+# --- whole searches -----------------------------------------------------------
+
+def compare_solve(p, ub_mode, pool_cap, budget=1 << 62, steplog_cap=1 << 16):
+    n = p.shape[0]
+    if ub_mode == "neh":
+        ms, perm = oracle.neh(p)
+        want = oracle.bnb(p, ms, perm, pool_cap=pool_cap, node_budget=budget, steplog_cap=steplog_cap)
+        ub0 = fspbb.UB_NEH
+    else:
+        want = oracle.bnb(p, fspbb.UB_NONE, None, pool_cap=pool_cap, node_budget=budget, steplog_cap=steplog_cap)
+        ub0 = fspbb.UB_NONE
+    with fspbb.create_instance(p) as inst:
+        got = fspbb.solve(inst, ub0, pool_cap, budget, steplog_cap)
+    assert got["opt"] == want["ub"]
+    assert bool(got["proven"]) == want["proven"]
+    assert got["nodes_bounded"] == want["nodes_bounded"]
+    assert got["steps"] == want["steps"]
+    assert got["improvements"] == want["improvements"]
+    assert got["max_stack"] == want["max_stack"]
+    assert (got["perm"] == want["incumbent"]).all()
+    assert (got["steplog"] == want["steplog"]).all()
+    return got
+
+
+@pytest.mark.parametrize("n,m,seed", [(6, 3, 11), (8, 4, 12), (9, 5, 13), (10, 3, 14)])
+@pytest.mark.parametrize("pool_cap", [1, 3, 16, 1 << 20])
+@pytest.mark.parametrize("ub_mode", ["neh", "none"])
+def test_solve_small_matches_oracle(n, m, seed, pool_cap, ub_mode):
+    require_gpu()
+    p = inst_times(n, m, seed)
+    got = compare_solve(p, ub_mode, pool_cap)
+    assert got["proven"]
+    if n <= 8:
+        assert got["opt"] == oracle.brute(p)
+
+
+@pytest.mark.parametrize("n,m,seed,pool_cap,budget", [(20, 5, 21, 256, 200000), (15, 8, 22, 64, 50000),
+                                                      (20, 10, 23, 4096, 60000), (50, 10, 24, 2048, 20000)])
+def test_solve_medium_matches_oracle(n, m, seed, pool_cap, budget):
+    require_gpu()
+    p = inst_times(n, m, seed)
+    compare_solve(p, "neh", pool_cap, budget)
+
+
+def test_solve_200x20_first_steps_match_oracle():
+    """The 200 x 20 configuration from NEH, four pool steps of 1024 children."""
+    require_gpu()
+    p = gen.processing_times(200, 20, gen.make_seed(2, 0, gen.PURPOSE_TIMES))
+    compare_solve(p, "neh", 1024, budget=1 + 3 * 1024)
+
+
+def test_solve_root_pruned_and_budget():
+    require_gpu()
+    p = inst_times(10, 5, 31)
+    lb0 = oracle.bound(p, [])
+    with fspbb.create_instance(p) as inst:
+        r = fspbb.solve(inst, lb0, 16, 1 << 40)
+        assert r["proven"] and r["nodes_bounded"] == 1 and r["steps"] == 0 and r["opt"] == lb0
+        assert (r["perm"] == -1).all()
+        r = fspbb.solve(inst, fspbb.UB_NONE, 4, 30)
+        assert r["status"] == fspbb.BUDGET and not r["proven"] and r["nodes_bounded"] >= 30
