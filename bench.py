@@ -55,6 +55,23 @@ def cpu_baseline(p, pre, dep, sample: int, threads: int) -> dict:
             "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per core"}
 
 
+def bnb_leg(inst, steps: int, stream) -> dict:
+    """Depth-first branch-and-bound from NEH on the same instance, pool steps of
+    262,144 children (the paper's largest pool), stack resident on the device."""
+    import torch
+
+    from paper_1208_3933_amd import fspbb
+    fspbb.solve(inst, fspbb.UB_NEH, POOL, 1 + POOL, 0, stream)  # warm-up: one step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fspbb.solve(inst, fspbb.UB_NEH, POOL, 1 + steps * POOL, 0, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"nodes_per_s": r["nodes_bounded"] / dt, "nodes_bounded": r["nodes_bounded"], "steps": r["steps"],
+            "ms_per_step": dt * 1e3 / max(r["steps"], 1), "ub": r["opt"], "ub0_neh": r["ub0"],
+            "pool_cap": POOL, "proven": bool(r["proven"])}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +79,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bnb-steps", type=int, default=8, help="pool steps of the 200x20 DFS leg (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the bound path runs on "
@@ -141,6 +159,8 @@ def main() -> int:
                      "decode_avg_ms": dec_ms / max(launches, 1)},
         "plain_nodes_per_s": value,
     }
+    if args.bnb_steps > 0:
+        result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
         result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads)

@@ -23,7 +23,7 @@ struct StepArgs {
     int32_t *out_lb;             // may be null
     int64_t out_base, out_cap;
     int out_reversed;
-    uint32_t *surv_per_parent;   // K, zeroed by the caller; may be null
+    uint32_t *surv_per_parent;   // K survivor counts per parent (written); may be null
     int32_t *incumbent;          // n; written when a complete child improves ub_in; may be null
 };
 

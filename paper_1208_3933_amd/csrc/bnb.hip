@@ -28,49 +28,64 @@ __device__ __forceinline__ int32_t parent_depth(const StepArgs &a, int64_t p)
     return a.pdepth[a.parents_reversed ? (a.parent_top - 1 - p) : p];
 }
 
-// Builds the scheduled set of a prefix in a 16-word LDS column (one lane);
-// returns false for a depth outside 0..n, a job outside 0..n-1 or a repeat.
-__device__ inline bool prefix_set(const int32_t *row, int d, int n, uint32_t *bits, int stride)
+// One wave per parent: the lanes build the parent's scheduled set in a 16-word
+// LDS mask (LDS atomics; a returned bit already set means a repeated job).
+// Returns, uniformly over the wave, whether the parent is valid: depth in
+// 0..n, every job in 0..n-1, no repeat.
+__device__ inline bool wave_prefix_set(const int32_t *row, int d, int n, uint32_t *mask, int lane)
 {
-#pragma unroll
-    for (int w = 0; w < kMaxJobs / 32; ++w) bits[w * stride] = 0u;
-    if (d < 0 || d > n) return false;
-    for (int t = 0; t < d; ++t) {
-        const int j = row[t];
-        if ((unsigned)j >= (unsigned)n) return false;
-        const uint32_t bit = 1u << (j & 31);
-        if (atomicOr(&bits[(j >> 5) * stride], bit) & bit) return false;
+    if (lane < kMaxJobs / 32) mask[lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    bool bad = d < 0 || d > n;
+    if (!bad) {
+        for (int t = lane; t < d; t += 64) {
+            const int j = row[t];
+            if ((unsigned)j >= (unsigned)n) { bad = true; continue; }
+            const uint32_t bit = 1u << (j & 31);
+            if (atomicOr(&mask[j >> 5], bit) & bit) bad = true;
+        }
     }
-    return true;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return __ballot(bad) == 0;
 }
 
 __global__ __launch_bounds__(256) void step_count_kernel(StepArgs a, StepScratch w)
 {
-    __shared__ uint32_t bits[(kMaxJobs / 32) * 256];
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.K) return;
+    __shared__ uint32_t mask[4][kMaxJobs / 32];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    if (p >= a.K) return;  // whole wave
     const int d = parent_depth(a, p);
-    const bool ok = prefix_set(parent_row(a, p), d, a.n, bits + threadIdx.x, 256);
-    w.cnt[p] = (ok && d < a.n) ? (uint32_t)(a.n - d) : 0u;
-    if (!ok) atomicAdd(w.bad, 1ull);
+    const bool ok = wave_prefix_set(parent_row(a, p), d, a.n, mask[wv], lane);
+    if (lane == 0) {
+        w.cnt[p] = (ok && d < a.n) ? (uint32_t)(a.n - d) : 0u;
+        if (!ok) atomicAdd(w.bad, 1ull);
+    }
 }
 
+// One wave per parent: each unscheduled job j goes to slot off[p] + (number
+// of unscheduled jobs below j), i.e. children in increasing job id.
 __global__ __launch_bounds__(256) void step_ulist_kernel(StepArgs a, StepScratch w)
 {
-    __shared__ uint32_t bits[(kMaxJobs / 32) * 256];
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.K) return;
-    if (w.cnt[p] == 0) return;
+    __shared__ uint32_t mask[4][kMaxJobs / 32];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    if (p >= a.K) return;  // whole wave
+    if (w.cnt[p] == 0) return;  // whole wave (uniform load)
     const int d = parent_depth(a, p);
-    uint32_t *mine = bits + threadIdx.x;
-    prefix_set(parent_row(a, p), d, a.n, mine, 256);
-    int64_t pos = w.off[p];
-    for (int j = 0; j < a.n; ++j) {
-        if (!((mine[(j >> 5) * 256] >> (j & 31)) & 1u)) {
-            w.ujob[pos] = j;
-            w.upar[pos] = (int32_t)p;
-            ++pos;
-        }
+    wave_prefix_set(parent_row(a, p), d, a.n, mask[wv], lane);
+    const int64_t base = w.off[p];
+    for (int j = lane; j < a.n; j += 64) {
+        const int wj = j >> 5;
+        const uint32_t mw = mask[wv][wj];
+        if ((mw >> (j & 31)) & 1u) continue;
+        int below = __popc(mw & ((1u << (j & 31)) - 1u));
+        for (int q = 0; q < wj; ++q) below += __popc(mask[wv][q]);
+        const int64_t slot = base + (j - below);
+        w.ujob[slot] = j;
+        w.upar[slot] = (int32_t)p;
     }
 }
 
@@ -123,9 +138,41 @@ __global__ __launch_bounds__(256) void step_scatter_kernel(StepArgs a, StepScrat
     if (lane == 0) {
         a.out_depth[dst] = d;
         if (a.out_lb) a.out_lb[dst] = w.clb[c];
-        if (a.surv_per_parent) atomicAdd(&a.surv_per_parent[w.upar[c]], 1u);
-        atomicAdd(w.fingerprint, (unsigned long long)(S - s) * (unsigned long long)(w.ujob[c] + 1));
     }
+}
+
+// Fingerprint of the survivor order: sum over survivors of (S - rank) * (job + 1),
+// one block reduction and one atomic per block.
+__global__ __launch_bounds__(256) void step_fingerprint_kernel(StepScratch w, int64_t nchild)
+{
+    __shared__ unsigned long long part[256];
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long v = 0;
+    if (c < nchild && w.keep[c]) {
+        const unsigned long long S = *w.nsurv;
+        v = (S - w.pos[c]) * (unsigned long long)(w.ujob[c] + 1);
+    }
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && part[0]) atomicAdd(w.fingerprint, part[0]);
+}
+
+// Survivors per parent: a parent's children are contiguous in child order, so
+// its survivor count is the difference of the compaction offsets at the ends
+// of its children.
+__global__ __launch_bounds__(256) void step_per_parent_kernel(StepArgs a, StepScratch w, int64_t nchild)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.K || !a.surv_per_parent) return;
+    const uint32_t cnt = w.cnt[p];
+    if (cnt == 0) { a.surv_per_parent[p] = 0u; return; }
+    const int64_t lo = w.off[p], hi = lo + cnt;
+    const uint32_t end = hi < nchild ? w.pos[hi] : *w.nsurv;
+    a.surv_per_parent[p] = end - w.pos[lo];
 }
 
 __global__ void step_incumbent_kernel(StepArgs a, StepScratch w)
@@ -151,7 +198,7 @@ hipError_t step_phase1(const StepArgs &a, const StepScratch &w, hipStream_t s)
 {
     step_init_kernel<<<1, 1, 0, s>>>(a, w);
     if (a.K > 0) {
-        step_count_kernel<<<blocks_for(a.K, 256), 256, 0, s>>>(a, w);
+        step_count_kernel<<<blocks_for(a.K, 4), 256, 0, s>>>(a, w);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -161,7 +208,7 @@ hipError_t step_phase1(const StepArgs &a, const StepScratch &w, hipStream_t s)
 hipError_t step_phase2(fsp_instance_s *I, const StepArgs &a, const StepScratch &w, int64_t nchild, hipStream_t s)
 {
     if (nchild > 0) {
-        step_ulist_kernel<<<blocks_for(a.K, 256), 256, 0, s>>>(a, w);
+        step_ulist_kernel<<<blocks_for(a.K, 4), 256, 0, s>>>(a, w);
         step_rows_kernel<<<blocks_for(nchild, 4), 256, 0, s>>>(a, w, nchild);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -175,6 +222,8 @@ hipError_t step_phase2(fsp_instance_s *I, const StepArgs &a, const StepScratch &
         e = exclusive_scan_u32(w.keep, w.pos, nchild, w.nsurv, w.scan_scratch, s);
         if (e != hipSuccess) return e;
         step_scatter_kernel<<<blocks_for(nchild, 4), 256, 0, s>>>(a, w, nchild);
+        step_fingerprint_kernel<<<blocks_for(nchild, 256), 256, 0, s>>>(w, nchild);
+        step_per_parent_kernel<<<blocks_for(a.K, 256), 256, 0, s>>>(a, w, nchild);
         step_incumbent_kernel<<<1, 256, 0, s>>>(a, w);
     } else {
         store_zero_kernel<<<1, 1, 0, s>>>(w.nsurv);

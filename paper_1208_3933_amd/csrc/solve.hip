@@ -107,12 +107,6 @@ fsp_status fail(hipError_t e)
     return e == hipErrorOutOfMemory ? FSP_E_NOMEM : FSP_E_DEVICE;
 }
 
-__global__ void zero_u32_kernel(uint32_t *p, int64_t count)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < count) p[i] = 0u;
-}
-
 // NEH (Nawaz, Enscore and Ham 1983) with Taillard's evaluation of all
 // insertion positions in O(L m) per job: e = heads of the current sequence,
 // q = tails, f = completion of the inserted job.  Jobs by decreasing total
@@ -342,9 +336,7 @@ fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t n
         a.out_reversed = 1;
         a.surv_per_parent = surv;
         a.incumbent = dinc;
-        zero_u32_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(surv, K);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = step_phase1(a, B.w, s);
+        e = step_phase1(a, B.w, s);
         if (e == hipSuccess) e = step_phase2(inst, a, B.w, nch, s);
         StepOut o{};
         if (e == hipSuccess) e = read_step_out(B.w, o, s);
