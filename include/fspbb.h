@@ -122,6 +122,53 @@ fsp_status fsp_bound_pool_variant(fsp_instance inst, const int32_t *prefixes,
                                   const int32_t *depths, int64_t N, int32_t *out_lb,
                                   int32_t variant, void *stream);
 
+/* ---- batched bounding --------------------------------------------------- */
+
+/* One pool of a batch: an instance and its pool buffers (as fsp_bound_pool). */
+typedef struct {
+    fsp_instance inst;
+    const int32_t *prefixes;   /* dev N*n */
+    const int32_t *depths;     /* dev N */
+    int64_t N;                 /* >= 0 */
+    int32_t *out_lb;           /* dev N */
+} fsp_pool_desc;
+
+typedef struct fsp_batch_s *fsp_batch;
+
+/* fsp_batch_create flag: capture the batch's launches in a HIP graph. */
+#define FSP_BATCH_GRAPH 1
+
+/*
+ * fsp_batch_create - plan the bounding of many pools (of any instances of the
+ * 16-bit path, on one device) as one decode launch per machine-count class
+ * plus one persistent scan launch whose workgroups take 128-node group tiles
+ * from a device queue, longest first.  The tile schedule (groups staged in
+ * LDS per tile, waves per group) comes from the tuner (fsp_autotune) or a
+ * rule of thumb.  With FSP_BATCH_GRAPH the launches are captured once in a
+ * HIP graph; fsp_batch_run then replays it.  The descriptors' buffers must
+ * stay valid, at the same addresses, for the life of the batch; their
+ * contents may change between runs.
+ *   pools   host, n_pools >= 1 descriptors.
+ * Errors: FSP_E_INVAL (null, N < 0, an instance outside the 16-bit path or
+ * on another device), FSP_E_NOMEM, FSP_E_DEVICE.  The batch owns a device
+ * workspace of about (6m + n/8 + 4) bytes per node.
+ */
+fsp_status fsp_batch_create(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, fsp_batch *out);
+
+/* fsp_batch_run - enqueue one bounding of every pool of the batch on stream
+ * (async).  Invalid nodes get FSP_LB_INVALID and raise their instance's
+ * counter, as with fsp_bound_pool.  Runs of one batch must not overlap. */
+fsp_status fsp_batch_run(fsp_batch b, void *stream);
+
+/* fsp_batch_destroy - synchronise the device and free the batch. */
+fsp_status fsp_batch_destroy(fsp_batch b);
+
+/* Total nodes, work items and persistent workgroups of a batch. */
+fsp_status fsp_batch_info(fsp_batch b, int64_t *total_nodes, int32_t *n_items, int32_t *grid);
+
+/* fsp_bound_pools_batched - one-shot: create (without graph), run, wait, destroy. */
+fsp_status fsp_bound_pools_batched(const fsp_pool_desc *pools, int32_t n_pools, void *stream);
+
 /* ---- branch-and-bound ---------------------------------------------------- */
 
 /* ub0 value of fsp_solve: start from the NEH heuristic's schedule. */

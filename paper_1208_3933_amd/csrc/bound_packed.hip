@@ -19,25 +19,9 @@
 #include <algorithm>
 #include <cstdlib>
 
-#include "bound_common.h"
+#include "scan16.h"
 
 namespace fspbb {
-
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ u16x2 as16(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
-__device__ __forceinline__ uint32_t as32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
-
-// Workspace of one pool, G = ceil(N / 128) groups.  Nodes are decoded and
-// scanned in depth order (order[i] = original index of the i-th node), so the
-// lanes of a wave walk prefixes of nearly equal length.
-struct Workspace16 {
-    uint32_t *dec;    // G x 3 x m x 64 dwords: releases R, closing sums Tk, tails Q
-    uint32_t *flg;    // G x NW x 128 dwords: unscheduled-job bits per node
-    uint32_t *st;     // G*128: 1 = valid node
-    int32_t *order;   // N: node index at each depth-sorted position
-    uint32_t *cnt;    // (n + 2) x B: per-block depth counts, then scatter offsets
-};
 
 // ---- counting sort of node indices by depth (bucket n+1 holds invalid depths)
 
@@ -102,13 +86,14 @@ __global__ __launch_bounds__(256) void depth_scatter_kernel(const int32_t *__res
 // unscheduled jobs).  MV = m rounded up to a multiple of 4.  The processing
 // times are staged in LDS; the tails are taken two machines at a time with
 // packed 16-bit minima over a scalar-loaded table.
+// Decodes block `blk` (256 nodes) of one pool; every thread of the block calls it.
+// sm: dynamic LDS of 16 x 256 words plus (n+1) x MV int32.
 template <int MV>
-__global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const int32_t *__restrict__ prefixes,
-                                                             const int32_t *__restrict__ depths, int64_t N,
-                                                             int64_t Npad, Workspace16 W,
-                                                             int32_t *__restrict__ out_lb)
+__device__ inline void decode16_block(const DevTables &T, const int32_t *__restrict__ prefixes,
+                                      const int32_t *__restrict__ depths, int64_t N, int64_t Npad,
+                                      const Workspace16 &W, int32_t *__restrict__ out_lb, int64_t blk,
+                                      uint32_t *sm)
 {
-    extern __shared__ uint32_t sm[];
     uint32_t *bits = sm;                                      // 16 words x 256 lanes
     int32_t *ptab = reinterpret_cast<int32_t *>(sm + kMaskWords * 256);  // (n+1) x MV
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
@@ -116,10 +101,10 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
     for (int e = tid; e < (n + 1) * MV; e += 256) ptab[e] = T.p32[(e / MV) * kMaxMachines + (e % MV)];
     __syncthreads();
 
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    const int64_t i = blk * 256 + tid;
     if (i >= Npad) return;
     const bool live = i < N;
-    const int64_t node = live ? W.order[i] : 0;
+    const int64_t node = live ? (W.order ? W.order[i] : i) : 0;
     int d = live ? depths[node] : 0;
     bool ok = live && d >= 0 && d <= n;
     if (!ok) d = 0;
@@ -205,150 +190,14 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
     }
 }
 
-__device__ __forceinline__ void scan_step(u16x2 &s, const unsigned char *lds_lane, uint32_t joff, uint32_t ce)
+template <int MV>
+__global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const int32_t *__restrict__ prefixes,
+                                                             const int32_t *__restrict__ depths, int64_t N,
+                                                             int64_t Npad, Workspace16 W,
+                                                             int32_t *__restrict__ out_lb)
 {
-    const uint32_t msk = *reinterpret_cast<const uint32_t *>(lds_lane + joff);
-    const unsigned short e = (unsigned short)(ce >> 16), c = (unsigned short)ce;
-    const u16x2 E = {e, e};
-    const u16x2 C = {c, c};
-    const u16x2 t = __builtin_elementwise_max(s, E) + C;
-    s = as16((msk & as32(t)) | (~msk & as32(s)));
-}
-
-// Mask rows of UNR slots through the LDS "add thread id" read: for each slot
-// M0 = row offset, and every lane reads the dword at M0 + 4 * lane, so no
-// vector instruction is spent on addresses.  M0 is saved and restored; the
-// block waits for its own reads (scalar loads are then complete as well).
-// A write of M0 by a scalar instruction needs one wait state before the read.
-// The scalar adds write SCC, which the block declares clobbered.
-template <int UNR>
-__device__ __forceinline__ void gather_rows_addtid(uint32_t (&x)[UNR], const uint32_t (&joff)[UNR], uint32_t base);
-
-#define FSP_ADDTID_1(i) "s_add_u32 m0, %[j" #i "], %[base]\n\ts_nop 0\n\tds_read_addtid_b32 %[x" #i "]\n\t"
-
-template <>
-__device__ __forceinline__ void gather_rows_addtid<8>(uint32_t (&x)[8], const uint32_t (&joff)[8], uint32_t base)
-{
-    uint32_t save;
-    asm volatile("s_mov_b32 %[sv], m0\n\t"
-                 FSP_ADDTID_1(0) FSP_ADDTID_1(1) FSP_ADDTID_1(2) FSP_ADDTID_1(3)
-                 FSP_ADDTID_1(4) FSP_ADDTID_1(5) FSP_ADDTID_1(6) FSP_ADDTID_1(7)
-                 "s_waitcnt lgkmcnt(0)\n\t"
-                 "s_mov_b32 m0, %[sv]"
-                 : [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [x3] "=&v"(x[3]),
-                   [x4] "=&v"(x[4]), [x5] "=&v"(x[5]), [x6] "=&v"(x[6]), [x7] "=&v"(x[7]), [sv] "=&s"(save)
-                 : [j0] "s"(joff[0]), [j1] "s"(joff[1]), [j2] "s"(joff[2]), [j3] "s"(joff[3]),
-                   [j4] "s"(joff[4]), [j5] "s"(joff[5]), [j6] "s"(joff[6]), [j7] "s"(joff[7]),
-                   [base] "s"(base)
-                 : "scc");
-}
-
-template <>
-__device__ __forceinline__ void gather_rows_addtid<4>(uint32_t (&x)[4], const uint32_t (&joff)[4], uint32_t base)
-{
-    uint32_t save;
-    asm volatile("s_mov_b32 %[sv], m0\n\t"
-                 FSP_ADDTID_1(0) FSP_ADDTID_1(1) FSP_ADDTID_1(2) FSP_ADDTID_1(3)
-                 "s_waitcnt lgkmcnt(0)\n\t"
-                 "s_mov_b32 m0, %[sv]"
-                 : [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [x3] "=&v"(x[3]), [sv] "=&s"(save)
-                 : [j0] "s"(joff[0]), [j1] "s"(joff[1]), [j2] "s"(joff[2]), [j3] "s"(joff[3]),
-                   [base] "s"(base)
-                 : "scc");
-}
-
-template <>
-__device__ __forceinline__ void gather_rows_addtid<16>(uint32_t (&x)[16], const uint32_t (&joff)[16], uint32_t base)
-{
-    uint32_t save;
-    asm volatile("s_mov_b32 %[sv], m0\n\t"
-                 FSP_ADDTID_1(0) FSP_ADDTID_1(1) FSP_ADDTID_1(2) FSP_ADDTID_1(3)
-                 FSP_ADDTID_1(4) FSP_ADDTID_1(5) FSP_ADDTID_1(6) FSP_ADDTID_1(7)
-                 FSP_ADDTID_1(8) FSP_ADDTID_1(9) FSP_ADDTID_1(10) FSP_ADDTID_1(11)
-                 FSP_ADDTID_1(12) FSP_ADDTID_1(13) FSP_ADDTID_1(14) FSP_ADDTID_1(15)
-                 "s_waitcnt lgkmcnt(0)\n\t"
-                 "s_mov_b32 m0, %[sv]"
-                 : [x0] "=&v"(x[0]), [x1] "=&v"(x[1]), [x2] "=&v"(x[2]), [x3] "=&v"(x[3]),
-                   [x4] "=&v"(x[4]), [x5] "=&v"(x[5]), [x6] "=&v"(x[6]), [x7] "=&v"(x[7]),
-                   [x8] "=&v"(x[8]), [x9] "=&v"(x[9]), [x10] "=&v"(x[10]), [x11] "=&v"(x[11]),
-                   [x12] "=&v"(x[12]), [x13] "=&v"(x[13]), [x14] "=&v"(x[14]), [x15] "=&v"(x[15]),
-                   [sv] "=&s"(save)
-                 : [j0] "s"(joff[0]), [j1] "s"(joff[1]), [j2] "s"(joff[2]), [j3] "s"(joff[3]),
-                   [j4] "s"(joff[4]), [j5] "s"(joff[5]), [j6] "s"(joff[6]), [j7] "s"(joff[7]),
-                   [j8] "s"(joff[8]), [j9] "s"(joff[9]), [j10] "s"(joff[10]), [j11] "s"(joff[11]),
-                   [j12] "s"(joff[12]), [j13] "s"(joff[13]), [j14] "s"(joff[14]), [j15] "s"(joff[15]),
-                   [base] "s"(base)
-                 : "scc");
-}
-
-template <>
-__device__ __forceinline__ void gather_rows_addtid<32>(uint32_t (&x)[32], const uint32_t (&joff)[32], uint32_t base)
-{
-    uint32_t lo[16], hi[16], jl[16], jh[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) { jl[c] = joff[c]; jh[c] = joff[16 + c]; }
-    gather_rows_addtid<16>(lo, jl, base);
-    gather_rows_addtid<16>(hi, jh, base);
-#pragma unroll
-    for (int c = 0; c < 16; ++c) { x[c] = lo[c]; x[16 + c] = hi[c]; }
-}
-#undef FSP_ADDTID_1
-
-__device__ __forceinline__ void scan_update(u16x2 &s, uint32_t msk, uint32_t ce)
-{
-    const unsigned short e = (unsigned short)(ce >> 16), c = (unsigned short)ce;
-    const u16x2 E = {e, e};
-    const u16x2 C = {c, c};
-    const u16x2 t = __builtin_elementwise_max(s, E) + C;
-    s = as16((msk & as32(t)) | (~msk & as32(s)));
-}
-
-// Scans NCH machine pairs in lockstep over their Johnson-order slots.  The
-// chains are independent, so their dependent packed operations interleave.
-template <int UNR, int NCH, bool ADDTID>
-__device__ __forceinline__ void scan_pairs(const DevTables &T, const int (&prs)[NCH], u16x2 (&s)[NCH],
-                                           const unsigned char *lds_lane, uint32_t lds_base)
-{
-    const int npad = T.npad;  // multiple of 4; padding slots read the zero row
-    cptr<uint32_t> rec[NCH];
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-        rec[ch] = as_const(reinterpret_cast<const uint32_t *>(T.rec16 + (size_t)prs[ch] * npad));
-    int i = 0;
-    for (; i + UNR <= npad; i += UNR) {
-        uint32_t r[NCH][2 * UNR];
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-            for (int c = 0; c < 2 * UNR; ++c) r[ch][c] = rec[ch][2 * i + c];
-        if constexpr (ADDTID) {
-            uint32_t jo[NCH * UNR], x[NCH * UNR];
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int c = 0; c < UNR; ++c) jo[ch * UNR + c] = r[ch][2 * c];
-            gather_rows_addtid<NCH * UNR>(x, jo, lds_base);
-#pragma unroll
-            for (int c = 0; c < UNR; ++c)
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) scan_update(s[ch], x[ch * UNR + c], r[ch][2 * c + 1]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < UNR; ++c)
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) scan_step(s[ch], lds_lane, r[ch][2 * c], r[ch][2 * c + 1]);
-        }
-    }
-    for (; i < npad; i += 4) {
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            uint32_t r[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) r[c] = rec[ch][2 * i + c];
-#pragma unroll
-            for (int c = 0; c < 8; c += 2) scan_step(s[ch], lds_lane, r[c], r[c + 1]);
-        }
-    }
+    extern __shared__ uint32_t sm[];
+    decode16_block<MV>(T, prefixes, depths, N, Npad, W, out_lb, blockIdx.x, sm);
 }
 
 template <int WAVES, int UNR, bool ADDTID, int NCH>
@@ -414,9 +263,164 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
 #pragma unroll
         for (int w = 1; w < WAVES; ++w) best = __builtin_elementwise_max(best, as16(lds[w * 64 + lane]));
         const int64_t a = G * 128 + lane, b = a + 64;
-        if (a < N && W.st[a]) out_lb[W.order[a]] = (int32_t)best.x;
-        if (b < N && W.st[b]) out_lb[W.order[b]] = (int32_t)best.y;
+        if (a < N && W.st[a]) out_lb[W.order ? W.order[a] : a] = (int32_t)best.x;
+        if (b < N && W.st[b]) out_lb[W.order ? W.order[b] : b] = (int32_t)best.y;
     }
+}
+
+
+// ---- batched bounding: many pools in one decode launch per machine-count
+// class and one persistent scan launch fed by a device work queue.
+
+// Copies a struct from a wave-uniform address with scalar loads.
+template <class S>
+__device__ __forceinline__ S load_uniform(const S *p)
+{
+    static_assert(sizeof(S) % 4 == 0, "dword-sized struct");
+    S out;
+    uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+    cptr<uint32_t> q = as_const(reinterpret_cast<const uint32_t *>(p));
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(S) / 4); ++w) o[w] = q[w];
+    return out;
+}
+
+template <int MV>
+__global__ __launch_bounds__(256) void batch_decode16_kernel(const BatchPool *__restrict__ pools,
+                                                             const int64_t *__restrict__ blk_off,
+                                                             const int32_t *__restrict__ cls_pools, int ncls)
+{
+    extern __shared__ uint32_t sm[];
+    cptr<int64_t> off = as_const(blk_off);
+    int lo = 0, hi = ncls - 1;  // last class pool whose first block is <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchPool P = load_uniform(pools + as_const(cls_pools)[lo]);
+    decode16_block<MV>(P.T, P.prefixes, P.depths, P.N, P.Npad, P.W, P.out_lb, (int64_t)blockIdx.x - off[lo], sm);
+}
+
+// Persistent scan: each workgroup takes work items from a device counter
+// until none is left.  An item stages the masks of up to 16 / wpg groups of one
+// pool in LDS; wpg waves scan the machine pairs of each group (two chains per
+// wave), then one wave per group takes the maximum over its waves.
+template <int UNR>
+__global__ __launch_bounds__(64 * kBatchWaves) void batch_scan16_kernel(const BatchPool *__restrict__ pools,
+                                                                       const WorkItem *__restrict__ items,
+                                                                       int n_items, uint32_t *__restrict__ counter)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t *)lds);
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;  // the counter only grows: every wave leaves
+        const WorkItem wi = load_uniform(items + it);
+        const BatchPool P = load_uniform(pools + wi.pool);
+        const int n = P.T.n, m = P.T.m, NW = (n + 31) >> 5, np1 = n + 1;
+        const int wpg = P.wpg;
+        for (int r = wave; r < wi.ngroups * np1; r += kBatchWaves) {
+            const int gi = r / np1, j = r - gi * np1;
+            uint32_t m2 = 0;
+            if (j < n) {
+                const uint32_t *fw = P.W.flg + ((int64_t)(wi.group0 + gi) * NW + (j >> 5)) * 128;
+                const uint32_t a = (fw[lane] >> (j & 31)) & 1u, b = (fw[64 + lane] >> (j & 31)) & 1u;
+                m2 = (a ? 0x0000ffffu : 0u) | (b ? 0xffff0000u : 0u);
+            }
+            lds[(gi * np1 + j) * 64 + lane] = m2;
+        }
+        __syncthreads();
+        const int gi = wave / wpg, sw = wave - gi * wpg;
+        u16x2 lb = {0, 0};
+        if (gi < wi.ngroups) {
+            const int64_t G = wi.group0 + gi;
+            const uint32_t gbase = lds0 + (uint32_t)(gi * np1) * 256u;
+            const unsigned char *lds_lane =
+                reinterpret_cast<const unsigned char *>(lds) + (size_t)gi * np1 * 256 + lane * 4;
+            const uint32_t *dR = P.W.dec + (G * 3 + 0) * m * 64 + lane;
+            const uint32_t *dT = dR + m * 64;
+            const uint32_t *dQ = dT + m * 64;
+            cptr<int32_t> pairs = as_const(P.T.pairs);
+            int pr = sw;
+            for (; pr + wpg < P.T.P; pr += 2 * wpg) {
+                int prs[2] = {pr, pr + wpg};
+                u16x2 sv[2];
+                uint32_t tk[2], ql[2];
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {
+                    const int k = pairs[2 * prs[ch]], l = pairs[2 * prs[ch] + 1];
+                    sv[ch] = as16(dR[l * 64]) - as16(dR[k * 64]);
+                    tk[ch] = dT[k * 64];
+                    ql[ch] = dQ[l * 64];
+                }
+                scan_pairs<UNR, 2, true>(P.T, prs, sv, lds_lane, gbase);
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) lb = __builtin_elementwise_max(lb, as16(tk[ch]) + sv[ch] + as16(ql[ch]));
+            }
+            for (; pr < P.T.P; pr += wpg) {
+                const int prs[1] = {pr};
+                const int k = pairs[2 * pr], l = pairs[2 * pr + 1];
+                u16x2 sv[1] = {as16(dR[l * 64]) - as16(dR[k * 64])};
+                const uint32_t tk = dT[k * 64], ql = dQ[l * 64];
+                scan_pairs<UNR, 1, true>(P.T, prs, sv, lds_lane, gbase);
+                lb = __builtin_elementwise_max(lb, as16(tk) + sv[0] + as16(ql));
+            }
+        }
+        __syncthreads();
+        lds[wave * 64 + lane] = as32(lb);
+        __syncthreads();
+        if (wave < wi.ngroups) {
+            const int64_t G = wi.group0 + wave;
+            u16x2 best = as16(lds[(wave * wpg) * 64 + lane]);
+            for (int w = 1; w < wpg; ++w) best = __builtin_elementwise_max(best, as16(lds[(wave * wpg + w) * 64 + lane]));
+            const int64_t a = G * 128 + lane, b = a + 64;
+            if (a < P.N && P.W.st[a]) P.out_lb[a] = (int32_t)best.x;
+            if (b < P.N && P.W.st[b]) P.out_lb[b] = (int32_t)best.y;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_decode(int MV, const BatchPool *pools, const int64_t *blk_off, const int32_t *cls_pools,
+                               int ncls, int64_t nblocks, size_t lds_bytes, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nblocks), block(256);
+#define FSP_BDECODE(MVV) \
+    case MVV: batch_decode16_kernel<MVV><<<grid, block, lds_bytes, s>>>(pools, blk_off, cls_pools, ncls); break;
+    switch (MV) {
+        FSP_BDECODE(4) FSP_BDECODE(8) FSP_BDECODE(12) FSP_BDECODE(16)
+        FSP_BDECODE(20) FSP_BDECODE(24) FSP_BDECODE(28) FSP_BDECODE(32)
+    default: return hipErrorInvalidValue;
+    }
+#undef FSP_BDECODE
+    return hipGetLastError();
+}
+
+__global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
+
+hipError_t launch_batch_scan(const BatchPool *pools, const WorkItem *items, int n_items, uint32_t *counter,
+                             int grid, size_t lds_bytes, hipStream_t s)
+{
+    batch_reset_kernel<<<1, 1, 0, s>>>(counter);
+    batch_scan16_kernel<8><<<grid, 64 * kBatchWaves, lds_bytes, s>>>(pools, items, n_items, counter);
+    return hipGetLastError();
+}
+
+int batch_scan_blocks_per_cu(size_t lds_bytes)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_scan16_kernel<8>, 64 * kBatchWaves, lds_bytes) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
 }
 
 static int scan_waves(int P)

@@ -61,6 +61,13 @@ class SolveResult(ctypes.Structure):
                 ("max_stack", ctypes.c_int64)]
 
 
+class PoolDesc(ctypes.Structure):
+    _fields_ = [("inst", ctypes.c_void_p), ("prefixes", ctypes.c_void_p), ("depths", ctypes.c_void_p),
+                ("N", ctypes.c_int64), ("out_lb", ctypes.c_void_p)]
+
+
+BATCH_GRAPH = 1
+
 _lib = None
 _SIGNATURES = {
     "fsp_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -76,6 +83,13 @@ _SIGNATURES = {
                                               ctypes.c_int64, _vp, ctypes.POINTER(StepResult), _vp]),
     "fsp_solve": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(SolveResult),
                                    _i32p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, _vp]),
+    "fsp_batch_create": (ctypes.c_int32, [ctypes.POINTER(PoolDesc), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(_vp)]),
+    "fsp_batch_run": (ctypes.c_int32, [_vp, _vp]),
+    "fsp_batch_destroy": (ctypes.c_int32, [_vp]),
+    "fsp_batch_info": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "fsp_bound_pools_batched": (ctypes.c_int32, [ctypes.POINTER(PoolDesc), ctypes.c_int32, _vp]),
     "fsp_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
     "fsp_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -268,3 +282,63 @@ def solve(inst: Instance, ub0: int = UB_NEH, pool_cap: int = 1 << 18, node_budge
     out["perm"] = perm
     out["steplog"] = log[:min(res.steps, steplog_cap)] if steplog_cap else None
     return out
+
+
+def _pool_descs(pools):
+    """pools: list of (instance, prefixes, depths, out_lb) with device tensors."""
+    arr = (PoolDesc * len(pools))()
+    keep = []
+    for i, (inst, pre, dep, out) in enumerate(pools):
+        N = int(dep.shape[0])
+        arr[i].inst = inst.handle.value
+        arr[i].prefixes = _dev_i32(pre, "prefixes", (N, inst.n)) if N else None
+        arr[i].depths = _dev_i32(dep, "depths", (N,)) if N else None
+        arr[i].N = N
+        arr[i].out_lb = _dev_i32(out, "out_lb", (N,)) if N else None
+        keep.append((inst, pre, dep, out))
+    return arr, keep
+
+
+class Batch:
+    """A planned batch (fsp_batch_create); run() enqueues one bounding of every pool."""
+
+    def __init__(self, pools, graph: bool = True):
+        self._arr, self._keep = _pool_descs(pools)
+        h = _vp()
+        _check(lib().fsp_batch_create(self._arr, len(pools), BATCH_GRAPH if graph else 0, ctypes.byref(h)),
+               "fsp_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().fsp_batch_run(self._h, _stream_handle(stream)), "fsp_batch_run")
+
+    def info(self):
+        t, k, g = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fsp_batch_info(self._h, ctypes.byref(t), ctypes.byref(k), ctypes.byref(g)), "fsp_batch_info")
+        return {"total_nodes": t.value, "items": k.value, "grid": g.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fsp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def batch_create(pools, graph: bool = True) -> Batch:
+    return Batch(pools, graph)
+
+
+def bound_pools_batched(pools, stream=None) -> None:
+    arr, _keep = _pool_descs(pools)
+    _check(lib().fsp_bound_pools_batched(arr, len(pools), _stream_handle(stream)), "fsp_bound_pools_batched")

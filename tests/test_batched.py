@@ -1,0 +1,132 @@
+"""Batched bounding (many pools, one persistent graph-captured launch) against
+the plain per-pool launch and the oracle, element by element."""
+import numpy as np
+import pytest
+
+from helpers import oracle_bounds, require_gpu, to_dev
+from paper_1208_3933_amd import fspbb, gen
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(20, 5), (20, 10), (20, 20), (50, 10), (100, 20), (200, 20)]
+
+
+def make_batch(torch, n_pools, sizes, config=3, invalid_in=None):
+    pools, host = [], []
+    insts = {}
+    for i in range(n_pools):
+        n, m = SHAPES[i % len(SHAPES)]
+        key = (n, m, i // len(SHAPES) % 2)  # two instances per shape, pools share them
+        if key not in insts:
+            p = gen.processing_times(n, m, gen.make_seed(config, len(insts), gen.PURPOSE_TIMES))
+            insts[key] = (fspbb.create_instance(p), p)
+        inst, p = insts[key]
+        N = int(sizes[i])
+        pre, dep = gen.random_pool(n, N, gen.make_seed(config, 100 + i, gen.PURPOSE_POOL))
+        if invalid_in is not None and i == invalid_in and N > 3:
+            dep = dep.copy()
+            dep[1] = n + 5
+        pre_d, dep_d = to_dev(torch, pre, dep)
+        out = torch.full((N,), -7, dtype=torch.int32, device="cuda")
+        pools.append((inst, pre_d, dep_d, out))
+        host.append((p, pre, dep))
+    return pools, host, insts
+
+
+def plain_bounds(torch, pools):
+    res = []
+    for inst, pre_d, dep_d, _ in pools:
+        N = int(dep_d.shape[0])
+        o = torch.full((N,), -9, dtype=torch.int32, device="cuda")
+        if N:
+            fspbb.bound_pool(inst, pre_d, dep_d, o)
+        res.append(o)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in res]
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_mixed_batch_matches_plain_and_oracle(graph):
+    torch = require_gpu()
+    sizes = [300, 1000, 129, 0, 2048, 700, 128, 4000, 64, 513, 1, 3000]
+    pools, host, insts = make_batch(torch, len(sizes), sizes, invalid_in=2)
+    want_plain = plain_bounds(torch, pools)
+    with fspbb.batch_create(pools, graph=graph) as b:
+        assert b.info()["total_nodes"] == sum(sizes)
+        b.run()
+        torch.cuda.synchronize()
+    for i, (inst, _, _, out) in enumerate(pools):
+        got = out.cpu().numpy()
+        assert (got == want_plain[i]).all(), i
+        p, pre, dep = host[i]
+        if len(dep):
+            idx = np.arange(0, len(dep), max(1, len(dep) // 300))
+            assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all(), i
+    for inst, _ in insts.values():
+        fspbb.pool_status(inst)
+        inst.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    torch = require_gpu()
+    sizes = [500, 257, 1200, 64, 900, 300]
+    pools, host, insts = make_batch(torch, len(sizes), sizes, config=5)
+    with fspbb.batch_create(pools, graph=True) as b:
+        for rep in range(4):
+            # change the pools' contents in place (same buffers), with eager work between replays
+            for i, (inst, pre_d, dep_d, out) in enumerate(pools):
+                n = inst.n
+                g = torch.Generator(device="cpu").manual_seed(1000 * rep + i)
+                dep_d.copy_(torch.randint(0, n + 1, (dep_d.shape[0],), generator=g, dtype=torch.int32))
+                out.fill_(-5)
+            scratch = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+            want = plain_bounds(torch, pools)
+            b.run()
+            torch.cuda.synchronize()
+            assert torch.isfinite(scratch)
+            for i, (_, _, _, out) in enumerate(pools):
+                assert (out.cpu().numpy() == want[i]).all(), (rep, i)
+    for inst, _ in insts.values():
+        inst.close()
+
+
+def test_one_shot_batched():
+    torch = require_gpu()
+    sizes = [100, 2000, 333]
+    pools, host, insts = make_batch(torch, len(sizes), sizes, config=6)
+    want = plain_bounds(torch, pools)
+    fspbb.bound_pools_batched(pools)
+    for i, (_, _, _, out) in enumerate(pools):
+        assert (out.cpu().numpy() == want[i]).all()
+    for inst, _ in insts.values():
+        inst.close()
+
+
+def test_full_batched_configuration():
+    """64 seeded instances of mixed shape, log-normal pool sizes 256..131072."""
+    torch = require_gpu()
+    sizes = gen.lognormal_pool_sizes(64, gen.make_seed(3, 0, gen.PURPOSE_SIZES))
+    pools, host, insts = make_batch(torch, 64, sizes)
+    want = plain_bounds(torch, pools)
+    with fspbb.batch_create(pools, graph=True) as b:
+        b.run()
+        b.run()
+        torch.cuda.synchronize()
+    for i, (_, _, _, out) in enumerate(pools):
+        got = out.cpu().numpy()
+        assert (got == want[i]).all(), i
+        p, pre, dep = host[i]
+        idx = np.arange(0, len(dep), max(1, len(dep) // 24))
+        assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all(), i
+    for inst, _ in insts.values():
+        inst.close()
+
+
+def test_batch_rejects_bad_descriptors():
+    torch = require_gpu()
+    p = gen.processing_times(10, 4, gen.make_seed(7, 0, 0), 1, 100000)  # beyond the 16-bit path
+    with fspbb.create_instance(p) as inst:
+        d = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        pre = torch.zeros((1, 10), dtype=torch.int32, device="cuda")
+        with pytest.raises(fspbb.FspError):
+            fspbb.batch_create([(inst, pre, d, d)])
