@@ -42,7 +42,8 @@ enum {
     FSP_E_DEVICE = -4,    /* a HIP runtime call failed (see fsp_last_error_string) */
     FSP_E_BADNODE = -5,   /* the pool held invalid nodes (their bound is FSP_LB_INVALID) */
     FSP_E_NODEVICE = -6,  /* no gfx950 device is visible */
-    FSP_BUDGET = 1        /* a search stopped at its node budget without a proof */
+    FSP_BUDGET = 1,       /* a search stopped at its node budget without a proof */
+    FSP_PENDING = 2       /* a served search has not finished yet */
 };
 
 /* Bound written for an invalid node: depth outside 0..n, a job outside
@@ -169,6 +170,33 @@ fsp_status fsp_batch_info(fsp_batch b, int64_t *total_nodes, int32_t *n_items, i
 /* fsp_bound_pools_batched - one-shot: create (without graph), run, wait, destroy. */
 fsp_status fsp_bound_pools_batched(const fsp_pool_desc *pools, int32_t n_pools, void *stream);
 
+/* ---- tile-schedule tuning ------------------------------------------------ */
+
+typedef struct {
+    int32_t waves_per_group;  /* chosen schedule: waves per 128-node group */
+    int32_t candidates;       /* schedules measured */
+    double best_us;           /* device time of one batch run of the sample, chosen schedule */
+    double default_us;        /* same for the rule-of-thumb schedule */
+    int32_t cand_wpg[8];
+    double cand_us[8];
+} fsp_tune_result;
+
+/*
+ * fsp_autotune - time every scan tile schedule for this instance's shape (n,
+ * m) on a seeded sample pool of sample_nodes nodes (best of reps runs each)
+ * and store the fastest in the process-wide tuning table, which
+ * fsp_bound_pool and fsp_batch_create consult.  The pool size used by the
+ * paper was chosen the same way, by trying sizes at run time (Sec. IV-A).
+ * Synchronous; allocates and frees its own sample buffers.  16-bit path only.
+ */
+fsp_status fsp_autotune(fsp_instance inst, int64_t sample_nodes, int32_t reps, fsp_tune_result *res);
+/* Tuning table access: current schedule for a shape (tuned = 0 for the rule
+ * of thumb), explicit setting (1, 2, 4, 8 or 16), save/load as text. */
+fsp_status fsp_tune_get(int32_t n, int32_t m, int32_t *waves_per_group, int32_t *tuned);
+fsp_status fsp_tune_set(int32_t n, int32_t m, int32_t waves_per_group);
+fsp_status fsp_tune_save(const char *path);
+fsp_status fsp_tune_load(const char *path);
+
 /* ---- branch-and-bound ---------------------------------------------------- */
 
 /* ub0 value of fsp_solve: start from the NEH heuristic's schedule. */
@@ -243,6 +271,66 @@ fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t n
 /* fsp_neh - NEH heuristic schedule (host computation): perm_out (host n, may
  * be NULL) and its makespan. */
 fsp_status fsp_neh(fsp_instance inst, int32_t *perm_out, int32_t *makespan);
+
+/*
+ * Serving: a loop of concurrent depth-first searches (fsp_solve semantics
+ * each) that share every launch.  Searches are admitted first come first
+ * served while a slot and the device-memory budget allow; every call to
+ * fsp_server_step then advances each admitted search by one pool step, with
+ * the step kernels of all of them in one set of launches and all their
+ * children bounded by one merged batched launch (Sec. III-A pools, merged
+ * across requests).  Search stacks, step scratch and instance tables stay on
+ * the device.  A search's result (optimum, schedule, node and step counts,
+ * step fingerprints) depends only on its own (instance, ub0, pool_cap,
+ * node_budget), not on what it shared launches with.
+ */
+typedef struct fsp_server_s *fsp_server;
+
+typedef struct {
+    int64_t mem_budget_bytes;  /* device bytes for admitted searches' stacks and
+                                  step scratch, at their initial size (> 0) */
+    int32_t max_active;        /* most searches admitted at once (>= 1) */
+    int64_t tick_children;     /* cap on children bounded per step call, summed
+                                  over searches (0 = none); searches left out
+                                  step first in the next call, and one search
+                                  always steps */
+} fsp_server_config;
+
+typedef struct {
+    int32_t active, pending;   /* admitted searches, searches waiting for admission */
+    int64_t mem_used;          /* device bytes held by admitted searches now */
+    int64_t ticks;             /* step calls that advanced at least one search */
+    int64_t nodes_bounded;     /* over all searches so far */
+    int64_t last_children;     /* children bounded by the last step call */
+    int32_t last_searches;     /* searches advanced by the last step call */
+} fsp_server_stats;
+
+/* fsp_server_create - cfg host; stream: every launch and copy of the server
+ * goes to it.  The server keeps references to the instances it is given:
+ * an instance must outlive the searches submitted on it. */
+fsp_status fsp_server_create(const fsp_server_config *cfg, void *stream, fsp_server *out);
+
+/* fsp_server_submit - queue a search (arguments as in fsp_solve); id_out host.
+ * FSP_E_NOMEM when its initial device memory exceeds the whole budget. */
+fsp_status fsp_server_submit(fsp_server srv, fsp_instance inst, int32_t ub0, int64_t pool_cap,
+                             int64_t node_budget, int64_t *id_out);
+
+/* fsp_server_step - admit what fits, then one step of every admitted search
+ * (synchronous on the stream).  done_ids host (done_cap entries, may be NULL):
+ * ids of the searches that finished in this call, *n_done their count (ids
+ * beyond done_cap are not listed but can still be polled).  stats may be NULL.
+ * An error here leaves every admitted search failed with that status. */
+fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, int32_t *n_done,
+                           fsp_server_stats *stats);
+
+/* fsp_server_poll - FSP_PENDING while search id runs or waits; then its
+ * fsp_solve status (FSP_OK, FSP_BUDGET or an error) with res and perm_out
+ * (host n, may be NULL) filled, once: the result is then forgotten, and
+ * later polls of the id give FSP_E_INVAL. */
+fsp_status fsp_server_poll(fsp_server srv, int64_t id, fsp_solve_result *res, int32_t *perm_out);
+
+/* fsp_server_destroy - waits for the stream, frees every search. */
+fsp_status fsp_server_destroy(fsp_server srv);
 
 /*
  * Kernel timing (instrumentation).  When enabled on an instance, each bound

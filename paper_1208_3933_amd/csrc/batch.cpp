@@ -1,6 +1,8 @@
 // Batched bounding of many pools (possibly of different instances and
 // shapes) in one decode launch per machine-count class and one persistent
-// scan launch, captured once in a HIP graph and replayed.
+// scan launch, either captured once in a HIP graph and replayed
+// (fsp_batch_*), or re-planned per call into a reusable device region (the
+// merged bounding step of concurrent searches).
 //
 // Plan: every pool is cut into 128-node groups; a work item holds as many
 // groups of one pool as its tile schedule stages in LDS at once (16 / wpg,
@@ -21,6 +23,8 @@ namespace fspbb {
 namespace {
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, ScanTuning> g_tune;
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 ScanTuning scan_tuning(int n, int m)
@@ -43,29 +47,201 @@ void set_scan_tuning(int n, int m, ScanTuning t)
     g_tune[{n, m}] = t;
 }
 
+bool has_scan_tuning(int n, int m)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune.count({n, m}) != 0;
+}
+
+void scan_tuning_entries(std::vector<std::pair<std::pair<int, int>, ScanTuning>> &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    out.assign(g_tune.begin(), g_tune.end());
+}
+
+fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out)
+{
+    if (!pools || n_pools < 1) return FSP_E_INVAL;
+    const int dev = pools[0].inst ? pools[0].inst->device : -1;
+    for (int i = 0; i < n_pools; ++i) {
+        const fsp_pool_desc &d = pools[i];
+        if (!d.inst || d.N < 0 || d.inst->device != dev) return FSP_E_INVAL;
+        if (!d.inst->packed16) return FSP_E_INVAL;
+        if (d.N > 0 && (!d.prefixes || !d.depths || !d.out_lb)) return FSP_E_INVAL;
+    }
+    *dev_out = dev;
+    return FSP_OK;
+}
+
+void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, BatchPlan &pl)
+{
+    pl = BatchPlan{};
+    pl.pools.resize(n_pools);
+    pl.ws_off.resize(n_pools);
+    struct Cost { int64_t cost; WorkItem w; };
+    std::vector<Cost> items;
+    size_t ws = 0;
+    pl.scan_lds = 64 * kBatchWaves * 4;  // the cross-wave reduction reuses the mask area
+    for (int i = 0; i < n_pools; ++i) {
+        const fsp_pool_desc &d = pools[i];
+        const fsp_instance_s *I = d.inst;
+        const int n = I->n, m = I->m, NW = (n + 31) >> 5;
+        const int64_t G = (d.N + kGroup - 1) / kGroup, Npad = G * kGroup;
+        pl.ws_off[i] = ws;
+        ws += al256((size_t)G * 3 * m * 64 * 4) + al256((size_t)G * NW * 128 * 4) + al256((size_t)Npad * 4);
+        BatchPool &P = pl.pools[i];
+        std::memset(&P, 0, sizeof(P));
+        P.T = I->dt;
+        P.prefixes = d.prefixes;
+        P.depths = d.depths;
+        P.out_lb = d.out_lb;
+        P.N = d.N;
+        P.Npad = Npad;
+        P.wpg = wpg_force ? wpg_force : scan_tuning(n, m).waves_per_group;
+        const int gpp = kBatchWaves / P.wpg;
+        const int64_t per_wave = (I->P + P.wpg - 1) / P.wpg;
+        for (int64_t g0 = 0; g0 < G; g0 += gpp) {
+            const int ng = (int)std::min<int64_t>(gpp, G - g0);
+            items.push_back({per_wave * I->dt.npad, WorkItem{i, (int32_t)g0, ng, 0}});
+        }
+        if (G > 0) pl.scan_lds = std::max(pl.scan_lds, (size_t)std::min<int64_t>(gpp, G) * (n + 1) * 256);
+        pl.total_nodes += d.N;
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Cost &x, const Cost &y) { return x.cost > y.cost; });
+    for (auto &c : items) pl.items.push_back(c.w);
+    pl.ws_bytes = al256(ws);
+
+    std::map<int, std::vector<int32_t>> cls;
+    for (int i = 0; i < n_pools; ++i)
+        if (pools[i].N > 0) cls[(pools[i].inst->m + 3) & ~3].push_back(i);
+    for (auto &kv : cls) {
+        BatchPlan::Cls c;
+        c.MV = kv.first;
+        c.idx = kv.second;
+        c.off.assign(kv.second.size() + 1, 0);
+        int nmax = 0;
+        for (size_t q = 0; q < kv.second.size(); ++q) {
+            const BatchPool &P = pl.pools[kv.second[q]];
+            c.off[q + 1] = c.off[q] + (P.Npad + 255) / 256;
+            nmax = std::max(nmax, (int)P.T.n);
+        }
+        c.nblocks = c.off.back();
+        c.lds = (size_t)16 * 256 * 4 + (size_t)(nmax + 1) * c.MV * 4;
+        pl.classes.push_back(std::move(c));
+    }
+    size_t meta = 0;
+    pl.meta_pools = meta;
+    meta += al256(sizeof(BatchPool) * n_pools);
+    pl.meta_items = meta;
+    meta += al256(sizeof(WorkItem) * std::max<size_t>(1, pl.items.size()));
+    pl.meta_counter = meta;
+    meta += 256;
+    for (auto &c : pl.classes) {
+        c.meta_off = meta;
+        meta += al256(sizeof(int64_t) * c.off.size());
+        c.meta_idx = meta;
+        meta += al256(sizeof(int32_t) * c.idx.size());
+    }
+    pl.meta_bytes = meta;
+}
+
+void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host)
+{
+    for (size_t i = 0; i < pl.pools.size(); ++i) {
+        BatchPool &P = pl.pools[i];
+        const int n = P.T.n, m = P.T.m, NW = (n + 31) >> 5;
+        const int64_t G = P.Npad / kGroup;
+        char *w = base + pl.ws_off[i];
+        const size_t a = al256((size_t)G * 3 * m * 64 * 4), b = al256((size_t)G * NW * 128 * 4);
+        P.W.dec = (uint32_t *)w;
+        P.W.flg = (uint32_t *)(w + a);
+        P.W.st = (uint32_t *)(w + a + b);
+        P.W.order = nullptr;
+        P.W.cnt = nullptr;
+    }
+    pl.dmeta = base + pl.ws_bytes;
+    host.assign(pl.meta_bytes, 0);
+    std::memcpy(host.data() + pl.meta_pools, pl.pools.data(), sizeof(BatchPool) * pl.pools.size());
+    if (!pl.items.empty())
+        std::memcpy(host.data() + pl.meta_items, pl.items.data(), sizeof(WorkItem) * pl.items.size());
+    for (auto &c : pl.classes) {
+        std::memcpy(host.data() + c.meta_off, c.off.data(), sizeof(int64_t) * c.off.size());
+        std::memcpy(host.data() + c.meta_idx, c.idx.data(), sizeof(int32_t) * c.idx.size());
+    }
+}
+
+hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s)
+{
+    const BatchPool *dpools = (const BatchPool *)(pl.dmeta + pl.meta_pools);
+    for (const auto &c : pl.classes) {
+        hipError_t e = launch_batch_decode(c.MV, dpools, (const int64_t *)(pl.dmeta + c.meta_off),
+                                           (const int32_t *)(pl.dmeta + c.meta_idx), (int)c.idx.size(), c.nblocks,
+                                           c.lds, s);
+        if (e != hipSuccess) return e;
+    }
+    if (pl.items.empty()) return hipSuccess;
+    return launch_batch_scan(dpools, (const WorkItem *)(pl.dmeta + pl.meta_items), (int)pl.items.size(),
+                             (uint32_t *)(pl.dmeta + pl.meta_counter), grid, pl.scan_lds, s);
+}
+
+int batch_grid(int dev, size_t scan_lds)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    return prop.multiProcessorCount * batch_scan_blocks_per_cu(scan_lds);
+}
+
+hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s)
+{
+    plan_batch(pools, n_pools, 0, plan);
+    const size_t need = plan.ws_bytes + plan.meta_bytes;
+    if (need > dev_bytes) {
+        const size_t cap = std::max(need, dev_bytes * 2);
+        if (dev) hipFreeAsync(dev, s);
+        dev = nullptr;
+        dev_bytes = 0;
+        hipError_t e = hipMallocAsync(&dev, cap, s);
+        if (e != hipSuccess) return e;
+        dev_bytes = cap;
+    }
+    layout_batch(plan, (char *)dev, meta);
+    if (meta.size() > pinned_bytes) {
+        if (pinned) hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_bytes = 0;
+        hipError_t e = hipHostMalloc(&pinned, meta.size() * 2, 0);
+        if (e != hipSuccess) return e;
+        pinned_bytes = meta.size() * 2;
+    }
+    std::memcpy(pinned, meta.data(), meta.size());
+    hipError_t e = hipMemcpyAsync(plan.dmeta, pinned, meta.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    int d = 0;
+    e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    return enqueue_batch(plan, batch_grid(d, plan.scan_lds), s);
+}
+
+void BatchArena::release(hipStream_t s)
+{
+    if (dev) hipFreeAsync(dev, s);
+    dev = nullptr;
+    dev_bytes = 0;
+    if (pinned) {
+        hipStreamSynchronize(s);
+        hipHostFree(pinned);
+    }
+    pinned = nullptr;
+    pinned_bytes = 0;
+}
+
 }  // namespace fspbb
 
 struct fsp_batch_s {
     int device = 0;
-    int n_pools = 0;
-    int64_t total_nodes = 0;
-    std::vector<BatchPool> hpools;
-    std::vector<WorkItem> hitems;
-    struct DecodeClass {
-        int MV;
-        int64_t nblocks;
-        size_t lds;
-        int64_t *dblk_off;
-        int32_t *dcls;
-        int ncls;
-    };
-    std::vector<DecodeClass> classes;
-    BatchPool *dpools = nullptr;
-    WorkItem *ditems = nullptr;
-    uint32_t *dcounter = nullptr;
+    BatchPlan plan;
     void *dblob = nullptr;
     int grid = 0;
-    size_t scan_lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -93,16 +269,6 @@ fsp_status fail(hipError_t e)
     return e == hipErrorOutOfMemory ? FSP_E_NOMEM : FSP_E_DEVICE;
 }
 
-hipError_t enqueue(const fsp_batch_s *b, hipStream_t s)
-{
-    for (const auto &c : b->classes) {
-        hipError_t e = launch_batch_decode(c.MV, b->dpools, c.dblk_off, c.dcls, c.ncls, c.nblocks, c.lds, s);
-        if (e != hipSuccess) return e;
-    }
-    if (b->hitems.empty()) return hipSuccess;
-    return launch_batch_scan(b->dpools, b->ditems, (int)b->hitems.size(), b->dcounter, b->grid, b->scan_lds, s);
-}
-
 void free_batch(fsp_batch_s *b)
 {
     if (b->exec) hipGraphExecDestroy(b->exec);
@@ -113,133 +279,55 @@ void free_batch(fsp_batch_s *b)
 
 }  // namespace
 
-extern "C" {
+namespace fspbb {
 
-fsp_status fsp_batch_create(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, fsp_batch *out)
+// fsp_batch_create with an optional forced waves-per-group (0 = tuned).
+fsp_status create_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, int32_t wpg_force,
+                        fsp_batch *out)
 {
     if (!out) return FSP_E_INVAL;
     *out = nullptr;
-    if (!pools || n_pools < 1) return FSP_E_INVAL;
-    const int dev = pools[0].inst ? pools[0].inst->device : -1;
-    for (int i = 0; i < n_pools; ++i) {
-        const fsp_pool_desc &d = pools[i];
-        if (!d.inst || d.N < 0 || d.inst->device != dev) return FSP_E_INVAL;
-        if (!d.inst->packed16) return FSP_E_INVAL;
-        if (d.N > 0 && (!d.prefixes || !d.depths || !d.out_lb)) return FSP_E_INVAL;
-    }
+    int dev = -1;
+    fsp_status st = check_pools(pools, n_pools, &dev);
+    if (st != FSP_OK) return st;
     DeviceGuard g(dev);
     if (!g.ok) return FSP_E_DEVICE;
-
     fsp_batch_s *b = new fsp_batch_s();
     b->device = dev;
-    b->n_pools = n_pools;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-
-    // workspace layout and pool records
-    std::vector<size_t> ws_off(n_pools);
-    size_t ws = 0;
-    b->hpools.resize(n_pools);
-    struct Cost { int64_t cost; WorkItem w; };
-    std::vector<Cost> items;
-    size_t scan_lds = 64 * kBatchWaves * 4;  // the cross-wave reduction reuses the mask area
-    for (int i = 0; i < n_pools; ++i) {
-        const fsp_pool_desc &d = pools[i];
-        const fsp_instance_s *I = d.inst;
-        const int n = I->n, m = I->m, NW = (n + 31) >> 5;
-        const int64_t G = (d.N + kGroup - 1) / kGroup, Npad = G * kGroup;
-        ws_off[i] = ws;
-        ws += al((size_t)G * 3 * m * 64 * 4) + al((size_t)G * NW * 128 * 4) + al((size_t)Npad * 4);
-        BatchPool &P = b->hpools[i];
-        std::memset(&P, 0, sizeof(P));
-        P.T = I->dt;
-        P.prefixes = d.prefixes;
-        P.depths = d.depths;
-        P.out_lb = d.out_lb;
-        P.N = d.N;
-        P.Npad = Npad;
-        P.wpg = scan_tuning(n, m).waves_per_group;
-        const int gpp = kBatchWaves / P.wpg;
-        for (int64_t g0 = 0; g0 < G; g0 += gpp) {
-            const int ng = (int)std::min<int64_t>(gpp, G - g0);
-            const int64_t per_wave = (I->P + P.wpg - 1) / P.wpg;
-            items.push_back({per_wave * I->dt.npad, WorkItem{i, (int32_t)g0, ng, 0}});
-        }
-        if (G > 0) scan_lds = std::max(scan_lds, (size_t)std::min<int64_t>(gpp, G) * (n + 1) * 256);
-        b->total_nodes += d.N;
-    }
-    std::stable_sort(items.begin(), items.end(), [](const Cost &x, const Cost &y) { return x.cost > y.cost; });
-    for (auto &c : items) b->hitems.push_back(c.w);
-    b->scan_lds = scan_lds;
-
-    // decode classes by machine count rounded up to 4
-    std::map<int, std::vector<int>> cls;
-    for (int i = 0; i < n_pools; ++i)
-        if (pools[i].N > 0) cls[(pools[i].inst->m + 3) & ~3].push_back(i);
-    size_t meta = al(sizeof(BatchPool) * n_pools) + al(sizeof(WorkItem) * std::max<size_t>(1, b->hitems.size())) + 256;
-    for (auto &kv : cls) meta += al(sizeof(int64_t) * (kv.second.size() + 1)) + al(sizeof(int32_t) * kv.second.size());
-    hipError_t e = hipMalloc(&b->dblob, al(ws) + meta);
+    plan_batch(pools, n_pools, wpg_force, b->plan);
+    hipError_t e = hipMalloc(&b->dblob, b->plan.ws_bytes + b->plan.meta_bytes);
     if (e != hipSuccess) { free_batch(b); return fail(e); }
-    char *base = (char *)b->dblob;
-    for (int i = 0; i < n_pools; ++i) {
-        const fsp_instance_s *I = pools[i].inst;
-        const int n = I->n, m = I->m, NW = (n + 31) >> 5;
-        const int64_t G = (pools[i].N + kGroup - 1) / kGroup;
-        char *w = base + ws_off[i];
-        BatchPool &P = b->hpools[i];
-        P.W.dec = (uint32_t *)w;
-        P.W.flg = (uint32_t *)(w + al((size_t)G * 3 * m * 64 * 4));
-        P.W.st = (uint32_t *)(w + al((size_t)G * 3 * m * 64 * 4) + al((size_t)G * NW * 128 * 4));
-        P.W.order = nullptr;
-        P.W.cnt = nullptr;
-    }
-    char *mp = base + al(ws);
-    b->dpools = (BatchPool *)mp; mp += al(sizeof(BatchPool) * n_pools);
-    b->ditems = (WorkItem *)mp; mp += al(sizeof(WorkItem) * std::max<size_t>(1, b->hitems.size()));
-    b->dcounter = (uint32_t *)mp; mp += 256;
-    e = hipMemcpy(b->dpools, b->hpools.data(), sizeof(BatchPool) * n_pools, hipMemcpyHostToDevice);
-    if (e == hipSuccess && !b->hitems.empty())
-        e = hipMemcpy(b->ditems, b->hitems.data(), sizeof(WorkItem) * b->hitems.size(), hipMemcpyHostToDevice);
-    for (auto &kv : cls) {
-        fsp_batch_s::DecodeClass c{};
-        c.MV = kv.first;
-        std::vector<int64_t> off(kv.second.size() + 1, 0);
-        int nmax = 0;
-        for (size_t q = 0; q < kv.second.size(); ++q) {
-            const BatchPool &P = b->hpools[kv.second[q]];
-            off[q + 1] = off[q] + (P.Npad + 255) / 256;
-            nmax = std::max(nmax, (int)P.T.n);
-        }
-        c.nblocks = off.back();
-        c.ncls = (int)kv.second.size();
-        c.lds = (size_t)16 * 256 * 4 + (size_t)(nmax + 1) * c.MV * 4;
-        c.dblk_off = (int64_t *)mp; mp += al(sizeof(int64_t) * off.size());
-        c.dcls = (int32_t *)mp; mp += al(sizeof(int32_t) * kv.second.size());
-        if (e == hipSuccess) e = hipMemcpy(c.dblk_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(c.dcls, kv.second.data(), sizeof(int32_t) * kv.second.size(), hipMemcpyHostToDevice);
-        b->classes.push_back(c);
-    }
+    std::vector<char> meta;
+    layout_batch(b->plan, (char *)b->dblob, meta);
+    e = hipMemcpy(b->plan.dmeta, meta.data(), meta.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { free_batch(b); return fail(e); }
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, dev);
-    if (e != hipSuccess) { free_batch(b); return fail(e); }
-    b->grid = prop.multiProcessorCount * batch_scan_blocks_per_cu(b->scan_lds);
-
+    b->grid = batch_grid(dev, b->plan.scan_lds);
     if (flags & FSP_BATCH_GRAPH) {
         hipStream_t cs;
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t e1 = enqueue(b, cs);
-            hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
-            e = e1 != hipSuccess ? e1 : e2;
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e1 = enqueue_batch(b->plan, b->grid, cs);
+                hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+                e = e1 != hipSuccess ? e1 : e2;
+            }
+            hipStreamDestroy(cs);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        hipStreamDestroy(cs);
         if (e != hipSuccess) { free_batch(b); return fail(e); }
     }
     *out = b;
     return FSP_OK;
+}
+
+}  // namespace fspbb
+
+extern "C" {
+
+fsp_status fsp_batch_create(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, fsp_batch *out)
+{
+    return create_batch(pools, n_pools, flags, 0, out);
 }
 
 fsp_status fsp_batch_run(fsp_batch b, void *stream)
@@ -248,7 +336,7 @@ fsp_status fsp_batch_run(fsp_batch b, void *stream)
     DeviceGuard g(b->device);
     if (!g.ok) return FSP_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = b->exec ? hipGraphLaunch(b->exec, s) : enqueue(b, s);
+    hipError_t e = b->exec ? hipGraphLaunch(b->exec, s) : enqueue_batch(b->plan, b->grid, s);
     return e == hipSuccess ? FSP_OK : fail(e);
 }
 
@@ -264,8 +352,8 @@ fsp_status fsp_batch_destroy(fsp_batch b)
 fsp_status fsp_batch_info(fsp_batch b, int64_t *total_nodes, int32_t *n_items, int32_t *grid)
 {
     if (!b) return FSP_E_INVAL;
-    if (total_nodes) *total_nodes = b->total_nodes;
-    if (n_items) *n_items = (int32_t)b->hitems.size();
+    if (total_nodes) *total_nodes = b->plan.total_nodes;
+    if (n_items) *n_items = (int32_t)b->plan.items.size();
     if (grid) *grid = b->grid;
     return FSP_OK;
 }

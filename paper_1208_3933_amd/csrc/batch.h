@@ -1,6 +1,9 @@
 // Batched bounding of many pools in one persistent launch (host/device shared).
 #pragma once
 
+#include <utility>
+#include <vector>
+
 #include "fspbb_internal.h"
 
 namespace fspbb {
@@ -48,5 +51,55 @@ struct ScanTuning {
 };
 ScanTuning scan_tuning(int n, int m);
 void set_scan_tuning(int n, int m, ScanTuning t);
+bool has_scan_tuning(int n, int m);
+void scan_tuning_entries(std::vector<std::pair<std::pair<int, int>, ScanTuning>> &out);
+
+fsp_status create_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, int32_t wpg_force,
+                        fsp_batch *out);
+
+// Launch plan of a batch: pool records, LPT-ordered work items, decode
+// classes (pools grouped by machine count rounded up to 4), and the layout
+// of one device region = per-pool decode workspace (ws_bytes) followed by the
+// metadata the kernels read (meta_bytes).
+struct BatchPlan {
+    struct Cls {
+        int MV = 0;
+        std::vector<int32_t> idx;     // pools of this class
+        std::vector<int64_t> off;     // decode block offsets, idx.size() + 1
+        int64_t nblocks = 0;
+        size_t lds = 0;
+        size_t meta_off = 0, meta_idx = 0;
+    };
+    std::vector<BatchPool> pools;
+    std::vector<size_t> ws_off;
+    std::vector<WorkItem> items;
+    std::vector<Cls> classes;
+    size_t scan_lds = 0, ws_bytes = 0, meta_bytes = 0;
+    size_t meta_pools = 0, meta_items = 0, meta_counter = 0;
+    int64_t total_nodes = 0;
+    char *dmeta = nullptr;            // device address of the metadata once laid out
+};
+
+fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out);
+void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, BatchPlan &pl);
+void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host_meta);
+hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s);
+int batch_grid(int dev, size_t scan_lds);
+
+// A reusable device region for batches re-planned on every call (the merged
+// bounding step of concurrent searches).  The region grows by doubling and is
+// kept; the metadata goes up through a pinned staging buffer with one async
+// copy.  A call must not start before the previous call's copy has completed
+// (the caller synchronizes its stream between calls).
+struct BatchArena {
+    BatchPlan plan;
+    std::vector<char> meta;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipError_t run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s);
+    void release(hipStream_t s);
+};
 
 }  // namespace fspbb

@@ -1,13 +1,15 @@
-// One pool-synchronous branch-and-bound step on the device (Sec. II-A
-// operators: branching, bounding, elimination; Sec. III-A: the pool of
-// sub-problems is bounded in parallel).
+// Pool-synchronous branch-and-bound steps on the device, for R independent
+// searches at once (Sec. II-A operators: branching, bounding, elimination;
+// Sec. III-A: the pool of sub-problems is bounded in parallel).  Every kernel
+// has a 2-D grid: y selects the search, x covers its parents or children;
+// blocks past a search's size return at once.
 //
-// Given K parents in pop order, the step
+// For each search, given K parents in pop order, the step
 //   1. validates each parent and counts its children (n - d),
 //   2. takes child offsets by an exclusive prefix sum,
 //   3. lists each parent's unscheduled jobs in increasing id (forward
 //      branching: child k appends the k-th unscheduled job, Sec. II-B),
-//   4. writes the child rows and bounds them with the bound kernels,
+//   4. writes the child rows (they are then bounded by the bound kernels),
 //   5. takes the best complete child below the upper bound with a 64-bit
 //      atomic minimum over (bound << 32 | child index), so the first child in
 //      child order wins ties whatever the order of the atomics,
@@ -15,17 +17,22 @@
 //      and compacts them stably (prefix sum), optionally in reverse child
 //      order so that pushing them on a stack leaves the first child on top.
 #include "bnb.h"
-#include "scan.h"
+#include "bound_common.h"
 
 namespace fspbb {
 
-__device__ __forceinline__ const int32_t *parent_row(const StepArgs &a, int64_t p)
+using ReqP = cptr<StepReq>;
+
+__device__ __forceinline__ ReqP req_of(const StepReq *reqs) { return as_const(reqs + blockIdx.y); }
+
+__device__ __forceinline__ const int32_t *parent_row(ReqP q, int64_t p)
 {
-    return a.parents + (a.parents_reversed ? (a.parent_top - 1 - p) : p) * (int64_t)a.n;
+    const int64_t r = q->a.parents_reversed ? (q->a.parent_top - 1 - p) : p;
+    return q->a.parents + r * (int64_t)q->a.n;
 }
-__device__ __forceinline__ int32_t parent_depth(const StepArgs &a, int64_t p)
+__device__ __forceinline__ int32_t parent_depth(ReqP q, int64_t p)
 {
-    return a.pdepth[a.parents_reversed ? (a.parent_top - 1 - p) : p];
+    return q->a.pdepth[q->a.parents_reversed ? (q->a.parent_top - 1 - p) : p];
 }
 
 // One wave per parent: the lanes build the parent's scheduled set in a 16-word
@@ -51,106 +58,130 @@ __device__ inline bool wave_prefix_set(const int32_t *row, int d, int n, uint32_
     return __ballot(bad) == 0;
 }
 
-__global__ __launch_bounds__(256) void step_count_kernel(StepArgs a, StepScratch w)
+__global__ void mstep_init_kernel(const StepReq *__restrict__ reqs)
+{
+    ReqP q = req_of(reqs);
+    *q->w.best = ((unsigned long long)(uint32_t)q->a.ub_in << 32) | 0xffffffffull;
+    *q->w.fingerprint = 0ull;
+    *q->w.bad = 0ull;
+}
+
+__global__ __launch_bounds__(256) void mstep_count_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ uint32_t mask[4][kMaxJobs / 32];
+    ReqP q = req_of(reqs);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * 4 + wv;
-    if (p >= a.K) return;  // whole wave
-    const int d = parent_depth(a, p);
-    const bool ok = wave_prefix_set(parent_row(a, p), d, a.n, mask[wv], lane);
+    if (p >= q->a.K) return;  // whole wave
+    const int n = q->a.n;
+    const int d = parent_depth(q, p);
+    const bool ok = wave_prefix_set(parent_row(q, p), d, n, mask[wv], lane);
     if (lane == 0) {
-        w.cnt[p] = (ok && d < a.n) ? (uint32_t)(a.n - d) : 0u;
-        if (!ok) atomicAdd(w.bad, 1ull);
+        q->w.cnt[p] = (ok && d < n) ? (uint32_t)(n - d) : 0u;
+        if (!ok) atomicAdd(q->w.bad, 1ull);
     }
 }
 
 // One wave per parent: each unscheduled job j goes to slot off[p] + (number
 // of unscheduled jobs below j), i.e. children in increasing job id.
-__global__ __launch_bounds__(256) void step_ulist_kernel(StepArgs a, StepScratch w)
+__global__ __launch_bounds__(256) void mstep_ulist_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ uint32_t mask[4][kMaxJobs / 32];
+    ReqP q = req_of(reqs);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * 4 + wv;
-    if (p >= a.K) return;  // whole wave
-    if (w.cnt[p] == 0) return;  // whole wave (uniform load)
-    const int d = parent_depth(a, p);
-    wave_prefix_set(parent_row(a, p), d, a.n, mask[wv], lane);
-    const int64_t base = w.off[p];
-    for (int j = lane; j < a.n; j += 64) {
+    if (p >= q->a.K) return;      // whole wave
+    if (q->w.cnt[p] == 0) return;  // whole wave
+    const int n = q->a.n;
+    const int d = parent_depth(q, p);
+    wave_prefix_set(parent_row(q, p), d, n, mask[wv], lane);
+    const int64_t base = q->w.off[p];
+    int32_t *ujob = q->w.ujob, *upar = q->w.upar;
+    for (int j = lane; j < n; j += 64) {
         const int wj = j >> 5;
         const uint32_t mw = mask[wv][wj];
         if ((mw >> (j & 31)) & 1u) continue;
         int below = __popc(mw & ((1u << (j & 31)) - 1u));
-        for (int q = 0; q < wj; ++q) below += __popc(mask[wv][q]);
+        for (int t = 0; t < wj; ++t) below += __popc(mask[wv][t]);
         const int64_t slot = base + (j - below);
-        w.ujob[slot] = j;
-        w.upar[slot] = (int32_t)p;
+        ujob[slot] = j;
+        upar[slot] = (int32_t)p;
     }
 }
 
 // One wave per child: child row = parent prefix followed by the appended job.
-__global__ __launch_bounds__(256) void step_rows_kernel(StepArgs a, StepScratch w, int64_t nchild)
+__global__ __launch_bounds__(256) void mstep_rows_kernel(const StepReq *__restrict__ reqs)
 {
+    ReqP q = req_of(reqs);
     const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (c >= nchild) return;
-    const int64_t p = w.upar[c];
-    const int d = parent_depth(a, p);
-    const int32_t *prow = parent_row(a, p);
-    int32_t *crow = w.crow + c * (int64_t)a.n;
-    for (int t = lane; t <= d; t += 64) crow[t] = t < d ? prow[t] : w.ujob[c];
-    if (lane == 0) w.cdepth[c] = d + 1;
+    if (c >= q->nchild) return;
+    const int n = q->a.n;
+    const int64_t p = q->w.upar[c];
+    const int d = parent_depth(q, p);
+    const int32_t *prow = parent_row(q, p);
+    int32_t *crow = q->w.crow + c * (int64_t)n;
+    const int32_t j = q->w.ujob[c];
+    for (int t = lane; t <= d; t += 64) crow[t] = t < d ? prow[t] : j;
+    if (lane == 0) q->w.cdepth[c] = d + 1;
 }
 
-__global__ __launch_bounds__(256) void step_leaf_kernel(StepArgs a, StepScratch w, int64_t nchild)
+__global__ __launch_bounds__(256) void mstep_leaf_kernel(const StepReq *__restrict__ reqs)
 {
+    ReqP q = req_of(reqs);
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= nchild) return;
-    const int32_t lb = w.clb[c];
-    if (w.cdepth[c] == a.n && lb >= 0 && lb < a.ub_in)
-        atomicMin(w.best, ((unsigned long long)(uint32_t)lb << 32) | (unsigned long long)c);
+    if (c >= q->nchild) return;
+    const int32_t lb = q->w.clb[c];
+    if (q->w.cdepth[c] == q->a.n && lb >= 0 && lb < q->a.ub_in)
+        atomicMin(q->w.best, ((unsigned long long)(uint32_t)lb << 32) | (unsigned long long)c);
 }
 
-__global__ __launch_bounds__(256) void step_keep_kernel(StepArgs a, StepScratch w, int64_t nchild)
+__global__ __launch_bounds__(256) void mstep_keep_kernel(const StepReq *__restrict__ reqs)
 {
+    ReqP q = req_of(reqs);
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= nchild) return;
-    const int32_t ub = (int32_t)(*w.best >> 32);
-    w.keep[c] = (w.cdepth[c] < a.n && w.clb[c] >= 0 && w.clb[c] < ub) ? 1u : 0u;
+    if (c >= q->nchild) return;
+    const int32_t ub = (int32_t)(*q->w.best >> 32);
+    const int32_t lb = q->w.clb[c];
+    q->w.keep[c] = (q->w.cdepth[c] < q->a.n && lb >= 0 && lb < ub) ? 1u : 0u;
 }
 
 // One wave per child: survivors are copied to their compacted slot.
-__global__ __launch_bounds__(256) void step_scatter_kernel(StepArgs a, StepScratch w, int64_t nchild)
+__global__ __launch_bounds__(256) void mstep_scatter_kernel(const StepReq *__restrict__ reqs)
 {
+    ReqP q = req_of(reqs);
     const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (c >= nchild) return;
-    if (!w.keep[c]) return;
-    const int64_t S = *w.nsurv;
-    const int64_t s = w.pos[c];
-    const int64_t dst = a.out_reversed ? a.out_base + (S - 1 - s) : a.out_base + s;
-    if (dst < 0 || dst >= a.out_cap) return;  // overflow is reported by the host
-    const int d = w.cdepth[c];
-    const int32_t *src = w.crow + c * (int64_t)a.n;
-    int32_t *out = a.out_rows + dst * (int64_t)a.n;
+    if (c >= q->nchild) return;
+    if (!q->w.keep[c]) return;
+    const int n = q->a.n;
+    const int64_t S = *q->w.nsurv;
+    const int64_t s = q->w.pos[c];
+    const int64_t dst = q->a.out_reversed ? q->a.out_base + (S - 1 - s) : q->a.out_base + s;
+    if (dst < 0 || dst >= q->a.out_cap) return;  // overflow is reported by the host
+    const int d = q->w.cdepth[c];
+    const int32_t *src = q->w.crow + c * (int64_t)n;
+    int32_t *out = q->a.out_rows + dst * (int64_t)n;
     for (int t = lane; t < d; t += 64) out[t] = src[t];
     if (lane == 0) {
-        a.out_depth[dst] = d;
-        if (a.out_lb) a.out_lb[dst] = w.clb[c];
+        q->a.out_depth[dst] = d;
+        if (q->a.out_lb) q->a.out_lb[dst] = q->w.clb[c];
     }
 }
 
 // Fingerprint of the survivor order: sum over survivors of (S - rank) * (job + 1),
 // one block reduction and one atomic per block.
-__global__ __launch_bounds__(256) void step_fingerprint_kernel(StepScratch w, int64_t nchild)
+__global__ __launch_bounds__(256) void mstep_fingerprint_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ unsigned long long part[256];
+    ReqP q = req_of(reqs);
+    const int64_t nch = q->nchild;
+    if ((int64_t)blockIdx.x * 256 >= nch) return;  // whole block
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long v = 0;
-    if (c < nchild && w.keep[c]) {
-        const unsigned long long S = *w.nsurv;
-        v = (S - w.pos[c]) * (unsigned long long)(w.ujob[c] + 1);
+    if (c < nch && q->w.keep[c]) {
+        const unsigned long long S = *q->w.nsurv;
+        v = (S - q->w.pos[c]) * (unsigned long long)(q->w.ujob[c] + 1);
     }
     part[threadIdx.x] = v;
     __syncthreads();
@@ -158,76 +189,99 @@ __global__ __launch_bounds__(256) void step_fingerprint_kernel(StepScratch w, in
         if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && part[0]) atomicAdd(w.fingerprint, part[0]);
+    if (threadIdx.x == 0 && part[0]) atomicAdd(q->w.fingerprint, part[0]);
 }
 
 // Survivors per parent: a parent's children are contiguous in child order, so
 // its survivor count is the difference of the compaction offsets at the ends
 // of its children.
-__global__ __launch_bounds__(256) void step_per_parent_kernel(StepArgs a, StepScratch w, int64_t nchild)
+__global__ __launch_bounds__(256) void mstep_per_parent_kernel(const StepReq *__restrict__ reqs)
 {
+    ReqP q = req_of(reqs);
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.K || !a.surv_per_parent) return;
-    const uint32_t cnt = w.cnt[p];
-    if (cnt == 0) { a.surv_per_parent[p] = 0u; return; }
-    const int64_t lo = w.off[p], hi = lo + cnt;
-    const uint32_t end = hi < nchild ? w.pos[hi] : *w.nsurv;
-    a.surv_per_parent[p] = end - w.pos[lo];
-}
-
-__global__ void step_incumbent_kernel(StepArgs a, StepScratch w)
-{
-    const unsigned long long b = *w.best;
-    const uint32_t idx = (uint32_t)(b & 0xffffffffu);
-    if (idx == 0xffffffffu || !a.incumbent) return;
-    for (int t = threadIdx.x; t < a.n; t += blockDim.x) a.incumbent[t] = w.crow[(int64_t)idx * a.n + t];
-}
-
-__global__ void step_init_kernel(StepArgs a, StepScratch w)
-{
-    *w.best = ((unsigned long long)(uint32_t)a.ub_in << 32) | 0xffffffffull;
-    *w.fingerprint = 0ull;
-    *w.bad = 0ull;
-}
-
-__global__ void store_zero_kernel(uint32_t *p) { *p = 0u; }
-
-static unsigned blocks_for(int64_t items, int per_block) { return (unsigned)((items + per_block - 1) / per_block); }
-
-hipError_t step_phase1(const StepArgs &a, const StepScratch &w, hipStream_t s)
-{
-    step_init_kernel<<<1, 1, 0, s>>>(a, w);
-    if (a.K > 0) {
-        step_count_kernel<<<blocks_for(a.K, 4), 256, 0, s>>>(a, w);
+    if (p >= q->a.K || !q->a.surv_per_parent) return;
+    const uint32_t cnt = q->w.cnt[p];
+    uint32_t v = 0u;
+    if (cnt) {
+        const int64_t lo = q->w.off[p], hi = lo + cnt;
+        const uint32_t end = hi < q->nchild ? q->w.pos[hi] : *q->w.nsurv;
+        v = end - q->w.pos[lo];
     }
+    q->a.surv_per_parent[p] = v;
+}
+
+__global__ void mstep_incumbent_kernel(const StepReq *__restrict__ reqs)
+{
+    ReqP q = req_of(reqs);
+    const unsigned long long b = *q->w.best;
+    const uint32_t idx = (uint32_t)(b & 0xffffffffu);
+    int32_t *inc = q->a.incumbent;
+    if (idx == 0xffffffffu || !inc) return;
+    const int n = q->a.n;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) inc[t] = q->w.crow[(int64_t)idx * n + t];
+}
+
+// Gathers each search's scalars and survivor counts for one copy to the host.
+__global__ __launch_bounds__(256) void mstep_gather_kernel(const StepReq *__restrict__ reqs,
+                                                           StepResultDev *__restrict__ results,
+                                                           uint32_t *__restrict__ surv_all)
+{
+    ReqP q = req_of(reqs);
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p == 0) {
+        StepResultDev r;
+        r.best = *q->w.best;
+        r.fingerprint = *q->w.fingerprint;
+        r.bad = *q->w.bad;
+        r.nchild = *q->w.nchild;
+        r.nsurv = q->nchild > 0 ? *q->w.nsurv : 0u;
+        results[blockIdx.y] = r;
+    }
+    if (surv_all && q->a.surv_per_parent && p < q->a.K)
+        surv_all[q->out_slot + p] = q->nchild > 0 ? q->a.surv_per_parent[p] : 0u;
+}
+
+static unsigned blocks_for(int64_t items, int per_block)
+{
+    const int64_t b = (items + per_block - 1) / per_block;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+hipError_t mstep_phase1(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, hipStream_t s)
+{
+    if (R <= 0) return hipSuccess;
+    mstep_init_kernel<<<dim3(1, R), 1, 0, s>>>(reqs);
+    if (maxK > 0) mstep_count_kernel<<<dim3(blocks_for(maxK, 4), R), 256, 0, s>>>(reqs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return exclusive_scan_u32(w.cnt, w.off, a.K, w.nchild, w.scan_scratch, s);
+    return exclusive_scan_segments(segs, R, maxK, s);
 }
 
-hipError_t step_phase2(fsp_instance_s *I, const StepArgs &a, const StepScratch &w, int64_t nchild, hipStream_t s)
+hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s)
 {
-    if (nchild > 0) {
-        step_ulist_kernel<<<blocks_for(a.K, 4), 256, 0, s>>>(a, w);
-        step_rows_kernel<<<blocks_for(nchild, 4), 256, 0, s>>>(a, w, nchild);
+    if (R <= 0 || maxC <= 0) return hipSuccess;
+    mstep_ulist_kernel<<<dim3(blocks_for(maxK, 4), R), 256, 0, s>>>(reqs);
+    mstep_rows_kernel<<<dim3(blocks_for(maxC, 4), R), 256, 0, s>>>(reqs);
+    return hipGetLastError();
+}
+
+hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, int64_t maxC,
+                        StepResultDev *results, uint32_t *surv_all, hipStream_t s)
+{
+    if (R <= 0) return hipSuccess;
+    if (maxC > 0) {
+        mstep_leaf_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
+        mstep_keep_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = I->packed16 ? launch_bound_packed(I, w.crow, w.cdepth, nchild, w.clb, s)
-                        : launch_bound_lane32(I, w.crow, w.cdepth, nchild, w.clb, s);
+        e = exclusive_scan_segments(segs, R, maxC, s);
         if (e != hipSuccess) return e;
-        step_leaf_kernel<<<blocks_for(nchild, 256), 256, 0, s>>>(a, w, nchild);
-        step_keep_kernel<<<blocks_for(nchild, 256), 256, 0, s>>>(a, w, nchild);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = exclusive_scan_u32(w.keep, w.pos, nchild, w.nsurv, w.scan_scratch, s);
-        if (e != hipSuccess) return e;
-        step_scatter_kernel<<<blocks_for(nchild, 4), 256, 0, s>>>(a, w, nchild);
-        step_fingerprint_kernel<<<blocks_for(nchild, 256), 256, 0, s>>>(w, nchild);
-        step_per_parent_kernel<<<blocks_for(a.K, 256), 256, 0, s>>>(a, w, nchild);
-        step_incumbent_kernel<<<1, 256, 0, s>>>(a, w);
-    } else {
-        store_zero_kernel<<<1, 1, 0, s>>>(w.nsurv);
+        mstep_scatter_kernel<<<dim3(blocks_for(maxC, 4), R), 256, 0, s>>>(reqs);
+        mstep_fingerprint_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
+        mstep_per_parent_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs);
+        mstep_incumbent_kernel<<<dim3(1, R), 256, 0, s>>>(reqs);
     }
+    mstep_gather_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs, results, surv_all);
     return hipGetLastError();
 }
 

@@ -423,17 +423,13 @@ int batch_scan_blocks_per_cu(size_t lds_bytes)
     return nb > 0 ? nb : 1;
 }
 
-static int scan_waves(int P)
+static int scan_waves(int n, int m)
 {
     if (const char *e = getenv("FSPBB_SCAN_WAVES")) {
         const int w = atoi(e);
         if (w == 1 || w == 2 || w == 4 || w == 8 || w == 16) return w;
     }
-    if (P >= 128) return 16;
-    if (P >= 64) return 8;
-    if (P >= 16) return 4;
-    if (P >= 4) return 2;
-    return 1;
+    return scan_tuning(n, m).waves_per_group;
 }
 
 static int scan_unroll()
@@ -527,7 +523,7 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
     e = hipGetLastError();
     timing_mark(I, 1, s);
     if (e == hipSuccess) {
-        const int waves = scan_waves(I->P);
+        const int waves = scan_waves(n, m);
         const size_t lds_b = (size_t)((n + 1) > waves ? (n + 1) : waves) * 256;
         const dim3 grid((unsigned)G);
         const int unr = scan_unroll();

@@ -45,8 +45,6 @@ struct DevTables {
     const int32_t *pairs;     // P x 2: (k, l), k < l, lexicographic (MM)
     const Rec32 *rec32;       // P x n
     const Rec16 *rec16;       // P x npad
-    const uint32_t *recw;     // n x P: slot-major records of the wave-per-node kernel:
-                              // job | (E << 9) | ((C + 32768) << ... ) see bound_wavepair.hip
     unsigned long long *bad;  // invalid-node counter
 };
 
@@ -78,8 +76,6 @@ hipError_t launch_bound_lane32(fsp_instance_s *I, const int32_t *prefixes, const
                                int64_t N, int32_t *out_lb, hipStream_t s);
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
                                int64_t N, int32_t *out_lb, hipStream_t s);
-hipError_t launch_bound_wavepair(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
-                                 int64_t N, int32_t *out_lb, hipStream_t s);
 
 void set_last_error(hipError_t e);
 

@@ -62,6 +62,7 @@ const char *fsp_status_string(fsp_status s)
     case FSP_E_BADNODE: return "FSP_E_BADNODE: pool held invalid nodes";
     case FSP_E_NODEVICE: return "FSP_E_NODEVICE: no gfx950 device";
     case FSP_BUDGET: return "FSP_BUDGET: node budget reached";
+    case FSP_PENDING: return "FSP_PENDING: search not finished";
     default: return "unknown status";
     }
 }
@@ -99,7 +100,6 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     std::vector<int32_t> hp((size_t)(n + 1) * S, 0), colsum(S, 0), tails((size_t)n * S, 0), pairs(2 * P);
     std::vector<Rec32> rec32((size_t)P * n);
     std::vector<Rec16> rec16((size_t)P * npad);
-    std::vector<uint32_t> recw((size_t)n * P);
     for (int j = 0; j < n; ++j)
         for (int k = 0; k < m; ++k) hp[(size_t)j * S + k] = p[j * m + k];
     for (int j = 0; j < n; ++j)
@@ -128,10 +128,6 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
                     int32_t E = lagv[j] + a, C = b - a;
                     rec32[(size_t)pr * n + i] = Rec32{(uint32_t)(j >> 5), (uint32_t)(j & 31), E, C};
                     r16 = Rec16{(uint32_t)j * 256u, ((uint32_t)E << 16) | ((uint32_t)C & 0xffffu)};
-                    // slot-major word for the wave-per-node kernel: job (9 bits),
-                    // E (11 bits), C + 1024 (11 bits); only used when it fits
-                    recw[(size_t)i * P + pr] = (uint32_t)j | ((uint32_t)(E & 0x7ff) << 9) |
-                                               ((uint32_t)((C + 1024) & 0x7ff) << 20);
                 }
                 rec16[(size_t)pr * npad + i] = r16;
             }
@@ -147,8 +143,7 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     size_t off_pr = align(off_t16 + tails16.size() * 4);
     size_t off_r32 = align(off_pr + pairs.size() * 4);
     size_t off_r16 = align(off_r32 + rec32.size() * sizeof(Rec32));
-    size_t off_rw = align(off_r16 + rec16.size() * sizeof(Rec16));
-    size_t off_bad = align(off_rw + recw.size() * 4);
+    size_t off_bad = align(off_r16 + rec16.size() * sizeof(Rec16));
     size_t total = align(off_bad + sizeof(unsigned long long));
     std::vector<unsigned char> blob(total, 0);
     std::memcpy(blob.data() + off_p, hp.data(), hp.size() * 4);
@@ -158,7 +153,6 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     std::memcpy(blob.data() + off_pr, pairs.data(), pairs.size() * 4);
     std::memcpy(blob.data() + off_r32, rec32.data(), rec32.size() * sizeof(Rec32));
     std::memcpy(blob.data() + off_r16, rec16.data(), rec16.size() * sizeof(Rec16));
-    std::memcpy(blob.data() + off_rw, recw.data(), recw.size() * 4);
 
     void *d = nullptr;
     e = hipMalloc(&d, total);
@@ -185,7 +179,6 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     I->dt.pairs = (const int32_t *)(b + off_pr);
     I->dt.rec32 = (const Rec32 *)(b + off_r32);
     I->dt.rec16 = (const Rec16 *)(b + off_r16);
-    I->dt.recw = (const uint32_t *)(b + off_rw);
     I->dt.bad = (unsigned long long *)(b + off_bad);
     *out = I;
     return FSP_OK;

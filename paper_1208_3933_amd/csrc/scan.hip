@@ -1,4 +1,5 @@
-// Device-wide exclusive prefix sum (see scan.h).
+// Device-wide exclusive prefix sums over independent segments (see scan.h).
+// The grid's y index selects the segment; blocks past a segment's tiles exit.
 #include "scan.h"
 
 namespace fspbb {
@@ -20,74 +21,72 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *s
     return r;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_tile_sums_kernel(const uint32_t *__restrict__ in,
-                                                                      int64_t count, uint32_t *__restrict__ sums)
+__global__ __launch_bounds__(kScanThreads) void seg_tile_sums_kernel(const ScanSeg *__restrict__ segs)
 {
     __shared__ uint32_t sh[kScanThreads];
+    const ScanSeg g = segs[blockIdx.y];
+    const int64_t tiles = (g.count + kScanTile - 1) / kScanTile;
+    if ((int64_t)blockIdx.x >= tiles) return;  // whole block
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
-        if (base + i < count) v += in[base + i];
+        if (base + i < g.count) v += g.in[base + i];
     v = block_inclusive_scan(v, sh);
-    if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = v;
+    if (threadIdx.x == kScanThreads - 1) g.sums[blockIdx.x] = v;
 }
 
-// Exclusive scan of the tile sums in place (one block); total -> *total.
-__global__ __launch_bounds__(kScanThreads) void scan_sums_kernel(uint32_t *__restrict__ sums, int64_t nb,
-                                                                 uint32_t *__restrict__ total)
+// One block per segment: exclusive scan of its tile sums in place; total.
+__global__ __launch_bounds__(kScanThreads) void seg_sums_kernel(const ScanSeg *__restrict__ segs)
 {
     __shared__ uint32_t sh[kScanThreads];
     __shared__ uint32_t last;
+    const ScanSeg g = segs[blockIdx.x];
+    const int64_t tiles = (g.count + kScanTile - 1) / kScanTile;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    for (int64_t b0 = 0; b0 < tiles; b0 += kScanThreads) {
         const int64_t b = b0 + threadIdx.x;
-        const uint32_t v = b < nb ? sums[b] : 0u;
+        const uint32_t v = b < tiles ? g.sums[b] : 0u;
         const uint32_t inc = block_inclusive_scan(v, sh);
-        if (b < nb) sums[b] = carry + inc - v;
+        if (b < tiles) g.sums[b] = carry + inc - v;
         if (threadIdx.x == kScanThreads - 1) last = inc;
         __syncthreads();
         carry += last;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = carry;
+    if (threadIdx.x == 0) *g.total = carry;
 }
 
-__global__ void store_u32_kernel(uint32_t *p, uint32_t v) { *p = v; }
-
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t *in, uint32_t *out, int64_t count,
-                                                                  const uint32_t *__restrict__ sums)
+__global__ __launch_bounds__(kScanThreads) void seg_apply_kernel(const ScanSeg *__restrict__ segs)
 {
     __shared__ uint32_t sh[kScanThreads];
+    const ScanSeg g = segs[blockIdx.y];
+    const int64_t tiles = (g.count + kScanTile - 1) / kScanTile;
+    if ((int64_t)blockIdx.x >= tiles) return;  // whole block
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t tsum = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        v[i] = base + i < count ? in[base + i] : 0u;
+        v[i] = base + i < g.count ? g.in[base + i] : 0u;
         tsum += v[i];
     }
     const uint32_t inc = block_inclusive_scan(tsum, sh);
-    uint32_t run = sums[blockIdx.x] + inc - tsum;
+    uint32_t run = g.sums[blockIdx.x] + inc - tsum;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < count) out[base + i] = run;
+        if (base + i < g.count) g.out[base + i] = run;
         run += v[i];
     }
 }
 
-hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total, void *scratch,
-                              hipStream_t s)
+hipError_t exclusive_scan_segments(const ScanSeg *segs, int R, int64_t max_count, hipStream_t s)
 {
-    const int64_t nb = (count + kScanTile - 1) / kScanTile;
-    uint32_t *sums = (uint32_t *)scratch;
-    if (count <= 0) {
-        store_u32_kernel<<<1, 1, 0, s>>>(total, 0u);
-        return hipGetLastError();
-    }
-    scan_tile_sums_kernel<<<(unsigned)nb, kScanThreads, 0, s>>>(in, count, sums);
-    scan_sums_kernel<<<1, kScanThreads, 0, s>>>(sums, nb, total);
-    scan_apply_kernel<<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, count, sums);
+    if (R <= 0) return hipSuccess;
+    const int64_t tiles = (max_count + kScanTile - 1) / kScanTile;
+    if (tiles > 0) seg_tile_sums_kernel<<<dim3((unsigned)tiles, (unsigned)R), kScanThreads, 0, s>>>(segs);
+    seg_sums_kernel<<<dim3((unsigned)R), kScanThreads, 0, s>>>(segs);
+    if (tiles > 0) seg_apply_kernel<<<dim3((unsigned)tiles, (unsigned)R), kScanThreads, 0, s>>>(segs);
     return hipGetLastError();
 }
 

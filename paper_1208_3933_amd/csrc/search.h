@@ -1,0 +1,98 @@
+// Host-side state of depth-first branch-and-bound searches whose stacks live
+// on the device, and the step ("tick") that advances any number of them with
+// one set of launches: the step kernels run on 2-D grids (one row per
+// search) and the children of all searches are bounded by one merged batched
+// launch.  fsp_solve drives one search; the server drives many.
+#pragma once
+
+#include <utility>
+#include <vector>
+
+#include "batch.h"
+#include "bnb.h"
+
+namespace fspbb {
+
+// Device scratch of one search's steps: the parent part (K) and the child
+// part (C) grow independently, so the parent outputs survive a child resize.
+struct StepBuffers {
+    StepScratch w{};
+    uint32_t *sums_k = nullptr, *sums_c = nullptr;  // scan tile sums
+    void *kblob = nullptr, *cblob = nullptr;
+    int64_t Kcap = 0, Ccap = 0;
+    int n = 0;
+    hipError_t ensure_k(int64_t K, hipStream_t s);
+    hipError_t ensure_c(int64_t C, int n, hipStream_t s);
+    void release(hipStream_t s);
+    size_t bytes() const;
+};
+
+// Per-tick device table and its pinned host image: StepReq[R], the phase-1
+// and finish scan segments, then the gathered results and survivor counts.
+struct TickContext {
+    hipStream_t s = nullptr;
+    void *dtab = nullptr, *htab = nullptr;
+    size_t dcap = 0, hcap = 0;
+    BatchArena arena;
+    hipError_t reserve(size_t bytes);
+    void release();
+};
+
+struct Search {
+    fsp_instance_s *inst = nullptr;
+    int n = 0;
+    int64_t pool_cap = 0, node_budget = 0;
+    int32_t UB = 0, ub0 = 0;
+    std::vector<int32_t> inc;                         // host copy of the incumbent
+    int32_t *srows = nullptr, *sdep = nullptr;        // stack, cap_stack rows
+    int32_t *dinc = nullptr;                          // device incumbent (n)
+    uint32_t *dsurv = nullptr;                        // survivors per popped parent
+    int64_t cap_stack = 0;
+    StepBuffers B;
+    std::vector<std::pair<int32_t, int64_t>> runs;    // run-length mirror of stack depths
+    std::vector<std::pair<int32_t, int64_t>> taken;   // this step's pops (depth, count)
+    int64_t top = 0, nodes = 0, steps = 0, max_stack = 0;
+    int32_t improvements = 0;
+    int64_t *steplog = nullptr;                        // optional, 6 int64 per step
+    int64_t steplog_cap = 0;
+    int64_t K = 0, nch = 0, base = 0;                  // the step in flight
+    bool done = false;
+    fsp_status status = FSP_OK;
+
+    // NEH or the given upper bound, device state, and the root bound.
+    // Synchronous on s.
+    hipError_t start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap, int64_t node_budget, hipStream_t s);
+    void release(hipStream_t s);
+    size_t device_bytes() const;
+    void result(fsp_solve_result *res, int32_t *perm_out) const;
+};
+
+// Advances every search in `active` (not done, same device) by one step.
+// Synchronous on ctx.s.  A search whose step fails gets done = true and a
+// status; a returned error means the device state of all of them is lost.
+hipError_t tick(std::vector<Search *> &active, TickContext &ctx);
+
+int32_t neh(const int32_t *p, int n, int m, int32_t *perm);
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+inline fsp_status fail_status(hipError_t e)
+{
+    set_last_error(e);
+    return e == hipErrorOutOfMemory ? FSP_E_NOMEM : FSP_E_DEVICE;
+}
+
+}  // namespace fspbb

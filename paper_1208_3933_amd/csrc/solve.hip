@@ -1,8 +1,8 @@
 // Host side of the branch-and-bound: the C ABI step call, the NEH initial
-// upper bound, and the depth-first solve loop that keeps the search stack on
-// the device.
+// upper bound, the depth-first search state with its stack on the device, and
+// the step that advances one or many searches with one set of launches.
 //
-// The solve is pool-synchronous (Sec. III-A: the CPU selects a pool, the GPU
+// A search is pool-synchronous (Sec. III-A: the CPU selects a pool, the GPU
 // bounds it): each step pops parents from the top of the stack while their
 // children fit in pool_cap (the first parent is always taken), branches them
 // in pop order with children in increasing job id, bounds every child,
@@ -10,102 +10,117 @@
 // order on ties), and pushes the children whose bound is below the upper
 // bound in reverse child order, so the first child is popped first.  With a
 // fixed (instance, initial upper bound, pool_cap) every count is a
-// deterministic function of the search, step by step.
+// deterministic function of the search, step by step, whichever other
+// searches share its launches.
 #include <algorithm>
 #include <cstring>
 #include <vector>
 
-#include "bnb.h"
-#include "scan.h"
+#include "search.h"
 
 using namespace fspbb;
 
+namespace fspbb {
+
 namespace {
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
-    }
-};
+// ---------------------------------------------------------------- scratch
 
-// Owns the device scratch of steps with up to Kcap parents and Ccap children.
-struct StepBuffers {
-    StepScratch w{};
-    void *blob = nullptr;
-    int64_t Kcap = 0, Ccap = 0;
-    int n = 0;
-
-    hipError_t ensure(int64_t K, int64_t C, int n_, hipStream_t s)
-    {
-        if (K <= Kcap && C <= Ccap && n_ == n && blob) return hipSuccess;
-        release(s);
-        Kcap = std::max<int64_t>(K, 1);
-        Ccap = std::max<int64_t>(C, 1);
-        n = n_;
-        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-        const size_t kb = al((size_t)Kcap * 4), cb = al((size_t)Ccap * 4);
-        const size_t rows = al((size_t)Ccap * n * 4);
-        const size_t scan = al(scan_scratch_bytes(std::max(Kcap, Ccap)));
-        const size_t total = 2 * kb + 6 * cb + rows + scan + 256 * 2;
-        hipError_t e = hipMallocAsync(&blob, total, s);
-        if (e != hipSuccess) { blob = nullptr; Kcap = Ccap = 0; return e; }
-        char *p = (char *)blob;
-        w.cnt = (uint32_t *)p; p += kb;
-        w.off = (uint32_t *)p; p += kb;
-        w.ujob = (int32_t *)p; p += cb;
-        w.upar = (int32_t *)p; p += cb;
-        w.cdepth = (int32_t *)p; p += cb;
-        w.clb = (int32_t *)p; p += cb;
-        w.keep = (uint32_t *)p; p += cb;
-        w.pos = (uint32_t *)p; p += cb;
-        w.crow = (int32_t *)p; p += rows;
-        w.scan_scratch = p; p += scan;
-        w.nchild = (uint32_t *)p;
-        w.nsurv = (uint32_t *)(p + 4);
-        w.best = (unsigned long long *)(p + 64);
-        w.fingerprint = (unsigned long long *)(p + 128);
-        w.bad = (unsigned long long *)(p + 192);
-        return hipSuccess;
-    }
-    void release(hipStream_t s)
-    {
-        if (blob) hipFreeAsync(blob, s);
-        blob = nullptr;
-        Kcap = Ccap = 0;
-    }
-};
-
-// Scalars read back after each step.
-struct StepOut {
-    uint32_t nchild, nsurv;
-    unsigned long long best, fingerprint, bad;
-};
-
-hipError_t read_step_out(const StepScratch &w, StepOut &o, hipStream_t s)
+hipError_t StepBuffers::ensure_k(int64_t K, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(&o.nchild, w.nchild, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&o.nsurv, w.nsurv, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&o.best, w.best, 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&o.fingerprint, w.fingerprint, 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&o.bad, w.bad, 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return e;
+    if (kblob && K <= Kcap) return hipSuccess;
+    if (kblob) hipFreeAsync(kblob, s);
+    kblob = nullptr;
+    Kcap = std::max<int64_t>(K, 1);
+    const size_t kb = al256((size_t)Kcap * 4), sb = al256(scan_scratch_bytes(Kcap));
+    hipError_t e = hipMallocAsync(&kblob, 2 * kb + sb + 5 * 64, s);
+    if (e != hipSuccess) { kblob = nullptr; Kcap = 0; return e; }
+    char *p = (char *)kblob;
+    w.cnt = (uint32_t *)p; p += kb;
+    w.off = (uint32_t *)p; p += kb;
+    sums_k = (uint32_t *)p; p += sb;
+    w.nchild = (uint32_t *)p;
+    w.nsurv = (uint32_t *)(p + 64);
+    w.best = (unsigned long long *)(p + 128);
+    w.fingerprint = (unsigned long long *)(p + 192);
+    w.bad = (unsigned long long *)(p + 256);
+    return hipSuccess;
 }
 
-fsp_status fail(hipError_t e)
+hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
 {
-    set_last_error(e);
-    return e == hipErrorOutOfMemory ? FSP_E_NOMEM : FSP_E_DEVICE;
+    if (cblob && C <= Ccap && n_ == n) return hipSuccess;
+    if (cblob) hipFreeAsync(cblob, s);
+    cblob = nullptr;
+    Ccap = std::max<int64_t>(C, 1);
+    n = n_;
+    const size_t cb = al256((size_t)Ccap * 4), rows = al256((size_t)Ccap * n * 4);
+    const size_t sb = al256(scan_scratch_bytes(Ccap));
+    hipError_t e = hipMallocAsync(&cblob, 6 * cb + rows + sb, s);
+    if (e != hipSuccess) { cblob = nullptr; Ccap = 0; return e; }
+    char *p = (char *)cblob;
+    w.ujob = (int32_t *)p; p += cb;
+    w.upar = (int32_t *)p; p += cb;
+    w.cdepth = (int32_t *)p; p += cb;
+    w.clb = (int32_t *)p; p += cb;
+    w.keep = (uint32_t *)p; p += cb;
+    w.pos = (uint32_t *)p; p += cb;
+    w.crow = (int32_t *)p; p += rows;
+    sums_c = (uint32_t *)p;
+    return hipSuccess;
 }
+
+void StepBuffers::release(hipStream_t s)
+{
+    if (kblob) hipFreeAsync(kblob, s);
+    if (cblob) hipFreeAsync(cblob, s);
+    kblob = cblob = nullptr;
+    Kcap = Ccap = 0;
+}
+
+size_t StepBuffers::bytes() const
+{
+    return (size_t)Kcap * 8 + (size_t)Ccap * (24 + 4 * (size_t)n) + scan_scratch_bytes(Kcap) +
+           scan_scratch_bytes(Ccap) + 320;
+}
+
+hipError_t TickContext::reserve(size_t bytes)
+{
+    if (bytes > dcap) {
+        if (dtab) hipFreeAsync(dtab, s);
+        dtab = nullptr;
+        dcap = 0;
+        const size_t c = std::max(bytes, (size_t)64 * 1024);
+        hipError_t e = hipMallocAsync(&dtab, c, s);
+        if (e != hipSuccess) return e;
+        dcap = c;
+    }
+    if (bytes > hcap) {
+        // the previous tick ended with a stream synchronization: no copy reads htab
+        if (htab) hipHostFree(htab);
+        htab = nullptr;
+        hcap = 0;
+        const size_t c = std::max(bytes, (size_t)64 * 1024);
+        hipError_t e = hipHostMalloc(&htab, c, 0);
+        if (e != hipSuccess) return e;
+        hcap = c;
+    }
+    return hipSuccess;
+}
+
+void TickContext::release()
+{
+    if (dtab) hipFreeAsync(dtab, s);
+    arena.release(s);
+    hipStreamSynchronize(s);
+    if (htab) hipHostFree(htab);
+    dtab = htab = nullptr;
+    dcap = hcap = 0;
+}
+
+// ---------------------------------------------------------------- NEH
 
 // NEH (Nawaz, Enscore and Ham 1983) with Taillard's evaluation of all
 // insertion positions in O(L m) per job: e = heads of the current sequence,
@@ -160,7 +175,270 @@ int32_t neh(const int32_t *p, int n, int m, int32_t *perm)
     return (int32_t)C[m - 1];
 }
 
+// ---------------------------------------------------------------- search
+
+static hipError_t bound_rows(fsp_instance_s *I, const int32_t *rows, const int32_t *depths, int64_t N, int32_t *lb,
+                             hipStream_t s)
+{
+    if (N <= 0) return hipSuccess;
+    return I->packed16 ? launch_bound_packed(I, rows, depths, N, lb, s)
+                       : launch_bound_lane32(I, rows, depths, N, lb, s);
+}
+
+hipError_t Search::start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in, int64_t node_budget_in,
+                         hipStream_t s)
+{
+    inst = I;
+    n = I->n;
+    pool_cap = pool_cap_in;
+    node_budget = node_budget_in;
+    inc.assign(n, -1);
+    UB = ub0_in == FSP_UB_NEH ? neh(I->p_host, n, I->m, inc.data()) : ub0_in;
+    ub0 = UB;
+    cap_stack = std::max<int64_t>(1024, 2 * pool_cap);
+    hipError_t e = hipMallocAsync((void **)&srows, (size_t)cap_stack * n * 4, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&sdep, (size_t)cap_stack * 4, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&dsurv, (size_t)pool_cap * 4, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&dinc, (size_t)n * 4, s);
+    if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
+    if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
+    // the root: an all-zero row of depth 0, bounded into the child bounds
+    if (e == hipSuccess) e = hipMemsetAsync(srows, 0, (size_t)n * 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(sdep, 0, 4, s);
+    if (e == hipSuccess) e = bound_rows(I, srows, sdep, 1, B.w.clb, s);
+    int32_t lb0 = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&lb0, B.w.clb, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    nodes = 1;
+    if (lb0 < UB) {
+        top = 1;
+        runs.push_back({0, 1});
+        max_stack = 1;
+    }
+    done = top == 0 || nodes >= node_budget;
+    status = top == 0 ? FSP_OK : (done ? FSP_BUDGET : FSP_OK);
+    return hipSuccess;
+}
+
+void Search::release(hipStream_t s)
+{
+    if (srows) hipFreeAsync(srows, s);
+    if (sdep) hipFreeAsync(sdep, s);
+    if (dsurv) hipFreeAsync(dsurv, s);
+    if (dinc) hipFreeAsync(dinc, s);
+    srows = sdep = dinc = nullptr;
+    dsurv = nullptr;
+    B.release(s);
+}
+
+size_t Search::device_bytes() const
+{
+    return (size_t)cap_stack * (n + 1) * 4 + (size_t)pool_cap * 4 + (size_t)n * 4 + B.bytes();
+}
+
+void Search::result(fsp_solve_result *res, int32_t *perm_out) const
+{
+    std::memset(res, 0, sizeof(*res));
+    res->opt = UB;
+    res->proven = top == 0;
+    res->nodes_bounded = nodes;
+    res->steps = steps;
+    res->ub0 = ub0;
+    res->improvements = improvements;
+    res->max_stack = max_stack;
+    if (perm_out) std::copy(inc.begin(), inc.end(), perm_out);
+}
+
+// Pops parents for one step and makes room for their children.
+static hipError_t prepare_step(Search &S, hipStream_t s)
+{
+    S.taken.clear();
+    int64_t K = 0, nch = 0;
+    while (!S.runs.empty()) {
+        auto &r = S.runs.back();
+        const int64_t c = S.n - r.first;
+        int64_t x = (S.pool_cap - nch) / c;
+        if (K == 0) x = std::max<int64_t>(x, 1);
+        x = std::min(x, r.second);
+        if (x <= 0) break;
+        S.taken.push_back({r.first, x});
+        K += x;
+        nch += x * c;
+        r.second -= x;
+        if (r.second > 0) break;
+        S.runs.pop_back();
+    }
+    S.K = K;
+    S.nch = nch;
+    S.base = S.top - K;
+    if (S.base + nch > S.cap_stack) {
+        int64_t nc = S.cap_stack;
+        while (S.base + nch > nc) nc *= 2;
+        int32_t *r2 = nullptr, *d2 = nullptr;
+        hipError_t e = hipMallocAsync((void **)&r2, (size_t)nc * S.n * 4, s);
+        if (e == hipSuccess) e = hipMallocAsync((void **)&d2, (size_t)nc * 4, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(r2, S.srows, (size_t)S.top * S.n * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d2, S.sdep, (size_t)S.top * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            if (r2) hipFreeAsync(r2, s);
+            if (d2) hipFreeAsync(d2, s);
+            return e;
+        }
+        hipFreeAsync(S.srows, s);
+        hipFreeAsync(S.sdep, s);
+        S.srows = r2;
+        S.sdep = d2;
+        S.cap_stack = nc;
+    }
+    hipError_t e = S.B.ensure_k(std::max(S.pool_cap, K), s);
+    if (e == hipSuccess) e = S.B.ensure_c(std::max(S.pool_cap, nch), S.n, s);  // one parent may exceed pool_cap
+    return e;
+}
+
+namespace {
+struct TabLayout {
+    size_t req, seg1, seg2, res, surv, total;
+    TabLayout(int R, int64_t sumK)
+    {
+        req = 0;
+        seg1 = al256(sizeof(StepReq) * R);
+        seg2 = seg1 + al256(sizeof(ScanSeg) * R);
+        res = seg2 + al256(sizeof(ScanSeg) * R);
+        surv = res + al256(sizeof(StepResultDev) * R);
+        total = surv + al256((size_t)std::max<int64_t>(sumK, 1) * 4);
+    }
+};
 }  // namespace
+
+hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
+{
+    hipStream_t s = ctx.s;
+    const int R = (int)act.size();
+    if (R == 0) return hipSuccess;
+    int64_t maxK = 0, maxC = 0, sumK = 0;
+    for (Search *S : act) {
+        hipError_t e = prepare_step(*S, s);
+        if (e != hipSuccess) return e;
+        maxK = std::max(maxK, S->K);
+        maxC = std::max(maxC, S->nch);
+        sumK += S->K;
+    }
+    const TabLayout L(R, sumK);
+    hipError_t e = ctx.reserve(L.total);
+    if (e != hipSuccess) return e;
+    char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
+    StepReq *hq = (StepReq *)(h + L.req);
+    ScanSeg *hs1 = (ScanSeg *)(h + L.seg1), *hs2 = (ScanSeg *)(h + L.seg2);
+    int64_t slot = 0;
+    for (int r = 0; r < R; ++r) {
+        Search &S = *act[r];
+        StepReq q;
+        std::memset(&q, 0, sizeof(q));
+        q.a.n = S.n;
+        q.a.ub_in = S.UB;
+        q.a.parents = S.srows;
+        q.a.pdepth = S.sdep;
+        q.a.K = S.K;
+        q.a.parents_reversed = 1;
+        q.a.parent_top = S.top;
+        q.a.out_rows = S.srows;
+        q.a.out_depth = S.sdep;
+        q.a.out_lb = nullptr;
+        q.a.out_base = S.base;
+        q.a.out_cap = S.cap_stack;
+        q.a.out_reversed = 1;
+        q.a.surv_per_parent = S.dsurv;
+        q.a.incumbent = S.dinc;
+        q.w = S.B.w;
+        q.nchild = S.nch;
+        q.out_slot = slot;
+        slot += S.K;
+        hq[r] = q;
+        hs1[r] = ScanSeg{S.B.w.cnt, S.B.w.off, S.K, S.B.w.nchild, S.B.sums_k};
+        hs2[r] = ScanSeg{S.B.w.keep, S.B.w.pos, S.nch, S.B.w.nsurv, S.B.sums_c};
+    }
+    const StepReq *dq = (const StepReq *)(d + L.req);
+    const ScanSeg *ds1 = (const ScanSeg *)(d + L.seg1), *ds2 = (const ScanSeg *)(d + L.seg2);
+    StepResultDev *dres = (StepResultDev *)(d + L.res);
+    uint32_t *dsurv = (uint32_t *)(d + L.surv);
+    e = hipMemcpyAsync(d, h, L.res, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = mstep_phase1(dq, ds1, R, maxK, s);
+    if (e == hipSuccess) e = mstep_branch(dq, R, maxK, maxC, s);
+    if (e != hipSuccess) return e;
+    // bounding: one plain launch for a single search, else one merged batch
+    if (R == 1) {
+        Search &S = *act[0];
+        e = bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s);
+    } else {
+        std::vector<fsp_pool_desc> descs;
+        descs.reserve(R);
+        for (Search *S : act) {
+            if (S->inst->packed16)
+                descs.push_back(fsp_pool_desc{S->inst, S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb});
+            else if (e == hipSuccess)
+                e = bound_rows(S->inst, S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb, s);
+        }
+        if (e == hipSuccess && !descs.empty()) e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s);
+    }
+    if (e == hipSuccess) e = mstep_finish(dq, ds2, R, maxK, maxC, dres, dsurv, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, d + L.res, L.total - L.res, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+
+    const StepResultDev *hres = (const StepResultDev *)(h + L.res);
+    const uint32_t *hsurv = (const uint32_t *)(h + L.surv);
+    bool copies = false;
+    for (int r = 0; r < R; ++r) {
+        Search &S = *act[r];
+        const StepResultDev &o = hres[r];
+        if (o.bad || (int64_t)o.nchild != S.nch) {
+            S.done = true;
+            S.status = FSP_E_BADNODE;
+            continue;
+        }
+        S.nodes += S.nch;
+        const uint32_t idx = (uint32_t)(o.best & 0xffffffffu);
+        if (idx != 0xffffffffu) {
+            S.UB = (int32_t)(o.best >> 32);
+            ++S.improvements;
+            e = hipMemcpyAsync(S.inc.data(), S.dinc, (size_t)S.n * 4, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+            copies = true;
+        }
+        // survivors sit bottom-to-top as: children of the last popped parent ... of the first
+        const uint32_t *sv = hsurv + hq[r].out_slot;
+        int64_t p = S.K;
+        for (auto it = S.taken.rbegin(); it != S.taken.rend(); ++it) {
+            for (int64_t x = 0; x < it->second; ++x) {
+                --p;
+                const int64_t cnt = sv[p];
+                if (!cnt) continue;
+                const int32_t dd = it->first + 1;
+                if (!S.runs.empty() && S.runs.back().first == dd) S.runs.back().second += cnt;
+                else S.runs.push_back({dd, cnt});
+            }
+        }
+        S.top = S.base + o.nsurv;
+        S.max_stack = std::max(S.max_stack, S.top);
+        if (S.steplog && S.steps < S.steplog_cap) {
+            int64_t *Lg = S.steplog + S.steps * 6;
+            Lg[0] = S.K; Lg[1] = S.nch; Lg[2] = S.UB; Lg[3] = o.nsurv; Lg[4] = S.top; Lg[5] = (int64_t)o.fingerprint;
+        }
+        ++S.steps;
+        if (S.top == 0) {
+            S.done = true;
+            S.status = FSP_OK;
+        } else if (S.nodes >= S.node_budget) {
+            S.done = true;
+            S.status = FSP_BUDGET;
+        }
+    }
+    if (copies) e = hipStreamSynchronize(s);
+    return e;
+}
+
+}  // namespace fspbb
 
 extern "C" {
 
@@ -184,33 +462,59 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     if (!g.ok) return FSP_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
     StepBuffers B;
-    hipError_t e = B.ensure(K, 1, inst->n, s);
-    if (e != hipSuccess) return fail(e);
-    StepArgs a{};
-    a.n = inst->n;
-    a.ub_in = ub_in;
-    a.parents = parents;
-    a.pdepth = parent_depths;
-    a.K = K;
-    a.out_rows = children;
-    a.out_depth = child_depths;
-    a.out_lb = child_lb;
-    a.out_base = 0;
-    a.out_cap = cap;
-    a.incumbent = incumbent;
-    e = step_phase1(a, B.w, s);
-    StepOut o{};
-    if (e == hipSuccess) e = read_step_out(B.w, o, s);
-    if (e != hipSuccess) { B.release(s); return fail(e); }
-    const int64_t nchild = o.nchild;
-    e = B.ensure(K, nchild, inst->n, s);
-    if (e == hipSuccess) e = step_phase1(a, B.w, s);  // the scratch may have moved
-    if (e == hipSuccess) e = step_phase2(inst, a, B.w, nchild, s);
-    if (e == hipSuccess) e = read_step_out(B.w, o, s);
-    B.release(s);
-    hipError_t e2 = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = e2;
-    if (e != hipSuccess) return fail(e);
+    TickContext ctx;
+    ctx.s = s;
+    auto cleanup = [&]() {
+        B.release(s);
+        ctx.release();
+    };
+    const TabLayout L(1, K);
+    hipError_t e = B.ensure_k(K, s);
+    if (e == hipSuccess) e = B.ensure_c(1, inst->n, s);
+    if (e == hipSuccess) e = ctx.reserve(L.total);
+    if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    StepReq q;
+    std::memset(&q, 0, sizeof(q));
+    q.a.n = inst->n;
+    q.a.ub_in = ub_in;
+    q.a.parents = parents;
+    q.a.pdepth = parent_depths;
+    q.a.K = K;
+    q.a.out_rows = children;
+    q.a.out_depth = child_depths;
+    q.a.out_lb = child_lb;
+    q.a.out_base = 0;
+    q.a.out_cap = cap;
+    q.a.incumbent = incumbent;
+    q.w = B.w;
+    char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
+    const StepReq *dq = (const StepReq *)(d + L.req);
+    *(StepReq *)(h + L.req) = q;
+    *(ScanSeg *)(h + L.seg1) = ScanSeg{B.w.cnt, B.w.off, K, B.w.nchild, B.sums_k};
+    uint32_t nchild = 0;
+    e = hipMemcpyAsync(d, h, L.res, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = mstep_phase1(dq, (const ScanSeg *)(d + L.seg1), 1, K, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, B.w.nchild, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        nchild = *(const uint32_t *)(h + L.res);
+        e = B.ensure_c(nchild, inst->n, s);
+    }
+    if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    q.w = B.w;
+    q.nchild = nchild;
+    *(StepReq *)(h + L.req) = q;
+    *(ScanSeg *)(h + L.seg2) = ScanSeg{B.w.keep, B.w.pos, (int64_t)nchild, B.w.nsurv, B.sums_c};
+    e = hipMemcpyAsync(d, h, L.res, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = mstep_branch(dq, 1, K, nchild, s);
+    if (e == hipSuccess) e = bound_rows(inst, B.w.crow, B.w.cdepth, nchild, B.w.clb, s);
+    if (e == hipSuccess)
+        e = mstep_finish(dq, (const ScanSeg *)(d + L.seg2), 1, K, nchild, (StepResultDev *)(d + L.res), nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, d + L.res, sizeof(StepResultDev), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    const StepResultDev o = *(const StepResultDev *)(h + L.res);
+    cleanup();
     res->n_children = nchild;
     res->n_survivors = o.nsurv;
     const uint32_t idx = (uint32_t)(o.best & 0xffffffffu);
@@ -231,158 +535,25 @@ fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t n
     DeviceGuard g(inst->device);
     if (!g.ok) return FSP_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
-    const int n = inst->n;
-    std::vector<int32_t> inc(n, -1);
-    int32_t UB = ub0;
-    if (ub0 == FSP_UB_NEH) UB = neh(inst->p_host, n, inst->m, inc.data());
-    res->ub0 = UB;
-
-    // device state: stack rows and depths, parents' survivor counts, incumbent
-    int64_t cap_stack = std::max<int64_t>(1024, 2 * pool_cap);
-    int32_t *srows = nullptr, *sdep = nullptr, *dinc = nullptr, *root_lb = nullptr;
-    uint32_t *surv = nullptr;
-    StepBuffers B;
+    Search S;
+    TickContext ctx;
+    ctx.s = s;
     auto cleanup = [&]() {
-        if (srows) hipFreeAsync(srows, s);
-        if (sdep) hipFreeAsync(sdep, s);
-        if (surv) hipFreeAsync(surv, s);
-        if (dinc) hipFreeAsync(dinc, s);
-        if (root_lb) hipFreeAsync(root_lb, s);
-        B.release(s);
-        hipStreamSynchronize(s);
+        S.release(s);
+        ctx.release();
     };
-    hipError_t e = hipMallocAsync((void **)&srows, (size_t)cap_stack * n * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&sdep, (size_t)cap_stack * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&surv, (size_t)pool_cap * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&dinc, (size_t)n * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&root_lb, 4, s);
-    if (e == hipSuccess) e = B.ensure(pool_cap, pool_cap, n, s);
-    if (e != hipSuccess) { cleanup(); return fail(e); }
-
-    // root: an all-zero row of depth 0
-    std::vector<int32_t> zrow(n, 0);
-    const int32_t zdepth = 0;
-    e = hipMemcpyAsync(srows, zrow.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(sdep, &zdepth, 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = inst->packed16 ? launch_bound_packed(inst, srows, sdep, 1, root_lb, s)
-                           : launch_bound_lane32(inst, srows, sdep, 1, root_lb, s);
-    int32_t lb0 = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&lb0, root_lb, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) { cleanup(); return fail(e); }
-
-    int64_t nodes = 1, steps = 0, top = 0, max_stack = 0;
-    int32_t improvements = 0;
-    // run-length mirror of the stack depths, bottom to top
-    std::vector<std::pair<int32_t, int64_t>> runs;
-    if (lb0 < UB) {
-        top = 1;
-        runs.push_back({0, 1});
-        max_stack = 1;
-    }
-    std::vector<uint32_t> hsurv;
-    std::vector<std::pair<int32_t, int64_t>> taken;  // (depth, count) in pop order
-    while (top > 0 && nodes < node_budget) {
-        // selection
-        taken.clear();
-        int64_t K = 0, nch = 0;
-        while (!runs.empty()) {
-            auto &r = runs.back();
-            const int64_t c = n - r.first;
-            int64_t x = (pool_cap - nch) / c;
-            if (K == 0) x = std::max<int64_t>(x, 1);
-            x = std::min(x, r.second);
-            if (x <= 0) break;
-            taken.push_back({r.first, x});
-            K += x;
-            nch += x * c;
-            r.second -= x;
-            if (r.second > 0) break;
-            runs.pop_back();
-        }
-        const int64_t base = top - K;
-        // room for every child on the stack
-        if (base + nch > cap_stack) {
-            int64_t nc = cap_stack;
-            while (base + nch > nc) nc *= 2;
-            int32_t *r2 = nullptr, *d2 = nullptr;
-            e = hipMallocAsync((void **)&r2, (size_t)nc * n * 4, s);
-            if (e == hipSuccess) e = hipMallocAsync((void **)&d2, (size_t)nc * 4, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(r2, srows, (size_t)top * n * 4, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(d2, sdep, (size_t)top * 4, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) { cleanup(); return fail(e); }
-            hipFreeAsync(srows, s);
-            hipFreeAsync(sdep, s);
-            srows = r2;
-            sdep = d2;
-            cap_stack = nc;
-        }
-        e = B.ensure(pool_cap, std::max(pool_cap, nch), n, s);  // one parent may exceed pool_cap
-        if (e != hipSuccess) { cleanup(); return fail(e); }
-        StepArgs a{};
-        a.n = n;
-        a.ub_in = UB;
-        a.parents = srows;
-        a.pdepth = sdep;
-        a.K = K;
-        a.parents_reversed = 1;
-        a.parent_top = top;
-        a.out_rows = srows;
-        a.out_depth = sdep;
-        a.out_lb = nullptr;
-        a.out_base = base;
-        a.out_cap = cap_stack;
-        a.out_reversed = 1;
-        a.surv_per_parent = surv;
-        a.incumbent = dinc;
-        e = step_phase1(a, B.w, s);
-        if (e == hipSuccess) e = step_phase2(inst, a, B.w, nch, s);
-        StepOut o{};
-        if (e == hipSuccess) e = read_step_out(B.w, o, s);
-        if (e != hipSuccess) { cleanup(); return fail(e); }
-        if (o.bad || (int64_t)o.nchild != nch) { cleanup(); return FSP_E_BADNODE; }
-        hsurv.resize(K);
-        e = hipMemcpyAsync(hsurv.data(), surv, (size_t)K * 4, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { cleanup(); return fail(e); }
-        nodes += nch;
-        const uint32_t idx = (uint32_t)(o.best & 0xffffffffu);
-        if (idx != 0xffffffffu) {
-            UB = (int32_t)(o.best >> 32);
-            ++improvements;
-            e = hipMemcpyAsync(inc.data(), dinc, (size_t)n * 4, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) { cleanup(); return fail(e); }
-        }
-        // survivors sit bottom-to-top as: children of the last popped parent ... of the first
-        int64_t p = K;
-        for (auto it = taken.rbegin(); it != taken.rend(); ++it) {
-            for (int64_t x = 0; x < it->second; ++x) {
-                --p;
-                const int64_t cnt = hsurv[p];
-                if (!cnt) continue;
-                const int32_t d = it->first + 1;
-                if (!runs.empty() && runs.back().first == d) runs.back().second += cnt;
-                else runs.push_back({d, cnt});
-            }
-        }
-        top = base + o.nsurv;
-        max_stack = std::max(max_stack, top);
-        if (steplog && steps < steplog_cap) {
-            int64_t *L = steplog + steps * 6;
-            L[0] = K; L[1] = nch; L[2] = UB; L[3] = o.nsurv; L[4] = top; L[5] = (int64_t)o.fingerprint;
-        }
-        ++steps;
+    hipError_t e = S.start(inst, ub0, pool_cap, node_budget, s);
+    if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    S.steplog = steplog;
+    S.steplog_cap = steplog ? steplog_cap : 0;
+    std::vector<Search *> act{&S};
+    while (!S.done) {
+        e = tick(act, ctx);
+        if (e != hipSuccess) { cleanup(); return fail_status(e); }
     }
     cleanup();
-    res->opt = UB;
-    res->proven = top == 0;
-    res->nodes_bounded = nodes;
-    res->steps = steps;
-    res->improvements = improvements;
-    res->max_stack = max_stack;
-    if (perm_out) std::copy(inc.begin(), inc.end(), perm_out);
+    if (S.status != FSP_OK && S.status != FSP_BUDGET) return S.status;
+    S.result(res, perm_out);
     return res->proven ? FSP_OK : FSP_BUDGET;
 }
 

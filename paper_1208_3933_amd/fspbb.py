@@ -25,6 +25,7 @@ E_DEVICE = -4
 E_BADNODE = -5
 E_NODEVICE = -6
 BUDGET = 1
+PENDING = 2
 LB_INVALID = -1
 
 UB_NEH = -1
@@ -68,6 +69,22 @@ class PoolDesc(ctypes.Structure):
 
 BATCH_GRAPH = 1
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_int32), ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double),
+                ("default_us", ctypes.c_double), ("cand_wpg", ctypes.c_int32 * 8), ("cand_us", ctypes.c_double * 8)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32),
+                ("tick_children", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("pending", ctypes.c_int32), ("mem_used", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("nodes_bounded", ctypes.c_int64), ("last_children", ctypes.c_int64),
+                ("last_searches", ctypes.c_int32)]
+
+
 _lib = None
 _SIGNATURES = {
     "fsp_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -90,6 +107,19 @@ _SIGNATURES = {
     "fsp_batch_info": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]),
     "fsp_bound_pools_batched": (ctypes.c_int32, [ctypes.POINTER(PoolDesc), ctypes.c_int32, _vp]),
+    "fsp_autotune": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(TuneResult)]),
+    "fsp_tune_get": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "fsp_tune_set": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "fsp_tune_save": (ctypes.c_int32, [ctypes.c_char_p]),
+    "fsp_tune_load": (ctypes.c_int32, [ctypes.c_char_p]),
+    "fsp_server_create": (ctypes.c_int32, [ctypes.POINTER(ServerConfig), _vp, ctypes.POINTER(_vp)]),
+    "fsp_server_submit": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64)]),
+    "fsp_server_step": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ServerStats)]),
+    "fsp_server_poll": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.POINTER(SolveResult), _i32p]),
+    "fsp_server_destroy": (ctypes.c_int32, [_vp]),
     "fsp_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
     "fsp_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -342,3 +372,99 @@ def batch_create(pools, graph: bool = True) -> Batch:
 def bound_pools_batched(pools, stream=None) -> None:
     arr, _keep = _pool_descs(pools)
     _check(lib().fsp_bound_pools_batched(arr, len(pools), _stream_handle(stream)), "fsp_bound_pools_batched")
+
+
+def autotune(inst: Instance, sample_nodes: int = 16384, reps: int = 3) -> dict:
+    """Time every scan tile schedule for the instance's shape and keep the fastest."""
+    r = TuneResult()
+    _check(lib().fsp_autotune(inst.handle, int(sample_nodes), int(reps), ctypes.byref(r)), "fsp_autotune")
+    return {"waves_per_group": r.waves_per_group, "best_us": r.best_us, "default_us": r.default_us,
+            "candidates": {int(r.cand_wpg[i]): float(r.cand_us[i]) for i in range(r.candidates)}}
+
+
+def tune_get(n: int, m: int):
+    """(waves_per_group, tuned) for a shape."""
+    w, t = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().fsp_tune_get(int(n), int(m), ctypes.byref(w), ctypes.byref(t)), "fsp_tune_get")
+    return int(w.value), bool(t.value)
+
+
+def tune_set(n: int, m: int, waves_per_group: int) -> None:
+    _check(lib().fsp_tune_set(int(n), int(m), int(waves_per_group)), "fsp_tune_set")
+
+
+def tune_save(path: str) -> None:
+    _check(lib().fsp_tune_save(path.encode()), "fsp_tune_save")
+
+
+def tune_load(path: str) -> None:
+    _check(lib().fsp_tune_load(path.encode()), "fsp_tune_load")
+
+
+class Server:
+    """A serving loop of concurrent searches (fsp_server_*).  Instances given
+    to submit() are kept referenced here until their search is polled."""
+
+    def __init__(self, mem_budget_bytes: int, max_active: int = 64, tick_children: int = 0, stream=None):
+        cfg = ServerConfig(int(mem_budget_bytes), int(max_active), int(tick_children))
+        h = _vp()
+        _check(lib().fsp_server_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)),
+               "fsp_server_create")
+        self._h = h
+        self._insts = {}
+        self._ids = np.zeros(4096, np.int64)
+
+    def submit(self, inst: Instance, ub0: int = UB_NEH, pool_cap: int = 1 << 14, node_budget: int = 1 << 62) -> int:
+        i = ctypes.c_int64()
+        _check(lib().fsp_server_submit(self._h, inst.handle, int(ub0), int(pool_cap), int(node_budget),
+                                       ctypes.byref(i)), "fsp_server_submit")
+        self._insts[int(i.value)] = inst
+        return int(i.value)
+
+    def step(self):
+        """One step call: (ids finished in it, stats dict)."""
+        nd = ctypes.c_int32()
+        st = ServerStats()
+        rc = lib().fsp_server_step(self._h, self._ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   len(self._ids), ctypes.byref(nd), ctypes.byref(st))
+        _check(rc, "fsp_server_step")
+        ids = [int(x) for x in self._ids[:min(nd.value, len(self._ids))]]
+        return ids, {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def poll(self, id_: int):
+        """None while pending, else the result dict of fsp_solve (with status)."""
+        res = SolveResult()
+        inst = self._insts.get(int(id_))
+        perm = np.empty(inst.n if inst is not None else 1, np.int32)
+        st = lib().fsp_server_poll(self._h, int(id_), ctypes.byref(res), perm.ctypes.data_as(_i32p))
+        if st == PENDING:
+            return None
+        if st not in (OK, BUDGET):
+            _check(st, "fsp_server_poll")
+        self._insts.pop(int(id_), None)
+        out = {fn: getattr(res, fn) for fn, _ in SolveResult._fields_}
+        out["status"] = st
+        out["perm"] = perm
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fsp_server_destroy(self._h)
+            self._h = None
+            self._insts = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def server_create(mem_budget_bytes: int, max_active: int = 64, tick_children: int = 0, stream=None) -> Server:
+    return Server(mem_budget_bytes, max_active, tick_children, stream)

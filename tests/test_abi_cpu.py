@@ -67,3 +67,26 @@ def test_null_arguments():
     assert L.fsp_destroy_instance(None) == fspbb.OK
     assert L.fsp_get_instance_info(None, None) == fspbb.E_INVAL
     assert L.fsp_pool_status(None, None, None) == fspbb.E_INVAL
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    assert fspbb.tune_get(37, 7)[1] is False
+    w0, _ = fspbb.tune_get(37, 7)
+    assert w0 in (1, 2, 4, 8, 16)
+    fspbb.tune_set(37, 7, 4)
+    assert fspbb.tune_get(37, 7) == (4, True)
+    path = str(tmp_path / "tune.txt")
+    fspbb.tune_save(path)
+    fspbb.tune_set(37, 7, 16)
+    fspbb.tune_load(path)
+    assert fspbb.tune_get(37, 7) == (4, True)
+    with pytest.raises(fspbb.FspError):
+        fspbb.tune_set(37, 7, 3)
+
+
+def test_rule_of_thumb_schedules():
+    # about four machine pairs per wave and chain, at most 16 waves per group
+    assert fspbb.tune_get(200, 20)[0] == 16   # 190 pairs
+    assert fspbb.tune_get(50, 10)[0] == 8     # 45 pairs
+    assert fspbb.tune_get(20, 5)[0] == 2      # 10 pairs
+    assert fspbb.tune_get(9, 2)[0] == 1       # 1 pair

@@ -130,3 +130,21 @@ def test_batch_rejects_bad_descriptors():
         pre = torch.zeros((1, 10), dtype=torch.int32, device="cuda")
         with pytest.raises(fspbb.FspError):
             fspbb.batch_create([(inst, pre, d, d)])
+
+
+@pytest.mark.parametrize("n,m", [(20, 5), (50, 10), (200, 20)])
+def test_autotune_picks_a_measured_schedule(n, m):
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(8, n, 0))
+    with fspbb.create_instance(p) as inst:
+        r = fspbb.autotune(inst, sample_nodes=4096, reps=2)
+        assert r["waves_per_group"] in r["candidates"]
+        assert r["best_us"] == min(r["candidates"].values())
+        assert fspbb.tune_get(n, m) == (r["waves_per_group"], True)
+        # bounds stay identical under the tuned schedule
+        pre, dep = gen.random_pool(n, 3000, gen.make_seed(8, n, 1))
+        pre_d, dep_d = to_dev(torch, pre, dep)
+        out = torch.empty(3000, dtype=torch.int32, device="cuda")
+        fspbb.bound_pool(inst, pre_d, dep_d, out)
+        idx = np.arange(0, 3000, 10)
+        assert (out.cpu().numpy()[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
