@@ -8,15 +8,16 @@ from paper_1208_3933_amd import fspbb, gen
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(20, 5), (20, 10), (20, 20), (50, 10), (100, 20), (200, 20)]
+CONFIG3_SHAPES = [(20, 5), (20, 10), (20, 20), (50, 10), (100, 20), (200, 20)]
+SHAPES = CONFIG3_SHAPES + [(500, 20)]  # 500 x 20: the mask tile alone fills most of LDS
 
 
-def make_batch(torch, n_pools, sizes, config=3, invalid_in=None):
+def make_batch(torch, n_pools, sizes, config=3, invalid_in=None, shapes=SHAPES):
     pools, host = [], []
     insts = {}
     for i in range(n_pools):
-        n, m = SHAPES[i % len(SHAPES)]
-        key = (n, m, i // len(SHAPES) % 2)  # two instances per shape, pools share them
+        n, m = shapes[i % len(shapes)]
+        key = (n, m, i // len(shapes) % 2)  # two instances per shape, pools share them
         if key not in insts:
             p = gen.processing_times(n, m, gen.make_seed(config, len(insts), gen.PURPOSE_TIMES))
             insts[key] = (fspbb.create_instance(p), p)
@@ -106,7 +107,7 @@ def test_full_batched_configuration():
     """64 seeded instances of mixed shape, log-normal pool sizes 256..131072."""
     torch = require_gpu()
     sizes = gen.lognormal_pool_sizes(64, gen.make_seed(3, 0, gen.PURPOSE_SIZES))
-    pools, host, insts = make_batch(torch, 64, sizes)
+    pools, host, insts = make_batch(torch, 64, sizes, shapes=CONFIG3_SHAPES)
     want = plain_bounds(torch, pools)
     with fspbb.batch_create(pools, graph=True) as b:
         b.run()

@@ -1,0 +1,174 @@
+"""The serving loop: concurrent searches sharing every launch give, each, the
+same result as the search run alone (fsp_solve) and as the oracle's search,
+under memory-limited admission, a per-call cap on children, and arrivals
+while others run."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import require_gpu
+from paper_1208_3933_amd import fspbb, gen
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("opt", "proven", "nodes_bounded", "steps", "ub0", "improvements", "max_stack")
+
+
+def times(n, m, idx, lo=1, hi=99):
+    return gen.processing_times(n, m, gen.make_seed(9, idx, gen.PURPOSE_TIMES), lo, hi)
+
+
+# (n, m, seed index, pool_cap, node_budget, ub mode, value range): trees the
+# oracle finishes in well under a second, mixed pool caps, one search stopped
+# by its node budget (30000), one instance beyond the 16-bit path, several
+# solved at the root.
+REQUESTS = [
+    (8, 4, 0, 16, 1 << 40, "neh", 99), (9, 5, 1, 1, 1 << 40, "neh", 99), (10, 3, 2, 64, 1 << 40, "neh", 99),
+    (11, 4, 3, 1024, 1 << 40, "none", 99), (12, 5, 4, 256, 1 << 40, "neh", 99), (10, 6, 5, 3, 1 << 40, "neh", 99),
+    (20, 5, 6, 512, 1 << 40, "neh", 99), (12, 4, 7, 100, 1 << 40, "neh", 100000),
+    (9, 3, 8, 7, 1 << 40, "none", 99), (15, 8, 101, 2048, 30000, "neh", 99), (10, 10, 10, 128, 1 << 40, "neh", 99),
+    (8, 2, 11, 8, 1 << 40, "neh", 99),
+]
+
+
+def make_requests():
+    reqs = []
+    for n, m, idx, cap, budget, mode, hi in REQUESTS:
+        p = times(n, m, idx, 1, hi)
+        reqs.append(dict(p=p, pool_cap=cap, budget=budget, ub0=fspbb.UB_NEH if mode == "neh" else fspbb.UB_NONE))
+    return reqs
+
+
+def solve_alone(insts, reqs):
+    out = []
+    for inst, r in zip(insts, reqs):
+        out.append(fspbb.solve(inst, r["ub0"], r["pool_cap"], r["budget"]))
+    return out
+
+
+def oracle_solve(r):
+    p = r["p"]
+    if r["ub0"] == fspbb.UB_NEH:
+        ms, perm = oracle.neh(p)
+        return oracle.bnb(p, ms, perm, pool_cap=r["pool_cap"], node_budget=r["budget"])
+    return oracle.bnb(p, fspbb.UB_NONE, None, pool_cap=r["pool_cap"], node_budget=r["budget"])
+
+
+def same(a, b):
+    return all(a[f] == b[f] for f in FIELDS) and a["status"] == b["status"] and (a["perm"] == b["perm"]).all()
+
+
+def run_served(insts, reqs, mem_budget, max_active, tick_children, arrivals_per_step=3, check=None):
+    """Submits arrivals_per_step requests per step call (arrivals while others
+    run), steps until all finish, and returns the results in request order."""
+    results = {}
+    ids = {}
+    with fspbb.server_create(mem_budget, max_active, tick_children) as srv:
+        nxt = 0
+        while len(results) < len(reqs):
+            for _ in range(arrivals_per_step):
+                if nxt < len(reqs):
+                    r = reqs[nxt]
+                    ids[srv.submit(insts[nxt], r["ub0"], r["pool_cap"], r["budget"])] = nxt
+                    nxt += 1
+            done, stats = srv.step()
+            if check:
+                check(stats)
+            for i in done:
+                res = srv.poll(i)
+                assert res is not None
+                results[ids[i]] = res
+            assert stats["nodes_bounded"] > 0
+    return [results[k] for k in range(len(reqs))]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    require_gpu()
+    reqs = make_requests()
+    insts = [fspbb.create_instance(r["p"]) for r in reqs]
+    alone = solve_alone(insts, reqs)
+    yield reqs, insts, alone
+    for inst in insts:
+        inst.close()
+
+
+def test_alone_matches_oracle(setup):
+    reqs, insts, alone = setup
+    assert not insts[7].info()["packed16"]  # the 32-bit kernel is in the mix
+    for r, a in zip(reqs, alone):
+        w = oracle_solve(r)
+        assert (a["opt"], bool(a["proven"]), a["nodes_bounded"], a["steps"], a["improvements"], a["max_stack"]) == \
+            (w["ub"], w["proven"], w["nodes_bounded"], w["steps"], w["improvements"], w["max_stack"])
+        assert (a["perm"] == w["incumbent"]).all()
+    assert not alone[9]["proven"] and alone[9]["status"] == fspbb.BUDGET
+    assert any(a["steps"] == 0 for a in alone) and any(a["steps"] > 50 for a in alone)
+
+
+def test_mix_identical_to_alone(setup):
+    reqs, insts, alone = setup
+    served = run_served(insts, reqs, 1 << 34, 64, 0)
+    for k, (a, s) in enumerate(zip(alone, served)):
+        assert same(a, s), (k, a, s)
+
+
+def test_memory_admission_limits_active_searches(setup):
+    reqs, insts, alone = setup
+    # the largest initial footprint among the requests, measured by admitting it alone
+    foot = 0
+    for inst, r in zip(insts, reqs):
+        with fspbb.server_create(1 << 34, 1) as srv:
+            i = srv.submit(inst, r["ub0"], r["pool_cap"], r["budget"])
+            _, st = srv.step()
+            foot = max(foot, st["mem_used"])
+            while srv.poll(i) is None:
+                srv.step()
+    budget = int(1.2 * foot)  # below the sum of the footprints, above the largest
+    seen = []
+
+    def check(stats):
+        seen.append((stats["active"], stats["pending"]))
+
+    served = run_served(insts, reqs, budget, 64, 0, arrivals_per_step=12, check=check)
+    assert max(a for a, _ in seen) >= 2
+    # with 64 slots free, only the memory budget holds searches back
+    assert any(p > 0 for _, p in seen)
+    for k, (a, s) in enumerate(zip(alone, served)):
+        assert same(a, s), k
+
+
+def test_children_cap_and_slots(setup):
+    reqs, insts, alone = setup
+    seen = []
+
+    def check(stats):
+        seen.append((stats["last_children"], stats["last_searches"], stats["active"]))
+        assert stats["active"] <= 3
+        assert stats["last_children"] <= 600 or stats["last_searches"] == 1
+
+    served = run_served(insts, reqs, 1 << 34, 3, 600, check=check)
+    for k, (a, s) in enumerate(zip(alone, served)):
+        assert same(a, s), k
+    assert any(ls >= 2 for _, ls, _ in seen)
+
+
+def test_poll_and_submit_errors(setup):
+    reqs, insts, alone = setup
+    with fspbb.server_create(1 << 24, 4) as srv:
+        with pytest.raises(fspbb.FspError):
+            srv.poll(12345)
+        with pytest.raises(fspbb.FspError):
+            srv.submit(insts[0], fspbb.UB_NEH, 0, 10)
+        with pytest.raises(fspbb.FspError) as ei:
+            srv.submit(insts[6], fspbb.UB_NEH, 1 << 24, 10)  # stack and scratch beyond the budget
+        assert ei.value.status == fspbb.E_NOMEM
+        i = srv.submit(insts[0], reqs[0]["ub0"], reqs[0]["pool_cap"], reqs[0]["budget"])
+        assert srv.poll(i) is None  # pending before any step
+        while True:
+            srv.step()
+            r = srv.poll(i)
+            if r is not None:
+                break
+        assert same(r, alone[0])
+        with pytest.raises(fspbb.FspError):
+            srv.poll(i)  # a result is returned once
