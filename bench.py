@@ -1,14 +1,22 @@
-"""Benchmark: nodes bounded per second on one MI355X.
+"""Benchmark: nodes bounded per second on one MI355X, plain and batched, and
+the latency of served branch-and-bound solves.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload (the 200 jobs x 20 machines plain-bounding configuration): one seeded
-instance with processing times i.i.d. U[1,99], a pool of 262,144 nodes whose
-depths are uniform on 0..199 and whose prefixes are seeded random job
-sequences; inputs are resident in HBM before timing starts.  A step is one
+Headline workload (the 200 jobs x 20 machines plain-bounding configuration):
+one seeded instance with processing times i.i.d. U[1,99], a pool of 262,144
+nodes whose depths are uniform on 0..199 and whose prefixes are seeded random
+job sequences; inputs are resident in HBM before timing starts.  A step is one
 fsp_bound_pool call over the whole pool (decode + scan kernels).  Prints one
-JSON line.  The oracle leg times the plain C oracle on a bounded prefix of
-the same pool on the host cores.
+JSON line.  Further legs:
+  batched  the same pool as 64 pools of 4,096 in one graph-captured batch vs
+           64 plain launches, and 64 seeded instances of mixed shape with
+           log-normal pool sizes, batched vs plain;
+  bnb      depth-first branch-and-bound from NEH on the 200 x 20 instance;
+  serving  a Poisson stream of solves over mixed shapes through the serving
+           loop: p50/p99 latency, nodes/s, and identity with each solve alone;
+  cpu_baseline  the plain C oracle on a bounded prefix of the pool on the
+           host cores (its bounds are also compared with the GPU's).
 """
 from __future__ import annotations
 
@@ -41,7 +49,7 @@ def algorithmic_scan_ops(n: int, m: int, depths: np.ndarray) -> float:
     return float(P * (n * len(depths) + 4 * nprime + 2 * len(depths)))
 
 
-def cpu_baseline(p, pre, dep, sample: int, threads: int) -> dict:
+def cpu_baseline(p, pre, dep, sample: int, threads: int, gpu_lb: np.ndarray) -> dict:
     import concurrent.futures as cf
 
     import oracle
@@ -49,10 +57,112 @@ def cpu_baseline(p, pre, dep, sample: int, threads: int) -> dict:
     chunks = np.array_split(idx, threads * 4)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
-        list(ex.map(lambda c: oracle.bound_pool(p, pre[c], dep[c]), chunks))
+        parts = list(ex.map(lambda c: oracle.bound_pool(p, pre[c], dep[c]), chunks))
     dt = time.perf_counter() - t0
+    want = np.concatenate(parts)
     return {"value": len(idx) / dt, "unit": "nodes/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per core"}
+            "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per core",
+            "gpu_bounds_equal": bool((gpu_lb[idx] == want).all())}
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
+    """Batched (one graph-captured persistent launch) vs plain (one launch per
+    pool) on the same pools, outputs compared element by element."""
+    import torch
+
+    from paper_1208_3933_amd import fspbb, gen
+    out = {}
+
+    def compare(name, pools):
+        plain_out = [torch.full_like(o, -7) for _, _, _, o in pools]
+
+        def plain():
+            for (i, a, b, _), o in zip(pools, plain_out):
+                fspbb.bound_pool(i, a, b, o, stream)
+        with fspbb.batch_create(pools, graph=True) as b:
+            for _ in range(3):
+                plain()
+                b.run(stream)
+            t_plain = _time(plain, reps)
+            t_batch = _time(lambda: b.run(stream), reps)
+            info = b.info()
+        same = all(bool(torch.equal(o, q)) for (_, _, _, o), q in zip(pools, plain_out))
+        nodes = info["total_nodes"]
+        out[name] = {"pools": len(pools), "nodes": nodes, "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
+                     "plain_nodes_per_s": nodes / t_plain, "batched_nodes_per_s": nodes / t_batch,
+                     "speedup": t_plain / t_batch, "identical": same, "graph_items": info["items"]}
+
+    # the 200 x 20 pool as 64 pools of 4096 nodes
+    N = int(dep_d.shape[0])
+    k = 64
+    step = N // k
+    pools = [(inst, pre_d[i * step:(i + 1) * step], dep_d[i * step:(i + 1) * step],
+              torch.empty(step, dtype=torch.int32, device=dep_d.device)) for i in range(k)]
+    compare("200x20_64x4096", pools)
+    # the whole pool as one batch entry
+    compare("200x20_whole_pool", [(inst, pre_d, dep_d, torch.empty(N, dtype=torch.int32, device=dep_d.device))])
+    # 64 seeded instances of mixed shape with log-normal pool sizes
+    shapes = [(20, 5), (20, 10), (20, 20), (50, 10), (100, 20), (200, 20)]
+    sizes = gen.lognormal_pool_sizes(64, gen.make_seed(3, 0, gen.PURPOSE_SIZES))
+    insts, pools = [], []
+    for i in range(64):
+        n, m = shapes[i % 6]
+        ins = fspbb.create_instance(gen.processing_times(n, m, gen.make_seed(3, i, gen.PURPOSE_TIMES)))
+        pr, dp = gen.random_pool(n, int(sizes[i]), gen.make_seed(3, i, gen.PURPOSE_POOL))
+        insts.append(ins)
+        pools.append((ins, torch.from_numpy(pr).cuda(), torch.from_numpy(dp).cuda(),
+                      torch.empty(int(sizes[i]), dtype=torch.int32, device="cuda")))
+    compare("mixed_64_instances", pools)
+    for ins in insts:
+        ins.close()
+    return out
+
+
+def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: int, stream) -> dict:
+    """Poisson stream of solves at 0.7 x the measured saturation rate."""
+    from paper_1208_3933_amd import gen, serve
+    cands = serve.candidates(seeds_per_shape)
+    serve.screen(cands[:4], pool_cap, budget, stream)  # warm-up
+    serve.screen(cands, pool_cap, budget, stream)
+    unsolved = {}
+    for c in cands:
+        if not c.alone["proven"]:
+            key = "%dx%d" % serve.SHAPES[c.shape]
+            unsolved[key] = unsolved.get(key, 0) + 1
+    mem = 32 << 30
+    sat_reqs = serve.sample_requests(cands, max(50, n_requests // 8), gen.make_seed(serve.CONFIG, 1, gen.PURPOSE_ARRIVALS))
+    sat = serve.run(cands, sat_reqs, None, pool_cap, budget, mem, 256, 0, stream)
+    sat_rate = len(sat_reqs) / sat["wall_s"]
+    alone_s = sum(cands[r].alone_s for r in sat_reqs)
+    reqs = serve.sample_requests(cands, n_requests, gen.make_seed(serve.CONFIG, 2, gen.PURPOSE_ARRIVALS))
+    rate = 0.7 * sat_rate
+    arr = serve.poisson_arrivals(n_requests, rate, gen.make_seed(serve.CONFIG, 3, gen.PURPOSE_ARRIVALS))
+    r = serve.run(cands, reqs, arr, pool_cap, budget, mem, 256, 0, stream)
+    lat_ms = r["latency_s"] * 1e3
+    for c in cands:
+        c.inst.close()
+    return {"requests": n_requests, "rate_per_s": rate, "p50_ms": serve.percentile(lat_ms, 50),
+            "p99_ms": serve.percentile(lat_ms, 99), "mean_ms": float(lat_ms.mean()),
+            "nodes_per_s": r["nodes_bounded"] / r["wall_s"], "solves_per_s": n_requests / r["wall_s"],
+            "wall_s": r["wall_s"], "mean_searches_per_step": r["mean_searches_per_tick"],
+            "mismatches_vs_alone": r["mismatches"] + sat["mismatches"],
+            "saturation": {"requests": len(sat_reqs), "solves_per_s": sat_rate,
+                           "nodes_per_s": sat["nodes_bounded"] / sat["wall_s"],
+                           "alone_sequential_solves_per_s": len(sat_reqs) / alone_s,
+                           "speedup_vs_alone_sequential": alone_s / sat["wall_s"]},
+            "pool_cap": pool_cap, "node_budget": budget,
+            "screened": len(cands), "proven": sum(1 for c in cands if c.alone["proven"]),
+            "unsolved_by_shape": unsolved}
 
 
 def bnb_leg(inst, steps: int, stream) -> dict:
@@ -80,6 +190,14 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bnb-steps", type=int, default=8, help="pool steps of the 200x20 DFS leg (0 = skip)")
+    ap.add_argument("--batched-reps", type=int, default=20, help="repetitions of the batched leg (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving leg (0 = skip)")
+    ap.add_argument("--serve-seeds", type=int, default=10, help="screened instances per shape")
+    ap.add_argument("--serve-pool-cap", type=int, default=8192)
+    ap.add_argument("--serve-budget", type=int, default=2000000)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run one plain device copy of this many bytes before timing (a kernel of known "
+                         "traffic, to scale HBM counters read under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the bound path runs on "
@@ -105,19 +223,20 @@ def main() -> int:
     inst = fspbb.create_instance(p)
     stream = torch.cuda.current_stream()
 
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)  # one elementwise kernel: reads and writes copy_bytes each
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         fspbb.bound_pool(inst, pre_d, dep_d, out, stream)
     torch.cuda.synchronize()
     if fspbb.pool_status(inst, stream) != 0:
         raise RuntimeError("invalid nodes in the benchmark pool")
 
-    # spot check against the oracle before timing
-    import oracle
-    got = out.cpu().numpy()
-    idx = np.arange(0, POOL, POOL // 64)
-    want = oracle.bound_pool(p, pre[idx], dep[idx])
-    if not (got[idx] == want).all():
-        raise RuntimeError("benchmark bounds differ from the oracle")
+    gpu_lb = out.cpu().numpy()
 
     fspbb.timing_enable(inst, True)
     fspbb.timing_read(inst)
@@ -159,11 +278,21 @@ def main() -> int:
                      "decode_avg_ms": dec_ms / max(launches, 1)},
         "plain_nodes_per_s": value,
     }
+    if args.batched_reps > 0:
+        result["batched"] = batched_leg(inst, pre_d, dep_d, args.batched_reps, stream)
+        print("[bench] batched leg done", file=sys.stderr, flush=True)
     if args.bnb_steps > 0:
         result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)
+        print("[bench] bnb leg done", file=sys.stderr, flush=True)
+    if args.serve_requests > 0:
+        result["serving"] = serving_leg(args.serve_requests, args.serve_seeds, args.serve_pool_cap,
+                                        args.serve_budget, stream)
+        s = result["serving"]
+        result["p50_ms"], result["p99_ms"] = s["p50_ms"], s["p99_ms"]
+        print("[bench] serving leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
-        result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads)
+        result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads, gpu_lb)
     inst.close()
     print(json.dumps(result), flush=True)
     return 0
