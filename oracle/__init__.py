@@ -67,6 +67,11 @@ def lib():
         L.orc_bound_pool.restype = ctypes.c_int64
         L.orc_bound_pool.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p, _i32p,
                                      ctypes.c_int64, _i32p]
+        L.orc_bound_heads.restype = ctypes.c_int32
+        L.orc_bound_heads.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int]
+        L.orc_bound_pool_mode.restype = ctypes.c_int64
+        L.orc_bound_pool_mode.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p, _i32p,
+                                          ctypes.c_int64, _i32p, ctypes.c_int]
         L.orc_brute.restype = ctypes.c_int32
         L.orc_brute.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int]
         L.orc_neh.restype = ctypes.c_int32
@@ -74,7 +79,7 @@ def lib():
         L.orc_bnb.restype = ctypes.c_int
         L.orc_bnb.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _i32p,
                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
-                              ctypes.POINTER(BnbResult), _i32p, _i64p, ctypes.c_int64]
+                              ctypes.POINTER(BnbResult), _i32p, _i64p, ctypes.c_int64, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -105,6 +110,15 @@ def bound(p, prefix) -> int:
     buf = np.zeros(max(n, 1), np.int32)
     buf[:len(s)] = s
     return int(lib().orc_bound(_p(p), n, m, _p(buf), len(s)))
+
+
+def bound_heads(p, prefix) -> int:
+    """The bound with the heads variant of the machine releases."""
+    p, n, m = _mat(p)
+    s = _seq(prefix)
+    buf = np.zeros(max(n, 1), np.int32)
+    buf[:len(s)] = s
+    return int(lib().orc_bound_heads(_p(p), n, m, _p(buf), len(s)))
 
 
 def bound_tie(p, prefix, tiekey, eq_in_s2: bool) -> int:
@@ -139,13 +153,16 @@ def pair_scan(p, prefix, k: int, l: int):
     return int(t2.value), int(q.value)
 
 
-def bound_pool(p, prefixes, depths) -> np.ndarray:
+def bound_pool(p, prefixes, depths, heads: bool = False) -> np.ndarray:
     p, n, m = _mat(p)
     pre = np.ascontiguousarray(prefixes, dtype=np.int32).reshape(-1, n)
     dep = np.ascontiguousarray(depths, dtype=np.int32).reshape(-1)
     assert pre.shape[0] == dep.shape[0]
     out = np.empty(dep.shape[0], np.int32)
-    lib().orc_bound_pool(_p(p), n, m, _p(pre), _p(dep), dep.shape[0], _p(out))
+    if heads:
+        lib().orc_bound_pool_mode(_p(p), n, m, _p(pre), _p(dep), dep.shape[0], _p(out), 1)
+    else:
+        lib().orc_bound_pool(_p(p), n, m, _p(pre), _p(dep), dep.shape[0], _p(out))
     return out
 
 
@@ -165,8 +182,9 @@ def neh(p):
 
 
 def bnb(p, ub0: int, incumbent0=None, pool_cap: int = 1 << 18, node_budget: int = 1 << 62,
-        strict_gt: bool = False, steplog_cap: int = 0):
-    """Pool-synchronous DFS branch-and-bound.  Returns a dict."""
+        strict_gt: bool = False, steplog_cap: int = 0, heads: bool = False):
+    """Pool-synchronous DFS branch-and-bound (heads: the heads variant of the
+    bound).  Returns a dict."""
     p, n, m = _mat(p)
     res = BnbResult()
     inc = np.empty(n, np.int32)
@@ -174,7 +192,7 @@ def bnb(p, ub0: int, incumbent0=None, pool_cap: int = 1 << 18, node_budget: int 
     log = np.zeros((max(steplog_cap, 1), 6), np.int64)
     rc = lib().orc_bnb(_p(p), n, m, int(ub0), None if inc0 is None else _p(inc0),
                        int(pool_cap), int(node_budget), int(strict_gt), ctypes.byref(res),
-                       _p(inc), log.ctypes.data_as(_i64p), int(steplog_cap))
+                       _p(inc), log.ctypes.data_as(_i64p), int(steplog_cap), int(heads))
     if rc != 0:
         raise ValueError("bad arguments")
     return {"ub": int(res.ub), "proven": bool(res.proven), "nodes_bounded": int(res.nodes_bounded),

@@ -15,7 +15,11 @@
  * Readings of the paper taken here (each is also listed with its reason in the
  * design notes of the repository):
  *   - Machine releases (RM) are the completion times of the scheduled prefix
- *     on each machine; the root has all releases 0.
+ *     on each machine; the root has all releases 0.  The "heads" variant
+ *     takes RM literally as the earliest starting times of the unscheduled
+ *     jobs (Table I, Fig. 2 lines taking a minimum of RM over jobs): the
+ *     release of machine k is the least, over unscheduled jobs j, of the time
+ *     j would start on k if it were scheduled next.
  *   - The tail of machine l (QM) is the minimum over unscheduled jobs of the
  *     job's total time on machines after l; 0 when no job is unscheduled.
  *   - The lag of job j on pair (k,l) (LM) is its total time on the machines
@@ -144,7 +148,7 @@ static keyed_job johnson_fields(int32_t j, int64_t a, int64_t b, int64_t L, int6
  * Returns ORC_INVALID for an invalid node. */
 static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix, int d,
                           const int32_t *tiekey, int eq_in_s2, orc_counts *cnt,
-                          int only_k, int only_l, int64_t *pair_t2, int64_t *pair_q)
+                          int only_k, int only_l, int64_t *pair_t2, int64_t *pair_q, int heads)
 {
     unsigned char *scheduled = (unsigned char *)malloc((size_t)n + 1);
     if (!decode_node(n, prefix, d, scheduled)) { free(scheduled); return ORC_INVALID; }
@@ -152,6 +156,27 @@ static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix,
     /* RM: completion times of the prefix on each machine. */
     int64_t *r = (int64_t *)calloc((size_t)m, sizeof(int64_t));
     completion_times(p, m, prefix, d, r);
+
+    if (heads) {
+        /* RM as earliest starting times: job j scheduled next would start on
+         * machine k at max(release of k, completion of j on k-1); the
+         * machine's release becomes the least such start over unscheduled j. */
+        int64_t *h = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+        int any = 0;
+        for (int j = 0; j < n; ++j) {
+            if (scheduled[j]) continue;
+            int64_t prev_done = 0;  /* completion of j on machine k-1 */
+            for (int k = 0; k < m; ++k) {
+                int64_t start = r[k] > prev_done ? r[k] : prev_done;
+                if (!any || start < h[k]) h[k] = start;
+                prev_done = start + p[(int64_t)j * m + k];
+            }
+            any = 1;
+        }
+        if (any)
+            for (int k = 0; k < m; ++k) r[k] = h[k];
+        free(h);
+    }
 
     /* QM: min over unscheduled jobs of the time left after machine l. */
     int64_t *q = (int64_t *)calloc((size_t)m, sizeof(int64_t));
@@ -207,7 +232,13 @@ static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix,
 
 int32_t orc_bound(const int32_t *p, int n, int m, const int32_t *prefix, int d)
 {
-    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL);
+    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL, 0);
+}
+
+/* The bound with the heads variant of RM (see the header). */
+int32_t orc_bound_heads(const int32_t *p, int n, int m, const int32_t *prefix, int d)
+{
+    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL, 1);
 }
 
 /* Same bound with a custom tie-break key per job and a choice of group for
@@ -215,7 +246,7 @@ int32_t orc_bound(const int32_t *p, int n, int m, const int32_t *prefix, int d)
 int32_t orc_bound_tie(const int32_t *p, int n, int m, const int32_t *prefix, int d,
                       const int32_t *tiekey, int eq_in_s2)
 {
-    return bound_impl(p, n, m, prefix, d, tiekey, eq_in_s2, NULL, -1, -1, NULL, NULL);
+    return bound_impl(p, n, m, prefix, d, tiekey, eq_in_s2, NULL, -1, -1, NULL, NULL, 0);
 }
 
 /* Same bound, counting accesses to the Table I structures. */
@@ -223,7 +254,7 @@ int32_t orc_bound_counted(const int32_t *p, int n, int m, const int32_t *prefix,
                           orc_counts *cnt)
 {
     memset(cnt, 0, sizeof(*cnt));
-    return bound_impl(p, n, m, prefix, d, NULL, 0, cnt, -1, -1, NULL, NULL);
+    return bound_impl(p, n, m, prefix, d, NULL, 0, cnt, -1, -1, NULL, NULL, 0);
 }
 
 /* One pair only: *t2 = timeOnM2 after the scan (before the tail), *q = tail
@@ -232,13 +263,25 @@ int32_t orc_pair_scan(const int32_t *p, int n, int m, const int32_t *prefix, int
                       int k, int l, int64_t *t2, int64_t *q)
 {
     if (k < 0 || l <= k || l >= m) return ORC_INVALID;
-    int32_t v = bound_impl(p, n, m, prefix, d, NULL, 0, NULL, k, l, t2, q);
+    int32_t v = bound_impl(p, n, m, prefix, d, NULL, 0, NULL, k, l, t2, q, 0);
     return v == ORC_INVALID ? ORC_INVALID : 0;
 }
 
 /* Bounds of a pool: prefixes is count x n (row i holds depths[i] scheduled
  * jobs first), out[i] = bound or ORC_INVALID.  Returns the number of invalid
  * rows. */
+int64_t orc_bound_pool_mode(const int32_t *p, int n, int m, const int32_t *prefixes,
+                            const int32_t *depths, int64_t count, int32_t *out, int heads)
+{
+    int64_t bad = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        out[i] = bound_impl(p, n, m, prefixes + i * (int64_t)n, depths[i], NULL, 0, NULL, -1, -1, NULL, NULL,
+                            heads);
+        if (out[i] == ORC_INVALID) ++bad;
+    }
+    return bad;
+}
+
 int64_t orc_bound_pool(const int32_t *p, int n, int m, const int32_t *prefixes,
                        const int32_t *depths, int64_t count, int32_t *out)
 {
@@ -377,7 +420,7 @@ typedef struct {
 int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
             int64_t pool_cap, int64_t node_budget, int strict_gt,
             orc_bnb_result *res, int32_t *incumbent_out,
-            int64_t *steplog, int64_t steplog_cap)
+            int64_t *steplog, int64_t steplog_cap, int heads)
 {
     memset(res, 0, sizeof(*res));
     if (n < 1 || m < 2 || pool_cap < 1) return -1;
@@ -392,7 +435,7 @@ int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
 #define NODE(i) (stack + (int64_t)(i) * (n + 1))
 
     int64_t nodes = 1;
-    int32_t root_lb = orc_bound(p, n, m, NULL, 0);
+    int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, heads);
     int pruned_root = strict_gt ? (root_lb > UB) : (root_lb >= UB);
     if (!pruned_root) {
         NODE(0)[0] = 0;
@@ -439,7 +482,7 @@ int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
         /* 4. bounding */
         for (int64_t i = 0; i < nchild; ++i) {
             int32_t *ch = children + i * (n + 1);
-            lbs[i] = orc_bound(p, n, m, ch + 1, ch[0]);
+            lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, heads);
         }
         nodes += nchild;
         /* 5. complete children update the upper bound */

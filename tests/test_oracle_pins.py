@@ -351,3 +351,79 @@ def test_bnb_steplog_consistency():
     assert 1 + int(log[:, 1].sum()) == r["nodes_bounded"]
     assert (log[:, 1] <= 20).all() or (log[:, 0] == 1).all()
     assert int(log[-1, 4]) == 0
+
+
+# --- heads variant: machine releases as earliest starting times (Table I RM) ----
+
+def test_heads_hand_worked_example():
+    """p = [[1, 6, 6], [4, 8, 8]] at the root, worked by hand.
+
+    Earliest starts of a job scheduled first: machine 0 at 0 for both;
+    machine 1 at 1 (job 0) or 4 (job 1), least 1; machine 2 at 1 + 6 = 7 or
+    4 + 8 = 12, least 7.  Pair (1,2) then runs from (1, 7) over the Johnson
+    order 0, 1: job 0 gives t1 = 7, t2 = max(7, 7) + 6 = 13; job 1 gives
+    t1 = 15, t2 = max(13, 15) + 8 = 23.  Pairs (0,1) (15 plus tail 6) and
+    (0,2) (21) give 21.  With every release 0 the pair (1,2) gives
+    t2 = 12, then max(12, 14) + 8 = 22, so the plain bound is 22.  The order
+    0, 1 has makespan 23, the order 1, 0 has 26."""
+    p = np.array([[1, 6, 6], [4, 8, 8]], np.int32)
+    assert oracle.bound(p, []) == 22
+    assert oracle.bound_heads(p, []) == 23
+    assert oracle.brute(p) == 23
+    assert oracle.makespan(p, [0, 1]) == 23 and oracle.makespan(p, [1, 0]) == 26
+
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 231), (6, 4, 232), (7, 5, 233), (8, 3, 234), (8, 6, 235)])
+def test_heads_between_plain_bound_and_optimum(n, m, seed):
+    """The heads only raise releases to times no job can beat, so the bound is
+    at least the plain one and at most the optimum of the node."""
+    p = inst(n, m, seed)
+    for pre in all_prefixes(n, 2):
+        plain = oracle.bound(p, pre)
+        h = oracle.bound_heads(p, pre)
+        opt = oracle.brute(p, pre)
+        assert plain <= h <= opt, (pre, plain, h, opt)
+
+
+def test_heads_raise_some_bounds_on_random_pools():
+    """On a 20 x 10 pool a share of nodes gets a strictly larger bound, none a
+    smaller one."""
+    p = inst(20, 10, 236)
+    pre, dep = gen.random_pool(20, 2000, gen.make_seed(90, 237, gen.PURPOSE_POOL))
+    plain = oracle.bound_pool(p, pre, dep)
+    h = oracle.bound_pool(p, pre, dep, heads=True)
+    assert (h >= plain).all() and (h > plain).sum() > 0
+
+
+@pytest.mark.parametrize("n,seed", [(4, 241), (6, 242), (7, 243)])
+def test_heads_two_machines_exact(n, seed):
+    p = inst(n, 2, seed)
+    for pre in all_prefixes(n, min(n, 3)):
+        assert oracle.bound_heads(p, pre) == oracle.brute(p, pre), pre
+
+
+@pytest.mark.parametrize("n,m,seed", [(6, 4, 251), (20, 5, 252), (50, 10, 253)])
+def test_heads_exact_with_at_most_one_job_left(n, m, seed):
+    p = inst(n, m, seed)
+    rng = np.random.default_rng(seed)
+    for _ in range(20):
+        perm = rng.permutation(n)
+        ms = path_makespan(p, perm) if n <= 6 else oracle.makespan(p, perm)
+        assert oracle.bound_heads(p, perm) == ms
+        assert oracle.bound_heads(p, perm[:-1]) == ms
+
+
+@pytest.mark.parametrize("n,m,seed", [(6, 3, 261), (7, 4, 262), (8, 5, 263)])
+def test_heads_bnb_finds_the_optimum(n, m, seed):
+    p = inst(n, m, seed)
+    opt = oracle.brute(p)
+    ms, perm = oracle.neh(p)
+    for cap in [1, 9, 1 << 20]:
+        r = oracle.bnb(p, ms, perm, pool_cap=cap, heads=True)
+        assert r["proven"] and r["ub"] == opt
+        assert oracle.makespan(p, r["incumbent"]) == opt
+    plain = oracle.bnb(p, opt, None, pool_cap=1 << 20)
+    heads = oracle.bnb(p, opt, None, pool_cap=1 << 20, heads=True)
+    # with UB0 = optimum the explored set is the nodes whose bound is below it:
+    # a stronger bound at every node cannot explore more
+    assert heads["nodes_bounded"] <= plain["nodes_bounded"]
