@@ -12,6 +12,8 @@ JSON line.  Further legs:
   batched  the same pool as 64 pools of 4,096 in one graph-captured batch vs
            64 plain launches, and 64 seeded instances of mixed shape with
            log-normal pool sizes, batched vs plain;
+  heads    the bound variant with earliest-start releases: throughput on the
+           same pool, and solves of small instances with either bound;
   bnb      depth-first branch-and-bound from NEH on the 200 x 20 instance;
   serving  a Poisson stream of solves over mixed shapes through the serving
            loop: p50/p99 latency, nodes/s, and identity with each solve alone;
@@ -128,6 +130,39 @@ def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
     return out
 
 
+def heads_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
+    """The heads variant (releases as earliest starts of unscheduled jobs): its
+    bound throughput on the same 200x20 pool, and depth-first solves from NEH
+    of seeded small instances with either bound (same pool_cap and budget)."""
+    from paper_1208_3933_amd import fspbb, serve
+    out = {}
+    with fspbb.create_instance(p, heads=True) as inst:
+        o = dep_d.new_empty(dep_d.shape)
+        for _ in range(2):
+            fspbb.bound_pool(inst, pre_d, dep_d, o, stream)
+        t = _time(lambda: fspbb.bound_pool(inst, pre_d, dep_d, o, stream), steps)
+        out["bound_200x20_nodes_per_s"] = int(dep_d.shape[0]) / t
+    shapes = [(20, 5), (20, 10), (50, 5), (100, 5)]
+    cands = serve.candidates(6, shapes)
+    budget, cap = 2_000_000, 8192
+    rows = {}
+    for c in cands:
+        key = "%dx%d" % shapes[c.shape]
+        r = rows.setdefault(key, {"instances": 0, "plain_proven": 0, "heads_proven": 0, "plain_nodes": 0,
+                                  "heads_nodes": 0, "plain_s": 0.0, "heads_s": 0.0})
+        r["instances"] += 1
+        for mode in ("plain", "heads"):
+            with fspbb.create_instance(c.p, heads=(mode == "heads")) as inst:
+                t0 = time.perf_counter()
+                res = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, 0, stream)
+                r[mode + "_s"] += time.perf_counter() - t0
+            r[mode + "_proven"] += int(res["proven"])
+            r[mode + "_nodes"] += int(res["nodes_bounded"])
+    out["solves"] = rows
+    out["pool_cap"], out["node_budget"] = cap, budget
+    return out
+
+
 def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: int, stream) -> dict:
     """Poisson stream of solves at 0.7 x the measured saturation rate."""
     from paper_1208_3933_amd import gen, serve
@@ -195,6 +230,8 @@ def main() -> int:
     ap.add_argument("--serve-seeds", type=int, default=10, help="screened instances per shape")
     ap.add_argument("--serve-pool-cap", type=int, default=8192)
     ap.add_argument("--serve-budget", type=int, default=2000000)
+    ap.add_argument("--no-heads", dest="heads", action="store_false",
+                    help="skip the leg of the heads bound variant")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes before timing (a kernel of known "
                          "traffic, to scale HBM counters read under a profiler)")
@@ -281,6 +318,9 @@ def main() -> int:
     if args.batched_reps > 0:
         result["batched"] = batched_leg(inst, pre_d, dep_d, args.batched_reps, stream)
         print("[bench] batched leg done", file=sys.stderr, flush=True)
+    if args.heads:
+        result["heads"] = heads_leg(p, pre_d, dep_d, args.steps, stream)
+        print("[bench] heads leg done", file=sys.stderr, flush=True)
     if args.bnb_steps > 0:
         result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)
         print("[bench] bnb leg done", file=sys.stderr, flush=True)

@@ -59,9 +59,19 @@ typedef struct {
     int32_t pairs;         /* m(m-1)/2 machine pairs */
     int32_t max_value;     /* (n+m-1) * max p: bound on every intermediate value */
     int32_t packed16;      /* 1 when max_value < 65536: the fast 16-bit path is used */
-    int32_t reserved;
+    int32_t flags;         /* FSP_INSTANCE_* flags it was created with */
     int64_t table_bytes;   /* device bytes held by the instance */
 } fsp_instance_info;
+
+/* Instance flag: the bound takes each machine's release as the earliest time
+ * any unscheduled job could start on it (RM as "earliest starting times of
+ * jobs", Table I, with the minimum over jobs of Fig. 2): for machine k, the
+ * least over unscheduled jobs j of max(prefix completion on k, completion of
+ * j on k-1 were j scheduled next).  Without it the release is the prefix
+ * completion on k.  The bound is never lower, still valid, and the same at
+ * m = 2 and with at most one job left.  Applies to every call on the
+ * instance: bounding, batches, steps, solves and served searches. */
+#define FSP_INSTANCE_HEADS 1
 
 /* Name of a status code (static string). */
 const char *fsp_status_string(fsp_status s);
@@ -81,6 +91,10 @@ const char *fsp_last_error_string(void);
  * later run on that same device.
  */
 fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_instance *out);
+
+/* fsp_create_instance with flags (0 or FSP_INSTANCE_HEADS); other bits:
+ * FSP_E_INVAL. */
+fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_t flags, fsp_instance *out);
 
 /* Release an instance (synchronises the device first).  NULL is a no-op. */
 fsp_status fsp_destroy_instance(fsp_instance inst);

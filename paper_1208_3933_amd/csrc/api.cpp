@@ -1,4 +1,8 @@
 // C ABI entry points of the bound path (include/fspbb.h).
+#include <cstdint>
+#include <map>
+#include <mutex>
+
 #include "fspbb_internal.h"
 
 using namespace fspbb;
@@ -24,6 +28,40 @@ struct DeviceGuard {
 }  // namespace
 
 namespace fspbb {
+
+hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s)
+{
+    static std::mutex mu;
+    static std::map<int, hipMemPool_t> pools;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = pools.find(dev);
+        if (it != pools.end()) {
+            pool = it->second;
+        } else {
+            hipMemPoolProps props{};
+            props.allocType = hipMemAllocationTypePinned;
+            props.handleTypes = hipMemHandleTypeNone;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            e = hipMemPoolCreate(&pool, &props);
+            if (e != hipSuccess) return e;
+            uint64_t keep = UINT64_MAX;
+            e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            if (e != hipSuccess) {
+                hipMemPoolDestroy(pool);
+                return e;
+            }
+            pools[dev] = pool;
+        }
+    }
+    return hipMallocFromPoolAsync(ptr, bytes, pool, s);
+}
+
 void timing_mark(fsp_instance_s *I, int which, hipStream_t s)
 {
     if (!I->timing) return;

@@ -73,7 +73,7 @@ fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out
     return FSP_OK;
 }
 
-void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, BatchPlan &pl)
+void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl)
 {
     pl = BatchPlan{};
     pl.pools.resize(n_pools);
@@ -91,6 +91,11 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         ws += al256((size_t)G * 3 * m * 64 * 4) + al256((size_t)G * NW * 128 * 4) + al256((size_t)Npad * 4);
         BatchPool &P = pl.pools[i];
         std::memset(&P, 0, sizeof(P));
+        if (sort_depths && d.N >= kSortMinNodes) {
+            P.sortB = (int32_t)std::min<int64_t>(1024, (d.N + 4095) / 4096);
+            P.sort_chunk = (d.N + P.sortB - 1) / P.sortB;
+            ws += al256((size_t)d.N * 4) + al256((size_t)(n + 2) * P.sortB * 4);
+        }
         P.T = I->dt;
         P.prefixes = d.prefixes;
         P.depths = d.depths;
@@ -129,6 +134,15 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         c.lds = (size_t)16 * 256 * 4 + (size_t)(nmax + 1) * c.MV * 4;
         pl.classes.push_back(std::move(c));
     }
+    pl.sort.off.assign(1, 0);
+    for (int i = 0; i < n_pools; ++i) {
+        const BatchPool &P = pl.pools[i];
+        if (P.sortB == 0) continue;
+        pl.sort.idx.push_back(i);
+        pl.sort.off.push_back(pl.sort.off.back() + P.sortB);
+        pl.sort.nmax = std::max(pl.sort.nmax, (int)P.T.n);
+    }
+    pl.sort.nblocks = pl.sort.off.back();
     size_t meta = 0;
     pl.meta_pools = meta;
     meta += al256(sizeof(BatchPool) * n_pools);
@@ -142,6 +156,10 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         c.meta_idx = meta;
         meta += al256(sizeof(int32_t) * c.idx.size());
     }
+    pl.sort.meta_off = meta;
+    meta += al256(sizeof(int64_t) * pl.sort.off.size());
+    pl.sort.meta_idx = meta;
+    meta += al256(sizeof(int32_t) * std::max<size_t>(1, pl.sort.idx.size()));
     pl.meta_bytes = meta;
 }
 
@@ -158,6 +176,11 @@ void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host)
         P.W.st = (uint32_t *)(w + a + b);
         P.W.order = nullptr;
         P.W.cnt = nullptr;
+        if (P.sortB > 0) {
+            const size_t c = al256((size_t)P.Npad * 4);
+            P.W.order = (int32_t *)(w + a + b + c);
+            P.W.cnt = (uint32_t *)(w + a + b + c + al256((size_t)P.N * 4));
+        }
     }
     pl.dmeta = base + pl.ws_bytes;
     host.assign(pl.meta_bytes, 0);
@@ -168,11 +191,20 @@ void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host)
         std::memcpy(host.data() + c.meta_off, c.off.data(), sizeof(int64_t) * c.off.size());
         std::memcpy(host.data() + c.meta_idx, c.idx.data(), sizeof(int32_t) * c.idx.size());
     }
+    std::memcpy(host.data() + pl.sort.meta_off, pl.sort.off.data(), sizeof(int64_t) * pl.sort.off.size());
+    if (!pl.sort.idx.empty())
+        std::memcpy(host.data() + pl.sort.meta_idx, pl.sort.idx.data(), sizeof(int32_t) * pl.sort.idx.size());
 }
 
 hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s)
 {
     const BatchPool *dpools = (const BatchPool *)(pl.dmeta + pl.meta_pools);
+    if (!pl.sort.idx.empty()) {
+        hipError_t e = launch_batch_depth_sort(dpools, (const int64_t *)(pl.dmeta + pl.sort.meta_off),
+                                               (const int32_t *)(pl.dmeta + pl.sort.meta_idx),
+                                               (int)pl.sort.idx.size(), pl.sort.nblocks, pl.sort.nmax, s);
+        if (e != hipSuccess) return e;
+    }
     for (const auto &c : pl.classes) {
         hipError_t e = launch_batch_decode(c.MV, dpools, (const int64_t *)(pl.dmeta + c.meta_off),
                                            (const int32_t *)(pl.dmeta + c.meta_idx), (int)c.idx.size(), c.nblocks,
@@ -193,14 +225,14 @@ int batch_grid(int dev, size_t scan_lds)
 
 hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s)
 {
-    plan_batch(pools, n_pools, 0, plan);
+    plan_batch(pools, n_pools, 0, false, plan);  // child pools of a step have few distinct depths
     const size_t need = plan.ws_bytes + plan.meta_bytes;
     if (need > dev_bytes) {
         const size_t cap = std::max(need, dev_bytes * 2);
         if (dev) hipFreeAsync(dev, s);
         dev = nullptr;
         dev_bytes = 0;
-        hipError_t e = hipMallocAsync(&dev, cap, s);
+        hipError_t e = stream_alloc((void **)&dev, cap, s);
         if (e != hipSuccess) return e;
         dev_bytes = cap;
     }
@@ -294,7 +326,7 @@ fsp_status create_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t fla
     if (!g.ok) return FSP_E_DEVICE;
     fsp_batch_s *b = new fsp_batch_s();
     b->device = dev;
-    plan_batch(pools, n_pools, wpg_force, b->plan);
+    plan_batch(pools, n_pools, wpg_force, true, b->plan);
     hipError_t e = hipMalloc(&b->dblob, b->plan.ws_bytes + b->plan.meta_bytes);
     if (e != hipSuccess) { free_batch(b); return fail(e); }
     std::vector<char> meta;

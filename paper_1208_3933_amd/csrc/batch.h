@@ -18,6 +18,7 @@ struct Workspace16 {
 };
 
 constexpr int kBatchWaves = 16;  // waves per workgroup of the persistent scan
+constexpr int64_t kSortMinNodes = 512;  // smaller pools are decoded in pool order
 
 // One pool of a batch.  wpg = waves per 128-node group (divides 16); a work
 // item stages 16 / wpg groups of the pool in LDS at once.
@@ -29,7 +30,8 @@ struct BatchPool {
     int32_t *out_lb;
     int64_t N, Npad;
     int32_t wpg;
-    int32_t reserved;
+    int32_t sortB;        // blocks of the depth sort; 0 = nodes taken in pool order (W.order null)
+    int64_t sort_chunk;   // nodes per depth-sort block
 };
 
 // A work item: ngroups consecutive 128-node groups of one pool.
@@ -37,6 +39,9 @@ struct WorkItem {
     int32_t pool, group0, ngroups, reserved;
 };
 
+// Counting sort of every sorted pool's nodes by depth (W.order), three launches.
+hipError_t launch_batch_depth_sort(const BatchPool *pools, const int64_t *blk_off, const int32_t *sort_pools,
+                                   int nsort, int64_t nblocks, int nmax, hipStream_t s);
 hipError_t launch_batch_decode(int MV, const BatchPool *pools, const int64_t *blk_off, const int32_t *cls_pools,
                                int ncls, int64_t nblocks, size_t lds_bytes, hipStream_t s);
 hipError_t launch_batch_scan(const BatchPool *pools, const WorkItem *items, int n_items, uint32_t *counter,
@@ -68,12 +73,14 @@ struct BatchPlan {
         std::vector<int64_t> off;     // decode block offsets, idx.size() + 1
         int64_t nblocks = 0;
         size_t lds = 0;
+        int nmax = 0;                 // largest n among the pools
         size_t meta_off = 0, meta_idx = 0;
     };
     std::vector<BatchPool> pools;
     std::vector<size_t> ws_off;
     std::vector<WorkItem> items;
     std::vector<Cls> classes;
+    Cls sort;                         // the depth-sorted pools (MV unused); empty = no sort
     size_t scan_lds = 0, ws_bytes = 0, meta_bytes = 0;
     size_t meta_pools = 0, meta_items = 0, meta_counter = 0;
     int64_t total_nodes = 0;
@@ -81,7 +88,9 @@ struct BatchPlan {
 };
 
 fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out);
-void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, BatchPlan &pl);
+// sort_depths: sort each pool's nodes by depth before decoding (fewer
+// divergent prefix loops on pools of mixed depths).
+void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl);
 void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host_meta);
 hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s);
 int batch_grid(int dev, size_t scan_lds);

@@ -84,6 +84,27 @@ __device__ inline void decode_node(const DevTables &T, const int32_t *__restrict
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : (n <= lo ? 0u : ((1u << (n - lo)) - 1u));
         act[w] = ok ? (~bits[w * stride] & valid) : 0u;
     }
+    // heads: with T.heads, each machine's release becomes the earliest start
+    // on it of an unscheduled job scheduled next (the job loop is uniform
+    // across lanes, so the time rows are scalar loads)
+    if (T.heads && ok && d < n) {
+        int32_t h[MV];
+#pragma unroll
+        for (int k = 0; k < MV; ++k) h[k] = 0x7fffffff;
+        for (int j = 0; j < n; ++j) {
+            const bool a = (act[j >> 5] >> (j & 31)) & 1u;
+            cptr<int32_t> pr = as_const(T.p32 + (size_t)j * kMaxMachines);
+            int32_t prev = 0;
+#pragma unroll
+            for (int k = 0; k < MV; ++k) {
+                const int32_t start = max(C[k], prev);
+                h[k] = a ? min(h[k], start) : h[k];
+                prev = start + pr[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MV; ++k) C[k] = h[k];
+    }
     // tails: least remaining time after machine l over the unscheduled jobs
     int32_t q[MV];
 #pragma unroll

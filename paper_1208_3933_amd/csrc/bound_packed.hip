@@ -27,22 +27,22 @@ namespace fspbb {
 
 __device__ __forceinline__ int depth_bucket(int d, int n) { return (d >= 0 && d <= n) ? d : n + 1; }
 
-__global__ __launch_bounds__(256) void depth_count_kernel(const int32_t *__restrict__ depths, int64_t N, int n,
-                                                          int64_t chunk, int B, uint32_t *__restrict__ cnt)
+// Block `blk` of B: histogram of the depths of nodes [blk*chunk, (blk+1)*chunk)
+// into cnt[bucket * B + blk].  h: n + 2 words of LDS.
+__device__ inline void depth_count_block(const int32_t *__restrict__ depths, int64_t N, int n, int64_t chunk, int B,
+                                         uint32_t *__restrict__ cnt, int64_t blk, uint32_t *h)
 {
-    extern __shared__ uint32_t h[];
     for (int b = threadIdx.x; b < n + 2; b += blockDim.x) h[b] = 0;
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(N, lo + chunk);
+    const int64_t lo = blk * chunk, hi = min(N, lo + chunk);
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[depth_bucket(depths[i], n)], 1u);
     __syncthreads();
-    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cnt[(int64_t)b * B + blockIdx.x] = h[b];
+    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cnt[(int64_t)b * B + blk] = h[b];
 }
 
-// Exclusive prefix sum of cnt[0..total) in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void depth_scan_kernel(uint32_t *__restrict__ cnt, int64_t total)
+// Exclusive prefix sum of cnt[0..total) in place, by one block of 1024 threads.
+__device__ inline void depth_scan_block(uint32_t *__restrict__ cnt, int64_t total, uint32_t *part)
 {
-    __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
     const int64_t per = (total + 1023) / 1024, lo = t * per, hi = min(total, lo + per);
     uint32_t sum = 0;
@@ -63,18 +63,39 @@ __global__ __launch_bounds__(1024) void depth_scan_kernel(uint32_t *__restrict__
     }
 }
 
+// Block `blk`: each node goes to the next free position of its depth bucket.
+__device__ inline void depth_scatter_block(const int32_t *__restrict__ depths, int64_t N, int n, int64_t chunk, int B,
+                                           const uint32_t *__restrict__ cnt, int32_t *__restrict__ order, int64_t blk,
+                                           uint32_t *cur)
+{
+    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cur[b] = cnt[(int64_t)b * B + blk];
+    __syncthreads();
+    const int64_t lo = blk * chunk, hi = min(N, lo + chunk);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint32_t pos = atomicAdd(&cur[depth_bucket(depths[i], n)], 1u);
+        order[pos] = (int32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(256) void depth_count_kernel(const int32_t *__restrict__ depths, int64_t N, int n,
+                                                          int64_t chunk, int B, uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t h[];
+    depth_count_block(depths, N, n, chunk, B, cnt, blockIdx.x, h);
+}
+
+__global__ __launch_bounds__(1024) void depth_scan_kernel(uint32_t *__restrict__ cnt, int64_t total)
+{
+    __shared__ uint32_t part[1024];
+    depth_scan_block(cnt, total, part);
+}
+
 __global__ __launch_bounds__(256) void depth_scatter_kernel(const int32_t *__restrict__ depths, int64_t N, int n,
                                                             int64_t chunk, int B, const uint32_t *__restrict__ cnt,
                                                             int32_t *__restrict__ order)
 {
     extern __shared__ uint32_t cur[];
-    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cur[b] = cnt[(int64_t)b * B + blockIdx.x];
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(N, lo + chunk);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint32_t pos = atomicAdd(&cur[depth_bucket(depths[i], n)], 1u);
-        order[pos] = (int32_t)i;
-    }
+    depth_scatter_block(depths, N, n, chunk, B, cnt, order, blockIdx.x, cur);
 }
 
 // ---- decode: one lane per node, nodes taken in depth order
@@ -153,6 +174,33 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
         const int lo = w * 32;
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : (n <= lo ? 0u : ((1u << (n - lo)) - 1u));
         act[w] = ok ? (~mybits[w * 256] & valid) : 0u;
+    }
+    // heads: with T.heads, each machine's release becomes the earliest start
+    // on it of an unscheduled job scheduled next (uniform job loop: the time
+    // rows are LDS broadcasts)
+    if (T.heads && ok && d < n) {
+        int32_t h[MV];
+#pragma unroll
+        for (int k = 0; k < MV; ++k) h[k] = 0x7fffffff;
+        for (int j = 0; j < n; ++j) {
+            const bool a = (act[j >> 5] >> (j & 31)) & 1u;
+            const int4 *pr = reinterpret_cast<const int4 *>(ptab + j * MV);
+            int32_t prev = 0;
+#pragma unroll
+            for (int q = 0; q < MV / 4; ++q) {
+                const int4 v = pr[q];
+                const int32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) {
+                    const int k = 4 * q + cc;
+                    const int32_t start = max(C[k], prev);
+                    h[k] = a ? min(h[k], start) : h[k];
+                    prev = start + x[cc];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MV; ++k) C[k] = h[k];
     }
     // tails, two machines per register: q = min over jobs of (Q | inactive mask)
     uint32_t q2[MV / 2];
@@ -285,21 +333,70 @@ __device__ __forceinline__ S load_uniform(const S *p)
     return out;
 }
 
+// Index of the last pool whose first block is <= blockIdx.x (off has npools + 1 entries).
+__device__ __forceinline__ int pool_of_block(const int64_t *blk_off, int npools)
+{
+    cptr<int64_t> off = as_const(blk_off);
+    int lo = 0, hi = npools - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void batch_depth_count_kernel(const BatchPool *__restrict__ pools,
+                                                                const int64_t *__restrict__ blk_off,
+                                                                const int32_t *__restrict__ sort_pools, int nsort)
+{
+    extern __shared__ uint32_t h[];
+    const int q = pool_of_block(blk_off, nsort);
+    const BatchPool P = load_uniform(pools + as_const(sort_pools)[q]);
+    depth_count_block(P.depths, P.N, P.T.n, P.sort_chunk, P.sortB, P.W.cnt,
+                      (int64_t)blockIdx.x - as_const(blk_off)[q], h);
+}
+
+__global__ __launch_bounds__(1024) void batch_depth_scan_kernel(const BatchPool *__restrict__ pools,
+                                                                const int32_t *__restrict__ sort_pools)
+{
+    __shared__ uint32_t part[1024];
+    const BatchPool P = load_uniform(pools + as_const(sort_pools)[blockIdx.x]);
+    depth_scan_block(P.W.cnt, (int64_t)(P.T.n + 2) * P.sortB, part);
+}
+
+__global__ __launch_bounds__(256) void batch_depth_scatter_kernel(const BatchPool *__restrict__ pools,
+                                                                  const int64_t *__restrict__ blk_off,
+                                                                  const int32_t *__restrict__ sort_pools, int nsort)
+{
+    extern __shared__ uint32_t cur[];
+    const int q = pool_of_block(blk_off, nsort);
+    const BatchPool P = load_uniform(pools + as_const(sort_pools)[q]);
+    depth_scatter_block(P.depths, P.N, P.T.n, P.sort_chunk, P.sortB, P.W.cnt, P.W.order,
+                        (int64_t)blockIdx.x - as_const(blk_off)[q], cur);
+}
+
+hipError_t launch_batch_depth_sort(const BatchPool *pools, const int64_t *blk_off, const int32_t *sort_pools,
+                                   int nsort, int64_t nblocks, int nmax, hipStream_t s)
+{
+    if (nsort <= 0 || nblocks <= 0) return hipSuccess;
+    const size_t hb = (size_t)(nmax + 2) * 4;
+    batch_depth_count_kernel<<<(unsigned)nblocks, 256, hb, s>>>(pools, blk_off, sort_pools, nsort);
+    batch_depth_scan_kernel<<<(unsigned)nsort, 1024, 0, s>>>(pools, sort_pools);
+    batch_depth_scatter_kernel<<<(unsigned)nblocks, 256, hb, s>>>(pools, blk_off, sort_pools, nsort);
+    return hipGetLastError();
+}
+
 template <int MV>
 __global__ __launch_bounds__(256) void batch_decode16_kernel(const BatchPool *__restrict__ pools,
                                                              const int64_t *__restrict__ blk_off,
                                                              const int32_t *__restrict__ cls_pools, int ncls)
 {
     extern __shared__ uint32_t sm[];
-    cptr<int64_t> off = as_const(blk_off);
-    int lo = 0, hi = ncls - 1;  // last class pool whose first block is <= blockIdx.x
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= (int64_t)blockIdx.x) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchPool P = load_uniform(pools + as_const(cls_pools)[lo]);
-    decode16_block<MV>(P.T, P.prefixes, P.depths, P.N, P.Npad, P.W, P.out_lb, (int64_t)blockIdx.x - off[lo], sm);
+    const int q = pool_of_block(blk_off, ncls);
+    const BatchPool P = load_uniform(pools + as_const(cls_pools)[q]);
+    decode16_block<MV>(P.T, P.prefixes, P.depths, P.N, P.Npad, P.W, P.out_lb,
+                       (int64_t)blockIdx.x - as_const(blk_off)[q], sm);
 }
 
 // Persistent scan: each workgroup takes work items from a device counter
@@ -381,8 +478,8 @@ __global__ __launch_bounds__(64 * kBatchWaves) void batch_scan16_kernel(const Ba
             u16x2 best = as16(lds[(wave * wpg) * 64 + lane]);
             for (int w = 1; w < wpg; ++w) best = __builtin_elementwise_max(best, as16(lds[(wave * wpg + w) * 64 + lane]));
             const int64_t a = G * 128 + lane, b = a + 64;
-            if (a < P.N && P.W.st[a]) P.out_lb[a] = (int32_t)best.x;
-            if (b < P.N && P.W.st[b]) P.out_lb[b] = (int32_t)best.y;
+            if (a < P.N && P.W.st[a]) P.out_lb[P.W.order ? P.W.order[a] : a] = (int32_t)best.x;
+            if (b < P.N && P.W.st[b]) P.out_lb[P.W.order ? P.W.order[b] : b] = (int32_t)best.y;
         }
         __syncthreads();
     }
@@ -494,7 +591,7 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
     const size_t dec_b = al((size_t)G * 3 * m * 64 * 4), flg_b = al((size_t)G * NW * 128 * 4),
                  st_b = al((size_t)Npad * 4), ord_b = al((size_t)N * 4), cnt_b = al((size_t)(n + 2) * B * 4);
     void *ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, dec_b + flg_b + st_b + ord_b + cnt_b, s);
+    hipError_t e = stream_alloc((void **)&ws, dec_b + flg_b + st_b + ord_b + cnt_b, s);
     if (e != hipSuccess) return e;
     char *w = (char *)ws;
     Workspace16 W;

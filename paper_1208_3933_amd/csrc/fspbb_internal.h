@@ -38,6 +38,8 @@ struct Rec16 {
 struct DevTables {
     int32_t n, m, P;
     int32_t npad;             // slots per pair in rec16 (n rounded up to 4)
+    int32_t heads;            // 1: releases are the earliest starts of unscheduled jobs
+    int32_t pad0;
     const int32_t *p32;       // (n+1) x 32, zero-padded; row n is zero (PTM)
     const int32_t *colsum32;  // 32: sum over all jobs of p[j][k], zero-padded
     const int32_t *tails32;   // n x 32: Q[j][l] = sum_{h>l} p[j][h], zero-padded
@@ -59,6 +61,7 @@ struct fsp_instance_s {
     int32_t n, m, P;
     int32_t max_value;
     int32_t packed16;
+    int32_t flags;
     int device;
     int64_t table_bytes;
     void *dev_blob;
@@ -78,6 +81,13 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
                                int64_t N, int32_t *out_lb, hipStream_t s);
 
 void set_last_error(hipError_t e);
+
+// Stream-ordered device allocation from a library-owned memory pool of the
+// current device whose release threshold is unbounded: memory freed with
+// hipFreeAsync stays in the pool across stream synchronizations and is
+// reused by later calls instead of going back to the driver.  The pool keeps
+// its peak size until the process ends.
+hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s);
 
 // Records event `which` (0 = start, 1 = after decode, 2 = after scan) of the
 // current launch when timing is on.  which = 0 opens a new record.

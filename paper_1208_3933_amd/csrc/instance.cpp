@@ -71,9 +71,15 @@ const char *fsp_last_error_string(void) { return g_last_error; }
 
 fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_instance *out)
 {
+    return fsp_create_instance_ex(p, n, m, 0, out);
+}
+
+fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_t flags, fsp_instance *out)
+{
     if (!out) return FSP_E_INVAL;
     *out = nullptr;
     if (!p || n < 1 || m < 2 || n > kMaxJobs || m > kMaxMachines) return FSP_E_INVAL;
+    if (flags & ~FSP_INSTANCE_HEADS) return FSP_E_INVAL;
     int64_t pmax = 0;
     for (int64_t i = 0; i < (int64_t)n * m; ++i) {
         if (p[i] < 0) return FSP_E_INVAL;
@@ -171,7 +177,9 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     I->p_host = new int32_t[(size_t)n * m];
     std::memcpy(I->p_host, p, sizeof(int32_t) * (size_t)n * m);
     unsigned char *b = (unsigned char *)d;
+    I->flags = flags;
     I->dt.n = n; I->dt.m = m; I->dt.P = P; I->dt.npad = npad;
+    I->dt.heads = (flags & FSP_INSTANCE_HEADS) ? 1 : 0;
     I->dt.p32 = (const int32_t *)(b + off_p);
     I->dt.colsum32 = (const int32_t *)(b + off_cs);
     I->dt.tails32 = (const int32_t *)(b + off_t);
@@ -202,7 +210,7 @@ fsp_status fsp_get_instance_info(fsp_instance inst, fsp_instance_info *info)
     info->pairs = inst->P;
     info->max_value = inst->max_value;
     info->packed16 = inst->packed16;
-    info->reserved = 0;
+    info->flags = inst->flags;
     info->table_bytes = inst->table_bytes;
     return FSP_OK;
 }

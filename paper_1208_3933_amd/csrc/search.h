@@ -62,10 +62,24 @@ struct Search {
     // NEH or the given upper bound, device state, and the root bound.
     // Synchronous on s.
     hipError_t start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap, int64_t node_budget, hipStream_t s);
+    // The parts of start: everything but the root bound (async on s), and the
+    // state once the root's bound lb0 is known.
+    hipError_t begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap, int64_t node_budget, hipStream_t s);
+    void finish_root(int32_t lb0);
     void release(hipStream_t s);
     size_t device_bytes() const;
     void result(fsp_solve_result *res, int32_t *perm_out) const;
 };
+
+struct StartArgs {
+    fsp_instance_s *inst;
+    int32_t ub0;
+    int64_t pool_cap, node_budget;
+};
+
+// Starts several searches with their root bounds in one merged launch and one
+// copy back (Search::start for each, with one synchronization).
+hipError_t start_many(std::vector<Search *> &ss, const std::vector<StartArgs> &args, TickContext &ctx);
 
 // Advances every search in `active` (not done, same device) by one step.
 // Synchronous on ctx.s.  A search whose step fails gets done = true and a

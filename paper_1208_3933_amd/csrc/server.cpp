@@ -134,31 +134,43 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
     if (!srv || done_cap < 0 || (done_cap > 0 && !done_ids)) return FSP_E_INVAL;
     DeviceGuard g(srv->device);
     if (!g.ok) return FSP_E_DEVICE;
-    hipStream_t s = srv->ctx.s;
     int32_t nd = 0;
     auto report = [&](int64_t id) {
         if (nd < done_cap) done_ids[nd] = id;
         ++nd;
     };
 
-    // admission, first come first served
+    // admission, first come first served; the admitted searches' roots are
+    // bounded together
     size_t used = srv->mem_used();
-    while (!srv->pending.empty() && (int)srv->active.size() < srv->cfg.max_active) {
+    std::vector<std::unique_ptr<Job>> admit;
+    while (!srv->pending.empty() && srv->active.size() + admit.size() < (size_t)srv->cfg.max_active) {
         Job &j = *srv->pending.front();
-        if (used + j.est > (size_t)srv->cfg.mem_budget_bytes && !srv->active.empty()) break;
-        std::unique_ptr<Job> jp = std::move(srv->pending.front());
+        const bool first = srv->active.empty() && admit.empty();
+        if (used + j.est > (size_t)srv->cfg.mem_budget_bytes && !first) break;
+        used += j.est;
+        admit.push_back(std::move(srv->pending.front()));
         srv->pending.pop_front();
-        jp->S = std::make_unique<Search>();
-        hipError_t e = jp->S->start(jp->inst, jp->ub0, jp->pool_cap, jp->node_budget, s);
-        if (e != hipSuccess || jp->S->done) {
-            srv->finish(*jp, e != hipSuccess ? fail_status(e) : jp->S->status);
-            srv->st.nodes_bounded += jp->S->nodes;
-            report(jp->id);
-            continue;
+    }
+    if (!admit.empty()) {
+        std::vector<Search *> ss;
+        std::vector<StartArgs> args;
+        for (auto &jp : admit) {
+            jp->S = std::make_unique<Search>();
+            ss.push_back(jp->S.get());
+            args.push_back(StartArgs{jp->inst, jp->ub0, jp->pool_cap, jp->node_budget});
         }
-        srv->st.nodes_bounded += jp->S->nodes;
-        used += jp->S->device_bytes();
-        srv->active.push_back(std::move(jp));
+        hipError_t e = start_many(ss, args, srv->ctx);
+        for (auto &jp : admit) {
+            if (e != hipSuccess || jp->S->done) {
+                srv->finish(*jp, e != hipSuccess ? fail_status(e) : jp->S->status);
+                if (e == hipSuccess) srv->st.nodes_bounded += jp->S->nodes;
+                report(jp->id);
+                continue;
+            }
+            srv->st.nodes_bounded += jp->S->nodes;
+            srv->active.push_back(std::move(jp));
+        }
     }
 
     // the searches of this step: all, or those that waited longest up to the cap

@@ -35,7 +35,7 @@ hipError_t StepBuffers::ensure_k(int64_t K, hipStream_t s)
     kblob = nullptr;
     Kcap = std::max<int64_t>(K, 1);
     const size_t kb = al256((size_t)Kcap * 4), sb = al256(scan_scratch_bytes(Kcap));
-    hipError_t e = hipMallocAsync(&kblob, 2 * kb + sb + 5 * 64, s);
+    hipError_t e = stream_alloc((void **)&kblob, 2 * kb + sb + 5 * 64, s);
     if (e != hipSuccess) { kblob = nullptr; Kcap = 0; return e; }
     char *p = (char *)kblob;
     w.cnt = (uint32_t *)p; p += kb;
@@ -58,7 +58,7 @@ hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
     n = n_;
     const size_t cb = al256((size_t)Ccap * 4), rows = al256((size_t)Ccap * n * 4);
     const size_t sb = al256(scan_scratch_bytes(Ccap));
-    hipError_t e = hipMallocAsync(&cblob, 6 * cb + rows + sb, s);
+    hipError_t e = stream_alloc((void **)&cblob, 6 * cb + rows + sb, s);
     if (e != hipSuccess) { cblob = nullptr; Ccap = 0; return e; }
     char *p = (char *)cblob;
     w.ujob = (int32_t *)p; p += cb;
@@ -93,7 +93,7 @@ hipError_t TickContext::reserve(size_t bytes)
         dtab = nullptr;
         dcap = 0;
         const size_t c = std::max(bytes, (size_t)64 * 1024);
-        hipError_t e = hipMallocAsync(&dtab, c, s);
+        hipError_t e = stream_alloc((void **)&dtab, c, s);
         if (e != hipSuccess) return e;
         dcap = c;
     }
@@ -185,7 +185,7 @@ static hipError_t bound_rows(fsp_instance_s *I, const int32_t *rows, const int32
                        : launch_bound_lane32(I, rows, depths, N, lb, s);
 }
 
-hipError_t Search::start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in, int64_t node_budget_in,
+hipError_t Search::begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in, int64_t node_budget_in,
                          hipStream_t s)
 {
     inst = I;
@@ -196,20 +196,20 @@ hipError_t Search::start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in,
     UB = ub0_in == FSP_UB_NEH ? neh(I->p_host, n, I->m, inc.data()) : ub0_in;
     ub0 = UB;
     cap_stack = std::max<int64_t>(1024, 2 * pool_cap);
-    hipError_t e = hipMallocAsync((void **)&srows, (size_t)cap_stack * n * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&sdep, (size_t)cap_stack * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&dsurv, (size_t)pool_cap * 4, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&dinc, (size_t)n * 4, s);
+    hipError_t e = stream_alloc((void **)&srows, (size_t)cap_stack * n * 4, s);
+    if (e == hipSuccess) e = stream_alloc((void **)&sdep, (size_t)cap_stack * 4, s);
+    if (e == hipSuccess) e = stream_alloc((void **)&dsurv, (size_t)pool_cap * 4, s);
+    if (e == hipSuccess) e = stream_alloc((void **)&dinc, (size_t)n * 4, s);
     if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
     if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
-    // the root: an all-zero row of depth 0, bounded into the child bounds
+    // the root: an all-zero row of depth 0 at the bottom of the stack
     if (e == hipSuccess) e = hipMemsetAsync(srows, 0, (size_t)n * 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(sdep, 0, 4, s);
-    if (e == hipSuccess) e = bound_rows(I, srows, sdep, 1, B.w.clb, s);
-    int32_t lb0 = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&lb0, B.w.clb, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
+    return e;
+}
+
+void Search::finish_root(int32_t lb0)
+{
     nodes = 1;
     if (lb0 < UB) {
         top = 1;
@@ -218,6 +218,58 @@ hipError_t Search::start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in,
     }
     done = top == 0 || nodes >= node_budget;
     status = top == 0 ? FSP_OK : (done ? FSP_BUDGET : FSP_OK);
+}
+
+hipError_t Search::start(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in, int64_t node_budget_in,
+                         hipStream_t s)
+{
+    hipError_t e = begin(I, ub0_in, pool_cap_in, node_budget_in, s);
+    if (e == hipSuccess) e = bound_rows(I, srows, sdep, 1, B.w.clb, s);
+    int32_t lb0 = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&lb0, B.w.clb, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    finish_root(lb0);
+    return hipSuccess;
+}
+
+hipError_t start_many(std::vector<Search *> &ss, const std::vector<StartArgs> &args, TickContext &ctx)
+{
+    hipStream_t s = ctx.s;
+    const size_t R = ss.size();
+    if (R == 0) return hipSuccess;
+    for (size_t i = 0; i < R; ++i) {
+        hipError_t e = ss[i]->begin(args[i].inst, args[i].ub0, args[i].pool_cap, args[i].node_budget, s);
+        if (e != hipSuccess) return e;
+    }
+    if (R == 1) {
+        Search &S = *ss[0];
+        hipError_t e = bound_rows(S.inst, S.srows, S.sdep, 1, S.B.w.clb, s);
+        int32_t lb0 = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&lb0, S.B.w.clb, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        S.finish_root(lb0);
+        return hipSuccess;
+    }
+    // every root bounded into one contiguous array: one merged launch, one copy back
+    const size_t bytes = al256(R * 4);
+    hipError_t e = ctx.reserve(bytes);
+    if (e != hipSuccess) return e;
+    int32_t *dlb = (int32_t *)ctx.dtab;
+    std::vector<fsp_pool_desc> descs;
+    for (size_t i = 0; i < R; ++i) {
+        Search &S = *ss[i];
+        if (S.inst->packed16)
+            descs.push_back(fsp_pool_desc{S.inst, S.srows, S.sdep, 1, dlb + i});
+        else if (e == hipSuccess)
+            e = bound_rows(S.inst, S.srows, S.sdep, 1, dlb + i, s);
+    }
+    if (e == hipSuccess && !descs.empty()) e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx.htab, dlb, R * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < R; ++i) ss[i]->finish_root(((const int32_t *)ctx.htab)[i]);
     return hipSuccess;
 }
 
@@ -276,8 +328,8 @@ static hipError_t prepare_step(Search &S, hipStream_t s)
         int64_t nc = S.cap_stack;
         while (S.base + nch > nc) nc *= 2;
         int32_t *r2 = nullptr, *d2 = nullptr;
-        hipError_t e = hipMallocAsync((void **)&r2, (size_t)nc * S.n * 4, s);
-        if (e == hipSuccess) e = hipMallocAsync((void **)&d2, (size_t)nc * 4, s);
+        hipError_t e = stream_alloc((void **)&r2, (size_t)nc * S.n * 4, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&d2, (size_t)nc * 4, s);
         if (e == hipSuccess) e = hipMemcpyAsync(r2, S.srows, (size_t)S.top * S.n * 4, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(d2, S.sdep, (size_t)S.top * 4, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) {

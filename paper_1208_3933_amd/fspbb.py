@@ -28,6 +28,8 @@ BUDGET = 1
 PENDING = 2
 LB_INVALID = -1
 
+INSTANCE_HEADS = 1
+
 UB_NEH = -1
 UB_NONE = 0x7FFFFFFF
 
@@ -48,7 +50,7 @@ class FspError(RuntimeError):
 class InstanceInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("pairs", ctypes.c_int32),
                 ("max_value", ctypes.c_int32), ("packed16", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("table_bytes", ctypes.c_int64)]
+                ("flags", ctypes.c_int32), ("table_bytes", ctypes.c_int64)]
 
 
 class StepResult(ctypes.Structure):
@@ -90,6 +92,8 @@ _SIGNATURES = {
     "fsp_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "fsp_last_error_string": (ctypes.c_char_p, []),
     "fsp_create_instance": (ctypes.c_int32, [_i32p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "fsp_create_instance_ex": (ctypes.c_int32, [_i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(_vp)]),
     "fsp_destroy_instance": (ctypes.c_int32, [_vp]),
     "fsp_get_instance_info": (ctypes.c_int32, [_vp, ctypes.POINTER(InstanceInfo)]),
     "fsp_bound_pool": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
@@ -176,14 +180,18 @@ def _dev_i32(t, name, shape=None):
 class Instance:
     """An instance created by fsp_create_instance (owns the device tables)."""
 
-    def __init__(self, p):
+    def __init__(self, p, heads: bool = False):
         p = np.ascontiguousarray(p, dtype=np.int32)
         if p.ndim != 2:
             raise ValueError("p must be an n x m matrix")
         self.n, self.m = int(p.shape[0]), int(p.shape[1])
         h = _vp()
-        _check(lib().fsp_create_instance(p.ctypes.data_as(_i32p), self.n, self.m, ctypes.byref(h)),
-               "fsp_create_instance")
+        if heads:
+            st = lib().fsp_create_instance_ex(p.ctypes.data_as(_i32p), self.n, self.m, INSTANCE_HEADS,
+                                              ctypes.byref(h))
+        else:
+            st = lib().fsp_create_instance(p.ctypes.data_as(_i32p), self.n, self.m, ctypes.byref(h))
+        _check(st, "fsp_create_instance")
         self._h = h
 
     @property
@@ -213,8 +221,9 @@ class Instance:
         self.close()
 
 
-def create_instance(p) -> Instance:
-    return Instance(p)
+def create_instance(p, heads: bool = False) -> Instance:
+    """heads: releases as the earliest starts of unscheduled jobs (FSP_INSTANCE_HEADS)."""
+    return Instance(p, heads)
 
 
 def destroy_instance(inst: Instance) -> None:

@@ -24,7 +24,7 @@ def make_batch(torch, n_pools, sizes, config=3, invalid_in=None, shapes=SHAPES):
         inst, p = insts[key]
         N = int(sizes[i])
         pre, dep = gen.random_pool(n, N, gen.make_seed(config, 100 + i, gen.PURPOSE_POOL))
-        if invalid_in is not None and i == invalid_in and N > 3:
+        if invalid_in is not None and i in invalid_in and N > 3:
             dep = dep.copy()
             dep[1] = n + 5
         pre_d, dep_d = to_dev(torch, pre, dep)
@@ -50,7 +50,8 @@ def plain_bounds(torch, pools):
 def test_mixed_batch_matches_plain_and_oracle(graph):
     torch = require_gpu()
     sizes = [300, 1000, 129, 0, 2048, 700, 128, 4000, 64, 513, 1, 3000]
-    pools, host, insts = make_batch(torch, len(sizes), sizes, invalid_in=2)
+    # invalid nodes in a pool decoded in depth order (1000 nodes) and in one decoded in pool order (129)
+    pools, host, insts = make_batch(torch, len(sizes), sizes, invalid_in=(1, 2))
     want_plain = plain_bounds(torch, pools)
     with fspbb.batch_create(pools, graph=graph) as b:
         assert b.info()["total_nodes"] == sum(sizes)
