@@ -42,6 +42,31 @@ CONFIG = 2
 PEAK_U16_OPS = 256 * 4 * 16 * 2 * 2.4e9
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scan16_200x20_pool262144_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per scan launch from the committed counter passes, or None
+    when the kernel sources have changed since they were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+    files = [line for line in text.splitlines() if line.startswith("(SHA-256 of the concatenated files ")]
+    if len(fields) != 2 or not files:
+        return None
+    names = files[0].split("files ", 1)[1].split(";")[0].split(", ")
+    h = hashlib.sha256()
+    for name in names:
+        h.update(open(os.path.join(ROOT, "paper_1208_3933_amd", "csrc", name.strip()), "rb").read())
+    if h.hexdigest() != fields["source_sha256"].strip():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def algorithmic_scan_ops(n: int, m: int, depths: np.ndarray) -> float:
     """Integer ops of the pair scans of one pool, counted as in Table I / Fig. 2:
     per node and pair, n membership tests, 4 ops per unscheduled job (two
@@ -310,7 +335,7 @@ def main() -> int:
                                "pool of 262144 nodes, depths U{0..199}",
                    "n": N_JOBS, "m": N_MACH, "pool": POOL, "kernel": "decode16 + scan16 (8 waves/group)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
                      "kernel": "bound_scan16_kernel", "kernel_avg_ms": scan_avg_s * 1e3,
                      "decode_avg_ms": dec_ms / max(launches, 1)},
         "plain_nodes_per_s": value,
