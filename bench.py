@@ -127,7 +127,8 @@ def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
         nodes = info["total_nodes"]
         out[name] = {"pools": len(pools), "nodes": nodes, "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3,
                      "plain_nodes_per_s": nodes / t_plain, "batched_nodes_per_s": nodes / t_batch,
-                     "speedup": t_plain / t_batch, "identical": same, "graph_items": info["items"]}
+                     "speedup": t_plain / t_batch, "identical": same, "work_items": info["items"],
+                     "scan_workgroups": info["grid"]}
 
     # the 200 x 20 pool as 64 pools of 4096 nodes
     N = int(dep_d.shape[0])

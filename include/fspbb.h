@@ -178,7 +178,8 @@ fsp_status fsp_batch_run(fsp_batch b, void *stream);
 /* fsp_batch_destroy - synchronise the device and free the batch. */
 fsp_status fsp_batch_destroy(fsp_batch b);
 
-/* Total nodes, work items and persistent workgroups of a batch. */
+/* Total nodes, work items and scan workgroups of a batch (the grid of a
+ * persistent launch, else one per work item). */
 fsp_status fsp_batch_info(fsp_batch b, int64_t *total_nodes, int32_t *n_items, int32_t *grid);
 
 /* fsp_bound_pools_batched - one-shot: create (without graph), run, wait, destroy. */
@@ -186,20 +187,30 @@ fsp_status fsp_bound_pools_batched(const fsp_pool_desc *pools, int32_t n_pools, 
 
 /* ---- tile-schedule tuning ------------------------------------------------ */
 
+/* Launch forms of the batched scan: persistent workgroups (CUs x occupancy)
+ * taking work items from a device counter, or one workgroup per work item
+ * dispatched by the hardware in item order (longest first). */
+#define FSP_FORM_PERSISTENT 0
+#define FSP_FORM_GRID 1
+
 typedef struct {
     int32_t waves_per_group;  /* chosen schedule: waves per 128-node group */
     int32_t candidates;       /* schedules measured */
     double best_us;           /* device time of one batch run of the sample, chosen schedule */
     double default_us;        /* same for the rule-of-thumb schedule */
     int32_t cand_wpg[8];
-    double cand_us[8];
+    double cand_us[8];        /* per waves-per-group candidate, in the one-per-item form */
+    int32_t form;             /* chosen launch form for the chosen schedule */
+    int32_t reserved;
+    double grid_us, persistent_us;  /* the chosen schedule in each launch form */
 } fsp_tune_result;
 
 /*
  * fsp_autotune - time every scan tile schedule for this instance's shape (n,
- * m) on a seeded sample pool of sample_nodes nodes (best of reps runs each)
- * and store the fastest in the process-wide tuning table, which
- * fsp_bound_pool and fsp_batch_create consult.  The pool size used by the
+ * m) on a seeded sample pool of sample_nodes nodes (best of reps runs each),
+ * then the fastest in both launch forms, and store the result in the
+ * process-wide tuning table, which fsp_bound_pool and fsp_batch_create
+ * consult (a batch runs persistent only when every pool's shape prefers it).  The pool size used by the
  * paper was chosen the same way, by trying sizes at run time (Sec. IV-A).
  * Synchronous; allocates and frees its own sample buffers.  16-bit path only.
  */
@@ -208,6 +219,10 @@ fsp_status fsp_autotune(fsp_instance inst, int64_t sample_nodes, int32_t reps, f
  * of thumb), explicit setting (1, 2, 4, 8 or 16), save/load as text. */
 fsp_status fsp_tune_get(int32_t n, int32_t m, int32_t *waves_per_group, int32_t *tuned);
 fsp_status fsp_tune_set(int32_t n, int32_t m, int32_t waves_per_group);
+/* Launch form preferred for a shape (FSP_FORM_GRID unless tuned or set). */
+fsp_status fsp_tune_get_form(int32_t n, int32_t m, int32_t *form);
+fsp_status fsp_tune_set_form(int32_t n, int32_t m, int32_t form);
+/* The table as text, one "n m waves_per_group form" line per shape. */
 fsp_status fsp_tune_save(const char *path);
 fsp_status fsp_tune_load(const char *path);
 

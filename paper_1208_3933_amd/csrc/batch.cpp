@@ -38,7 +38,7 @@ ScanTuning scan_tuning(int n, int m)
     const int P = m * (m - 1) / 2;
     int w = 1;
     while (w < kBatchWaves && 4 * 2 * w <= P) w *= 2;
-    return ScanTuning{w, 8};
+    return ScanTuning{w, 8, kBatchGrid};
 }
 
 void set_scan_tuning(int n, int m, ScanTuning t)
@@ -73,7 +73,8 @@ fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out
     return FSP_OK;
 }
 
-void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl)
+void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl,
+                int32_t form_force)
 {
     pl = BatchPlan{};
     pl.pools.resize(n_pools);
@@ -112,6 +113,11 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         if (G > 0) pl.scan_lds = std::max(pl.scan_lds, (size_t)std::min<int64_t>(gpp, G) * (n + 1) * 256);
         pl.total_nodes += d.N;
     }
+    bool all_persistent = true;
+    for (int i = 0; i < n_pools; ++i)
+        if (pools[i].N > 0 && scan_tuning(pools[i].inst->n, pools[i].inst->m).form != kBatchPersistent)
+            all_persistent = false;
+    pl.form = form_force >= 0 ? form_force : (all_persistent ? kBatchPersistent : kBatchGrid);
     std::stable_sort(items.begin(), items.end(), [](const Cost &x, const Cost &y) { return x.cost > y.cost; });
     for (auto &c : items) pl.items.push_back(c.w);
     pl.ws_bytes = al256(ws);
@@ -213,7 +219,7 @@ hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s)
     }
     if (pl.items.empty()) return hipSuccess;
     return launch_batch_scan(dpools, (const WorkItem *)(pl.dmeta + pl.meta_items), (int)pl.items.size(),
-                             (uint32_t *)(pl.dmeta + pl.meta_counter), grid, pl.scan_lds, s);
+                             (uint32_t *)(pl.dmeta + pl.meta_counter), grid, pl.scan_lds, pl.form, s);
 }
 
 int batch_grid(int dev, size_t scan_lds)
@@ -251,7 +257,7 @@ hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStrea
     int d = 0;
     e = hipGetDevice(&d);
     if (e != hipSuccess) return e;
-    return enqueue_batch(plan, batch_grid(d, plan.scan_lds), s);
+    return enqueue_batch(plan, plan.form == kBatchPersistent ? batch_grid(d, plan.scan_lds) : 0, s);
 }
 
 void BatchArena::release(hipStream_t s)
@@ -315,7 +321,7 @@ namespace fspbb {
 
 // fsp_batch_create with an optional forced waves-per-group (0 = tuned).
 fsp_status create_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, int32_t wpg_force,
-                        fsp_batch *out)
+                        int32_t form_force, fsp_batch *out)
 {
     if (!out) return FSP_E_INVAL;
     *out = nullptr;
@@ -326,14 +332,14 @@ fsp_status create_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t fla
     if (!g.ok) return FSP_E_DEVICE;
     fsp_batch_s *b = new fsp_batch_s();
     b->device = dev;
-    plan_batch(pools, n_pools, wpg_force, true, b->plan);
+    plan_batch(pools, n_pools, wpg_force, true, b->plan, form_force);
     hipError_t e = hipMalloc(&b->dblob, b->plan.ws_bytes + b->plan.meta_bytes);
     if (e != hipSuccess) { free_batch(b); return fail(e); }
     std::vector<char> meta;
     layout_batch(b->plan, (char *)b->dblob, meta);
     e = hipMemcpy(b->plan.dmeta, meta.data(), meta.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { free_batch(b); return fail(e); }
-    b->grid = batch_grid(dev, b->plan.scan_lds);
+    b->grid = b->plan.form == kBatchPersistent ? batch_grid(dev, b->plan.scan_lds) : (int)b->plan.items.size();
     if (flags & FSP_BATCH_GRAPH) {
         hipStream_t cs;
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -359,7 +365,7 @@ extern "C" {
 
 fsp_status fsp_batch_create(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, fsp_batch *out)
 {
-    return create_batch(pools, n_pools, flags, 0, out);
+    return create_batch(pools, n_pools, flags, 0, -1, out);
 }
 
 fsp_status fsp_batch_run(fsp_batch b, void *stream)

@@ -44,8 +44,11 @@ hipError_t launch_batch_depth_sort(const BatchPool *pools, const int64_t *blk_of
                                    int nsort, int64_t nblocks, int nmax, hipStream_t s);
 hipError_t launch_batch_decode(int MV, const BatchPool *pools, const int64_t *blk_off, const int32_t *cls_pools,
                                int ncls, int64_t nblocks, size_t lds_bytes, hipStream_t s);
+// Launch form of the batched scan: persistent workgroups fed by a counter
+// (grid = CUs x occupancy), or one workgroup per work item.
+constexpr int kBatchPersistent = FSP_FORM_PERSISTENT, kBatchGrid = FSP_FORM_GRID;
 hipError_t launch_batch_scan(const BatchPool *pools, const WorkItem *items, int n_items, uint32_t *counter,
-                             int grid, size_t lds_bytes, hipStream_t s);
+                             int grid, size_t lds_bytes, int form, hipStream_t s);
 int batch_scan_blocks_per_cu(size_t lds_bytes);
 
 // Tile schedule of the scan for an instance shape: waves per group and slots
@@ -53,14 +56,17 @@ int batch_scan_blocks_per_cu(size_t lds_bytes);
 struct ScanTuning {
     int waves_per_group;
     int unroll;
+    int form;  // batched-scan launch form preferred for the shape
 };
 ScanTuning scan_tuning(int n, int m);
 void set_scan_tuning(int n, int m, ScanTuning t);
 bool has_scan_tuning(int n, int m);
 void scan_tuning_entries(std::vector<std::pair<std::pair<int, int>, ScanTuning>> &out);
 
+// fsp_batch_create with a forced waves-per-group (0 = tuned) and launch form
+// (-1 = from the tuning table).
 fsp_status create_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t flags, int32_t wpg_force,
-                        fsp_batch *out);
+                        int32_t form_force, fsp_batch *out);
 
 // Launch plan of a batch: pool records, LPT-ordered work items, decode
 // classes (pools grouped by machine count rounded up to 4), and the layout
@@ -82,6 +88,7 @@ struct BatchPlan {
     std::vector<Cls> classes;
     Cls sort;                         // the depth-sorted pools (MV unused); empty = no sort
     size_t scan_lds = 0, ws_bytes = 0, meta_bytes = 0;
+    int form = kBatchGrid;
     size_t meta_pools = 0, meta_items = 0, meta_counter = 0;
     int64_t total_nodes = 0;
     char *dmeta = nullptr;            // device address of the metadata once laid out
@@ -90,7 +97,10 @@ struct BatchPlan {
 fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out);
 // sort_depths: sort each pool's nodes by depth before decoding (fewer
 // divergent prefix loops on pools of mixed depths).
-void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl);
+// form: the launch form: persistent when every pool's shape prefers it, else
+// one workgroup per item; form_force >= 0 overrides.
+void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl,
+                int32_t form_force = -1);
 void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host_meta);
 hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s);
 int batch_grid(int dev, size_t scan_lds);

@@ -399,90 +399,117 @@ __global__ __launch_bounds__(256) void batch_decode16_kernel(const BatchPool *__
                        (int64_t)blockIdx.x - as_const(blk_off)[q], sm);
 }
 
-// Persistent scan: each workgroup takes work items from a device counter
-// until none is left.  An item stages the masks of up to 16 / wpg groups of one
-// pool in LDS; wpg waves scan the machine pairs of each group (two chains per
-// wave), then one wave per group takes the maximum over its waves.
+// One work item of a batched scan: the masks of up to 16 / wpg groups of one
+// pool are staged in LDS; wpg waves scan the machine pairs of each group (two
+// chains per wave), then one wave per group takes the maximum over its waves.
+// Every thread of the workgroup calls it; it ends with the workgroup past the
+// reduction, LDS free for the next item.  before_reduce runs on thread 0 just
+// before the final reduction (it may start a memory operation whose result is
+// read after the item).
+template <int UNR, class F>
+__device__ inline void batch_scan_item(const BatchPool *__restrict__ pools, const WorkItem *__restrict__ items,
+                                       int it, uint32_t *lds, uint32_t lds0, int lane, int wave, F before_reduce)
+{
+    const WorkItem wi = load_uniform(items + it);
+    const BatchPool P = load_uniform(pools + wi.pool);
+    const int n = P.T.n, m = P.T.m, NW = (n + 31) >> 5, np1 = n + 1;
+    const int wpg = P.wpg;
+    for (int r = wave; r < wi.ngroups * np1; r += kBatchWaves) {
+        const int gi = r / np1, j = r - gi * np1;
+        uint32_t m2 = 0;
+        if (j < n) {
+            const uint32_t *fw = P.W.flg + ((int64_t)(wi.group0 + gi) * NW + (j >> 5)) * 128;
+            const uint32_t a = (fw[lane] >> (j & 31)) & 1u, b = (fw[64 + lane] >> (j & 31)) & 1u;
+            m2 = (a ? 0x0000ffffu : 0u) | (b ? 0xffff0000u : 0u);
+        }
+        lds[(gi * np1 + j) * 64 + lane] = m2;
+    }
+    __syncthreads();
+    const int gi = wave / wpg, sw = wave - gi * wpg;
+    u16x2 lb = {0, 0};
+    if (gi < wi.ngroups) {
+        const int64_t G = wi.group0 + gi;
+        const uint32_t gbase = lds0 + (uint32_t)(gi * np1) * 256u;
+        const unsigned char *lds_lane =
+            reinterpret_cast<const unsigned char *>(lds) + (size_t)gi * np1 * 256 + lane * 4;
+        const uint32_t *dR = P.W.dec + (G * 3 + 0) * m * 64 + lane;
+        const uint32_t *dT = dR + m * 64;
+        const uint32_t *dQ = dT + m * 64;
+        cptr<int32_t> pairs = as_const(P.T.pairs);
+        int pr = sw;
+        for (; pr + wpg < P.T.P; pr += 2 * wpg) {
+            int prs[2] = {pr, pr + wpg};
+            u16x2 sv[2];
+            uint32_t tk[2], ql[2];
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                const int k = pairs[2 * prs[ch]], l = pairs[2 * prs[ch] + 1];
+                sv[ch] = as16(dR[l * 64]) - as16(dR[k * 64]);
+                tk[ch] = dT[k * 64];
+                ql[ch] = dQ[l * 64];
+            }
+            scan_pairs<UNR, 2, true>(P.T, prs, sv, lds_lane, gbase);
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) lb = __builtin_elementwise_max(lb, as16(tk[ch]) + sv[ch] + as16(ql[ch]));
+        }
+        for (; pr < P.T.P; pr += wpg) {
+            const int prs[1] = {pr};
+            const int k = pairs[2 * pr], l = pairs[2 * pr + 1];
+            u16x2 sv[1] = {as16(dR[l * 64]) - as16(dR[k * 64])};
+            const uint32_t tk = dT[k * 64], ql = dQ[l * 64];
+            scan_pairs<UNR, 1, true>(P.T, prs, sv, lds_lane, gbase);
+            lb = __builtin_elementwise_max(lb, as16(tk) + sv[0] + as16(ql));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) before_reduce();
+    lds[wave * 64 + lane] = as32(lb);
+    __syncthreads();
+    if (wave < wi.ngroups) {
+        const int64_t G = wi.group0 + wave;
+        u16x2 best = as16(lds[(wave * wpg) * 64 + lane]);
+        for (int w = 1; w < wpg; ++w) best = __builtin_elementwise_max(best, as16(lds[(wave * wpg + w) * 64 + lane]));
+        const int64_t a = G * 128 + lane, b = a + 64;
+        if (a < P.N && P.W.st[a]) P.out_lb[P.W.order ? P.W.order[a] : a] = (int32_t)best.x;
+        if (b < P.N && P.W.st[b]) P.out_lb[P.W.order ? P.W.order[b] : b] = (int32_t)best.y;
+    }
+    __syncthreads();
+}
+
+// Persistent scan: gridDim.x workgroups; workgroup b takes item b, then items
+// from a device counter (offset by the grid) until none is left.  The next
+// index is fetched during the current item's reduction.
 template <int UNR>
 __global__ __launch_bounds__(64 * kBatchWaves) void batch_scan16_kernel(const BatchPool *__restrict__ pools,
                                                                        const WorkItem *__restrict__ items,
                                                                        int n_items, uint32_t *__restrict__ counter)
 {
     extern __shared__ uint32_t lds[];
-    __shared__ int s_item;
+    __shared__ int s_next;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
         (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t *)lds);
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
-        if (it >= n_items) break;  // the counter only grows: every wave leaves
-        const WorkItem wi = load_uniform(items + it);
-        const BatchPool P = load_uniform(pools + wi.pool);
-        const int n = P.T.n, m = P.T.m, NW = (n + 31) >> 5, np1 = n + 1;
-        const int wpg = P.wpg;
-        for (int r = wave; r < wi.ngroups * np1; r += kBatchWaves) {
-            const int gi = r / np1, j = r - gi * np1;
-            uint32_t m2 = 0;
-            if (j < n) {
-                const uint32_t *fw = P.W.flg + ((int64_t)(wi.group0 + gi) * NW + (j >> 5)) * 128;
-                const uint32_t a = (fw[lane] >> (j & 31)) & 1u, b = (fw[64 + lane] >> (j & 31)) & 1u;
-                m2 = (a ? 0x0000ffffu : 0u) | (b ? 0xffff0000u : 0u);
-            }
-            lds[(gi * np1 + j) * 64 + lane] = m2;
-        }
-        __syncthreads();
-        const int gi = wave / wpg, sw = wave - gi * wpg;
-        u16x2 lb = {0, 0};
-        if (gi < wi.ngroups) {
-            const int64_t G = wi.group0 + gi;
-            const uint32_t gbase = lds0 + (uint32_t)(gi * np1) * 256u;
-            const unsigned char *lds_lane =
-                reinterpret_cast<const unsigned char *>(lds) + (size_t)gi * np1 * 256 + lane * 4;
-            const uint32_t *dR = P.W.dec + (G * 3 + 0) * m * 64 + lane;
-            const uint32_t *dT = dR + m * 64;
-            const uint32_t *dQ = dT + m * 64;
-            cptr<int32_t> pairs = as_const(P.T.pairs);
-            int pr = sw;
-            for (; pr + wpg < P.T.P; pr += 2 * wpg) {
-                int prs[2] = {pr, pr + wpg};
-                u16x2 sv[2];
-                uint32_t tk[2], ql[2];
-#pragma unroll
-                for (int ch = 0; ch < 2; ++ch) {
-                    const int k = pairs[2 * prs[ch]], l = pairs[2 * prs[ch] + 1];
-                    sv[ch] = as16(dR[l * 64]) - as16(dR[k * 64]);
-                    tk[ch] = dT[k * 64];
-                    ql[ch] = dQ[l * 64];
-                }
-                scan_pairs<UNR, 2, true>(P.T, prs, sv, lds_lane, gbase);
-#pragma unroll
-                for (int ch = 0; ch < 2; ++ch) lb = __builtin_elementwise_max(lb, as16(tk[ch]) + sv[ch] + as16(ql[ch]));
-            }
-            for (; pr < P.T.P; pr += wpg) {
-                const int prs[1] = {pr};
-                const int k = pairs[2 * pr], l = pairs[2 * pr + 1];
-                u16x2 sv[1] = {as16(dR[l * 64]) - as16(dR[k * 64])};
-                const uint32_t tk = dT[k * 64], ql = dQ[l * 64];
-                scan_pairs<UNR, 1, true>(P.T, prs, sv, lds_lane, gbase);
-                lb = __builtin_elementwise_max(lb, as16(tk) + sv[0] + as16(ql));
-            }
-        }
-        __syncthreads();
-        lds[wave * 64 + lane] = as32(lb);
-        __syncthreads();
-        if (wave < wi.ngroups) {
-            const int64_t G = wi.group0 + wave;
-            u16x2 best = as16(lds[(wave * wpg) * 64 + lane]);
-            for (int w = 1; w < wpg; ++w) best = __builtin_elementwise_max(best, as16(lds[(wave * wpg + w) * 64 + lane]));
-            const int64_t a = G * 128 + lane, b = a + 64;
-            if (a < P.N && P.W.st[a]) P.out_lb[P.W.order ? P.W.order[a] : a] = (int32_t)best.x;
-            if (b < P.N && P.W.st[b]) P.out_lb[P.W.order ? P.W.order[b] : b] = (int32_t)best.y;
-        }
-        __syncthreads();
+    int it = blockIdx.x;
+    while (it < n_items) {  // uniform: every wave leaves together (the counter only grows)
+        batch_scan_item<UNR>(pools, items, it, lds, lds0, lane, wave,
+                             [&]() { s_next = (int)gridDim.x + (int)atomicAdd(counter, 1u); });
+        it = __builtin_amdgcn_readfirstlane(s_next);
     }
+}
+
+// One workgroup per work item (the hardware dispatches them in item order,
+// longest first).
+template <int UNR>
+__global__ __launch_bounds__(64 * kBatchWaves) void batch_scan16_grid_kernel(const BatchPool *__restrict__ pools,
+                                                                            const WorkItem *__restrict__ items)
+{
+    extern __shared__ uint32_t lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lds0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t *)lds);
+    batch_scan_item<UNR>(pools, items, (int)blockIdx.x, lds, lds0, lane, wave, []() {});
 }
 
 hipError_t launch_batch_decode(int MV, const BatchPool *pools, const int64_t *blk_off, const int32_t *cls_pools,
@@ -504,12 +531,18 @@ hipError_t launch_batch_decode(int MV, const BatchPool *pools, const int64_t *bl
 __global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
 
 hipError_t launch_batch_scan(const BatchPool *pools, const WorkItem *items, int n_items, uint32_t *counter,
-                             int grid, size_t lds_bytes, hipStream_t s)
+                             int grid, size_t lds_bytes, int form, hipStream_t s)
 {
-    batch_reset_kernel<<<1, 1, 0, s>>>(counter);
-    batch_scan16_kernel<8><<<grid, 64 * kBatchWaves, lds_bytes, s>>>(pools, items, n_items, counter);
+    if (n_items <= 0) return hipSuccess;
+    if (form == kBatchGrid) {
+        batch_scan16_grid_kernel<8><<<n_items, 64 * kBatchWaves, lds_bytes, s>>>(pools, items);
+    } else {
+        batch_reset_kernel<<<1, 1, 0, s>>>(counter);
+        batch_scan16_kernel<8><<<grid, 64 * kBatchWaves, lds_bytes, s>>>(pools, items, n_items, counter);
+    }
     return hipGetLastError();
 }
+
 
 int batch_scan_blocks_per_cu(size_t lds_bytes)
 {

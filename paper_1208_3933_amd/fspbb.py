@@ -71,9 +71,15 @@ class PoolDesc(ctypes.Structure):
 
 BATCH_GRAPH = 1
 
+FORM_PERSISTENT = 0
+FORM_GRID = 1
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int32), ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double),
-                ("default_us", ctypes.c_double), ("cand_wpg", ctypes.c_int32 * 8), ("cand_us", ctypes.c_double * 8)]
+                ("default_us", ctypes.c_double), ("cand_wpg", ctypes.c_int32 * 8), ("cand_us", ctypes.c_double * 8),
+                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32), ("grid_us", ctypes.c_double),
+                ("persistent_us", ctypes.c_double)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -115,6 +121,8 @@ _SIGNATURES = {
     "fsp_tune_get": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]),
     "fsp_tune_set": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "fsp_tune_get_form": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "fsp_tune_set_form": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "fsp_tune_save": (ctypes.c_int32, [ctypes.c_char_p]),
     "fsp_tune_load": (ctypes.c_int32, [ctypes.c_char_p]),
     "fsp_server_create": (ctypes.c_int32, [ctypes.POINTER(ServerConfig), _vp, ctypes.POINTER(_vp)]),
@@ -388,7 +396,8 @@ def autotune(inst: Instance, sample_nodes: int = 16384, reps: int = 3) -> dict:
     r = TuneResult()
     _check(lib().fsp_autotune(inst.handle, int(sample_nodes), int(reps), ctypes.byref(r)), "fsp_autotune")
     return {"waves_per_group": r.waves_per_group, "best_us": r.best_us, "default_us": r.default_us,
-            "candidates": {int(r.cand_wpg[i]): float(r.cand_us[i]) for i in range(r.candidates)}}
+            "candidates": {int(r.cand_wpg[i]): float(r.cand_us[i]) for i in range(r.candidates)},
+            "form": r.form, "grid_us": r.grid_us, "persistent_us": r.persistent_us}
 
 
 def tune_get(n: int, m: int):
@@ -400,6 +409,16 @@ def tune_get(n: int, m: int):
 
 def tune_set(n: int, m: int, waves_per_group: int) -> None:
     _check(lib().fsp_tune_set(int(n), int(m), int(waves_per_group)), "fsp_tune_set")
+
+
+def tune_get_form(n: int, m: int) -> int:
+    f = ctypes.c_int32()
+    _check(lib().fsp_tune_get_form(int(n), int(m), ctypes.byref(f)), "fsp_tune_get_form")
+    return int(f.value)
+
+
+def tune_set_form(n: int, m: int, form: int) -> None:
+    _check(lib().fsp_tune_set_form(int(n), int(m), int(form)), "fsp_tune_set_form")
 
 
 def tune_save(path: str) -> None:

@@ -76,10 +76,16 @@ def test_tuning_table_roundtrip(tmp_path):
     fspbb.tune_set(37, 7, 4)
     assert fspbb.tune_get(37, 7) == (4, True)
     path = str(tmp_path / "tune.txt")
+    assert fspbb.tune_get_form(37, 7) == fspbb.FORM_GRID
+    fspbb.tune_set_form(37, 7, fspbb.FORM_PERSISTENT)
     fspbb.tune_save(path)
     fspbb.tune_set(37, 7, 16)
+    fspbb.tune_set_form(37, 7, fspbb.FORM_GRID)
     fspbb.tune_load(path)
     assert fspbb.tune_get(37, 7) == (4, True)
+    assert fspbb.tune_get_form(37, 7) == fspbb.FORM_PERSISTENT
+    with pytest.raises(fspbb.FspError):
+        fspbb.tune_set_form(37, 7, 2)
     with pytest.raises(fspbb.FspError):
         fspbb.tune_set(37, 7, 3)
 

@@ -46,17 +46,28 @@ def plain_bounds(torch, pools):
     return [o.cpu().numpy() for o in res]
 
 
+@pytest.mark.parametrize("form", [fspbb.FORM_GRID, fspbb.FORM_PERSISTENT])
 @pytest.mark.parametrize("graph", [True, False])
-def test_mixed_batch_matches_plain_and_oracle(graph):
+def test_mixed_batch_matches_plain_and_oracle(graph, form):
     torch = require_gpu()
     sizes = [300, 1000, 129, 0, 2048, 700, 128, 4000, 64, 513, 1, 3000]
     # invalid nodes in a pool decoded in depth order (1000 nodes) and in one decoded in pool order (129)
     pools, host, insts = make_batch(torch, len(sizes), sizes, invalid_in=(1, 2))
     want_plain = plain_bounds(torch, pools)
-    with fspbb.batch_create(pools, graph=graph) as b:
-        assert b.info()["total_nodes"] == sum(sizes)
-        b.run()
-        torch.cuda.synchronize()
+    saved = {(n, m): fspbb.tune_get_form(n, m) for n, m in SHAPES}
+    for n, m in SHAPES:
+        fspbb.tune_set_form(n, m, form)
+    try:
+        with fspbb.batch_create(pools, graph=graph) as b:
+            info = b.info()
+            assert info["total_nodes"] == sum(sizes)
+            if form == fspbb.FORM_GRID:
+                assert info["grid"] == info["items"]
+            b.run()
+            torch.cuda.synchronize()
+    finally:
+        for (n, m), f in saved.items():
+            fspbb.tune_set_form(n, m, f)
     for i, (inst, _, _, out) in enumerate(pools):
         got = out.cpu().numpy()
         assert (got == want_plain[i]).all(), i
@@ -141,8 +152,10 @@ def test_autotune_picks_a_measured_schedule(n, m):
     with fspbb.create_instance(p) as inst:
         r = fspbb.autotune(inst, sample_nodes=4096, reps=2)
         assert r["waves_per_group"] in r["candidates"]
-        assert r["best_us"] == min(r["candidates"].values())
+        assert r["grid_us"] == min(r["candidates"].values())
         assert fspbb.tune_get(n, m) == (r["waves_per_group"], True)
+        assert r["form"] in (fspbb.FORM_GRID, fspbb.FORM_PERSISTENT) and fspbb.tune_get_form(n, m) == r["form"]
+        assert r["best_us"] == min(r["grid_us"], r["persistent_us"])
         # bounds stay identical under the tuned schedule
         pre, dep = gen.random_pool(n, 3000, gen.make_seed(8, n, 1))
         pre_d, dep_d = to_dev(torch, pre, dep)
