@@ -27,7 +27,7 @@ struct StepArgs {
     int32_t *out_lb;             // may be null
     int64_t out_base, out_cap;
     int out_reversed;
-    uint32_t *surv_per_parent;   // K survivor counts per parent (written); may be null
+    uint32_t *surv_per_parent;   // K survivor counts per parent (written, also for 0 children); may be null
     int32_t *incumbent;          // n; written when a complete child improves ub_in; may be null
 };
 
@@ -44,28 +44,33 @@ struct StepScratch {
     unsigned long long *bad;     // invalid parents
 };
 
-// One search in a step launch.
-struct StepReq {
-    StepArgs a;
-    StepScratch w;
-    int64_t nchild;              // children of this step (set before the branch phase)
-    int64_t out_slot;            // offset of this search's survivor counts in the gathered copy
-};
-
-// Per-search scalars gathered after a step (one device-to-host copy).
+// Per-search scalars of a step.  They live in the search's entry of the
+// request table: the upload that starts a step sets their initial values
+// (best = (ub_in << 32) | 0xffffffff, the rest 0) and the copy back that ends
+// it returns them, so no kernel initialises or gathers them.
 struct StepResultDev {
     unsigned long long best, fingerprint, bad;
     uint32_t nchild, nsurv;
 };
 
-// Phase 1: init, validate and count children, child offsets (-> w.nchild).
+// One search in a step launch.  The kernels read the request through the
+// constant (scalar) path and write the results only through the w pointers,
+// which the host points at `res` of the same entry on the device.
+struct StepReq {
+    StepArgs a;
+    StepScratch w;
+    int64_t nchild;              // children of this step (set before the branch phase)
+    int64_t reserved;
+    StepResultDev res;
+};
+
+// Phase 1: validate and count children, child offsets (-> w.nchild).
 hipError_t mstep_phase1(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, hipStream_t s);
 // Branch: children's job lists and rows (nchild known in each StepReq).
 hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
 // Finish (after the children are bounded into w.clb): upper bound, keep,
-// stable compaction, scatter, fingerprint, per-parent counts, incumbent,
-// and the gather of the per-search results and survivor counts.
+// stable compaction, scatter, fingerprint, per-parent counts, incumbent.
 hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, int64_t maxC,
-                        StepResultDev *results, uint32_t *surv_all, hipStream_t s);
+                        hipStream_t s);
 
 }  // namespace fspbb

@@ -58,14 +58,6 @@ __device__ inline bool wave_prefix_set(const int32_t *row, int d, int n, uint32_
     return __ballot(bad) == 0;
 }
 
-__global__ void mstep_init_kernel(const StepReq *__restrict__ reqs)
-{
-    ReqP q = req_of(reqs);
-    *q->w.best = ((unsigned long long)(uint32_t)q->a.ub_in << 32) | 0xffffffffull;
-    *q->w.fingerprint = 0ull;
-    *q->w.bad = 0ull;
-}
-
 __global__ __launch_bounds__(256) void mstep_count_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ uint32_t mask[4][kMaxJobs / 32];
@@ -221,26 +213,6 @@ __global__ void mstep_incumbent_kernel(const StepReq *__restrict__ reqs)
     for (int t = threadIdx.x; t < n; t += blockDim.x) inc[t] = q->w.crow[(int64_t)idx * n + t];
 }
 
-// Gathers each search's scalars and survivor counts for one copy to the host.
-__global__ __launch_bounds__(256) void mstep_gather_kernel(const StepReq *__restrict__ reqs,
-                                                           StepResultDev *__restrict__ results,
-                                                           uint32_t *__restrict__ surv_all)
-{
-    ReqP q = req_of(reqs);
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p == 0) {
-        StepResultDev r;
-        r.best = *q->w.best;
-        r.fingerprint = *q->w.fingerprint;
-        r.bad = *q->w.bad;
-        r.nchild = *q->w.nchild;
-        r.nsurv = q->nchild > 0 ? *q->w.nsurv : 0u;
-        results[blockIdx.y] = r;
-    }
-    if (surv_all && q->a.surv_per_parent && p < q->a.K)
-        surv_all[q->out_slot + p] = q->nchild > 0 ? q->a.surv_per_parent[p] : 0u;
-}
-
 static unsigned blocks_for(int64_t items, int per_block)
 {
     const int64_t b = (items + per_block - 1) / per_block;
@@ -250,7 +222,6 @@ static unsigned blocks_for(int64_t items, int per_block)
 hipError_t mstep_phase1(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, hipStream_t s)
 {
     if (R <= 0) return hipSuccess;
-    mstep_init_kernel<<<dim3(1, R), 1, 0, s>>>(reqs);
     if (maxK > 0) mstep_count_kernel<<<dim3(blocks_for(maxK, 4), R), 256, 0, s>>>(reqs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -266,7 +237,7 @@ hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, 
 }
 
 hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, int64_t maxC,
-                        StepResultDev *results, uint32_t *surv_all, hipStream_t s)
+                        hipStream_t s)
 {
     if (R <= 0) return hipSuccess;
     if (maxC > 0) {
@@ -278,10 +249,9 @@ hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t
         if (e != hipSuccess) return e;
         mstep_scatter_kernel<<<dim3(blocks_for(maxC, 4), R), 256, 0, s>>>(reqs);
         mstep_fingerprint_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
-        mstep_per_parent_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs);
         mstep_incumbent_kernel<<<dim3(1, R), 256, 0, s>>>(reqs);
     }
-    mstep_gather_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs, results, surv_all);
+    if (maxK > 0) mstep_per_parent_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs);
     return hipGetLastError();
 }
 

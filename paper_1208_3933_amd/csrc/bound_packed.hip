@@ -613,7 +613,7 @@ static void launch_scan(int unr, dim3 grid, size_t lds_b, hipStream_t s, const D
 }
 
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
-                               int64_t N, int32_t *out_lb, hipStream_t s)
+                               int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths)
 {
     if (N <= 0) return hipSuccess;
     const int n = I->n, m = I->m, NW = (n + 31) >> 5;
@@ -631,14 +631,16 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
     W.dec = (uint32_t *)w;
     W.flg = (uint32_t *)(w + dec_b);
     W.st = (uint32_t *)(w + dec_b + flg_b);
-    W.order = (int32_t *)(w + dec_b + flg_b + st_b);
+    W.order = sort_depths ? (int32_t *)(w + dec_b + flg_b + st_b) : nullptr;
     W.cnt = (uint32_t *)(w + dec_b + flg_b + st_b + ord_b);
 
     timing_mark(I, 0, s);
-    const size_t hb = (size_t)(n + 2) * 4;
-    depth_count_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt);
-    depth_scan_kernel<<<1, 1024, 0, s>>>(W.cnt, (int64_t)(n + 2) * B);
-    depth_scatter_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt, W.order);
+    if (sort_depths) {
+        const size_t hb = (size_t)(n + 2) * 4;
+        depth_count_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt);
+        depth_scan_kernel<<<1, 1024, 0, s>>>(W.cnt, (int64_t)(n + 2) * B);
+        depth_scatter_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt, W.order);
+    }
 
     const dim3 dgrid((unsigned)((Npad + 255) / 256)), dblock(256);
     const int MV = (m + 3) & ~3;

@@ -77,8 +77,10 @@ namespace fspbb {
 // Launchers (bound_*.hip).  Return a HIP error code.
 hipError_t launch_bound_lane32(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
                                int64_t N, int32_t *out_lb, hipStream_t s);
+// sort_depths: decode the nodes in depth order (a counting sort first), which
+// evens out the per-lane prefix loops of pools of mixed depths.
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
-                               int64_t N, int32_t *out_lb, hipStream_t s);
+                               int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths = true);
 
 void set_last_error(hipError_t e);
 

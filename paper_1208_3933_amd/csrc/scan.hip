@@ -80,9 +80,36 @@ __global__ __launch_bounds__(kScanThreads) void seg_apply_kernel(const ScanSeg *
     }
 }
 
+// Segments of at most one tile: the whole scan in one block per segment.
+__global__ __launch_bounds__(kScanThreads) void seg_small_kernel(const ScanSeg *__restrict__ segs)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const ScanSeg g = segs[blockIdx.x];
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = base + i < g.count ? g.in[base + i] : 0u;
+        tsum += v[i];
+    }
+    const uint32_t inc = block_inclusive_scan(tsum, sh);
+    uint32_t run = inc - tsum;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < g.count) g.out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == kScanThreads - 1) *g.total = inc;
+}
+
 hipError_t exclusive_scan_segments(const ScanSeg *segs, int R, int64_t max_count, hipStream_t s)
 {
     if (R <= 0) return hipSuccess;
+    if (max_count <= kScanTile) {
+        seg_small_kernel<<<dim3((unsigned)R), kScanThreads, 0, s>>>(segs);
+        return hipGetLastError();
+    }
     const int64_t tiles = (max_count + kScanTile - 1) / kScanTile;
     if (tiles > 0) seg_tile_sums_kernel<<<dim3((unsigned)tiles, (unsigned)R), kScanThreads, 0, s>>>(segs);
     seg_sums_kernel<<<dim3((unsigned)R), kScanThreads, 0, s>>>(segs);

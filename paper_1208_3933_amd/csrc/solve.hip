@@ -35,17 +35,12 @@ hipError_t StepBuffers::ensure_k(int64_t K, hipStream_t s)
     kblob = nullptr;
     Kcap = std::max<int64_t>(K, 1);
     const size_t kb = al256((size_t)Kcap * 4), sb = al256(scan_scratch_bytes(Kcap));
-    hipError_t e = stream_alloc((void **)&kblob, 2 * kb + sb + 5 * 64, s);
+    hipError_t e = stream_alloc((void **)&kblob, 2 * kb + sb, s);
     if (e != hipSuccess) { kblob = nullptr; Kcap = 0; return e; }
     char *p = (char *)kblob;
     w.cnt = (uint32_t *)p; p += kb;
     w.off = (uint32_t *)p; p += kb;
-    sums_k = (uint32_t *)p; p += sb;
-    w.nchild = (uint32_t *)p;
-    w.nsurv = (uint32_t *)(p + 64);
-    w.best = (unsigned long long *)(p + 128);
-    w.fingerprint = (unsigned long long *)(p + 192);
-    w.bad = (unsigned long long *)(p + 256);
+    sums_k = (uint32_t *)p;
     return hipSuccess;
 }
 
@@ -83,7 +78,7 @@ void StepBuffers::release(hipStream_t s)
 size_t StepBuffers::bytes() const
 {
     return (size_t)Kcap * 8 + (size_t)Ccap * (24 + 4 * (size_t)n) + scan_scratch_bytes(Kcap) +
-           scan_scratch_bytes(Ccap) + 320;
+           scan_scratch_bytes(Ccap);
 }
 
 hipError_t TickContext::reserve(size_t bytes)
@@ -177,11 +172,14 @@ int32_t neh(const int32_t *p, int n, int m, int32_t *perm)
 
 // ---------------------------------------------------------------- search
 
+// sort_depths as in launch_bound_packed: off for the children of a depth-first
+// step, which come from parents popped off the top of one stack and so sit at
+// one or a few depths.
 static hipError_t bound_rows(fsp_instance_s *I, const int32_t *rows, const int32_t *depths, int64_t N, int32_t *lb,
-                             hipStream_t s)
+                             hipStream_t s, bool sort_depths = true)
 {
     if (N <= 0) return hipSuccess;
-    return I->packed16 ? launch_bound_packed(I, rows, depths, N, lb, s)
+    return I->packed16 ? launch_bound_packed(I, rows, depths, N, lb, s, sort_depths)
                        : launch_bound_lane32(I, rows, depths, N, lb, s);
 }
 
@@ -198,7 +196,6 @@ hipError_t Search::begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in,
     cap_stack = std::max<int64_t>(1024, 2 * pool_cap);
     hipError_t e = stream_alloc((void **)&srows, (size_t)cap_stack * n * 4, s);
     if (e == hipSuccess) e = stream_alloc((void **)&sdep, (size_t)cap_stack * 4, s);
-    if (e == hipSuccess) e = stream_alloc((void **)&dsurv, (size_t)pool_cap * 4, s);
     if (e == hipSuccess) e = stream_alloc((void **)&dinc, (size_t)n * 4, s);
     if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
     if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
@@ -277,16 +274,14 @@ void Search::release(hipStream_t s)
 {
     if (srows) hipFreeAsync(srows, s);
     if (sdep) hipFreeAsync(sdep, s);
-    if (dsurv) hipFreeAsync(dsurv, s);
     if (dinc) hipFreeAsync(dinc, s);
     srows = sdep = dinc = nullptr;
-    dsurv = nullptr;
     B.release(s);
 }
 
 size_t Search::device_bytes() const
 {
-    return (size_t)cap_stack * (n + 1) * 4 + (size_t)pool_cap * 4 + (size_t)n * 4 + B.bytes();
+    return (size_t)cap_stack * (n + 1) * 4 + (size_t)n * 4 + B.bytes();
 }
 
 void Search::result(fsp_solve_result *res, int32_t *perm_out) const
@@ -349,18 +344,37 @@ static hipError_t prepare_step(Search &S, hipStream_t s)
 }
 
 namespace {
+// Request table of a step: StepReq[R] (with their results), the phase-1 and
+// finish scan segments, then the survivor counts of every popped parent.
 struct TabLayout {
-    size_t req, seg1, seg2, res, surv, total;
+    size_t req, seg1, seg2, surv, total;
     TabLayout(int R, int64_t sumK)
     {
         req = 0;
         seg1 = al256(sizeof(StepReq) * R);
         seg2 = seg1 + al256(sizeof(ScanSeg) * R);
-        res = seg2 + al256(sizeof(ScanSeg) * R);
-        surv = res + al256(sizeof(StepResultDev) * R);
+        surv = seg2 + al256(sizeof(ScanSeg) * R);
         total = surv + al256((size_t)std::max<int64_t>(sumK, 1) * 4);
     }
 };
+
+// Points the request's scalar outputs at its entry of the device table.
+void point_results(StepReq &q, StepReq *dq_entry)
+{
+    q.w.best = &dq_entry->res.best;
+    q.w.fingerprint = &dq_entry->res.fingerprint;
+    q.w.bad = &dq_entry->res.bad;
+    q.w.nchild = &dq_entry->res.nchild;
+    q.w.nsurv = &dq_entry->res.nsurv;
+}
+
+// point_results, and the initial values in the host image.
+void bind_results(StepReq &q, StepReq *dq_entry, int32_t ub_in)
+{
+    q.res = StepResultDev{};
+    q.res.best = ((unsigned long long)(uint32_t)ub_in << 32) | 0xffffffffull;
+    point_results(q, dq_entry);
+}
 }  // namespace
 
 hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
@@ -383,6 +397,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     StepReq *hq = (StepReq *)(h + L.req);
     ScanSeg *hs1 = (ScanSeg *)(h + L.seg1), *hs2 = (ScanSeg *)(h + L.seg2);
     int64_t slot = 0;
+    std::vector<int64_t> slots(R);
     for (int r = 0; r < R; ++r) {
         Search &S = *act[r];
         StepReq q;
@@ -400,28 +415,27 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         q.a.out_base = S.base;
         q.a.out_cap = S.cap_stack;
         q.a.out_reversed = 1;
-        q.a.surv_per_parent = S.dsurv;
+        q.a.surv_per_parent = (uint32_t *)(d + L.surv) + slot;
         q.a.incumbent = S.dinc;
         q.w = S.B.w;
         q.nchild = S.nch;
-        q.out_slot = slot;
+        bind_results(q, (StepReq *)(d + L.req) + r, S.UB);
+        slots[r] = slot;
         slot += S.K;
         hq[r] = q;
-        hs1[r] = ScanSeg{S.B.w.cnt, S.B.w.off, S.K, S.B.w.nchild, S.B.sums_k};
-        hs2[r] = ScanSeg{S.B.w.keep, S.B.w.pos, S.nch, S.B.w.nsurv, S.B.sums_c};
+        hs1[r] = ScanSeg{q.w.cnt, q.w.off, S.K, q.w.nchild, S.B.sums_k};
+        hs2[r] = ScanSeg{q.w.keep, q.w.pos, S.nch, q.w.nsurv, S.B.sums_c};
     }
     const StepReq *dq = (const StepReq *)(d + L.req);
     const ScanSeg *ds1 = (const ScanSeg *)(d + L.seg1), *ds2 = (const ScanSeg *)(d + L.seg2);
-    StepResultDev *dres = (StepResultDev *)(d + L.res);
-    uint32_t *dsurv = (uint32_t *)(d + L.surv);
-    e = hipMemcpyAsync(d, h, L.res, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = mstep_phase1(dq, ds1, R, maxK, s);
     if (e == hipSuccess) e = mstep_branch(dq, R, maxK, maxC, s);
     if (e != hipSuccess) return e;
     // bounding: one plain launch for a single search, else one merged batch
     if (R == 1) {
         Search &S = *act[0];
-        e = bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s);
+        e = bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s, false);
     } else {
         std::vector<fsp_pool_desc> descs;
         descs.reserve(R);
@@ -433,17 +447,16 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         }
         if (e == hipSuccess && !descs.empty()) e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s);
     }
-    if (e == hipSuccess) e = mstep_finish(dq, ds2, R, maxK, maxC, dres, dsurv, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, d + L.res, L.total - L.res, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = mstep_finish(dq, ds2, R, maxK, maxC, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, L.total, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
 
-    const StepResultDev *hres = (const StepResultDev *)(h + L.res);
     const uint32_t *hsurv = (const uint32_t *)(h + L.surv);
     bool copies = false;
     for (int r = 0; r < R; ++r) {
         Search &S = *act[r];
-        const StepResultDev &o = hres[r];
+        const StepResultDev o = hq[r].res;
         if (o.bad || (int64_t)o.nchild != S.nch) {
             S.done = true;
             S.status = FSP_E_BADNODE;
@@ -459,7 +472,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
             copies = true;
         }
         // survivors sit bottom-to-top as: children of the last popped parent ... of the first
-        const uint32_t *sv = hsurv + hq[r].out_slot;
+        const uint32_t *sv = hsurv + slots[r];
         int64_t p = S.K;
         for (auto it = S.taken.rbegin(); it != S.taken.rend(); ++it) {
             for (int64_t x = 0; x < it->second; ++x) {
@@ -540,32 +553,36 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     q.a.incumbent = incumbent;
     q.w = B.w;
     char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
-    const StepReq *dq = (const StepReq *)(d + L.req);
+    StepReq *dentry = (StepReq *)(d + L.req);
+    const StepReq *dq = dentry;
+    bind_results(q, dentry, ub_in);
     *(StepReq *)(h + L.req) = q;
-    *(ScanSeg *)(h + L.seg1) = ScanSeg{B.w.cnt, B.w.off, K, B.w.nchild, B.sums_k};
-    uint32_t nchild = 0;
-    e = hipMemcpyAsync(d, h, L.res, hipMemcpyHostToDevice, s);
+    *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
+    e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = mstep_phase1(dq, (const ScanSeg *)(d + L.seg1), 1, K, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, B.w.nchild, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + L.req, d + L.req, sizeof(StepReq), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    uint32_t nchild = 0;
     if (e == hipSuccess) {
-        nchild = *(const uint32_t *)(h + L.res);
-        e = B.ensure_c(nchild, inst->n, s);
+        nchild = ((const StepReq *)(h + L.req))->res.nchild;
+        e = B.ensure_c(nchild, inst->n, s);  // the child scratch may move; phase-1 results stay
     }
     if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    const StepResultDev after1 = ((const StepReq *)(h + L.req))->res;
     q.w = B.w;
+    point_results(q, dentry);
+    q.res = after1;
     q.nchild = nchild;
     *(StepReq *)(h + L.req) = q;
-    *(ScanSeg *)(h + L.seg2) = ScanSeg{B.w.keep, B.w.pos, (int64_t)nchild, B.w.nsurv, B.sums_c};
-    e = hipMemcpyAsync(d, h, L.res, hipMemcpyHostToDevice, s);
+    *(ScanSeg *)(h + L.seg2) = ScanSeg{q.w.keep, q.w.pos, (int64_t)nchild, q.w.nsurv, B.sums_c};
+    e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = mstep_branch(dq, 1, K, nchild, s);
-    if (e == hipSuccess) e = bound_rows(inst, B.w.crow, B.w.cdepth, nchild, B.w.clb, s);
-    if (e == hipSuccess)
-        e = mstep_finish(dq, (const ScanSeg *)(d + L.seg2), 1, K, nchild, (StepResultDev *)(d + L.res), nullptr, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, d + L.res, sizeof(StepResultDev), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = bound_rows(inst, q.w.crow, q.w.cdepth, nchild, q.w.clb, s);
+    if (e == hipSuccess) e = mstep_finish(dq, (const ScanSeg *)(d + L.seg2), 1, K, nchild, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + L.req, d + L.req, sizeof(StepReq), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { cleanup(); return fail_status(e); }
-    const StepResultDev o = *(const StepResultDev *)(h + L.res);
+    const StepResultDev o = ((const StepReq *)(h + L.req))->res;
     cleanup();
     res->n_children = nchild;
     res->n_survivors = o.nsurv;
