@@ -76,6 +76,10 @@ def lib():
         L.orc_brute.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int]
         L.orc_neh.restype = ctypes.c_int32
         L.orc_neh.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p]
+        L.orc_bnb_best_first.restype = ctypes.c_int
+        L.orc_bnb_best_first.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _i32p,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                         ctypes.POINTER(BnbResult), _i32p, _i64p, ctypes.c_int64, ctypes.c_int]
         L.orc_bnb.restype = ctypes.c_int
         L.orc_bnb.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _i32p,
                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
@@ -182,15 +186,17 @@ def neh(p):
 
 
 def bnb(p, ub0: int, incumbent0=None, pool_cap: int = 1 << 18, node_budget: int = 1 << 62,
-        strict_gt: bool = False, steplog_cap: int = 0, heads: bool = False):
-    """Pool-synchronous DFS branch-and-bound (heads: the heads variant of the
-    bound).  Returns a dict."""
+        strict_gt: bool = False, steplog_cap: int = 0, heads: bool = False, best_first: bool = False):
+    """Pool-synchronous branch-and-bound, depth-first or best-first (heads:
+    the heads variant of the bound).  Returns a dict; for best-first,
+    max_stack is the largest frontier."""
     p, n, m = _mat(p)
     res = BnbResult()
     inc = np.empty(n, np.int32)
     inc0 = None if incumbent0 is None else _seq(incumbent0)
     log = np.zeros((max(steplog_cap, 1), 6), np.int64)
-    rc = lib().orc_bnb(_p(p), n, m, int(ub0), None if inc0 is None else _p(inc0),
+    fn = lib().orc_bnb_best_first if best_first else lib().orc_bnb
+    rc = fn(_p(p), n, m, int(ub0), None if inc0 is None else _p(inc0),
                        int(pool_cap), int(node_budget), int(strict_gt), ctypes.byref(res),
                        _p(inc), log.ctypes.data_as(_i64p), int(steplog_cap), int(heads))
     if rc != 0:

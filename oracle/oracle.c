@@ -534,3 +534,169 @@ int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
     free(sched); free(children); free(lbs); free(stack); free(inc);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Best-first branch-and-bound, pool-synchronous (Sec. III-A: the GPU-side
+ * experiments select the sub-problems of a pool best first).  The frontier
+ * holds nodes with their bound and an insertion number, ordered by (bound,
+ * insertion number).  Each step:
+ *   1. drops the frontier nodes whose bound is >= UB (> UB with strict_gt);
+ *   2. takes parents from the front of the order while the children gathered
+ *      so far plus the next parent's n - d children fit in pool_cap (the first
+ *      parent is always taken);
+ *   3-5. branches the parents in that order (children in increasing appended
+ *      job), bounds every child and lowers UB with the best complete child,
+ *      the first in child order on ties, exactly as the depth-first search;
+ *   6. inserts the non-complete children whose bound is below UB, in child
+ *      order, with the next insertion numbers.
+ * The search stops when the frontier is empty after step 1 (proven) or, if
+ * not, when nodes_bounded has reached node_budget.  The result's max_stack is
+ * the largest frontier; steplog as for orc_bnb with [4] = frontier size after
+ * the step and [5] = sum over inserted children of (S - rank) * (appended job
+ * + 1), rank in child order, S the number inserted.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t lb;
+    int64_t seq;
+    int32_t *node;  /* [depth, job_0 .. job_{n-1}] */
+} bf_node;
+
+static int cmp_bf(const void *x, const void *y)
+{
+    const bf_node *a = (const bf_node *)x, *b = (const bf_node *)y;
+    if (a->lb != b->lb) return a->lb < b->lb ? -1 : 1;
+    return a->seq < b->seq ? -1 : (a->seq > b->seq ? 1 : 0);
+}
+
+int orc_bnb_best_first(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+                       int64_t pool_cap, int64_t node_budget, int strict_gt,
+                       orc_bnb_result *res, int32_t *incumbent_out,
+                       int64_t *steplog, int64_t steplog_cap, int heads)
+{
+    memset(res, 0, sizeof(*res));
+    if (n < 1 || m < 2 || pool_cap < 1) return -1;
+    int32_t UB = ub0;
+    int32_t *inc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int have_inc = 0;
+    if (inc0) { memcpy(inc, inc0, sizeof(int32_t) * (size_t)n); have_inc = 1; }
+
+    int64_t M = 0, capF = 16, seq = 0;
+    bf_node *F = (bf_node *)malloc(sizeof(bf_node) * (size_t)capF);
+    int64_t nodes = 1;
+    int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, heads);
+    if (!(strict_gt ? (root_lb > UB) : (root_lb >= UB))) {
+        F[0].lb = root_lb;
+        F[0].seq = seq++;
+        F[0].node = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+        M = 1;
+    }
+    int64_t steps = 0, improvements = 0, max_front = M;
+    int32_t *children = NULL, *lbs = NULL;
+    int64_t child_cap = 0;
+    unsigned char *sched = (unsigned char *)malloc((size_t)n);
+
+    for (;;) {
+        /* 1. drop the nodes the upper bound eliminates */
+        int64_t w = 0;
+        for (int64_t i = 0; i < M; ++i) {
+            int gone = strict_gt ? (F[i].lb > UB) : (F[i].lb >= UB);
+            if (gone) free(F[i].node);
+            else F[w++] = F[i];
+        }
+        M = w;
+        if (M == 0 || nodes >= node_budget) break;
+        qsort(F, (size_t)M, sizeof(bf_node), cmp_bf);
+
+        /* 2. selection from the front */
+        int64_t K = 0, nchild = 0;
+        while (K < M) {
+            int64_t c = n - F[K].node[0];
+            if (K > 0 && nchild + c > pool_cap) break;
+            nchild += c;
+            ++K;
+        }
+        if (nchild > child_cap) {
+            child_cap = nchild;
+            children = (int32_t *)realloc(children, sizeof(int32_t) * (size_t)(n + 1) * (size_t)child_cap);
+            lbs = (int32_t *)realloc(lbs, sizeof(int32_t) * (size_t)child_cap);
+        }
+        /* 3. branching in selection order */
+        int64_t c = 0;
+        for (int64_t k = 0; k < K; ++k) {
+            int32_t *par = F[k].node;
+            int32_t d = par[0];
+            memset(sched, 0, (size_t)n);
+            for (int i = 0; i < d; ++i) sched[par[1 + i]] = 1;
+            for (int j = 0; j < n; ++j) {
+                if (sched[j]) continue;
+                int32_t *ch = children + c * (n + 1);
+                ch[0] = d + 1;
+                memcpy(ch + 1, par + 1, sizeof(int32_t) * (size_t)d);
+                ch[1 + d] = j;
+                ++c;
+            }
+        }
+        for (int64_t k = 0; k < K; ++k) free(F[k].node);
+        memmove(F, F + K, sizeof(bf_node) * (size_t)(M - K));
+        M -= K;
+        /* 4. bounding */
+        for (int64_t i = 0; i < nchild; ++i) {
+            int32_t *ch = children + i * (n + 1);
+            lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, heads);
+        }
+        nodes += nchild;
+        /* 5. complete children update the upper bound */
+        int improved = 0;
+        for (int64_t i = 0; i < nchild; ++i) {
+            int32_t *ch = children + i * (n + 1);
+            if (ch[0] == n && lbs[i] < UB) {
+                UB = lbs[i];
+                memcpy(inc, ch + 1, sizeof(int32_t) * (size_t)n);
+                have_inc = 1;
+                improved = 1;
+            }
+        }
+        improvements += improved;
+        /* 6. insertion in child order */
+        int64_t S = 0;
+        for (int64_t i = 0; i < nchild; ++i) {
+            int32_t *ch = children + i * (n + 1);
+            if (ch[0] < n && (strict_gt ? !(lbs[i] > UB) : (lbs[i] < UB))) ++S;
+        }
+        int64_t rank = 0, fp = 0;
+        for (int64_t i = 0; i < nchild; ++i) {
+            int32_t *ch = children + i * (n + 1);
+            if (!(ch[0] < n && (strict_gt ? !(lbs[i] > UB) : (lbs[i] < UB)))) continue;
+            if (M >= capF) {
+                capF *= 2;
+                F = (bf_node *)realloc(F, sizeof(bf_node) * (size_t)capF);
+            }
+            F[M].lb = lbs[i];
+            F[M].seq = seq++;
+            F[M].node = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+            memcpy(F[M].node, ch, sizeof(int32_t) * (size_t)(n + 1));
+            ++M;
+            fp += (S - rank) * (int64_t)(ch[ch[0]] + 1);
+            ++rank;
+        }
+        if (M > max_front) max_front = M;
+        if (steplog && steps < steplog_cap) {
+            int64_t *s = steplog + steps * 6;
+            s[0] = K; s[1] = nchild; s[2] = UB; s[3] = S; s[4] = M; s[5] = fp;
+        }
+        ++steps;
+    }
+    res->ub = UB;
+    res->proven = (M == 0);
+    res->nodes_bounded = nodes;
+    res->steps = steps;
+    res->improvements = improvements;
+    res->max_stack = max_front;
+    if (incumbent_out) {
+        if (have_inc) memcpy(incumbent_out, inc, sizeof(int32_t) * (size_t)n);
+        else for (int j = 0; j < n; ++j) incumbent_out[j] = -1;
+    }
+    for (int64_t i = 0; i < M; ++i) free(F[i].node);
+    free(F); free(sched); free(children); free(lbs); free(inc);
+    return 0;
+}

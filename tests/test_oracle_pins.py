@@ -427,3 +427,99 @@ def test_heads_bnb_finds_the_optimum(n, m, seed):
     # with UB0 = optimum the explored set is the nodes whose bound is below it:
     # a stronger bound at every node cannot explore more
     assert heads["nodes_bounded"] <= plain["nodes_bounded"]
+
+
+# --- best-first selection ------------------------------------------------------
+
+def best_first_python(p, ub, pool_cap, incumbent=None):
+    """A second, heap-based statement of the pool-synchronous best-first search
+    (frontier ordered by (bound, insertion number); eliminated nodes dropped
+    before each selection; parents taken from the front while their children
+    fit, the first always; survivors inserted in child order).  Returns the
+    per-step (parents, children, UB, inserted, frontier) and the counters."""
+    import heapq
+    n = p.shape[0]
+    seq = 0
+    heap = []
+    root_lb = oracle.bound(p, ())
+    nodes = 1
+    if root_lb < ub:
+        heapq.heappush(heap, (root_lb, seq, ()))
+        seq += 1
+    log = []
+    while True:
+        heap = [x for x in heap if x[0] < ub]
+        heapq.heapify(heap)
+        if not heap:
+            break
+        parents, nch = [], 0
+        while heap:
+            lb, s, pre = heap[0]
+            c = n - len(pre)
+            if parents and nch + c > pool_cap:
+                break
+            heapq.heappop(heap)
+            parents.append(pre)
+            nch += c
+        kids = [pre + (j,) for pre in parents for j in range(n) if j not in pre]
+        lbs = [oracle.bound(p, k) for k in kids]
+        nodes += len(kids)
+        for k, lb in zip(kids, lbs):
+            if len(k) == n and lb < ub:
+                ub, incumbent = lb, k
+        ins = 0
+        for k, lb in zip(kids, lbs):
+            if len(k) < n and lb < ub:
+                heapq.heappush(heap, (lb, seq, k))
+                seq += 1
+                ins += 1
+        log.append((len(parents), len(kids), ub, ins, len(heap)))
+    return log, nodes, ub, incumbent
+
+
+@pytest.mark.parametrize("n,m,seed", [(6, 3, 301), (7, 4, 302), (8, 3, 303), (8, 5, 304)])
+@pytest.mark.parametrize("cap", [1, 5, 40])
+def test_best_first_matches_heap_statement(n, m, seed, cap):
+    p = inst(n, m, seed)
+    want_log, want_nodes, want_ub, want_inc = best_first_python(p, 1 << 30, cap)
+    r = oracle.bnb(p, 1 << 30, None, pool_cap=cap, best_first=True, steplog_cap=1 << 20)
+    assert r["proven"] and r["ub"] == want_ub == oracle.brute(p)
+    assert r["nodes_bounded"] == want_nodes
+    got = [tuple(int(x) for x in row[:5]) for row in r["steplog"]]
+    assert got == want_log
+    assert tuple(r["incumbent"]) == want_inc
+
+
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 311), (6, 4, 312), (7, 3, 313), (8, 4, 314)])
+def test_best_first_node_count_closed_form(n, m, seed):
+    """With UB0 = optimum the explored set does not depend on the order."""
+    p = inst(n, m, seed)
+    opt = oracle.brute(p)
+    want = expanded_count(p, opt)
+    for cap in [1, 2, 7, 50, 1 << 20]:
+        r = oracle.bnb(p, opt, None, pool_cap=cap, best_first=True)
+        assert r["nodes_bounded"] == want and r["proven"] and r["ub"] == opt
+
+
+@pytest.mark.parametrize("n,m,seed", [(8, 4, 321), (9, 5, 322), (10, 3, 323)])
+def test_best_first_from_neh(n, m, seed):
+    p = inst(n, m, seed)
+    opt = oracle.brute(p) if n <= 9 else None
+    ms, perm = oracle.neh(p)
+    for cap in [3, 64, 1 << 20]:
+        r = oracle.bnb(p, ms, perm, pool_cap=cap, best_first=True, steplog_cap=1 << 20)
+        assert r["proven"]
+        if opt is not None:
+            assert r["ub"] == opt
+        assert oracle.makespan(p, r["incumbent"]) == r["ub"]
+        log = r["steplog"]
+        assert log.shape[0] == r["steps"]
+        assert 1 + int(log[:, 1].sum()) == r["nodes_bounded"]
+        assert (log[:, 1] <= cap).all() or cap < p.shape[0]
+        assert (log[:, 2] <= ms).all() and (np.diff(log[:, 2]) <= 0).all()
+
+
+def test_best_first_budget():
+    p = inst(12, 5, 331)
+    r = oracle.bnb(p, 1 << 30, None, pool_cap=8, node_budget=200, best_first=True)
+    assert not r["proven"] and r["nodes_bounded"] >= 200
