@@ -12,9 +12,11 @@ JSON line.  Further legs:
   batched  the same pool as 64 pools of 4,096 in one graph-captured batch vs
            64 plain launches, and 64 seeded instances of mixed shape with
            log-normal pool sizes, batched vs plain;
-  heads    the bound variant with earliest-start releases: throughput on the
-           same pool, and solves of small instances with either bound;
-  bnb      depth-first branch-and-bound from NEH on the 200 x 20 instance;
+  variants the heads bound variant (earliest-start releases) and best-first
+           selection: heads throughput on the same pool, and solves of small
+           instances depth first, depth first with heads, and best first;
+  bnb      branch-and-bound from NEH on the 200 x 20 instance, depth first and
+           best first;
   serving  a Poisson stream of solves over mixed shapes through the serving
            loop: p50/p99 latency, nodes/s, and identity with each solve alone;
   cpu_baseline  the plain C oracle on a bounded prefix of the pool on the
@@ -156,10 +158,11 @@ def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
     return out
 
 
-def heads_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
-    """The heads variant (releases as earliest starts of unscheduled jobs): its
-    bound throughput on the same 200x20 pool, and depth-first solves from NEH
-    of seeded small instances with either bound (same pool_cap and budget)."""
+def variants_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
+    """The next rows of the path: the heads bound variant (releases as the
+    earliest starts of unscheduled jobs) and best-first selection.  Bound
+    throughput with heads on the same 200x20 pool, and solves from NEH of
+    seeded small instances with each strategy (same pool_cap and budget)."""
     from paper_1208_3933_amd import fspbb, serve
     out = {}
     with fspbb.create_instance(p, heads=True) as inst:
@@ -167,23 +170,24 @@ def heads_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
         for _ in range(2):
             fspbb.bound_pool(inst, pre_d, dep_d, o, stream)
         t = _time(lambda: fspbb.bound_pool(inst, pre_d, dep_d, o, stream), steps)
-        out["bound_200x20_nodes_per_s"] = int(dep_d.shape[0]) / t
+        out["heads_bound_200x20_nodes_per_s"] = int(dep_d.shape[0]) / t
     shapes = [(20, 5), (20, 10), (50, 5), (100, 5)]
     cands = serve.candidates(6, shapes)
     budget, cap = 2_000_000, 8192
+    modes = {"dfs": (False, False), "dfs_heads": (True, False), "best_first": (False, True)}
     rows = {}
     for c in cands:
         key = "%dx%d" % shapes[c.shape]
-        r = rows.setdefault(key, {"instances": 0, "plain_proven": 0, "heads_proven": 0, "plain_nodes": 0,
-                                  "heads_nodes": 0, "plain_s": 0.0, "heads_s": 0.0})
+        r = rows.setdefault(key, {"instances": 0})
         r["instances"] += 1
-        for mode in ("plain", "heads"):
-            with fspbb.create_instance(c.p, heads=(mode == "heads")) as inst:
+        for mode, (heads, bfirst) in modes.items():
+            with fspbb.create_instance(c.p, heads=heads) as inst:
                 t0 = time.perf_counter()
-                res = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, 0, stream)
-                r[mode + "_s"] += time.perf_counter() - t0
-            r[mode + "_proven"] += int(res["proven"])
-            r[mode + "_nodes"] += int(res["nodes_bounded"])
+                res = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, 0, stream, best_first=bfirst)
+                dt = time.perf_counter() - t0
+            r[mode + "_proven"] = r.get(mode + "_proven", 0) + int(res["proven"])
+            r[mode + "_nodes"] = r.get(mode + "_nodes", 0) + int(res["nodes_bounded"])
+            r[mode + "_s"] = r.get(mode + "_s", 0.0) + dt
     out["solves"] = rows
     out["pool_cap"], out["node_budget"] = cap, budget
     return out
@@ -226,21 +230,23 @@ def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: in
             "unsolved_by_shape": unsolved}
 
 
-def bnb_leg(inst, steps: int, stream) -> dict:
-    """Depth-first branch-and-bound from NEH on the same instance, pool steps of
-    262,144 children (the paper's largest pool), stack resident on the device."""
+def bnb_leg(inst, steps: int, stream, best_first: bool = False) -> dict:
+    """Branch-and-bound from NEH on the same instance, pool steps of 262,144
+    children (the paper's largest pool), search state resident on the device:
+    depth first (stack) or best first (frontier by bound)."""
     import torch
 
     from paper_1208_3933_amd import fspbb
-    fspbb.solve(inst, fspbb.UB_NEH, POOL, 1 + POOL, 0, stream)  # warm-up: one step
+    fspbb.solve(inst, fspbb.UB_NEH, POOL, 1 + POOL, 0, stream, best_first=best_first)  # warm-up: one step
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = fspbb.solve(inst, fspbb.UB_NEH, POOL, 1 + steps * POOL, 0, stream)
+    r = fspbb.solve(inst, fspbb.UB_NEH, POOL, 1 + steps * POOL, 0, stream, best_first=best_first)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"nodes_per_s": r["nodes_bounded"] / dt, "nodes_bounded": r["nodes_bounded"], "steps": r["steps"],
             "ms_per_step": dt * 1e3 / max(r["steps"], 1), "ub": r["opt"], "ub0_neh": r["ub0"],
-            "pool_cap": POOL, "proven": bool(r["proven"])}
+            "pool_cap": POOL, "proven": bool(r["proven"]),
+            ("max_frontier" if best_first else "max_stack"): r["max_stack"]}
 
 
 def main() -> int:
@@ -256,8 +262,8 @@ def main() -> int:
     ap.add_argument("--serve-seeds", type=int, default=10, help="screened instances per shape")
     ap.add_argument("--serve-pool-cap", type=int, default=8192)
     ap.add_argument("--serve-budget", type=int, default=2000000)
-    ap.add_argument("--no-heads", dest="heads", action="store_false",
-                    help="skip the leg of the heads bound variant")
+    ap.add_argument("--no-variants", "--no-heads", dest="heads", action="store_false",
+                    help="skip the leg of the bound and selection variants")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes before timing (a kernel of known "
                          "traffic, to scale HBM counters read under a profiler)")
@@ -345,10 +351,11 @@ def main() -> int:
         result["batched"] = batched_leg(inst, pre_d, dep_d, args.batched_reps, stream)
         print("[bench] batched leg done", file=sys.stderr, flush=True)
     if args.heads:
-        result["heads"] = heads_leg(p, pre_d, dep_d, args.steps, stream)
-        print("[bench] heads leg done", file=sys.stderr, flush=True)
+        result["variants"] = variants_leg(p, pre_d, dep_d, args.steps, stream)
+        print("[bench] variants leg done", file=sys.stderr, flush=True)
     if args.bnb_steps > 0:
         result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)
+        result["bnb_best_first"] = bnb_leg(inst, args.bnb_steps, stream, best_first=True)
         print("[bench] bnb leg done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         result["serving"] = serving_leg(args.serve_requests, args.serve_seeds, args.serve_pool_cap,

@@ -297,6 +297,21 @@ fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t n
                      fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
                      void *stream);
 
+/* Flag of fsp_solve_ex: select best first instead of depth first (Sec.
+ * III-A).  The frontier is ordered by (bound, insertion order).  Each step
+ * drops the frontier nodes with bound >= the upper bound, takes parents from
+ * the front while their children fit in pool_cap (the first always), runs
+ * the same branch/bound/upper-bound step as fsp_solve, and inserts the
+ * survivors in child order.  The search is proven when the frontier is empty
+ * after the drop.  max_stack reports the largest frontier; steplog[4] the
+ * frontier size after each step. */
+#define FSP_SOLVE_BEST_FIRST 1
+
+/* fsp_solve with flags (0 = depth first as fsp_solve, or FSP_SOLVE_BEST_FIRST). */
+fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t node_budget, int32_t flags,
+                        fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
+                        void *stream);
+
 /* fsp_neh - NEH heuristic schedule (host computation): perm_out (host n, may
  * be NULL) and its makespan. */
 fsp_status fsp_neh(fsp_instance inst, int32_t *perm_out, int32_t *makespan);

@@ -29,6 +29,13 @@ struct StepArgs {
     int out_reversed;
     uint32_t *surv_per_parent;   // K survivor counts per parent (written, also for 0 children); may be null
     int32_t *incumbent;          // n; written when a complete child improves ub_in; may be null
+    // Row indirection (best-first frontier in a slab of rows); null = direct.
+    // Parent p's row is parents + pslot[p] * n.  Survivor rank r's row goes to
+    // out_rows + oslot[r * oslot_step] * n (its depth and bound still go to
+    // out_depth/out_lb at out_base + r).
+    const int32_t *pslot;
+    const int32_t *oslot;
+    int64_t oslot_step;
 };
 
 // Device scratch of one search's step (children capacity C, parents capacity K).

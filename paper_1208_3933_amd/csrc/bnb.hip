@@ -28,7 +28,8 @@ __device__ __forceinline__ ReqP req_of(const StepReq *reqs) { return as_const(re
 __device__ __forceinline__ const int32_t *parent_row(ReqP q, int64_t p)
 {
     const int64_t r = q->a.parents_reversed ? (q->a.parent_top - 1 - p) : p;
-    return q->a.parents + r * (int64_t)q->a.n;
+    const int64_t row = q->a.pslot ? (int64_t)q->a.pslot[r] : r;
+    return q->a.parents + row * (int64_t)q->a.n;
 }
 __device__ __forceinline__ int32_t parent_depth(ReqP q, int64_t p)
 {
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(256) void mstep_scatter_kernel(const StepReq *__res
     if (dst < 0 || dst >= q->a.out_cap) return;  // overflow is reported by the host
     const int d = q->w.cdepth[c];
     const int32_t *src = q->w.crow + c * (int64_t)n;
-    int32_t *out = q->a.out_rows + dst * (int64_t)n;
+    const int64_t orow = q->a.oslot ? (int64_t)q->a.oslot[s * q->a.oslot_step] : dst;
+    int32_t *out = q->a.out_rows + orow * (int64_t)n;
     for (int t = lane; t < d; t += 64) out[t] = src[t];
     if (lane == 0) {
         q->a.out_depth[dst] = d;

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <vector>
 
+#include "best_first.h"
 #include "search.h"
 
 using namespace fspbb;
@@ -503,6 +504,243 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     return e;
 }
 
+// ---------------------------------------------------------------- best first
+
+namespace {
+
+// Device state of a best-first search: the row slab, the free-slot stack, the
+// frontier records (ping-pong), and the per-step survivor and sort buffers.
+struct BestFirst {
+    hipStream_t s = nullptr;
+    int n = 0;
+    int64_t C = 0;              // slots
+    int32_t *slab = nullptr;    // C x n
+    int32_t *fl = nullptr;      // C: free slots, the top nfree in use
+    int32_t *rec[2] = {nullptr, nullptr};  // each 3 x C: bound, depth, slot
+    int64_t nfree = 0;
+    int64_t Scap = 0;           // survivor buffers: depth, bound, keys, ranks, sorted keys, sorted ranks
+    int32_t *sbuf = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int64_t *sel = nullptr;     // 3 scalars of the selection
+    int32_t *dinc = nullptr;
+
+    Frontier F(int i) const { return Frontier{rec[i], rec[i] + C, rec[i] + 2 * C}; }
+    int32_t *S(int k) const { return sbuf + (size_t)k * Scap; }
+
+    hipError_t alloc(int64_t slots)
+    {
+        C = slots;
+        hipError_t e = stream_alloc((void **)&slab, (size_t)C * n * 4, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&fl, (size_t)C * 4, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&rec[0], (size_t)C * 12, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&rec[1], (size_t)C * 12, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&sel, 64, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&dinc, (size_t)n * 4, s);
+        return e;
+    }
+
+    // Room for `need` more rows: double the slot count until it fits, keep
+    // every slot's row, the live records of frontier `cur` and the free stack.
+    hipError_t grow(int64_t need, int cur, int64_t M)
+    {
+        if (nfree >= need) return hipSuccess;
+        int64_t C2 = C;
+        while (nfree + (C2 - C) < need) C2 *= 2;
+        int32_t *slab2 = nullptr, *fl2 = nullptr, *r0 = nullptr, *r1 = nullptr;
+        hipError_t e = stream_alloc((void **)&slab2, (size_t)C2 * n * 4, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&fl2, (size_t)C2 * 4, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&r0, (size_t)C2 * 12, s);
+        if (e == hipSuccess) e = stream_alloc((void **)&r1, (size_t)C2 * 12, s);
+        if (e != hipSuccess) return e;
+        const Frontier a = F(cur), b{r0, r0 + C2, r0 + 2 * C2};
+        e = hipMemcpyAsync(slab2, slab, (size_t)C * n * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(fl2, fl, (size_t)nfree * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = bf_fill_slots(fl2 + nfree, C2 - C, (int32_t)C, s);
+        if (e == hipSuccess && M > 0) e = hipMemcpyAsync(b.lb, a.lb, (size_t)M * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && M > 0) e = hipMemcpyAsync(b.depth, a.depth, (size_t)M * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && M > 0) e = hipMemcpyAsync(b.slot, a.slot, (size_t)M * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        hipFreeAsync(slab, s);
+        hipFreeAsync(fl, s);
+        hipFreeAsync(rec[0], s);
+        hipFreeAsync(rec[1], s);
+        slab = slab2;
+        fl = fl2;
+        rec[cur] = r0;
+        rec[cur ^ 1] = r1;
+        nfree += C2 - C;
+        C = C2;
+        return hipSuccess;
+    }
+
+    hipError_t ensure_survivors(int64_t cap)
+    {
+        if (cap <= Scap) return hipSuccess;
+        if (sbuf) hipFreeAsync(sbuf, s);
+        sbuf = nullptr;
+        Scap = std::max<int64_t>(cap, 1024);
+        hipError_t e = stream_alloc((void **)&sbuf, (size_t)Scap * 6 * 4, s);
+        if (e != hipSuccess) Scap = 0;
+        return e;
+    }
+
+    void release()
+    {
+        for (void *ptr : {(void *)slab, (void *)fl, (void *)rec[0], (void *)rec[1], (void *)sbuf, tmp, (void *)sel,
+                          (void *)dinc})
+            if (ptr) hipFreeAsync(ptr, s);
+        slab = fl = nullptr;
+        rec[0] = rec[1] = sbuf = dinc = nullptr;
+        tmp = nullptr;
+        sel = nullptr;
+    }
+};
+
+// Pool-synchronous best-first search (Sec. III-A), with the frontier on the
+// device.  Each step: drop the frontier records the upper bound eliminates,
+// take parents from the front while their children fit in pool_cap (the
+// first always), branch, bound and update the upper bound as the depth-first
+// step does, then merge the survivors (child order kept on equal bounds) into
+// the frontier.  Stops when the frontier is empty after the drop (proven) or
+// the node budget is reached.
+fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap, int64_t node_budget,
+                            fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
+                            hipStream_t s)
+{
+    const int n = inst->n;
+    std::vector<int32_t> inc(n, -1);
+    int32_t UB = ub0 == FSP_UB_NEH ? neh(inst->p_host, n, inst->m, inc.data()) : ub0;
+    const int32_t ub_start = UB;
+    BestFirst bf;
+    bf.s = s;
+    bf.n = n;
+    StepBuffers B;
+    TickContext ctx;
+    ctx.s = s;
+    auto cleanup = [&]() {
+        bf.release();
+        B.release(s);
+        ctx.release();
+    };
+    hipError_t e = bf.alloc(std::max<int64_t>(4096, 4 * pool_cap));
+    // the root: slot 0 holds an all-zero row; record 0 = (bound, depth 0, slot 0)
+    Frontier F0 = bf.F(0);
+    if (e == hipSuccess) e = hipMemsetAsync(bf.slab, 0, (size_t)n * 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(F0.depth, 0, 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(F0.slot, 0, 4, s);
+    if (e == hipSuccess) e = bound_rows(inst, bf.slab, F0.depth, 1, F0.lb, s);
+    int32_t lb0 = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&lb0, F0.lb, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    int64_t M = lb0 < UB ? 1 : 0;
+    e = bf_fill_slots(bf.fl, bf.C - M, (int32_t)M, s);
+    bf.nfree = bf.C - M;
+    int64_t nodes = 1, steps = 0, max_front = M;
+    int32_t improvements = 0;
+    int cur = 0;
+    bool proven = false;
+    while (e == hipSuccess) {
+        int64_t sel[3] = {0, 0, 0};
+        if (M > 0) {
+            e = bf_select(bf.F(cur), M, UB, n, pool_cap, bf.sel, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(sel, bf.sel, sizeof(sel), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) break;
+        }
+        const int64_t Mp = sel[0], K = sel[1], nch = sel[2];
+        if (Mp == 0) {
+            proven = true;
+            break;
+        }
+        if (nodes >= node_budget) break;
+        const TabLayout L(1, 1);
+        e = bf.grow(nch, cur, M);
+        if (e == hipSuccess) e = B.ensure_k(K, s);
+        if (e == hipSuccess) e = B.ensure_c(nch, n, s);
+        if (e == hipSuccess) e = bf.ensure_survivors(nch);
+        if (e == hipSuccess) e = ctx.reserve(L.total);
+        if (e != hipSuccess) break;
+        const Frontier Fc = bf.F(cur), Fn = bf.F(cur ^ 1);
+        char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
+        StepReq *dentry = (StepReq *)(d + L.req);
+        StepReq q;
+        std::memset(&q, 0, sizeof(q));
+        q.a.n = n;
+        q.a.ub_in = UB;
+        q.a.parents = bf.slab;
+        q.a.pslot = Fc.slot;
+        q.a.pdepth = Fc.depth;
+        q.a.K = K;
+        q.a.out_rows = bf.slab;
+        q.a.oslot = bf.fl + bf.nfree - 1;
+        q.a.oslot_step = -1;
+        q.a.out_depth = bf.S(0);
+        q.a.out_lb = bf.S(1);
+        q.a.out_base = 0;
+        q.a.out_cap = nch;
+        q.a.incumbent = bf.dinc;
+        q.w = B.w;
+        q.nchild = nch;
+        bind_results(q, dentry, UB);
+        *(StepReq *)(h + L.req) = q;
+        *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
+        *(ScanSeg *)(h + L.seg2) = ScanSeg{q.w.keep, q.w.pos, nch, q.w.nsurv, B.sums_c};
+        const uint32_t *dnsurv = &dentry->res.nsurv;
+        e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
+        if (e == hipSuccess) e = mstep_branch(dentry, 1, K, nch, s);
+        if (e == hipSuccess) e = bound_rows(inst, q.w.crow, q.w.cdepth, nch, q.w.clb, s);  // parents of mixed depths
+        if (e == hipSuccess) e = mstep_finish(dentry, (const ScanSeg *)(d + L.seg2), 1, K, nch, s);
+        if (e == hipSuccess)
+            e = bf_sort_survivors(bf.S(1), dnsurv, nch, bf.S(2), bf.S(3), bf.S(4), bf.S(5), &bf.tmp, &bf.tmp_bytes, s);
+        if (e == hipSuccess)
+            e = bf_merge(Fc, K, Mp - K, bf.S(4), bf.S(5), bf.S(0), dnsurv, nch, bf.fl, bf.nfree, Fn, s);
+        if (e == hipSuccess) e = bf_free_slots(Fc, K, Mp, M, bf.fl, bf.nfree, dnsurv, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h + L.req, d + L.req, sizeof(StepReq), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) break;
+        const StepResultDev o = ((const StepReq *)(h + L.req))->res;
+        if (o.bad || (int64_t)o.nchild != nch) {
+            cleanup();
+            return FSP_E_BADNODE;
+        }
+        const int64_t S = o.nsurv;
+        nodes += nch;
+        const uint32_t idx = (uint32_t)(o.best & 0xffffffffu);
+        if (idx != 0xffffffffu) {
+            UB = (int32_t)(o.best >> 32);
+            ++improvements;
+            e = hipMemcpyAsync(inc.data(), bf.dinc, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) break;
+        }
+        bf.nfree = bf.nfree - S + K + (M - Mp);
+        M = (Mp - K) + S;
+        cur ^= 1;
+        max_front = std::max(max_front, M);
+        if (steplog && steps < steplog_cap) {
+            int64_t *Lg = steplog + steps * 6;
+            Lg[0] = K; Lg[1] = nch; Lg[2] = UB; Lg[3] = S; Lg[4] = M; Lg[5] = (int64_t)o.fingerprint;
+        }
+        ++steps;
+    }
+    cleanup();
+    if (e != hipSuccess) return fail_status(e);
+    res->opt = UB;
+    res->proven = proven ? 1 : 0;
+    res->nodes_bounded = nodes;
+    res->steps = steps;
+    res->ub0 = ub_start;
+    res->improvements = improvements;
+    res->max_stack = max_front;
+    if (perm_out) std::copy(inc.begin(), inc.end(), perm_out);
+    return proven ? FSP_OK : FSP_BUDGET;
+}
+
+}  // namespace
+
 }  // namespace fspbb
 
 extern "C" {
@@ -599,11 +837,22 @@ fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t n
                      fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
                      void *stream)
 {
+    return fsp_solve_ex(inst, ub0, pool_cap, node_budget, 0, res, perm_out, steplog, steplog_cap, stream);
+}
+
+fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t node_budget, int32_t flags,
+                        fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
+                        void *stream)
+{
     if (!inst || !res || pool_cap < 1 || node_budget < 1 || (ub0 < 0 && ub0 != FSP_UB_NEH)) return FSP_E_INVAL;
+    if (flags & ~FSP_SOLVE_BEST_FIRST) return FSP_E_INVAL;
     std::memset(res, 0, sizeof(*res));
     DeviceGuard g(inst->device);
     if (!g.ok) return FSP_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
+    if (flags & FSP_SOLVE_BEST_FIRST)
+        return best_first_solve(inst, ub0, pool_cap, node_budget, res, perm_out, steplog, steplog ? steplog_cap : 0,
+                                s);
     Search S;
     TickContext ctx;
     ctx.s = s;

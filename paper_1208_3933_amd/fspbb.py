@@ -110,6 +110,9 @@ _SIGNATURES = {
                                               ctypes.c_int64, _vp, ctypes.POINTER(StepResult), _vp]),
     "fsp_solve": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(SolveResult),
                                    _i32p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, _vp]),
+    "fsp_solve_ex": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.POINTER(SolveResult), _i32p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int64, _vp]),
     "fsp_batch_create": (ctypes.c_int32, [ctypes.POINTER(PoolDesc), ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(_vp)]),
     "fsp_batch_run": (ctypes.c_int32, [_vp, _vp]),
@@ -313,15 +316,20 @@ def branch_and_prune(inst: Instance, parents, parent_depths, ub_in: int, childre
     return out
 
 
+SOLVE_BEST_FIRST = 1
+
+
 def solve(inst: Instance, ub0: int = UB_NEH, pool_cap: int = 1 << 18, node_budget: int = 1 << 62,
-          steplog_cap: int = 0, stream=None) -> dict:
-    """Depth-first branch-and-bound with the stack on the device."""
+          steplog_cap: int = 0, stream=None, best_first: bool = False) -> dict:
+    """Branch-and-bound with the search state on the device: depth first
+    (stack), or best first (frontier ordered by bound and insertion)."""
     res = SolveResult()
     perm = np.empty(inst.n, np.int32)
     log = np.zeros((max(steplog_cap, 1), 6), np.int64)
-    st = lib().fsp_solve(inst.handle, int(ub0), int(pool_cap), int(node_budget), ctypes.byref(res),
-                         perm.ctypes.data_as(_i32p), log.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                         int(steplog_cap), _stream_handle(stream))
+    st = lib().fsp_solve_ex(inst.handle, int(ub0), int(pool_cap), int(node_budget),
+                            SOLVE_BEST_FIRST if best_first else 0, ctypes.byref(res),
+                            perm.ctypes.data_as(_i32p), log.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            int(steplog_cap), _stream_handle(stream))
     if st not in (OK, BUDGET):
         _check(st, "fsp_solve")
     out = {fn: getattr(res, fn) for fn, _ in SolveResult._fields_}
