@@ -22,10 +22,12 @@ hipError_t bf_select(const Frontier &F, int64_t M, int32_t ub, int n, int64_t po
 hipError_t bf_fill_slots(int32_t *freelist, int64_t count, int32_t first, hipStream_t s);
 
 // Orders the survivors of a step by bound, keeping child order on ties: sets
-// keys[r] = lb[r] for r < *nsurv and INT32_MAX beyond (up to cap), then sorts
-// (key, rank) pairs stably into keys_out / rank_out.  tmp is grown as needed.
-hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t cap, int32_t *keys, int32_t *ranks,
-                             int32_t *keys_out, int32_t *rank_out, void **tmp, size_t *tmp_bytes, hipStream_t s);
+// keys[r] = lb[r] for r < *nsurv and a padding key >= ub beyond (up to cap),
+// then sorts (key, rank) pairs stably on the bits of ub into keys_out /
+// rank_out (every survivor's bound is below ub).  tmp is grown as needed.
+hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t cap, int32_t ub, int32_t *keys,
+                             int32_t *ranks, int32_t *keys_out, int32_t *rank_out, void **tmp, size_t *tmp_bytes,
+                             hipStream_t s);
 
 // Merges the remaining records A = F[a0, a0 + nA) with the *nsurv sorted
 // survivors (sorted bounds kb, ranks rk; survivor rank r has depth sdep[r] and

@@ -76,11 +76,11 @@ __global__ void bf_fill_kernel(int32_t *__restrict__ fl, int64_t count, int32_t 
 }
 
 __global__ void bf_keys_kernel(const int32_t *__restrict__ lb, const uint32_t *__restrict__ nsurv, int64_t cap,
-                               int32_t *__restrict__ keys, int32_t *__restrict__ ranks)
+                               int32_t pad, int32_t *__restrict__ keys, int32_t *__restrict__ ranks)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
-    keys[i] = i < (int64_t)*nsurv ? lb[i] : INT32_MAX;
+    keys[i] = i < (int64_t)*nsurv ? lb[i] : pad;
     ranks[i] = (int32_t)i;
 }
 
@@ -151,16 +151,22 @@ hipError_t bf_fill_slots(int32_t *freelist, int64_t count, int32_t first, hipStr
     return hipGetLastError();
 }
 
-hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t cap, int32_t *keys, int32_t *ranks,
-                             int32_t *keys_out, int32_t *rank_out, void **tmp, size_t *tmp_bytes, hipStream_t s)
+hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t cap, int32_t ub, int32_t *keys,
+                             int32_t *ranks, int32_t *keys_out, int32_t *rank_out, void **tmp, size_t *tmp_bytes,
+                             hipStream_t s)
 {
     if (cap <= 0) return hipSuccess;
-    bf_keys_kernel<<<blocks256(cap), 256, 0, s>>>(lb, nsurv, cap, keys, ranks);
+    // survivors have bounds below ub: sort on the bits of ub only, with the
+    // padding past the survivors at the largest key of that width (>= ub)
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) - 1 < (int64_t)ub) ++bits;
+    const int32_t pad = (int32_t)(((int64_t)1 << bits) - 1);
+    bf_keys_kernel<<<blocks256(cap), 256, 0, s>>>(lb, nsurv, cap, pad, keys, ranks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t need = 0;
     e = hipcub::DeviceRadixSort::SortPairs(nullptr, need, reinterpret_cast<const uint32_t *>(keys),
-                                           reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int)cap, 0, 32,
+                                           reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int)cap, 0, bits,
                                            s);
     if (e != hipSuccess) return e;
     if (need > *tmp_bytes) {
@@ -173,7 +179,7 @@ hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t c
     }
     return hipcub::DeviceRadixSort::SortPairs(*tmp, need, reinterpret_cast<const uint32_t *>(keys),
                                               reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int)cap, 0,
-                                              32, s);
+                                              bits, s);
 }
 
 hipError_t bf_merge(const Frontier &F, int64_t a0, int64_t nA, const int32_t *kb, const int32_t *rk,

@@ -624,6 +624,11 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         ctx.release();
     };
     hipError_t e = bf.alloc(std::max<int64_t>(4096, 4 * pool_cap));
+    // step buffers at their usual size up front (a parent with more children
+    // than pool_cap grows them later)
+    if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
+    if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
+    if (e == hipSuccess) e = bf.ensure_survivors(pool_cap);
     // the root: slot 0 holds an all-zero row; record 0 = (bound, depth 0, slot 0)
     Frontier F0 = bf.F(0);
     if (e == hipSuccess) e = hipMemsetAsync(bf.slab, 0, (size_t)n * 4, s);
@@ -694,7 +699,8 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         if (e == hipSuccess) e = bound_rows(inst, q.w.crow, q.w.cdepth, nch, q.w.clb, s);  // parents of mixed depths
         if (e == hipSuccess) e = mstep_finish(dentry, (const ScanSeg *)(d + L.seg2), 1, K, nch, s);
         if (e == hipSuccess)
-            e = bf_sort_survivors(bf.S(1), dnsurv, nch, bf.S(2), bf.S(3), bf.S(4), bf.S(5), &bf.tmp, &bf.tmp_bytes, s);
+            e = bf_sort_survivors(bf.S(1), dnsurv, nch, UB, bf.S(2), bf.S(3), bf.S(4), bf.S(5), &bf.tmp,
+                                  &bf.tmp_bytes, s);
         if (e == hipSuccess)
             e = bf_merge(Fc, K, Mp - K, bf.S(4), bf.S(5), bf.S(0), dnsurv, nch, bf.fl, bf.nfree, Fn, s);
         if (e == hipSuccess) e = bf_free_slots(Fc, K, Mp, M, bf.fl, bf.nfree, dnsurv, s);
