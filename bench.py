@@ -16,7 +16,8 @@ JSON line.  Further legs:
            selection: heads throughput on the same pool, and solves of small
            instances depth first, depth first with heads, and best first;
   bnb      branch-and-bound from NEH on the 200 x 20 instance, depth first and
-           best first;
+           best first; the hybrid scheme (host explorer threads, shared GPU
+           bounding over PCIe) against the device-resident search;
   serving  a Poisson stream of solves over mixed shapes through the serving
            loop: p50/p99 latency, nodes/s, and identity with each solve alone;
   cpu_baseline  the plain C oracle on a bounded prefix of the pool on the
@@ -193,6 +194,30 @@ def variants_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
     return out
 
 
+def hybrid_leg(inst, p200, stream, threads: int) -> dict:
+    """The paper's host-driven scheme with several host explorers (fsp_explore:
+    host stacks and branching, shared GPU bounding with PCIe copies of every
+    pool) against the device-resident depth-first search: time to the proof on
+    a seeded 20x5 instance, and nodes/s on the 200x20 instance with a budget."""
+    from paper_1208_3933_amd import fspbb, gen
+    out = {"threads": threads}
+    p = gen.processing_times(20, 5, gen.make_seed(4, 2, gen.PURPOSE_TIMES))  # proven within ~1.5 M nodes
+    with fspbb.create_instance(p) as i20:
+        fspbb.solve(i20, fspbb.UB_NEH, 8192, 10000, 0, stream)
+        t0 = time.perf_counter()
+        d = fspbb.solve(i20, fspbb.UB_NEH, 8192, 1 << 40, 0, stream)
+        td = time.perf_counter() - t0
+        h = fspbb.explore(i20, fspbb.UB_NEH, threads, 8192, 1 << 40, stream)
+    out["20x5_proof"] = {"device_dfs_s": td, "device_dfs_nodes": d["nodes_bounded"], "hybrid_s": h["seconds"],
+                         "hybrid_nodes": h["nodes_bounded"], "hybrid_launches": h["pools"],
+                         "same_optimum": bool(d["proven"] and h["proven"] and d["opt"] == h["opt"])}
+    budget = 4 * POOL
+    h = fspbb.explore(inst, fspbb.UB_NEH, threads, POOL // threads, budget, stream)
+    out["200x20_budget"] = {"hybrid_nodes_per_s": h["nodes_bounded"] / h["seconds"], "nodes": h["nodes_bounded"],
+                            "launches": h["pools"], "pool_cap_per_explorer": POOL // threads}
+    return out
+
+
 def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: int, stream) -> dict:
     """Poisson stream of solves at 0.7 x the measured saturation rate."""
     from paper_1208_3933_amd import gen, serve
@@ -356,6 +381,7 @@ def main() -> int:
     if args.bnb_steps > 0:
         result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)
         result["bnb_best_first"] = bnb_leg(inst, args.bnb_steps, stream, best_first=True)
+        result["hybrid"] = hybrid_leg(inst, p, stream, max(1, min(16, os.cpu_count() or 1)))
         print("[bench] bnb leg done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         result["serving"] = serving_leg(args.serve_requests, args.serve_seeds, args.serve_pool_cap,

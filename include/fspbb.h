@@ -312,6 +312,34 @@ fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_
                         fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
                         void *stream);
 
+typedef struct {
+    int32_t opt;           /* best makespan found (the optimum when proven) */
+    int32_t proven;        /* 1 when every subtree was explored within the budget */
+    int64_t nodes_bounded; /* root and children bounded (depends on thread timing) */
+    int64_t pools;         /* bounding launches (each merges the pools waiting at the time) */
+    int32_t threads;       /* host explorers */
+    int32_t ub0;           /* initial upper bound used */
+    double seconds;        /* wall time of the call */
+} fsp_explore_result;
+
+/*
+ * fsp_explore - hybrid search: host threads explore the tree, the GPU bounds
+ * their pools (Sec. III: the host selects and branches, the GPU bounds; with
+ * several host explorers, the multi-threaded exploration left to future work
+ * in Sec. V).  Each of `threads` explorers runs a depth-first search on its
+ * own host stack over subtrees taken from a shared list (the first levels of
+ * the tree, expanded breadth first until there are 4 per explorer): it pops
+ * parents while their children fit in pool_cap, writes the children's rows in
+ * host memory and hands them to one bounding thread, which merges the pools
+ * waiting at that moment into one host-to-device copy, one bound launch and
+ * one copy back.  The upper bound is shared (elimination: bound >= it).
+ * Node counts depend on thread timing; the optimum does not.  Synchronous.
+ *   ub0, pool_cap, node_budget as in fsp_solve; threads 1..256; perm_out host n.
+ * Returns FSP_OK (proven), FSP_BUDGET, or an error.
+ */
+fsp_status fsp_explore(fsp_instance inst, int32_t ub0, int32_t threads, int64_t pool_cap, int64_t node_budget,
+                       fsp_explore_result *res, int32_t *perm_out, void *stream);
+
 /* fsp_neh - NEH heuristic schedule (host computation): perm_out (host n, may
  * be NULL) and its makespan. */
 fsp_status fsp_neh(fsp_instance inst, int32_t *perm_out, int32_t *makespan);

@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfspbb.so")
 ARCH = "gfx950"
 SOURCES = ["instance.cpp", "api.cpp", "bound_lane32.hip", "bound_packed.hip", "scan.hip", "bnb.hip",
-           "solve.hip", "best_first.hip", "batch.cpp", "tune.cpp", "server.cpp"]
+           "solve.hip", "best_first.hip", "batch.cpp", "tune.cpp", "server.cpp",
+           "explore.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

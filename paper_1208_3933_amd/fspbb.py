@@ -64,6 +64,12 @@ class SolveResult(ctypes.Structure):
                 ("max_stack", ctypes.c_int64)]
 
 
+class ExploreResult(ctypes.Structure):
+    _fields_ = [("opt", ctypes.c_int32), ("proven", ctypes.c_int32), ("nodes_bounded", ctypes.c_int64),
+                ("pools", ctypes.c_int64), ("threads", ctypes.c_int32), ("ub0", ctypes.c_int32),
+                ("seconds", ctypes.c_double)]
+
+
 class PoolDesc(ctypes.Structure):
     _fields_ = [("inst", ctypes.c_void_p), ("prefixes", ctypes.c_void_p), ("depths", ctypes.c_void_p),
                 ("N", ctypes.c_int64), ("out_lb", ctypes.c_void_p)]
@@ -113,6 +119,8 @@ _SIGNATURES = {
     "fsp_solve_ex": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.POINTER(SolveResult), _i32p, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int64, _vp]),
+    "fsp_explore": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.POINTER(ExploreResult), _i32p, _vp]),
     "fsp_batch_create": (ctypes.c_int32, [ctypes.POINTER(PoolDesc), ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(_vp)]),
     "fsp_batch_run": (ctypes.c_int32, [_vp, _vp]),
@@ -336,6 +344,21 @@ def solve(inst: Instance, ub0: int = UB_NEH, pool_cap: int = 1 << 18, node_budge
     out["status"] = st
     out["perm"] = perm
     out["steplog"] = log[:min(res.steps, steplog_cap)] if steplog_cap else None
+    return out
+
+
+def explore(inst: Instance, ub0: int = UB_NEH, threads: int = 8, pool_cap: int = 1 << 14,
+            node_budget: int = 1 << 62, stream=None) -> dict:
+    """Hybrid search: host explorer threads, shared GPU bounding of their pools."""
+    res = ExploreResult()
+    perm = np.empty(inst.n, np.int32)
+    st = lib().fsp_explore(inst.handle, int(ub0), int(threads), int(pool_cap), int(node_budget),
+                           ctypes.byref(res), perm.ctypes.data_as(_i32p), _stream_handle(stream))
+    if st not in (OK, BUDGET):
+        _check(st, "fsp_explore")
+    out = {fn: getattr(res, fn) for fn, _ in ExploreResult._fields_}
+    out["status"] = st
+    out["perm"] = perm
     return out
 
 
