@@ -137,10 +137,17 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
 #pragma unroll
     for (int k = 0; k < MV; ++k) { C[k] = 0; S[k] = 0; }
     const int32_t *row = prefixes + node * (int64_t)n;
+    // rows of a multiple of 4 jobs are 16-byte aligned: one vector load per 4 jobs
+    const bool vec = (n & 3) == 0 && ((uintptr_t)prefixes & 15) == 0;
     for (int t = 0; t < d; t += 4) {
         int32_t jj[4];
+        if (vec) {
+            const int4 v = *reinterpret_cast<const int4 *>(row + t);
+            jj[0] = v.x; jj[1] = v.y; jj[2] = v.z; jj[3] = v.w;
+        } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) jj[c] = row[min(t + c, n - 1)];
+            for (int c = 0; c < 4; ++c) jj[c] = row[min(t + c, n - 1)];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (t + c < d && ok) {
