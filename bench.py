@@ -20,8 +20,11 @@ JSON line.  Further legs:
            bounding over PCIe) against the device-resident search;
   serving  a Poisson stream of solves over mixed shapes through the serving
            loop: p50/p99 latency, nodes/s, and identity with each solve alone;
+  tables   nodes/s over the shape x pool grid of the paper's Tables II/III,
+           device-resident and with the pool's transfers in the timed region;
   cpu_baseline  the plain C oracle on a bounded prefix of the pool on the
-           host cores (its bounds are also compared with the GPU's).
+           host cores (its bounds are also compared with the GPU's), and on
+           one core per table shape (the ratio the paper's tables report).
 """
 from __future__ import annotations
 
@@ -218,6 +221,67 @@ def hybrid_leg(inst, p200, stream, threads: int) -> dict:
     return out
 
 
+TABLE_SHAPES = [(200, 20), (100, 20), (50, 20), (20, 20)]
+TABLE_POOLS = [4096 << k for k in range(7)]
+
+
+def tables_leg(stream, reps: int) -> dict:
+    """The grid of the paper's Tables II/III (shapes 20..200 x 20, pools 4096 ..
+    262144 nodes): nodes/s with the pool resident on the device, and with the
+    pool copied from pinned host memory and the bounds copied back in the timed
+    region (the paper's timing includes those transfers)."""
+    import torch
+
+    from paper_1208_3933_amd import fspbb, gen
+    out = {}
+    for n, m in TABLE_SHAPES:
+        p = gen.processing_times(n, m, gen.make_seed(6, n, gen.PURPOSE_TIMES))
+        pre, dep = gen.random_pool(n, TABLE_POOLS[-1], gen.make_seed(6, n, gen.PURPOSE_POOL))
+        h_pre = torch.from_numpy(pre).pin_memory()
+        h_dep = torch.from_numpy(dep).pin_memory()
+        h_out = torch.empty(TABLE_POOLS[-1], dtype=torch.int32).pin_memory()
+        d_pre, d_dep = h_pre.cuda(), h_dep.cuda()
+        d_out = torch.empty(TABLE_POOLS[-1], dtype=torch.int32, device="cuda")
+        row = {}
+        with fspbb.create_instance(p) as inst:
+            for N in TABLE_POOLS:
+                a, b, o = d_pre[:N], d_dep[:N], d_out[:N]
+
+                def device_only():
+                    fspbb.bound_pool(inst, a, b, o, stream)
+
+                def with_transfers():
+                    a.copy_(h_pre[:N], non_blocking=True)
+                    b.copy_(h_dep[:N], non_blocking=True)
+                    fspbb.bound_pool(inst, a, b, o, stream)
+                    h_out[:N].copy_(o, non_blocking=True)
+
+                for fn in (device_only, with_transfers, device_only, with_transfers):
+                    fn()
+                t_dev = _time(device_only, reps)
+                t_xfer = _time(with_transfers, reps)
+                row[str(N)] = {"device_nodes_per_s": N / t_dev, "with_transfers_nodes_per_s": N / t_xfer}
+        out["%dx%d" % (n, m)] = row
+    return out
+
+
+def single_core_rates() -> dict:
+    """The plain oracle on one host thread per shape of the table grid, on a
+    sample of about half a second each (the paper's reference is one CPU
+    core)."""
+    import oracle
+    from paper_1208_3933_amd import gen
+    sample = {200: 256, 100: 512, 50: 1024, 20: 4096}
+    out = {}
+    for n, m in TABLE_SHAPES:
+        p = gen.processing_times(n, m, gen.make_seed(6, n, gen.PURPOSE_TIMES))
+        pre, dep = gen.random_pool(n, sample[n], gen.make_seed(6, n, gen.PURPOSE_POOL))
+        t0 = time.perf_counter()
+        oracle.bound_pool(p, pre, dep)
+        out["%dx%d" % (n, m)] = sample[n] / (time.perf_counter() - t0)
+    return out
+
+
 def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: int, stream) -> dict:
     """Poisson stream of solves at 0.7 x the measured saturation rate."""
     from paper_1208_3933_amd import gen, serve
@@ -287,6 +351,8 @@ def main() -> int:
     ap.add_argument("--serve-seeds", type=int, default=10, help="screened instances per shape")
     ap.add_argument("--serve-pool-cap", type=int, default=8192)
     ap.add_argument("--serve-budget", type=int, default=2000000)
+    ap.add_argument("--tables-reps", type=int, default=10,
+                    help="repetitions per point of the shape x pool grid of the paper's tables (0 = skip)")
     ap.add_argument("--no-variants", "--no-heads", dest="heads", action="store_false",
                     help="skip the leg of the bound and selection variants")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -389,9 +455,18 @@ def main() -> int:
         s = result["serving"]
         result["p50_ms"], result["p99_ms"] = s["p50_ms"], s["p99_ms"]
         print("[bench] serving leg done", file=sys.stderr, flush=True)
+    if args.tables_reps > 0:
+        result["tables"] = tables_leg(stream, args.tables_reps)
+        print("[bench] tables leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
         result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads, gpu_lb)
+        one = single_core_rates()
+        result["cpu_baseline"]["single_core_nodes_per_s"] = one
+        if "tables" in result:  # GPU (with transfers) over one oracle core, the form of the paper's tables
+            result["tables_ratio_vs_one_core"] = {
+                shape: {N: round(v["with_transfers_nodes_per_s"] / one[shape], 1) for N, v in row.items()}
+                for shape, row in result["tables"].items()}
     inst.close()
     print(json.dumps(result), flush=True)
     return 0
