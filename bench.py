@@ -12,9 +12,11 @@ JSON line.  Further legs:
   batched  the same pool as 64 pools of 4,096 in one graph-captured batch vs
            64 plain launches, and 64 seeded instances of mixed shape with
            log-normal pool sizes, batched vs plain;
-  variants the heads bound variant (earliest-start releases) and best-first
-           selection: heads throughput on the same pool, and solves of small
-           instances depth first, depth first with heads, and best first;
+  variants the three mappings of the bound (lane per two nodes, lane per
+           node, wave per node) on the 50 x 10 and 200 x 20 pools; the heads
+           bound variant (earliest-start releases) and best-first selection:
+           heads throughput on the same pool, and solves of small instances
+           depth first, depth first with heads, and best first;
   bnb      branch-and-bound from NEH on the 200 x 20 instance, depth first and
            best first; the hybrid scheme (host explorer threads, shared GPU
            bounding over PCIe) against the device-resident search;
@@ -162,11 +164,13 @@ def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
     return out
 
 
-def variants_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
+def variants_leg(p, pre_d, dep_d, steps: int, stream, solve_seeds: int = 6) -> dict:
     """The next rows of the path: the heads bound variant (releases as the
     earliest starts of unscheduled jobs) and best-first selection.  Bound
     throughput with heads on the same 200x20 pool, and solves from NEH of
     seeded small instances with each strategy (same pool_cap and budget)."""
+    import torch
+
     from paper_1208_3933_amd import fspbb, serve
     out = {}
     with fspbb.create_instance(p, heads=True) as inst:
@@ -175,8 +179,31 @@ def variants_leg(p, pre_d, dep_d, steps: int, stream) -> dict:
             fspbb.bound_pool(inst, pre_d, dep_d, o, stream)
         t = _time(lambda: fspbb.bound_pool(inst, pre_d, dep_d, o, stream), steps)
         out["heads_bound_200x20_nodes_per_s"] = int(dep_d.shape[0]) / t
+    # the three mappings of the bound on the 50 x 10 and 200 x 20 pools
+    from paper_1208_3933_amd import gen
+    mappings = {}
+    for (n, m, N, cfg) in [(50, 10, 65536, 1), (200, 20, 262144, 2)]:
+        if n == 200:
+            pp, a, b = p, pre_d, dep_d
+        else:
+            pp = gen.processing_times(n, m, gen.make_seed(cfg, 0, gen.PURPOSE_TIMES))
+            hp, hd = gen.random_pool(n, N, gen.make_seed(cfg, 0, gen.PURPOSE_POOL))
+            a, b = torch.from_numpy(hp).cuda(), torch.from_numpy(hd).cuda()
+        row = {}
+        with fspbb.create_instance(pp) as inst:
+            o = b.new_empty(b.shape)
+            for name, v in (("lane_per_two_nodes_u16", fspbb.VARIANT_PACKED16),
+                            ("lane_per_node_i32", fspbb.VARIANT_LANE32), ("wave_per_node_i32", fspbb.VARIANT_WAVEPAIR)):
+                fspbb.bound_pool(inst, a, b, o, stream, variant=v)
+                t = _time(lambda: fspbb.bound_pool(inst, a, b, o, stream, variant=v), max(2, steps // 4))
+                row[name] = N / t
+        mappings["%dx%d_pool%d" % (n, m, N)] = row
+    out["mappings_nodes_per_s"] = mappings
+
+    if solve_seeds <= 0:
+        return out
     shapes = [(20, 5), (20, 10), (50, 5), (100, 5)]
-    cands = serve.candidates(6, shapes)
+    cands = serve.candidates(solve_seeds, shapes)
     budget, cap = 2_000_000, 8192
     modes = {"dfs": (False, False), "dfs_heads": (True, False), "best_first": (False, True)}
     rows = {}
@@ -353,6 +380,8 @@ def main() -> int:
     ap.add_argument("--serve-budget", type=int, default=2000000)
     ap.add_argument("--tables-reps", type=int, default=10,
                     help="repetitions per point of the shape x pool grid of the paper's tables (0 = skip)")
+    ap.add_argument("--variant-solves", type=int, default=6,
+                    help="seeded instances per shape solved with each strategy in the variants leg (0 = skip)")
     ap.add_argument("--no-variants", "--no-heads", dest="heads", action="store_false",
                     help="skip the leg of the bound and selection variants")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -442,7 +471,7 @@ def main() -> int:
         result["batched"] = batched_leg(inst, pre_d, dep_d, args.batched_reps, stream)
         print("[bench] batched leg done", file=sys.stderr, flush=True)
     if args.heads:
-        result["variants"] = variants_leg(p, pre_d, dep_d, args.steps, stream)
+        result["variants"] = variants_leg(p, pre_d, dep_d, args.steps, stream, args.variant_solves)
         print("[bench] variants leg done", file=sys.stderr, flush=True)
     if args.bnb_steps > 0:
         result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)

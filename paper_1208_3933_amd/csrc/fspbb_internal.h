@@ -46,6 +46,7 @@ struct DevTables {
     const uint32_t *tails16;  // n x 16: (Q[j][2c], Q[j][2c+1]) as 16-bit halves (16-bit path)
     const int32_t *pairs;     // P x 2: (k, l), k < l, lexicographic (MM)
     const Rec32 *rec32;       // P x n
+    const Rec32 *rec32sm;     // n x P: the same records slot-major (wave-per-node kernel)
     const Rec16 *rec16;       // P x npad
     unsigned long long *bad;  // invalid-node counter
 };
@@ -81,6 +82,9 @@ hipError_t launch_bound_lane32(fsp_instance_s *I, const int32_t *prefixes, const
 // evens out the per-lane prefix loops of pools of mixed depths.
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
                                int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths = true);
+
+hipError_t launch_bound_wavepair(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
+                                 int64_t N, int32_t *out_lb, hipStream_t s);
 
 void set_last_error(hipError_t e);
 

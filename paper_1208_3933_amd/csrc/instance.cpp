@@ -104,7 +104,7 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     // host tables
     constexpr int S = kMaxMachines;  // row stride of the padded device tables
     std::vector<int32_t> hp((size_t)(n + 1) * S, 0), colsum(S, 0), tails((size_t)n * S, 0), pairs(2 * P);
-    std::vector<Rec32> rec32((size_t)P * n);
+    std::vector<Rec32> rec32((size_t)P * n), rec32sm((size_t)n * P);
     std::vector<Rec16> rec16((size_t)P * npad);
     for (int j = 0; j < n; ++j)
         for (int k = 0; k < m; ++k) hp[(size_t)j * S + k] = p[j * m + k];
@@ -133,6 +133,7 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
                     int32_t a = p[j * m + k], b = p[j * m + l];
                     int32_t E = lagv[j] + a, C = b - a;
                     rec32[(size_t)pr * n + i] = Rec32{(uint32_t)(j >> 5), (uint32_t)(j & 31), E, C};
+                    rec32sm[(size_t)i * P + pr] = rec32[(size_t)pr * n + i];
                     r16 = Rec16{(uint32_t)j * 256u, ((uint32_t)E << 16) | ((uint32_t)C & 0xffffu)};
                 }
                 rec16[(size_t)pr * npad + i] = r16;
@@ -148,7 +149,8 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     size_t off_t16 = align(off_t + tails.size() * 4);
     size_t off_pr = align(off_t16 + tails16.size() * 4);
     size_t off_r32 = align(off_pr + pairs.size() * 4);
-    size_t off_r16 = align(off_r32 + rec32.size() * sizeof(Rec32));
+    size_t off_rsm = align(off_r32 + rec32.size() * sizeof(Rec32));
+    size_t off_r16 = align(off_rsm + rec32sm.size() * sizeof(Rec32));
     size_t off_bad = align(off_r16 + rec16.size() * sizeof(Rec16));
     size_t total = align(off_bad + sizeof(unsigned long long));
     std::vector<unsigned char> blob(total, 0);
@@ -158,6 +160,7 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     std::memcpy(blob.data() + off_t16, tails16.data(), tails16.size() * 4);
     std::memcpy(blob.data() + off_pr, pairs.data(), pairs.size() * 4);
     std::memcpy(blob.data() + off_r32, rec32.data(), rec32.size() * sizeof(Rec32));
+    std::memcpy(blob.data() + off_rsm, rec32sm.data(), rec32sm.size() * sizeof(Rec32));
     std::memcpy(blob.data() + off_r16, rec16.data(), rec16.size() * sizeof(Rec16));
 
     void *d = nullptr;
@@ -186,6 +189,7 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     I->dt.tails16 = (const uint32_t *)(b + off_t16);
     I->dt.pairs = (const int32_t *)(b + off_pr);
     I->dt.rec32 = (const Rec32 *)(b + off_r32);
+    I->dt.rec32sm = (const Rec32 *)(b + off_rsm);
     I->dt.rec16 = (const Rec16 *)(b + off_r16);
     I->dt.bad = (unsigned long long *)(b + off_bad);
     *out = I;

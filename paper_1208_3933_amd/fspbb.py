@@ -36,6 +36,7 @@ UB_NONE = 0x7FFFFFFF
 VARIANT_AUTO = 0
 VARIANT_LANE32 = 1
 VARIANT_PACKED16 = 2
+VARIANT_WAVEPAIR = 3
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p

@@ -15,7 +15,7 @@ from paper_1208_3933_amd import fspbb, gen
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16]
+VARIANTS = [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16, fspbb.VARIANT_WAVEPAIR]
 
 
 def gpu_bounds(torch, inst, pre, dep, variant=fspbb.VARIANT_AUTO):
@@ -47,9 +47,10 @@ def test_200x20_full_pool_sampled_parity():
     with fspbb.create_instance(p) as inst:
         assert inst.info()["packed16"] == 1
         got = gpu_bounds(torch, inst, pre, dep)                           # the benchmarked launch
-        got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)   # the other kernel family
+        got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)   # the other kernel families
+        gotwp = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WAVEPAIR)
         assert fspbb.pool_status(inst) == 0
-    assert (got == got32).all()
+    assert (got == got32).all() and (got == gotwp).all()
     idx = np.unique(gen.splitmix64(gen.make_seed(2, 0, 9), 3000) % np.uint64(N)).astype(np.int64)
     want = oracle_bounds(p, pre[idx], dep[idx])
     assert (got[idx] == want).all()
@@ -127,6 +128,7 @@ def test_large_values_use_the_32bit_kernel():
     with fspbb.create_instance(p) as inst:
         assert inst.info()["packed16"] == 0
         assert (gpu_bounds(torch, inst, pre, dep) == want).all()
+        assert (gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WAVEPAIR) == want).all()
         with pytest.raises(fspbb.FspError):
             gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_PACKED16)
 
@@ -161,7 +163,8 @@ def test_500x20_sampled():
         assert inst.info()["packed16"] == 1
         got = gpu_bounds(torch, inst, pre, dep)
         got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)
-    assert (got == got32).all()
+        gotwp = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WAVEPAIR)
+    assert (got == got32).all() and (got == gotwp).all()
     idx = np.arange(0, N, 16)
     assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
 
