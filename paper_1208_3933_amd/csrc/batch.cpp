@@ -137,7 +137,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
             nmax = std::max(nmax, (int)P.T.n);
         }
         c.nblocks = c.off.back();
-        c.lds = (size_t)16 * 256 * 4 + (size_t)(nmax + 1) * c.MV * 4;
+        c.lds = decode16_lds_words(nmax, c.MV) * 4;
         pl.classes.push_back(std::move(c));
     }
     pl.sort.off.assign(1, 0);

@@ -8,6 +8,12 @@
 
 namespace fspbb {
 
+// LDS words of the 16-bit decode for n jobs and MV machine slots: the
+// scheduled bits of 256 lanes (ceil(n / 32) words each) and the (n + 1) rows
+// of MV / 2 packed processing-time pairs.  Monotone in n, so a launch sized
+// for the largest n of several pools serves all of them.
+inline size_t decode16_lds_words(int n, int MV) { return (size_t)((n + 31) >> 5) * 256 + (size_t)(n + 1) * (MV / 2); }
+
 // Decode workspace of one pool in the 16-bit path (see bound_packed.hip).
 struct Workspace16 {
     uint32_t *dec;    // G x 3 x m x 64 dwords: releases R, closing sums Tk, tails Q

@@ -104,22 +104,33 @@ __global__ __launch_bounds__(256) void depth_scatter_kernel(const int32_t *__res
 // repeated jobs), the completion times of its prefix on every machine (the
 // releases, RM of Table I), the time of the unscheduled jobs on each machine,
 // and the tails (QM of Table I: least time left after machine l over the
-// unscheduled jobs).  MV = m rounded up to a multiple of 4.  The processing
-// times are staged in LDS; the tails are taken two machines at a time with
-// packed 16-bit minima over a scalar-loaded table.
+// unscheduled jobs).  MV = m rounded up to a multiple of 4.
+//   - The processing times are staged in LDS as 16-bit pairs (machines 2c and
+//     2c+1 of a job in one dword): the sums of the scheduled jobs' times are
+//     packed adds, and the completion-time recurrence takes each time as a
+//     16-bit half of a dword.
+//   - Each lane keeps its scheduled set as bits in LDS, set by OR writes that
+//     return nothing; a repeated job shows at the end as fewer set bits than
+//     the depth.
+//   - The tails are taken two machines at a time with packed 16-bit minima
+//     over a scalar-loaded table, four jobs per batch of scalar loads.
 // Decodes block `blk` (256 nodes) of one pool; every thread of the block calls it.
-// sm: dynamic LDS of 16 x 256 words plus (n+1) x MV int32.
+// sm: dynamic LDS of decode16_lds_words(n, MV) words.
 template <int MV>
 __device__ inline void decode16_block(const DevTables &T, const int32_t *__restrict__ prefixes,
                                       const int32_t *__restrict__ depths, int64_t N, int64_t Npad,
                                       const Workspace16 &W, int32_t *__restrict__ out_lb, int64_t blk,
                                       uint32_t *sm)
 {
-    uint32_t *bits = sm;                                      // 16 words x 256 lanes
-    int32_t *ptab = reinterpret_cast<int32_t *>(sm + kMaskWords * 256);  // (n+1) x MV
+    constexpr int H = MV / 2;  // packed pairs per job row
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
+    uint32_t *bits = sm;             // NW words x 256 lanes
+    uint32_t *p16 = sm + NW * 256;   // (n + 1) x H; row n is zero
     const int tid = threadIdx.x;
-    for (int e = tid; e < (n + 1) * MV; e += 256) ptab[e] = T.p32[(e / MV) * kMaxMachines + (e % MV)];
+    for (int e = tid; e < (n + 1) * H; e += 256) {
+        const int32_t *r = T.p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H);
+        p16[e] = ((uint32_t)r[0] & 0xffffu) | ((uint32_t)r[1] << 16);
+    }
     __syncthreads();
 
     const int64_t i = blk * 256 + tid;
@@ -131,56 +142,76 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     if (!ok) d = 0;
 
     uint32_t *mybits = bits + tid;
+    for (int w = 0; w < NW; ++w) mybits[w * 256] = 0u;
+    int32_t C[MV];
+    u16x2 S2[H];
 #pragma unroll
-    for (int w = 0; w < kMaskWords; ++w) mybits[w * 256] = 0u;
-    int32_t C[MV], S[MV];
+    for (int k = 0; k < MV; ++k) C[k] = 0;
 #pragma unroll
-    for (int k = 0; k < MV; ++k) { C[k] = 0; S[k] = 0; }
-    const int32_t *row = prefixes + node * (int64_t)n;
-    // rows of a multiple of 4 jobs are 16-byte aligned: one vector load per 4 jobs
-    const bool vec = (n & 3) == 0 && ((uintptr_t)prefixes & 15) == 0;
-    for (int t = 0; t < d; t += 4) {
-        int32_t jj[4];
-        if (vec) {
-            const int4 v = *reinterpret_cast<const int4 *>(row + t);
-            jj[0] = v.x; jj[1] = v.y; jj[2] = v.z; jj[3] = v.w;
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) jj[c] = row[min(t + c, n - 1)];
-        }
+    for (int c = 0; c < H; ++c) S2[c] = u16x2{0, 0};
+    // Slots t..t+3 of the prefix, branch-free: a slot past the depth, or an
+    // out-of-range job, takes the zero row, which leaves the completion
+    // times unchanged (they never decrease along the machines) and sets no bit.
+    auto step4 = [&](int32_t j0, int32_t j1, int32_t j2, int32_t j3, int t) {
+        const int32_t jj[4] = {j0, j1, j2, j3};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            if (t + c < d && ok) {
-                const int j = jj[c];
-                if ((unsigned)j >= (unsigned)n) { ok = false; continue; }
-                const uint32_t bit = 1u << (j & 31);
-                const uint32_t old = atomicOr(&mybits[(j >> 5) * 256], bit);
-                if (old & bit) { ok = false; continue; }
-                const int4 *pr = reinterpret_cast<const int4 *>(ptab + j * MV);
-                int32_t prev = 0;
+            const bool in = t + c < d, good = (unsigned)jj[c] < (unsigned)n;
+            ok = ok && (good || !in);
+            const int j = in && good ? jj[c] : n;
+            const bool real = j < n;
+            atomicOr(&mybits[(real ? j >> 5 : 0) * 256], real ? 1u << (j & 31) : 0u);
+            const uint2 *pr = reinterpret_cast<const uint2 *>(p16 + __mul24(j, H));
+            int32_t prev = 0;
 #pragma unroll
-                for (int q = 0; q < MV / 4; ++q) {
-                    const int4 v = pr[q];
-                    const int32_t x[4] = {v.x, v.y, v.z, v.w};
+            for (int q = 0; q < MV / 4; ++q) {
+                const uint2 v = pr[q];
+                S2[2 * q] += as16(v.x);
+                S2[2 * q + 1] += as16(v.y);
+                const int32_t x[4] = {(int32_t)(v.x & 0xffffu), (int32_t)(v.x >> 16),
+                                      (int32_t)(v.y & 0xffffu), (int32_t)(v.y >> 16)};
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) {
-                        const int k = 4 * q + cc;
-                        const int32_t ck = max(C[k], prev) + x[cc];
-                        C[k] = ck;
-                        prev = ck;
-                        S[k] += x[cc];
-                    }
+                for (int cc = 0; cc < 4; ++cc) {
+                    const int k = 4 * q + cc;
+                    const int32_t ck = max(C[k], prev) + x[cc];
+                    C[k] = ck;
+                    prev = ck;
                 }
             }
         }
+    };
+    const int32_t *row = prefixes + node * (int64_t)n;
+    if ((n & 3) == 0 && ((uintptr_t)prefixes & 15) == 0) {
+        // rows of a multiple of 4 jobs are 16-byte aligned: one vector load
+        // per 4 jobs, two loads in flight (indices clamped into the row)
+        const int4 *r4 = reinterpret_cast<const int4 *>(row);
+        const int last = (n >> 2) - 1;
+        int4 a = r4[0];
+        for (int t = 0; t < d; t += 8) {
+            const int4 b = r4[min((t >> 2) + 1, last)];
+            step4(a.x, a.y, a.z, a.w, t);
+            a = r4[min((t >> 2) + 2, last)];
+            step4(b.x, b.y, b.z, b.w, t + 4);
+        }
+    } else {
+        for (int t = 0; t < d; t += 4)
+            step4(row[min(t, n - 1)], row[min(t + 1, n - 1)], row[min(t + 2, n - 1)], row[min(t + 3, n - 1)], t);
     }
 
     u32v<kMaskWords> act;
+    int nset = 0;
 #pragma unroll
     for (int w = 0; w < kMaskWords; ++w) {
         const int lo = w * 32;
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : (n <= lo ? 0u : ((1u << (n - lo)) - 1u));
-        act[w] = ok ? (~mybits[w * 256] & valid) : 0u;
+        const uint32_t b = w < NW ? mybits[w * 256] : 0u;
+        nset += __popc(b);
+        act[w] = ~b & valid;
+    }
+    ok = ok && nset == d;  // every job in range; fewer bits than jobs means a repeat
+    if (!ok) {
+#pragma unroll
+        for (int w = 0; w < kMaskWords; ++w) act[w] = 0u;
     }
     // heads: with T.heads, each machine's release becomes the earliest start
     // on it of an unscheduled job scheduled next (uniform job loop: the time
@@ -191,12 +222,13 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
         for (int k = 0; k < MV; ++k) h[k] = 0x7fffffff;
         for (int j = 0; j < n; ++j) {
             const bool a = (act[j >> 5] >> (j & 31)) & 1u;
-            const int4 *pr = reinterpret_cast<const int4 *>(ptab + j * MV);
+            const uint2 *pr = reinterpret_cast<const uint2 *>(p16 + j * H);
             int32_t prev = 0;
 #pragma unroll
             for (int q = 0; q < MV / 4; ++q) {
-                const int4 v = pr[q];
-                const int32_t x[4] = {v.x, v.y, v.z, v.w};
+                const uint2 v = pr[q];
+                const int32_t x[4] = {(int32_t)(v.x & 0xffffu), (int32_t)(v.x >> 16),
+                                      (int32_t)(v.y & 0xffffu), (int32_t)(v.y >> 16)};
 #pragma unroll
                 for (int cc = 0; cc < 4; ++cc) {
                     const int k = 4 * q + cc;
@@ -210,15 +242,31 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
         for (int k = 0; k < MV; ++k) C[k] = h[k];
     }
     // tails, two machines per register: q = min over jobs of (Q | inactive mask)
-    uint32_t q2[MV / 2];
+    uint32_t q2[H];
 #pragma unroll
-    for (int c = 0; c < MV / 2; ++c) q2[c] = 0xffffffffu;
-    for (int j = 0; j < n; ++j) {
-        const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)act[j >> 5], j & 31, 1);
-        cptr<uint32_t> qr = as_const(T.tails16 + (size_t)j * (kMaxMachines / 2));
+    for (int c = 0; c < H; ++c) q2[c] = 0xffffffffu;
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t aw = act[w];
+        const int jn = min(32, n - 32 * w);
+        cptr<uint32_t> qw = as_const(T.tails16 + (size_t)(32 * w) * (kMaxMachines / 2));
+        int b = 0;
+        for (; b + 4 <= jn; b += 4) {
 #pragma unroll
-        for (int c = 0; c < MV / 2; ++c)
-            q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b + u, 1);
+                cptr<uint32_t> qr = qw + (size_t)(b + u) * (kMaxMachines / 2);
+#pragma unroll
+                for (int c = 0; c < H; ++c)
+                    q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
+            }
+        }
+        for (; b < jn; ++b) {
+            const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b, 1);
+            cptr<uint32_t> qr = qw + (size_t)b * (kMaxMachines / 2);
+#pragma unroll
+            for (int c = 0; c < H; ++c)
+                q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
+        }
     }
 
     const bool empty = d == n;  // no unscheduled job: every tail is 0
@@ -230,8 +278,9 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     for (int k = 0; k < MV; ++k) {
         if (k < m) {
             const uint32_t qk = (q2[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+            const int32_t sk = (k & 1) ? S2[k >> 1].y : S2[k >> 1].x;
             d16[((G * 3 + 0) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[k] : 0);
-            d16[((G * 3 + 1) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[k] + (cs[k] - S[k]) : 0);
+            d16[((G * 3 + 1) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[k] + (cs[k] - sk) : 0);
             d16[((G * 3 + 2) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok && !empty ? qk : 0u);
         }
     }
@@ -651,7 +700,7 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
 
     const dim3 dgrid((unsigned)((Npad + 255) / 256)), dblock(256);
     const int MV = (m + 3) & ~3;
-    const size_t dlds = (size_t)kMaskWords * 256 * 4 + (size_t)(n + 1) * MV * 4;
+    const size_t dlds = decode16_lds_words(n, MV) * 4;
 #define FSP_DECODE(MVV) \
     case MVV: bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb); break;
     switch (MV) {
