@@ -93,7 +93,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         BatchPool &P = pl.pools[i];
         std::memset(&P, 0, sizeof(P));
         if (sort_depths && d.N >= kSortMinNodes) {
-            P.sortB = (int32_t)std::min<int64_t>(1024, (d.N + 4095) / 4096);
+            P.sortB = (int32_t)std::min<int64_t>(kSortMaxBlocks, (d.N + 4095) / 4096);
             P.sort_chunk = (d.N + P.sortB - 1) / P.sortB;
             ws += al256((size_t)d.N * 4) + al256((size_t)(n + 2) * P.sortB * 4);
         }

@@ -8,6 +8,10 @@
 
 namespace fspbb {
 
+// Blocks of a pool's depth sort: one per 4096 nodes, at most this many (each
+// scatter block sums the per-block counts of every bucket itself).
+constexpr int kSortMaxBlocks = 64;
+
 // LDS words of the 16-bit decode for n jobs and MV machine slots: the
 // scheduled bits of 256 lanes (ceil(n / 32) words each) and the (n + 1) rows
 // of MV / 2 packed processing-time pairs.  Monotone in n, so a launch sized

@@ -40,38 +40,51 @@ __device__ inline void depth_count_block(const int32_t *__restrict__ depths, int
     for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cnt[(int64_t)b * B + blk] = h[b];
 }
 
-// Exclusive prefix sum of cnt[0..total) in place, by one block of 1024 threads.
-__device__ inline void depth_scan_block(uint32_t *__restrict__ cnt, int64_t total, uint32_t *part)
+// Block `blk` of B: each node goes to the next free position of its depth
+// bucket.  The first position of bucket b in this block is the number of
+// nodes in smaller buckets (over all blocks) plus those of bucket b in the
+// blocks before it; the block sums the per-block counts itself (B is at most
+// kSortMaxBlocks, so this is a few thousand cached reads).
+// sh: 2 (n + 2) + 256 words of LDS.
+__device__ inline void depth_scatter_block(const int32_t *__restrict__ depths, int64_t N, int n, int64_t chunk, int B,
+                                           const uint32_t *__restrict__ cnt, int32_t *__restrict__ order, int64_t blk,
+                                           uint32_t *sh)
 {
-    const int t = threadIdx.x;
-    const int64_t per = (total + 1023) / 1024, lo = t * per, hi = min(total, lo + per);
-    uint32_t sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += cnt[i];
-    part[t] = sum;
+    const int t = threadIdx.x, nb = n + 2;
+    uint32_t *cur = sh, *tot = sh + nb, *part = sh + 2 * nb;
+    for (int b = t; b < nb; b += blockDim.x) {
+        const uint32_t *c = cnt + (int64_t)b * B;
+        uint32_t all = 0, before = 0;
+        for (int k = 0; k < B; ++k) {
+            const uint32_t v = c[k];
+            all += v;
+            before += k < blk ? v : 0u;
+        }
+        tot[b] = all;
+        cur[b] = before;
+    }
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
+    // exclusive scan of tot over the buckets: each thread sums a run of
+    // buckets, the runs are scanned across the block, then walked again
+    const int per = (nb + blockDim.x - 1) / blockDim.x, lo = t * per, hi = min(nb, lo + per);
+    uint32_t run = 0;
+    for (int b = lo; b < hi; ++b) run += tot[b];
+    part[t] = run;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
         const uint32_t v = t >= off ? part[t - off] : 0u;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
-    uint32_t run = part[t] - sum;
-    for (int64_t i = lo; i < hi; ++i) {
-        const uint32_t c = cnt[i];
-        cnt[i] = run;
-        run += c;
+    uint32_t base = part[t] - run;
+    for (int b = lo; b < hi; ++b) {
+        cur[b] += base;
+        base += tot[b];
     }
-}
-
-// Block `blk`: each node goes to the next free position of its depth bucket.
-__device__ inline void depth_scatter_block(const int32_t *__restrict__ depths, int64_t N, int n, int64_t chunk, int B,
-                                           const uint32_t *__restrict__ cnt, int32_t *__restrict__ order, int64_t blk,
-                                           uint32_t *cur)
-{
-    for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cur[b] = cnt[(int64_t)b * B + blk];
     __syncthreads();
-    const int64_t lo = blk * chunk, hi = min(N, lo + chunk);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int64_t lo_i = blk * chunk, hi_i = min(N, lo_i + chunk);
+    for (int64_t i = lo_i + t; i < hi_i; i += blockDim.x) {
         const uint32_t pos = atomicAdd(&cur[depth_bucket(depths[i], n)], 1u);
         order[pos] = (int32_t)i;
     }
@@ -84,18 +97,12 @@ __global__ __launch_bounds__(256) void depth_count_kernel(const int32_t *__restr
     depth_count_block(depths, N, n, chunk, B, cnt, blockIdx.x, h);
 }
 
-__global__ __launch_bounds__(1024) void depth_scan_kernel(uint32_t *__restrict__ cnt, int64_t total)
-{
-    __shared__ uint32_t part[1024];
-    depth_scan_block(cnt, total, part);
-}
-
 __global__ __launch_bounds__(256) void depth_scatter_kernel(const int32_t *__restrict__ depths, int64_t N, int n,
                                                             int64_t chunk, int B, const uint32_t *__restrict__ cnt,
                                                             int32_t *__restrict__ order)
 {
-    extern __shared__ uint32_t cur[];
-    depth_scatter_block(depths, N, n, chunk, B, cnt, order, blockIdx.x, cur);
+    extern __shared__ uint32_t sh[];
+    depth_scatter_block(depths, N, n, chunk, B, cnt, order, blockIdx.x, sh);
 }
 
 // ---- decode: one lane per node, nodes taken in depth order
@@ -413,33 +420,24 @@ __global__ __launch_bounds__(256) void batch_depth_count_kernel(const BatchPool 
                       (int64_t)blockIdx.x - as_const(blk_off)[q], h);
 }
 
-__global__ __launch_bounds__(1024) void batch_depth_scan_kernel(const BatchPool *__restrict__ pools,
-                                                                const int32_t *__restrict__ sort_pools)
-{
-    __shared__ uint32_t part[1024];
-    const BatchPool P = load_uniform(pools + as_const(sort_pools)[blockIdx.x]);
-    depth_scan_block(P.W.cnt, (int64_t)(P.T.n + 2) * P.sortB, part);
-}
-
 __global__ __launch_bounds__(256) void batch_depth_scatter_kernel(const BatchPool *__restrict__ pools,
                                                                   const int64_t *__restrict__ blk_off,
                                                                   const int32_t *__restrict__ sort_pools, int nsort)
 {
-    extern __shared__ uint32_t cur[];
+    extern __shared__ uint32_t sh[];
     const int q = pool_of_block(blk_off, nsort);
     const BatchPool P = load_uniform(pools + as_const(sort_pools)[q]);
     depth_scatter_block(P.depths, P.N, P.T.n, P.sort_chunk, P.sortB, P.W.cnt, P.W.order,
-                        (int64_t)blockIdx.x - as_const(blk_off)[q], cur);
+                        (int64_t)blockIdx.x - as_const(blk_off)[q], sh);
 }
 
 hipError_t launch_batch_depth_sort(const BatchPool *pools, const int64_t *blk_off, const int32_t *sort_pools,
                                    int nsort, int64_t nblocks, int nmax, hipStream_t s)
 {
     if (nsort <= 0 || nblocks <= 0) return hipSuccess;
-    const size_t hb = (size_t)(nmax + 2) * 4;
+    const size_t hb = (size_t)(nmax + 2) * 4, sb = ((size_t)(nmax + 2) * 2 + 256) * 4;
     batch_depth_count_kernel<<<(unsigned)nblocks, 256, hb, s>>>(pools, blk_off, sort_pools, nsort);
-    batch_depth_scan_kernel<<<(unsigned)nsort, 1024, 0, s>>>(pools, sort_pools);
-    batch_depth_scatter_kernel<<<(unsigned)nblocks, 256, hb, s>>>(pools, blk_off, sort_pools, nsort);
+    batch_depth_scatter_kernel<<<(unsigned)nblocks, 256, sb, s>>>(pools, blk_off, sort_pools, nsort);
     return hipGetLastError();
 }
 
@@ -674,7 +672,7 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
     if (N <= 0) return hipSuccess;
     const int n = I->n, m = I->m, NW = (n + 31) >> 5;
     const int64_t G = (N + kGroup - 1) / kGroup, Npad = G * kGroup;
-    const int B = (int)std::min<int64_t>(1024, (N + 4095) / 4096);
+    const int B = (int)std::min<int64_t>(kSortMaxBlocks, (N + 4095) / 4096);
     const int64_t chunk = (N + B - 1) / B;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t dec_b = al((size_t)G * 3 * m * 64 * 4), flg_b = al((size_t)G * NW * 128 * 4),
@@ -692,10 +690,9 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
 
     timing_mark(I, 0, s);
     if (sort_depths) {
-        const size_t hb = (size_t)(n + 2) * 4;
+        const size_t hb = (size_t)(n + 2) * 4, sb = ((size_t)(n + 2) * 2 + 256) * 4;
         depth_count_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt);
-        depth_scan_kernel<<<1, 1024, 0, s>>>(W.cnt, (int64_t)(n + 2) * B);
-        depth_scatter_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt, W.order);
+        depth_scatter_kernel<<<B, 256, sb, s>>>(depths, N, n, chunk, B, W.cnt, W.order);
     }
 
     const dim3 dgrid((unsigned)((Npad + 255) / 256)), dblock(256);
