@@ -27,6 +27,10 @@ struct Workspace16 {
     uint32_t *cnt;    // (n + 2) x B: per-block depth counts, then scatter offsets
 };
 
+// The 16-bit scan alone over a decoded workspace of N nodes (identity order
+// unless W.order is set), bounds to out_lb.
+hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s);
+
 constexpr int kBatchWaves = 16;  // waves per workgroup of the persistent scan
 constexpr int64_t kSortMinNodes = 512;  // smaller pools are decoded in pool order
 

@@ -49,6 +49,11 @@ struct StepScratch {
     unsigned long long *best;    // (bound << 32) | child index of the best complete child
     unsigned long long *fingerprint;
     unsigned long long *bad;     // invalid parents
+    // Set when the children are bounded from their parents (kids16_bound):
+    // K x n copy of the parent rows; child rows are then never written, and
+    // survivor rows and the incumbent are built from it and ujob.  Null =
+    // child rows in crow.
+    const int32_t *prow;
 };
 
 // Per-search scalars of a step.  They live in the search's entry of the
@@ -75,6 +80,8 @@ struct StepReq {
 hipError_t mstep_phase1(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, hipStream_t s);
 // Branch: children's job lists and rows (nchild known in each StepReq).
 hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
+// Branch without rows: the children's appended jobs and parents only.
+hipError_t mstep_list(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
 // Finish (after the children are bounded into w.clb): upper bound, keep,
 // stable compaction, scatter, fingerprint, per-parent counts, incumbent.
 hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, int64_t maxC,

@@ -16,48 +16,11 @@
 //   6. keeps the non-leaf children whose bound is below the new upper bound
 //      and compacts them stably (prefix sum), optionally in reverse child
 //      order so that pushing them on a stack leaves the first child on top.
-#include "bnb.h"
-#include "bound_common.h"
+#include <algorithm>
+
+#include "step_dev.h"
 
 namespace fspbb {
-
-using ReqP = cptr<StepReq>;
-
-__device__ __forceinline__ ReqP req_of(const StepReq *reqs) { return as_const(reqs + blockIdx.y); }
-
-__device__ __forceinline__ const int32_t *parent_row(ReqP q, int64_t p)
-{
-    const int64_t r = q->a.parents_reversed ? (q->a.parent_top - 1 - p) : p;
-    const int64_t row = q->a.pslot ? (int64_t)q->a.pslot[r] : r;
-    return q->a.parents + row * (int64_t)q->a.n;
-}
-__device__ __forceinline__ int32_t parent_depth(ReqP q, int64_t p)
-{
-    return q->a.pdepth[q->a.parents_reversed ? (q->a.parent_top - 1 - p) : p];
-}
-
-// One wave per parent: the lanes build the parent's scheduled set in a 16-word
-// LDS mask (LDS atomics; a returned bit already set means a repeated job).
-// Returns, uniformly over the wave, whether the parent is valid: depth in
-// 0..n, every job in 0..n-1, no repeat.
-__device__ inline bool wave_prefix_set(const int32_t *row, int d, int n, uint32_t *mask, int lane)
-{
-    if (lane < kMaxJobs / 32) mask[lane] = 0u;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    bool bad = d < 0 || d > n;
-    if (!bad) {
-        for (int t = lane; t < d; t += 64) {
-            const int j = row[t];
-            if ((unsigned)j >= (unsigned)n) { bad = true; continue; }
-            const uint32_t bit = 1u << (j & 31);
-            if (atomicOr(&mask[j >> 5], bit) & bit) bad = true;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    return __ballot(bad) == 0;
-}
 
 __global__ __launch_bounds__(256) void mstep_count_kernel(const StepReq *__restrict__ reqs)
 {
@@ -102,12 +65,18 @@ __global__ __launch_bounds__(256) void mstep_ulist_kernel(const StepReq *__restr
     }
 }
 
-// One wave per child: child row = parent prefix followed by the appended job.
+// Rows and survivor copies run kRowLanes lanes per child (8 children per
+// wave): a wave per child would leave most lanes idle on shallow rows and make
+// the dispatch of one wave per child the cost.
+constexpr int kRowLanes = 8;
+constexpr int kRowsPerBlock = 256 / kRowLanes;
+
+// Child row = parent prefix followed by the appended job.
 __global__ __launch_bounds__(256) void mstep_rows_kernel(const StepReq *__restrict__ reqs)
 {
     ReqP q = req_of(reqs);
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kRowLanes);
+    const int sub = threadIdx.x % kRowLanes;
     if (c >= q->nchild) return;
     const int n = q->a.n;
     const int64_t p = q->w.upar[c];
@@ -115,8 +84,8 @@ __global__ __launch_bounds__(256) void mstep_rows_kernel(const StepReq *__restri
     const int32_t *prow = parent_row(q, p);
     int32_t *crow = q->w.crow + c * (int64_t)n;
     const int32_t j = q->w.ujob[c];
-    for (int t = lane; t <= d; t += 64) crow[t] = t < d ? prow[t] : j;
-    if (lane == 0) q->w.cdepth[c] = d + 1;
+    for (int t = sub; t <= d; t += kRowLanes) crow[t] = t < d ? prow[t] : j;
+    if (sub == 0) q->w.cdepth[c] = d + 1;
 }
 
 __global__ __launch_bounds__(256) void mstep_leaf_kernel(const StepReq *__restrict__ reqs)
@@ -139,12 +108,12 @@ __global__ __launch_bounds__(256) void mstep_keep_kernel(const StepReq *__restri
     q->w.keep[c] = (q->w.cdepth[c] < q->a.n && lb >= 0 && lb < ub) ? 1u : 0u;
 }
 
-// One wave per child: survivors are copied to their compacted slot.
+// Survivors are copied to their compacted slot (kRowLanes lanes per child).
 __global__ __launch_bounds__(256) void mstep_scatter_kernel(const StepReq *__restrict__ reqs)
 {
     ReqP q = req_of(reqs);
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kRowLanes);
+    const int sub = threadIdx.x % kRowLanes;
     if (c >= q->nchild) return;
     if (!q->w.keep[c]) return;
     const int n = q->a.n;
@@ -153,30 +122,36 @@ __global__ __launch_bounds__(256) void mstep_scatter_kernel(const StepReq *__res
     const int64_t dst = q->a.out_reversed ? q->a.out_base + (S - 1 - s) : q->a.out_base + s;
     if (dst < 0 || dst >= q->a.out_cap) return;  // overflow is reported by the host
     const int d = q->w.cdepth[c];
-    const int32_t *src = q->w.crow + c * (int64_t)n;
     const int64_t orow = q->a.oslot ? (int64_t)q->a.oslot[s * q->a.oslot_step] : dst;
     int32_t *out = q->a.out_rows + orow * (int64_t)n;
-    for (int t = lane; t < d; t += 64) out[t] = src[t];
-    if (lane == 0) {
+    if (q->w.prow) {  // parent prefix (from the step's copy of the parent rows) + appended job
+        const int32_t *src = q->w.prow + (int64_t)q->w.upar[c] * n;
+        const int32_t j = q->w.ujob[c];
+        for (int t = sub; t < d; t += kRowLanes) out[t] = t + 1 < d ? src[t] : j;
+    } else {
+        const int32_t *src = q->w.crow + c * (int64_t)n;
+        for (int t = sub; t < d; t += kRowLanes) out[t] = src[t];
+    }
+    if (sub == 0) {
         q->a.out_depth[dst] = d;
         if (q->a.out_lb) q->a.out_lb[dst] = q->w.clb[c];
     }
 }
 
-// Fingerprint of the survivor order: sum over survivors of (S - rank) * (job + 1),
-// one block reduction and one atomic per block.
+// Fingerprint of the survivor order: sum over survivors of (S - rank) * (job + 1).
+// A grid-stride loop over at most kPrintBlocks blocks, one block reduction
+// and one atomic per block.
+constexpr int kPrintBlocks = 128;
 __global__ __launch_bounds__(256) void mstep_fingerprint_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ unsigned long long part[256];
     ReqP q = req_of(reqs);
     const int64_t nch = q->nchild;
     if ((int64_t)blockIdx.x * 256 >= nch) return;  // whole block
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long v = 0;
-    if (c < nch && q->w.keep[c]) {
-        const unsigned long long S = *q->w.nsurv;
-        v = (S - q->w.pos[c]) * (unsigned long long)(q->w.ujob[c] + 1);
-    }
+    const unsigned long long S = *q->w.nsurv;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < nch; c += (int64_t)gridDim.x * 256)
+        if (q->w.keep[c]) v += (S - q->w.pos[c]) * (unsigned long long)(q->w.ujob[c] + 1);
     part[threadIdx.x] = v;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -212,7 +187,13 @@ __global__ void mstep_incumbent_kernel(const StepReq *__restrict__ reqs)
     int32_t *inc = q->a.incumbent;
     if (idx == 0xffffffffu || !inc) return;
     const int n = q->a.n;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) inc[t] = q->w.crow[(int64_t)idx * n + t];
+    if (q->w.prow) {  // a complete child: n - 1 parent jobs and the appended one
+        const int32_t *src = q->w.prow + (int64_t)q->w.upar[idx] * n;
+        const int32_t j = q->w.ujob[idx];
+        for (int t = threadIdx.x; t < n; t += blockDim.x) inc[t] = t + 1 < n ? src[t] : j;
+    } else {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) inc[t] = q->w.crow[(int64_t)idx * n + t];
+    }
 }
 
 static unsigned blocks_for(int64_t items, int per_block)
@@ -230,11 +211,19 @@ hipError_t mstep_phase1(const StepReq *reqs, const ScanSeg *segs, int R, int64_t
     return exclusive_scan_segments(segs, R, maxK, s);
 }
 
-hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s)
+hipError_t mstep_list(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s)
 {
     if (R <= 0 || maxC <= 0) return hipSuccess;
     mstep_ulist_kernel<<<dim3(blocks_for(maxK, 4), R), 256, 0, s>>>(reqs);
-    mstep_rows_kernel<<<dim3(blocks_for(maxC, 4), R), 256, 0, s>>>(reqs);
+    return hipGetLastError();
+}
+
+hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s)
+{
+    if (R <= 0 || maxC <= 0) return hipSuccess;
+    hipError_t e = mstep_list(reqs, R, maxK, maxC, s);
+    if (e != hipSuccess) return e;
+    mstep_rows_kernel<<<dim3(blocks_for(maxC, kRowsPerBlock), R), 256, 0, s>>>(reqs);
     return hipGetLastError();
 }
 
@@ -249,8 +238,9 @@ hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t
         if (e != hipSuccess) return e;
         e = exclusive_scan_segments(segs, R, maxC, s);
         if (e != hipSuccess) return e;
-        mstep_scatter_kernel<<<dim3(blocks_for(maxC, 4), R), 256, 0, s>>>(reqs);
-        mstep_fingerprint_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
+        mstep_scatter_kernel<<<dim3(blocks_for(maxC, kRowsPerBlock), R), 256, 0, s>>>(reqs);
+        mstep_fingerprint_kernel<<<dim3((unsigned)std::min<int64_t>(blocks_for(maxC, 256), kPrintBlocks), R), 256, 0,
+                                   s>>>(reqs);
         mstep_incumbent_kernel<<<dim3(1, R), 256, 0, s>>>(reqs);
     }
     if (maxK > 0) mstep_per_parent_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs);

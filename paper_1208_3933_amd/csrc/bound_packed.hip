@@ -666,6 +666,24 @@ static void launch_scan(int unr, dim3 grid, size_t lds_b, hipStream_t s, const D
         launch_scan_u<WAVES, false>(unr, grid, lds_b, s, dt, W, N, out_lb);
 }
 
+hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s)
+{
+    if (N <= 0) return hipSuccess;
+    const int n = I->n, m = I->m;
+    const int waves = scan_waves(n, m);
+    const size_t lds_b = (size_t)((n + 1) > waves ? (n + 1) : waves) * 256;
+    const dim3 grid((unsigned)((N + kGroup - 1) / kGroup));
+    const int unr = scan_unroll();
+    switch (waves) {
+    case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+    case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+    case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+    case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+    default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
                                int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths)
 {
@@ -707,20 +725,7 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
 #undef FSP_DECODE
     e = hipGetLastError();
     timing_mark(I, 1, s);
-    if (e == hipSuccess) {
-        const int waves = scan_waves(n, m);
-        const size_t lds_b = (size_t)((n + 1) > waves ? (n + 1) : waves) * 256;
-        const dim3 grid((unsigned)G);
-        const int unr = scan_unroll();
-        switch (waves) {
-        case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-        case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-        case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-        case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-        default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-        }
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s);
     timing_mark(I, 2, s);
     hipError_t e2 = hipFreeAsync(ws, s);
     return e != hipSuccess ? e : e2;

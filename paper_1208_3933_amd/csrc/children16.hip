@@ -1,0 +1,290 @@
+// Bounding a step's children from their parents (16-bit instances, plain
+// releases).  A child appends one job j to its parent's prefix, so
+//   - its releases extend the parent's completion times by j (one pass over
+//     the machines),
+//   - its unscheduled time on machine k is the parent's minus p[j][k],
+//   - its tail on k is the least tail among the parent's unscheduled jobs
+//     other than j: the parent's least one, or the second least when j is
+//     the job holding the least,
+//   - its unscheduled set is the parent's without j.
+// Each parent is decoded once (order n m work) and each child in order m,
+// where decoding a child from its row costs order n m.  The children's scan
+// inputs go straight to the scan workspace and the pair scans are the plain
+// kernel's, so every bound equals the one computed from the child's row.
+// Child rows are never written: survivors are built from the parent copy.
+#include <algorithm>
+
+#include "kids16.h"
+#include "scan16.h"
+#include "step_dev.h"
+
+namespace fspbb {
+
+namespace {
+
+// Stages the processing times as 16-bit pairs: row j holds machines (2c, 2c+1)
+// in word c; row n is zero.  Every thread of the block calls it.
+template <int H>
+__device__ inline void stage_p16(const DevTables &T, uint32_t *p16)
+{
+    for (int e = threadIdx.x; e < (T.n + 1) * H; e += blockDim.x) {
+        const int32_t *r = T.p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H);
+        p16[e] = ((uint32_t)r[0] & 0xffffu) | ((uint32_t)r[1] << 16);
+    }
+    __syncthreads();
+}
+
+// One lane per parent: completion times of the prefix and the time of the
+// unscheduled jobs per machine.  Parents with no children (invalid, or
+// complete) are skipped; the count kernel has validated the others.
+template <int MV>
+__global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restrict__ reqs, DevTables T,
+                                                        int32_t *__restrict__ rec)
+{
+    constexpr int H = MV / 2;
+    extern __shared__ uint32_t p16[];
+    stage_p16<H>(T, p16);
+    ReqP q = req_of(reqs);
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= q->a.K || q->w.cnt[p] == 0) return;
+    const int d = parent_depth(q, p);
+    const int32_t *row = parent_row(q, p);
+    int32_t C[MV];
+    u16x2 S2[H];
+#pragma unroll
+    for (int k = 0; k < MV; ++k) C[k] = 0;
+#pragma unroll
+    for (int c = 0; c < H; ++c) S2[c] = u16x2{0, 0};
+    // four prefix slots at a time; a slot past the depth takes the zero row,
+    // which leaves the completion times unchanged
+    auto step4 = [&](int32_t j0, int32_t j1, int32_t j2, int32_t j3, int t) {
+        const int32_t jj[4] = {j0, j1, j2, j3};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = t + c < d ? jj[c] : T.n;
+            const uint2 *pr = reinterpret_cast<const uint2 *>(p16 + __mul24(j, H));
+            int32_t prev = 0;
+#pragma unroll
+            for (int q4 = 0; q4 < MV / 4; ++q4) {
+                const uint2 v = pr[q4];
+                S2[2 * q4] += as16(v.x);
+                S2[2 * q4 + 1] += as16(v.y);
+                const int32_t x[4] = {(int32_t)(v.x & 0xffffu), (int32_t)(v.x >> 16), (int32_t)(v.y & 0xffffu),
+                                      (int32_t)(v.y >> 16)};
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) {
+                    const int k = 4 * q4 + cc;
+                    C[k] = max(C[k], prev) + x[cc];
+                    prev = C[k];
+                }
+            }
+        }
+    };
+    const int n = T.n;
+    if ((n & 3) == 0 && ((uintptr_t)row & 15) == 0) {
+        // 16-byte row loads, two in flight (indices clamped into the row)
+        const int4 *r4 = reinterpret_cast<const int4 *>(row);
+        const int last = (n >> 2) - 1;
+        int4 a = r4[0];
+        for (int t = 0; t < d; t += 8) {
+            const int4 b = r4[min((t >> 2) + 1, last)];
+            step4(a.x, a.y, a.z, a.w, t);
+            a = r4[min((t >> 2) + 2, last)];
+            step4(b.x, b.y, b.z, b.w, t + 4);
+        }
+    } else {
+        for (int t = 0; t < d; t += 4)
+            step4(row[min(t, n - 1)], row[min(t + 1, n - 1)], row[min(t + 2, n - 1)], row[min(t + 3, n - 1)], t);
+    }
+    int32_t *r = rec + p * kKidRec;
+    cptr<int32_t> cs = as_const(T.colsum32);
+#pragma unroll
+    for (int k = 0; k < MV; ++k) {
+        r[kKidC + k] = C[k];
+        r[kKidU + k] = cs[k] - (int32_t)((k & 1) ? S2[k >> 1].y : S2[k >> 1].x);
+    }
+}
+
+// One wave per parent: copies the parent row, builds its unscheduled set, and
+// lane k (< m) finds the least and second least tails on machine k over the
+// unscheduled jobs, taken in increasing id.
+__global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restrict__ reqs, DevTables T,
+                                                        int32_t *__restrict__ rec, int32_t *__restrict__ prow)
+{
+    __shared__ uint32_t mask[4][kMaskWords];
+    ReqP q = req_of(reqs);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    if (p >= q->a.K) return;       // whole wave
+    if (q->w.cnt[p] == 0) return;  // whole wave
+    const int n = T.n, m = T.m, NW = (n + 31) >> 5;
+    const int d = parent_depth(q, p);
+    const int32_t *row = parent_row(q, p);
+    int32_t *pr = prow + p * (int64_t)n;
+    for (int t = lane; t < d; t += 64) pr[t] = row[t];
+    wave_prefix_set(row, d, n, mask[wv], lane);
+    int32_t *r = rec + p * kKidRec;
+    if (lane < NW) {
+        const int lo = lane * 32;
+        const uint32_t valid = n >= lo + 32 ? 0xffffffffu : ((1u << (n - lo)) - 1u);
+        r[kKidM + lane] = (int32_t)(~mask[wv][lane] & valid);
+    }
+    int32_t q1 = 0x7fffffff, j1 = 0, q2 = 0x7fffffff;
+    const int k = lane < m ? lane : 0;
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t sched = __builtin_amdgcn_readfirstlane(mask[wv][w]);
+        const int jn = min(32, n - 32 * w);
+        const int32_t *tw = T.tails32 + (size_t)(32 * w) * kMaxMachines + k;
+#pragma unroll 8
+        for (int b = 0; b < jn; ++b) {
+            const int32_t t = tw[(size_t)b * kMaxMachines];
+            const int32_t v = ((sched >> b) & 1u) ? 0x7fffffff : t;
+            const bool lt1 = v < q1;
+            q2 = lt1 ? q1 : min(q2, v);
+            j1 = lt1 ? 32 * w + b : j1;
+            q1 = lt1 ? v : q1;
+        }
+    }
+    if (lane < m) {
+        r[kKidQ1 + lane] = q1;
+        r[kKidJ1 + lane] = j1;
+        r[kKidQ2 + lane] = q2;
+    }
+}
+
+// One lane per child (and per padding slot up to the group boundary): writes
+// the scan inputs of child i in the decode kernel's layout, and its depth.
+template <int MV>
+__global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restrict__ reqs, DevTables T,
+                                                         const int32_t *__restrict__ rec, Workspace16 W, int64_t N,
+                                                         int64_t Npad)
+{
+    constexpr int H = MV / 2;
+    extern __shared__ uint32_t p16[];
+    stage_p16<H>(T, p16);
+    ReqP q = req_of(reqs);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= Npad) return;
+    const bool live = i < N;
+    const int n = T.n, m = T.m, NW = (n + 31) >> 5;
+    int32_t j = n;  // the zero row for padding slots
+    int64_t p = 0;
+    int d = 0;
+    if (live) {
+        j = q->w.ujob[i];
+        p = q->w.upar[i];
+        d = parent_depth(q, p) + 1;
+        q->w.cdepth[i] = d;
+    }
+    const int32_t *r = rec + p * kKidRec;
+    const uint2 *pj = reinterpret_cast<const uint2 *>(p16 + __mul24(j, H));
+    const bool empty = d == n;  // a complete child: no tail
+    const int64_t G = i >> 7;
+    const int g = (int)(i & 127), lane = g & 63, half = g >> 6;
+    uint16_t *d16 = reinterpret_cast<uint16_t *>(W.dec);
+    int32_t prev = 0;
+#pragma unroll
+    for (int q4 = 0; q4 < MV / 4; ++q4) {
+        const uint2 v = pj[q4];
+        const int32_t x[4] = {(int32_t)(v.x & 0xffffu), (int32_t)(v.x >> 16), (int32_t)(v.y & 0xffffu),
+                              (int32_t)(v.y >> 16)};
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const int k = 4 * q4 + cc;
+            const int32_t ck = max(r[kKidC + k], prev) + x[cc];
+            prev = ck;
+            if (k < m) {
+                const int32_t tk = ck + (r[kKidU + k] - x[cc]);
+                const int32_t qk = r[kKidJ1 + k] == j ? r[kKidQ2 + k] : r[kKidQ1 + k];
+                d16[((G * 3 + 0) * m + k) * 128 + lane * 2 + half] = (uint16_t)(live ? ck : 0);
+                d16[((G * 3 + 1) * m + k) * 128 + lane * 2 + half] = (uint16_t)(live ? tk : 0);
+                d16[((G * 3 + 2) * m + k) * 128 + lane * 2 + half] = (uint16_t)(live && !empty ? qk : 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) {
+        if (w < NW) {
+            const uint32_t drop = (j >> 5) == w ? 1u << (j & 31) : 0u;
+            W.flg[(G * NW + w) * 128 + g] = live ? ((uint32_t)r[kKidM + w] & ~drop) : 0u;
+        }
+    }
+    W.st[i] = live ? 1u : 0u;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <int MV>
+hipError_t launch_kids(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s)
+{
+    const size_t lds = (size_t)(I->n + 1) * (MV / 2) * 4;
+    const int64_t Npad = (k.nch + kGroup - 1) / kGroup * kGroup;
+    kid_chain_kernel<MV><<<dim3((unsigned)((k.K + 255) / 256), 1), 256, lds, s>>>(dreq, I->dt, k.rec);
+    kid_tails_kernel<<<dim3((unsigned)((k.K + 3) / 4), 1), 256, 0, s>>>(dreq, I->dt, k.rec, k.prow);
+    kid_decode_kernel<MV><<<dim3((unsigned)((Npad + 255) / 256), 1), 256, lds, s>>>(dreq, I->dt, k.rec, k.W,
+                                                                                     k.nch, Npad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_scan16(I, k.W, k.nch, clb, s);
+}
+
+}  // namespace
+
+bool kids16_eligible(const fsp_instance_s *I) { return I->packed16 && !I->dt.heads; }
+
+hipError_t kids16_ensure(Kids16 &k, const fsp_instance_s *I, int64_t K, int64_t nch, hipStream_t s)
+{
+    k.K = K;
+    k.nch = nch;
+    if (k.blob && K <= k.capK && nch <= k.capC && I->n == k.n && I->m == k.m) return hipSuccess;
+    if (k.blob) hipFreeAsync(k.blob, s);
+    k.blob = nullptr;
+    const int n = I->n, m = I->m, NW = (n + 31) >> 5;
+    const int64_t capK = std::max<int64_t>({K, 2 * k.capK, 1}), capC = std::max<int64_t>({nch, k.capC, kGroup});
+    const int64_t G = (capC + kGroup - 1) / kGroup;
+    const size_t rows_b = al256((size_t)capK * n * 4), rec_b = al256((size_t)capK * kKidRec * 4),
+                 dec_b = al256((size_t)G * 3 * m * 64 * 4), flg_b = al256((size_t)G * NW * 128 * 4),
+                 st_b = al256((size_t)G * kGroup * 4);
+    hipError_t e = stream_alloc(&k.blob, rows_b + rec_b + dec_b + flg_b + st_b, s);
+    if (e != hipSuccess) {
+        k = Kids16{};
+        return e;
+    }
+    k.capK = capK;
+    k.capC = capC;
+    k.bytes = rows_b + rec_b + dec_b + flg_b + st_b;
+    k.n = n;
+    k.m = m;
+    char *b = (char *)k.blob;
+    k.prow = (int32_t *)b;
+    k.rec = (int32_t *)(b + rows_b);
+    k.W.dec = (uint32_t *)(b + rows_b + rec_b);
+    k.W.flg = (uint32_t *)(b + rows_b + rec_b + dec_b);
+    k.W.st = (uint32_t *)(b + rows_b + rec_b + dec_b + flg_b);
+    k.W.order = nullptr;
+    k.W.cnt = nullptr;
+    return hipSuccess;
+}
+
+void kids16_release(Kids16 &k, hipStream_t s)
+{
+    if (k.blob) hipFreeAsync(k.blob, s);
+    k = Kids16{};
+}
+
+hipError_t kids16_bound(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s)
+{
+    if (k.nch <= 0 || k.K <= 0) return hipSuccess;
+    switch ((I->m + 3) & ~3) {
+    case 4: return launch_kids<4>(dreq, I, k, clb, s);
+    case 8: return launch_kids<8>(dreq, I, k, clb, s);
+    case 12: return launch_kids<12>(dreq, I, k, clb, s);
+    case 16: return launch_kids<16>(dreq, I, k, clb, s);
+    case 20: return launch_kids<20>(dreq, I, k, clb, s);
+    case 24: return launch_kids<24>(dreq, I, k, clb, s);
+    case 28: return launch_kids<28>(dreq, I, k, clb, s);
+    default: return launch_kids<32>(dreq, I, k, clb, s);
+    }
+}
+
+}  // namespace fspbb

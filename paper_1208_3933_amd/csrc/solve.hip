@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "best_first.h"
+#include "kids16.h"
 #include "search.h"
 
 using namespace fspbb;
@@ -184,6 +185,36 @@ static hipError_t bound_rows(fsp_instance_s *I, const int32_t *rows, const int32
                        : launch_bound_lane32(I, rows, depths, N, lb, s);
 }
 
+// Whether one step bounds its children from their parents, with the
+// (persistent, grow-only) scratch it uses.
+struct KidsStep {
+    Kids16 &k;
+    bool on = false;
+    explicit KidsStep(Kids16 &buf) : k(buf) {}
+    hipError_t start(const fsp_instance_s *I, int64_t K, int64_t nch, hipStream_t s)
+    {
+        on = kids16_eligible(I) && nch > 0;
+        return on ? kids16_ensure(k, I, K, nch, s) : hipSuccess;
+    }
+};
+
+// Branch and bound the children of the single search in dreq: from their
+// parents on the incremental path, else through child rows and the plain
+// bound launch.
+static hipError_t branch_and_bound1(const StepReq *dreq, fsp_instance_s *I, KidsStep &ks, int64_t K, int64_t nch,
+                                    const StepScratch &w, hipStream_t s, bool sort_depths)
+{
+    hipError_t e;
+    if (ks.on) {
+        e = mstep_list(dreq, 1, K, nch, s);
+        if (e == hipSuccess) e = kids16_bound(dreq, I, ks.k, w.clb, s);
+    } else {
+        e = mstep_branch(dreq, 1, K, nch, s);
+        if (e == hipSuccess) e = bound_rows(I, w.crow, w.cdepth, nch, w.clb, s, sort_depths);
+    }
+    return e;
+}
+
 hipError_t Search::begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in, int64_t node_budget_in,
                          hipStream_t s)
 {
@@ -278,11 +309,12 @@ void Search::release(hipStream_t s)
     if (dinc) hipFreeAsync(dinc, s);
     srows = sdep = dinc = nullptr;
     B.release(s);
+    kids16_release(kids, s);
 }
 
 size_t Search::device_bytes() const
 {
-    return (size_t)cap_stack * (n + 1) * 4 + (size_t)n * 4 + B.bytes();
+    return (size_t)cap_stack * (n + 1) * 4 + (size_t)n * 4 + B.bytes() + kids.bytes;
 }
 
 void Search::result(fsp_solve_result *res, int32_t *perm_out) const
@@ -394,6 +426,11 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     const TabLayout L(R, sumK);
     hipError_t e = ctx.reserve(L.total);
     if (e != hipSuccess) return e;
+    KidsStep ks(act[0]->kids);  // a search stepping alone bounds its children from their parents
+    if (R == 1) {
+        e = ks.start(act[0]->inst, act[0]->K, act[0]->nch, s);
+        if (e != hipSuccess) return e;
+    }
     char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
     StepReq *hq = (StepReq *)(h + L.req);
     ScanSeg *hs1 = (ScanSeg *)(h + L.seg1), *hs2 = (ScanSeg *)(h + L.seg2);
@@ -419,6 +456,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         q.a.surv_per_parent = (uint32_t *)(d + L.surv) + slot;
         q.a.incumbent = S.dinc;
         q.w = S.B.w;
+        if (ks.on) q.w.prow = ks.k.prow;
         q.nchild = S.nch;
         bind_results(q, (StepReq *)(d + L.req) + r, S.UB);
         slots[r] = slot;
@@ -431,13 +469,14 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     const ScanSeg *ds1 = (const ScanSeg *)(d + L.seg1), *ds2 = (const ScanSeg *)(d + L.seg2);
     e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = mstep_phase1(dq, ds1, R, maxK, s);
-    if (e == hipSuccess) e = mstep_branch(dq, R, maxK, maxC, s);
     if (e != hipSuccess) return e;
-    // bounding: one plain launch for a single search, else one merged batch
+    // bounding: one search alone from its parents (or one plain launch),
+    // several searches through one merged batch
     if (R == 1) {
         Search &S = *act[0];
-        e = bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s, false);
+        e = branch_and_bound1(dq, S.inst, ks, S.K, S.nch, S.B.w, s, false);
     } else {
+        e = mstep_branch(dq, R, maxK, maxC, s);
         std::vector<fsp_pool_desc> descs;
         descs.reserve(R);
         for (Search *S : act) {
@@ -616,11 +655,13 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
     bf.s = s;
     bf.n = n;
     StepBuffers B;
+    Kids16 kids;
     TickContext ctx;
     ctx.s = s;
     auto cleanup = [&]() {
         bf.release();
         B.release(s);
+        kids16_release(kids, s);
         ctx.release();
     };
     hipError_t e = bf.alloc(std::max<int64_t>(4096, 4 * pool_cap));
@@ -667,6 +708,9 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         if (e == hipSuccess) e = bf.ensure_survivors(nch);
         if (e == hipSuccess) e = ctx.reserve(L.total);
         if (e != hipSuccess) break;
+        KidsStep ks(kids);
+        e = ks.start(inst, K, nch, s);
+        if (e != hipSuccess) break;
         const Frontier Fc = bf.F(cur), Fn = bf.F(cur ^ 1);
         char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
         StepReq *dentry = (StepReq *)(d + L.req);
@@ -687,6 +731,7 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         q.a.out_cap = nch;
         q.a.incumbent = bf.dinc;
         q.w = B.w;
+        if (ks.on) q.w.prow = ks.k.prow;
         q.nchild = nch;
         bind_results(q, dentry, UB);
         *(StepReq *)(h + L.req) = q;
@@ -695,8 +740,8 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         const uint32_t *dnsurv = &dentry->res.nsurv;
         e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
-        if (e == hipSuccess) e = mstep_branch(dentry, 1, K, nch, s);
-        if (e == hipSuccess) e = bound_rows(inst, q.w.crow, q.w.cdepth, nch, q.w.clb, s);  // parents of mixed depths
+        // parents of mixed depths: the row path sorts its children by depth
+        if (e == hipSuccess) e = branch_and_bound1(dentry, inst, ks, K, nch, q.w, s, true);
         if (e == hipSuccess) e = mstep_finish(dentry, (const ScanSeg *)(d + L.seg2), 1, K, nch, s);
         if (e == hipSuccess)
             e = bf_sort_survivors(bf.S(1), dnsurv, nch, UB, bf.S(2), bf.S(3), bf.S(4), bf.S(5), &bf.tmp,
@@ -771,10 +816,12 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     if (!g.ok) return FSP_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
     StepBuffers B;
+    Kids16 kids;
     TickContext ctx;
     ctx.s = s;
     auto cleanup = [&]() {
         B.release(s);
+        kids16_release(kids, s);
         ctx.release();
     };
     const TabLayout L(1, K);
@@ -813,15 +860,18 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     }
     if (e != hipSuccess) { cleanup(); return fail_status(e); }
     const StepResultDev after1 = ((const StepReq *)(h + L.req))->res;
+    KidsStep ks(kids);
+    e = ks.start(inst, K, nchild, s);
+    if (e != hipSuccess) { cleanup(); return fail_status(e); }
     q.w = B.w;
+    if (ks.on) q.w.prow = ks.k.prow;
     point_results(q, dentry);
     q.res = after1;
     q.nchild = nchild;
     *(StepReq *)(h + L.req) = q;
     *(ScanSeg *)(h + L.seg2) = ScanSeg{q.w.keep, q.w.pos, (int64_t)nchild, q.w.nsurv, B.sums_c};
     e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = mstep_branch(dq, 1, K, nchild, s);
-    if (e == hipSuccess) e = bound_rows(inst, q.w.crow, q.w.cdepth, nchild, q.w.clb, s);
+    if (e == hipSuccess) e = branch_and_bound1(dq, inst, ks, K, nchild, q.w, s, true);
     if (e == hipSuccess) e = mstep_finish(dq, (const ScanSeg *)(d + L.seg2), 1, K, nchild, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h + L.req, d + L.req, sizeof(StepReq), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
