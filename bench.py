@@ -110,6 +110,12 @@ def _time(fn, reps: int) -> float:
     return (time.perf_counter() - t0) / reps
 
 
+def _time_best(fn, reps: int, rounds: int = 3) -> float:
+    """Per-call time of the fastest of `rounds` back-to-back timings of `reps`
+    calls (a host hiccup inside one round does not set the figure)."""
+    return min(_time(fn, reps) for _ in range(rounds))
+
+
 def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
     """Batched (one graph-captured persistent launch) vs plain (one launch per
     pool) on the same pools, outputs compared element by element."""
@@ -285,8 +291,8 @@ def tables_leg(stream, reps: int) -> dict:
 
                 for fn in (device_only, with_transfers, device_only, with_transfers):
                     fn()
-                t_dev = _time(device_only, reps)
-                t_xfer = _time(with_transfers, reps)
+                t_dev = _time_best(device_only, reps)
+                t_xfer = _time_best(with_transfers, reps)
                 row[str(N)] = {"device_nodes_per_s": N / t_dev, "with_transfers_nodes_per_s": N / t_xfer}
         out["%dx%d" % (n, m)] = row
     return out

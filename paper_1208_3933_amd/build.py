@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfspbb.so")
 ARCH = "gfx950"
-SOURCES = ["instance.cpp", "api.cpp", "bound_lane32.hip", "bound_packed.hip", "bound_wavepair.hip", "children16.hip", "scan.hip", "bnb.hip",
+SOURCES = ["instance.cpp", "api.cpp", "bound_lane32.hip", "bound_packed.hip", "scan16_plain.hip", "bound_wavepair.hip", "children16.hip", "scan.hip", "bnb.hip",
            "solve.hip", "best_first.hip", "batch.cpp", "tune.cpp", "server.cpp",
            "explore.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

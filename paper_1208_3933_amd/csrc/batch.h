@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "fspbb_internal.h"
+#include "ws16.h"
 
 namespace fspbb {
 
@@ -17,19 +18,6 @@ constexpr int kSortMaxBlocks = 64;
 // of MV / 2 packed processing-time pairs.  Monotone in n, so a launch sized
 // for the largest n of several pools serves all of them.
 inline size_t decode16_lds_words(int n, int MV) { return (size_t)((n + 31) >> 5) * 256 + (size_t)(n + 1) * (MV / 2); }
-
-// Decode workspace of one pool in the 16-bit path (see bound_packed.hip).
-struct Workspace16 {
-    uint32_t *dec;    // G x 3 x m x 64 dwords: releases R, closing sums Tk, tails Q
-    uint32_t *flg;    // G x NW x 128 dwords: unscheduled-job bits per node
-    uint32_t *st;     // G*128: 1 = valid node
-    int32_t *order;   // N: node index at each depth-sorted position, or null (identity)
-    uint32_t *cnt;    // (n + 2) x B: per-block depth counts, then scatter offsets
-};
-
-// The 16-bit scan alone over a decoded workspace of N nodes (identity order
-// unless W.order is set), bounds to out_lb.
-hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s);
 
 constexpr int kBatchWaves = 16;  // waves per workgroup of the persistent scan
 constexpr int64_t kSortMinNodes = 512;  // smaller pools are decoded in pool order

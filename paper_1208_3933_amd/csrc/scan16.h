@@ -3,7 +3,7 @@
 // scalar loads, per-(job, lane) masks in LDS read with M0-based addressing.
 #pragma once
 
-#include "batch.h"
+#include "ws16.h"
 #include "bound_common.h"
 
 namespace fspbb {

@@ -59,9 +59,15 @@ def expected_step(p, parents, depths, ub_in):
             "fingerprint": fp, "survivors": surv, "incumbent": inc}
 
 
+# With no upper bound every non-leaf child survives, so its bound is checked.
+# The 16-bit instances bound the children from their parents; the shapes
+# cover rows whose length is and is not a multiple of 4, m below, at and
+# above 20 (padded machine slots), and up to 32 machines.
 @pytest.mark.parametrize("n,m,K,seed,ub_mode", [(8, 4, 9, 1, "none"), (8, 4, 30, 2, "tight"),
                                                 (20, 5, 64, 3, "neh"), (50, 10, 40, 4, "neh"),
-                                                (12, 6, 50, 5, "deep")])
+                                                (12, 6, 50, 5, "deep"), (200, 20, 120, 6, "none"),
+                                                (50, 19, 150, 7, "none"), (300, 32, 16, 8, "none"),
+                                                (30, 7, 400, 9, "deep")])
 def test_branch_and_prune_step(n, m, K, seed, ub_mode):
     torch = require_gpu()
     p = inst_times(n, m, seed)
