@@ -365,7 +365,7 @@ def bnb_leg(inst, steps: int, stream, best_first: bool = False) -> dict:
     t0 = time.perf_counter()
     ub0, _ = fspbb.neh(inst)
     neh_ms = (time.perf_counter() - t0) * 1e3
-    fspbb.solve(inst, ub0, POOL, 1 + 2 * POOL, 0, stream, best_first=best_first)  # warm-up: the first steps
+    fspbb.solve(inst, ub0, POOL, 1 + steps * POOL, 0, stream, best_first=best_first)  # warm-up: the same search
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = fspbb.solve(inst, ub0, POOL, 1 + steps * POOL, 0, stream, best_first=best_first)

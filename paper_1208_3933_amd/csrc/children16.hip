@@ -240,7 +240,8 @@ hipError_t kids16_ensure(Kids16 &k, const fsp_instance_s *I, int64_t K, int64_t 
     if (k.blob) hipFreeAsync(k.blob, s);
     k.blob = nullptr;
     const int n = I->n, m = I->m, NW = (n + 31) >> 5;
-    const int64_t capK = std::max<int64_t>({K, 2 * k.capK, 1}), capC = std::max<int64_t>({nch, k.capC, kGroup});
+    // both grow by doubling: a search's steps vary by a few children
+    const int64_t capK = std::max<int64_t>({K, 2 * k.capK, 1}), capC = std::max<int64_t>({nch, 2 * k.capC, kGroup});
     const int64_t G = (capC + kGroup - 1) / kGroup;
     const size_t rows_b = al256((size_t)capK * n * 4), rec_b = al256((size_t)capK * kKidRec * 4),
                  dec_b = al256((size_t)G * 3 * m * 64 * 4), flg_b = al256((size_t)G * NW * 128 * 4),

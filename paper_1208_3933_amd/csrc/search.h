@@ -14,6 +14,11 @@
 
 namespace fspbb {
 
+// Stack rows a depth-first search allocates at its start: room for a few
+// pools' worth of survivors before the first doubling (each doubling copies
+// the stack).
+inline int64_t initial_stack_rows(int64_t pool_cap) { return pool_cap > 128 ? 8 * pool_cap : 1024; }
+
 // Device scratch of one search's steps: the parent part (K) and the child
 // part (C) grow independently, so the parent outputs survive a child resize.
 struct StepBuffers {

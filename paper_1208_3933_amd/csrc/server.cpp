@@ -36,7 +36,7 @@ size_t initial_bytes(int n, int64_t pool_cap)
     Search S;
     S.n = n;
     S.pool_cap = pool_cap;
-    S.cap_stack = std::max<int64_t>(1024, 2 * pool_cap);
+    S.cap_stack = initial_stack_rows(pool_cap);
     S.B.Kcap = pool_cap;
     S.B.Ccap = pool_cap;
     S.B.n = n;

@@ -225,7 +225,7 @@ hipError_t Search::begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in,
     inc.assign(n, -1);
     UB = ub0_in == FSP_UB_NEH ? neh(I->p_host, n, I->m, inc.data()) : ub0_in;
     ub0 = UB;
-    cap_stack = std::max<int64_t>(1024, 2 * pool_cap);
+    cap_stack = initial_stack_rows(pool_cap);
     hipError_t e = stream_alloc((void **)&srows, (size_t)cap_stack * n * 4, s);
     if (e == hipSuccess) e = stream_alloc((void **)&sdep, (size_t)cap_stack * 4, s);
     if (e == hipSuccess) e = stream_alloc((void **)&dinc, (size_t)n * 4, s);
