@@ -664,7 +664,9 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         kids16_release(kids, s);
         ctx.release();
     };
-    hipError_t e = bf.alloc(std::max<int64_t>(4096, 4 * pool_cap));
+    // slots for eight pools of survivors before the first doubling (a doubling
+    // copies the slab)
+    hipError_t e = bf.alloc(std::max<int64_t>(4096, 8 * pool_cap));
     // step buffers at their usual size up front (a parent with more children
     // than pool_cap grows them later)
     if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
