@@ -74,11 +74,12 @@ fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out
 }
 
 void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl,
-                int32_t form_force)
+                int32_t form_force, const Workspace16 *ready)
 {
     pl = BatchPlan{};
     pl.pools.resize(n_pools);
     pl.ws_off.resize(n_pools);
+    pl.decoded.assign(n_pools, 0);
     struct Cost { int64_t cost; WorkItem w; };
     std::vector<Cost> items;
     size_t ws = 0;
@@ -88,11 +89,15 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         const fsp_instance_s *I = d.inst;
         const int n = I->n, m = I->m, NW = (n + 31) >> 5;
         const int64_t G = (d.N + kGroup - 1) / kGroup, Npad = G * kGroup;
+        const bool given = ready && ready[i].dec;
+        pl.decoded[i] = given ? 1 : 0;
         pl.ws_off[i] = ws;
-        ws += al256((size_t)G * 3 * m * 64 * 4) + al256((size_t)G * NW * 128 * 4) + al256((size_t)Npad * 4);
+        if (!given)
+            ws += al256((size_t)G * 3 * m * 64 * 4) + al256((size_t)G * NW * 128 * 4) + al256((size_t)Npad * 4);
         BatchPool &P = pl.pools[i];
         std::memset(&P, 0, sizeof(P));
-        if (sort_depths && d.N >= kSortMinNodes) {
+        if (given) P.W = ready[i];
+        if (!given && sort_depths && d.N >= kSortMinNodes) {
             P.sortB = (int32_t)std::min<int64_t>(kSortMaxBlocks, (d.N + 4095) / 4096);
             P.sort_chunk = (d.N + P.sortB - 1) / P.sortB;
             ws += al256((size_t)d.N * 4) + al256((size_t)(n + 2) * P.sortB * 4);
@@ -124,7 +129,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
 
     std::map<int, std::vector<int32_t>> cls;
     for (int i = 0; i < n_pools; ++i)
-        if (pools[i].N > 0) cls[(pools[i].inst->m + 3) & ~3].push_back(i);
+        if (pools[i].N > 0 && !pl.decoded[i]) cls[(pools[i].inst->m + 3) & ~3].push_back(i);
     for (auto &kv : cls) {
         BatchPlan::Cls c;
         c.MV = kv.first;
@@ -173,6 +178,7 @@ void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host)
 {
     for (size_t i = 0; i < pl.pools.size(); ++i) {
         BatchPool &P = pl.pools[i];
+        if (pl.decoded[i]) continue;  // the caller's workspace
         const int n = P.T.n, m = P.T.m, NW = (n + 31) >> 5;
         const int64_t G = P.Npad / kGroup;
         char *w = base + pl.ws_off[i];
@@ -229,9 +235,9 @@ int batch_grid(int dev, size_t scan_lds)
     return prop.multiProcessorCount * batch_scan_blocks_per_cu(scan_lds);
 }
 
-hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s)
+hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s, const Workspace16 *ready)
 {
-    plan_batch(pools, n_pools, 0, false, plan);  // child pools of a step have few distinct depths
+    plan_batch(pools, n_pools, 0, false, plan, -1, ready);  // child pools of a step have few distinct depths
     const size_t need = plan.ws_bytes + plan.meta_bytes;
     if (need > dev_bytes) {
         const size_t cap = std::max(need, dev_bytes * 2);

@@ -93,6 +93,7 @@ struct BatchPlan {
     int form = kBatchGrid;
     size_t meta_pools = 0, meta_items = 0, meta_counter = 0;
     int64_t total_nodes = 0;
+    std::vector<char> decoded;        // per pool: workspace given by the caller (not laid out)
     char *dmeta = nullptr;            // device address of the metadata once laid out
 };
 
@@ -101,8 +102,11 @@ fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out
 // divergent prefix loops on pools of mixed depths).
 // form: the launch form: persistent when every pool's shape prefers it, else
 // one workgroup per item; form_force >= 0 overrides.
+// ready (optional, one entry per pool): a pool whose entry has a non-null dec
+// is already decoded into that workspace (identity order); it is neither
+// sorted nor decoded and takes no workspace of the plan.
 void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl,
-                int32_t form_force = -1);
+                int32_t form_force = -1, const Workspace16 *ready = nullptr);
 void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host_meta);
 hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s);
 int batch_grid(int dev, size_t scan_lds);
@@ -119,7 +123,7 @@ struct BatchArena {
     size_t dev_bytes = 0;
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
-    hipError_t run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s);
+    hipError_t run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s, const Workspace16 *ready = nullptr);
     void release(hipStream_t s);
 };
 

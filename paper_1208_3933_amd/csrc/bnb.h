@@ -6,6 +6,7 @@
 
 #include "fspbb_internal.h"
 #include "scan.h"
+#include "ws16.h"
 
 namespace fspbb {
 
@@ -52,8 +53,11 @@ struct StepScratch {
     // Set when the children are bounded from their parents (kids16_bound):
     // K x n copy of the parent rows; child rows are then never written, and
     // survivor rows and the incumbent are built from it and ujob.  Null =
-    // child rows in crow.
-    const int32_t *prow;
+    // child rows in crow.  krec holds the parent records and kw the
+    // children's scan inputs (see kids16.h).
+    int32_t *prow;
+    int32_t *krec;
+    Workspace16 kw;
 };
 
 // Per-search scalars of a step.  They live in the search's entry of the
@@ -71,6 +75,7 @@ struct StepResultDev {
 struct StepReq {
     StepArgs a;
     StepScratch w;
+    DevTables T;                 // the search's instance tables
     int64_t nchild;              // children of this step (set before the branch phase)
     int64_t reserved;
     StepResultDev res;

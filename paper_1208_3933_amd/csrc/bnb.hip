@@ -75,6 +75,7 @@ constexpr int kRowsPerBlock = 256 / kRowLanes;
 __global__ __launch_bounds__(256) void mstep_rows_kernel(const StepReq *__restrict__ reqs)
 {
     ReqP q = req_of(reqs);
+    if (q->w.prow) return;  // whole block: children bounded from their parents
     const int64_t c = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kRowLanes);
     const int sub = threadIdx.x % kRowLanes;
     if (c >= q->nchild) return;

@@ -25,10 +25,10 @@ namespace {
 // Stages the processing times as 16-bit pairs: row j holds machines (2c, 2c+1)
 // in word c; row n is zero.  Every thread of the block calls it.
 template <int H>
-__device__ inline void stage_p16(const DevTables &T, uint32_t *p16)
+__device__ inline void stage_p16(int n, const int32_t *p32, uint32_t *p16)
 {
-    for (int e = threadIdx.x; e < (T.n + 1) * H; e += blockDim.x) {
-        const int32_t *r = T.p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H);
+    for (int e = threadIdx.x; e < (n + 1) * H; e += blockDim.x) {
+        const int32_t *r = p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H);
         p16[e] = ((uint32_t)r[0] & 0xffffu) | ((uint32_t)r[1] << 16);
     }
     __syncthreads();
@@ -38,13 +38,15 @@ __device__ inline void stage_p16(const DevTables &T, uint32_t *p16)
 // unscheduled jobs per machine.  Parents with no children (invalid, or
 // complete) are skipped; the count kernel has validated the others.
 template <int MV>
-__global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restrict__ reqs, DevTables T,
-                                                        int32_t *__restrict__ rec)
+__global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restrict__ reqs)
 {
     constexpr int H = MV / 2;
     extern __shared__ uint32_t p16[];
-    stage_p16<H>(T, p16);
     ReqP q = req_of(reqs);
+    if (!q->w.prow || (int64_t)blockIdx.x * 256 >= q->a.K) return;  // whole block
+    const int n = q->T.n;
+    stage_p16<H>(n, q->T.p32, p16);
+    int32_t *__restrict__ rec = q->w.krec;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= q->a.K || q->w.cnt[p] == 0) return;
     const int d = parent_depth(q, p);
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restric
         const int32_t jj[4] = {j0, j1, j2, j3};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int j = t + c < d ? jj[c] : T.n;
+            const int j = t + c < d ? jj[c] : n;
             const uint2 *pr = reinterpret_cast<const uint2 *>(p16 + __mul24(j, H));
             int32_t prev = 0;
 #pragma unroll
@@ -80,7 +82,6 @@ __global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restric
             }
         }
     };
-    const int n = T.n;
     if ((n & 3) == 0 && ((uintptr_t)row & 15) == 0) {
         // 16-byte row loads, two in flight (indices clamped into the row)
         const int4 *r4 = reinterpret_cast<const int4 *>(row);
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restric
             step4(row[min(t, n - 1)], row[min(t + 1, n - 1)], row[min(t + 2, n - 1)], row[min(t + 3, n - 1)], t);
     }
     int32_t *r = rec + p * kKidRec;
-    cptr<int32_t> cs = as_const(T.colsum32);
+    cptr<int32_t> cs = as_const(q->T.colsum32);
 #pragma unroll
     for (int k = 0; k < MV; ++k) {
         r[kKidC + k] = C[k];
@@ -108,16 +109,19 @@ __global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restric
 // One wave per parent: copies the parent row, builds its unscheduled set, and
 // lane k (< m) finds the least and second least tails on machine k over the
 // unscheduled jobs, taken in increasing id.
-__global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restrict__ reqs, DevTables T,
-                                                        int32_t *__restrict__ rec, int32_t *__restrict__ prow)
+__global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ uint32_t mask[4][kMaskWords];
     ReqP q = req_of(reqs);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    if (!q->w.prow) return;        // whole block: the request bounds children from rows
     if (p >= q->a.K) return;       // whole wave
     if (q->w.cnt[p] == 0) return;  // whole wave
-    const int n = T.n, m = T.m, NW = (n + 31) >> 5;
+    int32_t *__restrict__ rec = q->w.krec;
+    int32_t *__restrict__ prow = q->w.prow;
+    const int32_t *__restrict__ tails32 = q->T.tails32;
+    const int n = q->T.n, m = q->T.m, NW = (n + 31) >> 5;
     const int d = parent_depth(q, p);
     const int32_t *row = parent_row(q, p);
     int32_t *pr = prow + p * (int64_t)n;
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restric
     for (int w = 0; w < NW; ++w) {
         const uint32_t sched = __builtin_amdgcn_readfirstlane(mask[wv][w]);
         const int jn = min(32, n - 32 * w);
-        const int32_t *tw = T.tails32 + (size_t)(32 * w) * kMaxMachines + k;
+        const int32_t *tw = tails32 + (size_t)(32 * w) * kMaxMachines + k;
 #pragma unroll 8
         for (int b = 0; b < jn; ++b) {
             const int32_t t = tw[(size_t)b * kMaxMachines];
@@ -155,18 +159,20 @@ __global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restric
 // One lane per child (and per padding slot up to the group boundary): writes
 // the scan inputs of child i in the decode kernel's layout, and its depth.
 template <int MV>
-__global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restrict__ reqs, DevTables T,
-                                                         const int32_t *__restrict__ rec, Workspace16 W, int64_t N,
-                                                         int64_t Npad)
+__global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restrict__ reqs)
 {
     constexpr int H = MV / 2;
     extern __shared__ uint32_t p16[];
-    stage_p16<H>(T, p16);
     ReqP q = req_of(reqs);
+    const int64_t N = q->nchild, Npad = (N + kGroup - 1) / kGroup * kGroup;
+    if (!q->w.prow || (int64_t)blockIdx.x * 256 >= Npad) return;  // whole block
+    const int n = q->T.n, m = q->T.m, NW = (n + 31) >> 5;
+    stage_p16<H>(n, q->T.p32, p16);
+    const int32_t *__restrict__ rec = q->w.krec;
+    uint32_t *const Wdec = q->w.kw.dec, *const Wflg = q->w.kw.flg, *const Wst = q->w.kw.st;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= Npad) return;
     const bool live = i < N;
-    const int n = T.n, m = T.m, NW = (n + 31) >> 5;
     int32_t j = n;  // the zero row for padding slots
     int64_t p = 0;
     int d = 0;
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
     const bool empty = d == n;  // a complete child: no tail
     const int64_t G = i >> 7;
     const int g = (int)(i & 127), lane = g & 63, half = g >> 6;
-    uint16_t *d16 = reinterpret_cast<uint16_t *>(W.dec);
+    uint16_t *d16 = reinterpret_cast<uint16_t *>(Wdec);
     int32_t prev = 0;
 #pragma unroll
     for (int q4 = 0; q4 < MV / 4; ++q4) {
@@ -206,26 +212,23 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
     for (int w = 0; w < kMaskWords; ++w) {
         if (w < NW) {
             const uint32_t drop = (j >> 5) == w ? 1u << (j & 31) : 0u;
-            W.flg[(G * NW + w) * 128 + g] = live ? ((uint32_t)r[kKidM + w] & ~drop) : 0u;
+            Wflg[(G * NW + w) * 128 + g] = live ? ((uint32_t)r[kKidM + w] & ~drop) : 0u;
         }
     }
-    W.st[i] = live ? 1u : 0u;
+    Wst[i] = live ? 1u : 0u;
 }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 template <int MV>
-hipError_t launch_kids(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s)
+hipError_t launch_kids(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, hipStream_t s)
 {
-    const size_t lds = (size_t)(I->n + 1) * (MV / 2) * 4;
-    const int64_t Npad = (k.nch + kGroup - 1) / kGroup * kGroup;
-    kid_chain_kernel<MV><<<dim3((unsigned)((k.K + 255) / 256), 1), 256, lds, s>>>(dreq, I->dt, k.rec);
-    kid_tails_kernel<<<dim3((unsigned)((k.K + 3) / 4), 1), 256, 0, s>>>(dreq, I->dt, k.rec, k.prow);
-    kid_decode_kernel<MV><<<dim3((unsigned)((Npad + 255) / 256), 1), 256, lds, s>>>(dreq, I->dt, k.rec, k.W,
-                                                                                     k.nch, Npad);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_scan16(I, k.W, k.nch, clb, s);
+    const size_t lds = (size_t)(nmax + 1) * (MV / 2) * 4;
+    const int64_t Npad = (maxC + kGroup - 1) / kGroup * kGroup;
+    kid_chain_kernel<MV><<<dim3((unsigned)((maxK + 255) / 256), R), 256, lds, s>>>(dreqs);
+    kid_tails_kernel<<<dim3((unsigned)((maxK + 3) / 4), R), 256, 0, s>>>(dreqs);
+    kid_decode_kernel<MV><<<dim3((unsigned)((Npad + 255) / 256), R), 256, lds, s>>>(dreqs);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -267,25 +270,102 @@ hipError_t kids16_ensure(Kids16 &k, const fsp_instance_s *I, int64_t K, int64_t 
     return hipSuccess;
 }
 
+namespace {
+// Byte sizes of one search's scratch: parent rows, parent records, decode,
+// bits, valid flags (each 256-byte aligned).
+struct KidsSizes {
+    size_t rows, rec, dec, flg, st;
+    KidsSizes(int n, int m, int64_t K, int64_t C)
+    {
+        const int NW = (n + 31) >> 5;
+        const int64_t G = std::max<int64_t>((C + kGroup - 1) / kGroup, 1);
+        rows = al256((size_t)std::max<int64_t>(K, 1) * n * 4);
+        rec = al256((size_t)std::max<int64_t>(K, 1) * kKidRec * 4);
+        dec = al256((size_t)G * 3 * m * 64 * 4);
+        flg = al256((size_t)G * NW * 128 * 4);
+        st = al256((size_t)G * kGroup * 4);
+    }
+    size_t total() const { return rows + rec + dec + flg + st; }
+    void point(char *b, Kids16 &k) const
+    {
+        k.prow = (int32_t *)b;
+        k.rec = (int32_t *)(b + rows);
+        k.W.dec = (uint32_t *)(b + rows + rec);
+        k.W.flg = (uint32_t *)(b + rows + rec + dec);
+        k.W.st = (uint32_t *)(b + rows + rec + dec + flg);
+        k.W.order = nullptr;
+        k.W.cnt = nullptr;
+    }
+};
+}  // namespace
+
+hipError_t KidsArena::layout(const std::vector<const fsp_instance_s *> &I, const std::vector<int64_t> &K,
+                             const std::vector<int64_t> &nch, std::vector<Kids16> &out, hipStream_t s)
+{
+    size_t need = 0;
+    for (size_t i = 0; i < I.size(); ++i) need += KidsSizes(I[i]->n, I[i]->m, K[i], nch[i]).total();
+    if (need > cap) {
+        const size_t c = std::max(need, 2 * cap);
+        if (blob) hipFreeAsync(blob, s);
+        blob = nullptr;
+        cap = 0;
+        hipError_t e = stream_alloc(&blob, c, s);
+        if (e != hipSuccess) return e;
+        cap = c;
+    }
+    out.assign(I.size(), Kids16{});
+    char *b = (char *)blob;
+    for (size_t i = 0; i < I.size(); ++i) {
+        const KidsSizes z(I[i]->n, I[i]->m, K[i], nch[i]);
+        z.point(b, out[i]);
+        out[i].K = K[i];
+        out[i].nch = nch[i];
+        b += z.total();
+    }
+    return hipSuccess;
+}
+
+void KidsArena::release(hipStream_t s)
+{
+    if (blob) hipFreeAsync(blob, s);
+    blob = nullptr;
+    cap = 0;
+}
+
 void kids16_release(Kids16 &k, hipStream_t s)
 {
     if (k.blob) hipFreeAsync(k.blob, s);
     k = Kids16{};
 }
 
+void kids16_point(StepScratch &w, const Kids16 &k)
+{
+    w.prow = k.prow;
+    w.krec = k.rec;
+    w.kw = k.W;
+}
+
+hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s)
+{
+    if (R <= 0 || maxK <= 0 || maxC <= 0) return hipSuccess;
+    switch ((mmax + 3) & ~3) {
+    case 4: return launch_kids<4>(dreqs, R, maxK, maxC, nmax, s);
+    case 8: return launch_kids<8>(dreqs, R, maxK, maxC, nmax, s);
+    case 12: return launch_kids<12>(dreqs, R, maxK, maxC, nmax, s);
+    case 16: return launch_kids<16>(dreqs, R, maxK, maxC, nmax, s);
+    case 20: return launch_kids<20>(dreqs, R, maxK, maxC, nmax, s);
+    case 24: return launch_kids<24>(dreqs, R, maxK, maxC, nmax, s);
+    case 28: return launch_kids<28>(dreqs, R, maxK, maxC, nmax, s);
+    default: return launch_kids<32>(dreqs, R, maxK, maxC, nmax, s);
+    }
+}
+
 hipError_t kids16_bound(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s)
 {
     if (k.nch <= 0 || k.K <= 0) return hipSuccess;
-    switch ((I->m + 3) & ~3) {
-    case 4: return launch_kids<4>(dreq, I, k, clb, s);
-    case 8: return launch_kids<8>(dreq, I, k, clb, s);
-    case 12: return launch_kids<12>(dreq, I, k, clb, s);
-    case 16: return launch_kids<16>(dreq, I, k, clb, s);
-    case 20: return launch_kids<20>(dreq, I, k, clb, s);
-    case 24: return launch_kids<24>(dreq, I, k, clb, s);
-    case 28: return launch_kids<28>(dreq, I, k, clb, s);
-    default: return launch_kids<32>(dreq, I, k, clb, s);
-    }
+    hipError_t e = kids16_decode(dreq, 1, k.K, k.nch, I->n, I->m, s);
+    if (e != hipSuccess) return e;
+    return launch_scan16(I, k.W, k.nch, clb, s);
 }
 
 }  // namespace fspbb

@@ -2,6 +2,8 @@
 // instances on the 16-bit path with the plain releases.
 #pragma once
 
+#include <vector>
+
 #include "batch.h"
 #include "bnb.h"
 
@@ -31,14 +33,34 @@ struct Kids16 {
     int n = 0, m = 0;
 };
 
+// One region holding the scratch of every search of a merged step, laid out
+// anew at each step.  It grows by doubling and is kept: searches that live a
+// few dozen steps would otherwise allocate on every few steps.
+struct KidsArena {
+    void *blob = nullptr;
+    size_t cap = 0;
+    // out[i] views the region for a search of instance I[i] with K[i] parents
+    // and nch[i] children.
+    hipError_t layout(const std::vector<const fsp_instance_s *> &I, const std::vector<int64_t> &K,
+                      const std::vector<int64_t> &nch, std::vector<Kids16> &out, hipStream_t s);
+    void release(hipStream_t s);
+};
+
 // Whether children of this instance are bounded from their parents.
 bool kids16_eligible(const fsp_instance_s *I);
 // Sets the step's sizes, growing the buffers if needed (stream ordered).
 hipError_t kids16_ensure(Kids16 &k, const fsp_instance_s *I, int64_t K, int64_t nch, hipStream_t s);
 void kids16_release(Kids16 &k, hipStream_t s);
-// After mstep_list of the single search in dreq (whose w.prow is k.prow):
-// decodes its parents, then its children into k.W, writes the children's
-// depths (w.cdepth) and their bounds to clb (its w.clb).
+// Points a request's scratch at the buffers (w.prow, w.krec, w.kw); a request
+// whose w.prow is null bounds its children from rows instead.
+void kids16_point(StepScratch &w, const Kids16 &k);
+// After mstep_list: for every request of the R in dreqs whose w.prow is set,
+// decodes its parents, then its children into w.kw, and writes the children's
+// depths (w.cdepth).  maxK / maxC bound the requests' parents and children;
+// nmax / mmax their jobs and machines.
+hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s);
+// The single search in dreq: kids16_decode, then the plain scan of its
+// children, bounds to clb (its w.clb).
 hipError_t kids16_bound(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s);
 
 }  // namespace fspbb

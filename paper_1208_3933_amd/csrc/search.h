@@ -40,6 +40,7 @@ struct TickContext {
     void *dtab = nullptr, *htab = nullptr;
     size_t dcap = 0, hcap = 0;
     BatchArena arena;
+    KidsArena kids;  // the incremental scratch of a step's searches
     hipError_t reserve(size_t bytes);
     void release();
 };
@@ -55,7 +56,6 @@ struct Search {
     uint32_t *dsurv = nullptr;                        // survivors per popped parent
     int64_t cap_stack = 0;
     StepBuffers B;
-    Kids16 kids;  // scratch of the steps that bound children from their parents
     std::vector<std::pair<int32_t, int64_t>> runs;    // run-length mirror of stack depths
     std::vector<std::pair<int32_t, int64_t>> taken;   // this step's pops (depth, count)
     int64_t top = 0, nodes = 0, steps = 0, max_stack = 0;

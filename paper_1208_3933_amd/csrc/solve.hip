@@ -111,6 +111,7 @@ void TickContext::release()
 {
     if (dtab) hipFreeAsync(dtab, s);
     arena.release(s);
+    kids.release(s);
     hipStreamSynchronize(s);
     if (htab) hipHostFree(htab);
     dtab = htab = nullptr;
@@ -309,12 +310,11 @@ void Search::release(hipStream_t s)
     if (dinc) hipFreeAsync(dinc, s);
     srows = sdep = dinc = nullptr;
     B.release(s);
-    kids16_release(kids, s);
 }
 
 size_t Search::device_bytes() const
 {
-    return (size_t)cap_stack * (n + 1) * 4 + (size_t)n * 4 + B.bytes() + kids.bytes;
+    return (size_t)cap_stack * (n + 1) * 4 + (size_t)n * 4 + B.bytes();
 }
 
 void Search::result(fsp_solve_result *res, int32_t *perm_out) const
@@ -426,9 +426,32 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     const TabLayout L(R, sumK);
     hipError_t e = ctx.reserve(L.total);
     if (e != hipSuccess) return e;
-    KidsStep ks(act[0]->kids);  // a search stepping alone bounds its children from their parents
-    if (R == 1) {
-        e = ks.start(act[0]->inst, act[0]->K, act[0]->nch, s);
+    // searches on the 16-bit path with the plain releases bound their
+    // children from their parents; the others from child rows
+    std::vector<int> kid_of(R, -1);  // index into kv, or -1 (child rows)
+    std::vector<const fsp_instance_s *> kI;
+    std::vector<int64_t> kKs, kCs;
+    int64_t kK = 0, kC = 0;
+    int knmax = 0, kmmax = 0;
+    bool any_rows = false;
+    for (int r = 0; r < R; ++r) {
+        Search &S = *act[r];
+        if (kids16_eligible(S.inst) && S.nch > 0) {
+            kid_of[r] = (int)kI.size();
+            kI.push_back(S.inst);
+            kKs.push_back(S.K);
+            kCs.push_back(S.nch);
+            kK = std::max(kK, S.K);
+            kC = std::max(kC, S.nch);
+            knmax = std::max(knmax, S.n);
+            kmmax = std::max(kmmax, (int)S.inst->m);
+        } else {
+            any_rows = true;
+        }
+    }
+    std::vector<Kids16> kv;
+    if (!kI.empty()) {
+        e = ctx.kids.layout(kI, kKs, kCs, kv, s);
         if (e != hipSuccess) return e;
     }
     char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
@@ -456,7 +479,8 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         q.a.surv_per_parent = (uint32_t *)(d + L.surv) + slot;
         q.a.incumbent = S.dinc;
         q.w = S.B.w;
-        if (ks.on) q.w.prow = ks.k.prow;
+        if (kid_of[r] >= 0) kids16_point(q.w, kv[kid_of[r]]);
+        q.T = S.inst->dt;
         q.nchild = S.nch;
         bind_results(q, (StepReq *)(d + L.req) + r, S.UB);
         slots[r] = slot;
@@ -470,22 +494,35 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = mstep_phase1(dq, ds1, R, maxK, s);
     if (e != hipSuccess) return e;
-    // bounding: one search alone from its parents (or one plain launch),
-    // several searches through one merged batch
+    // branching: job lists for all, child rows for the searches without the
+    // incremental path; the others decode their children from their parents
+    e = any_rows ? mstep_branch(dq, R, maxK, maxC, s) : mstep_list(dq, R, maxK, maxC, s);
+    if (e == hipSuccess && kK > 0) e = kids16_decode(dq, R, kK, kC, knmax, kmmax, s);
+    if (e != hipSuccess) return e;
+    // bounding: one plain launch for a search alone, else one merged batch
+    // (decoded workspaces go straight to its scan)
     if (R == 1) {
         Search &S = *act[0];
-        e = branch_and_bound1(dq, S.inst, ks, S.K, S.nch, S.B.w, s, false);
+        e = kid_of[0] >= 0 ? launch_scan16(S.inst, kv[0].W, S.nch, S.B.w.clb, s)
+                           : bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s, false);
     } else {
-        e = mstep_branch(dq, R, maxK, maxC, s);
         std::vector<fsp_pool_desc> descs;
+        std::vector<Workspace16> ready;
         descs.reserve(R);
-        for (Search *S : act) {
-            if (S->inst->packed16)
-                descs.push_back(fsp_pool_desc{S->inst, S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb});
-            else if (e == hipSuccess)
+        ready.reserve(R);
+        for (int r = 0; r < R; ++r) {
+            Search *S = act[r];
+            if (S->inst->packed16) {
+                const bool k = kid_of[r] >= 0;
+                descs.push_back(fsp_pool_desc{S->inst, k ? nullptr : S->B.w.crow, S->B.w.cdepth, S->nch,
+                                              S->B.w.clb});
+                ready.push_back(k ? kv[kid_of[r]].W : Workspace16{});
+            } else if (e == hipSuccess) {
                 e = bound_rows(S->inst, S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb, s);
+            }
         }
-        if (e == hipSuccess && !descs.empty()) e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s);
+        if (e == hipSuccess && !descs.empty())
+            e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s, ready.data());
     }
     if (e == hipSuccess) e = mstep_finish(dq, ds2, R, maxK, maxC, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h, d, L.total, hipMemcpyDeviceToHost, s);
@@ -733,7 +770,8 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         q.a.out_cap = nch;
         q.a.incumbent = bf.dinc;
         q.w = B.w;
-        if (ks.on) q.w.prow = ks.k.prow;
+        if (ks.on) kids16_point(q.w, ks.k);
+        q.T = inst->dt;
         q.nchild = nch;
         bind_results(q, dentry, UB);
         *(StepReq *)(h + L.req) = q;
@@ -845,6 +883,7 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     q.a.out_cap = cap;
     q.a.incumbent = incumbent;
     q.w = B.w;
+    q.T = inst->dt;
     char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
     StepReq *dentry = (StepReq *)(d + L.req);
     const StepReq *dq = dentry;
@@ -866,7 +905,7 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     e = ks.start(inst, K, nchild, s);
     if (e != hipSuccess) { cleanup(); return fail_status(e); }
     q.w = B.w;
-    if (ks.on) q.w.prow = ks.k.prow;
+    if (ks.on) kids16_point(q.w, ks.k);
     point_results(q, dentry);
     q.res = after1;
     q.nchild = nchild;
