@@ -27,6 +27,7 @@ struct StepBuffers {
     void *kblob = nullptr, *cblob = nullptr;
     int64_t Kcap = 0, Ccap = 0;
     int n = 0;
+    bool rows = true;  // child rows (crow); off for instances whose children are bounded from their parents
     hipError_t ensure_k(int64_t K, hipStream_t s);
     hipError_t ensure_c(int64_t C, int n, hipStream_t s);
     void release(hipStream_t s);

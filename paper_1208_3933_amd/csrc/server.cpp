@@ -31,7 +31,7 @@ struct Done {
 };
 
 // Device bytes a search holds right after Search::start.
-size_t initial_bytes(int n, int64_t pool_cap)
+size_t initial_bytes(int n, int64_t pool_cap, bool rows)
 {
     Search S;
     S.n = n;
@@ -40,6 +40,7 @@ size_t initial_bytes(int n, int64_t pool_cap)
     S.B.Kcap = pool_cap;
     S.B.Ccap = pool_cap;
     S.B.n = n;
+    S.B.rows = rows;
     return S.device_bytes();
 }
 
@@ -120,7 +121,7 @@ fsp_status fsp_server_submit(fsp_server srv, fsp_instance inst, int32_t ub0, int
     j->ub0 = ub0;
     j->pool_cap = pool_cap;
     j->node_budget = node_budget;
-    j->est = initial_bytes(inst->n, pool_cap);
+    j->est = initial_bytes(inst->n, pool_cap, !kids16_eligible(inst));
     if ((int64_t)j->est > srv->cfg.mem_budget_bytes) return FSP_E_NOMEM;
     j->id = srv->next_id++;
     *id_out = j->id;

@@ -53,9 +53,9 @@ hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
     cblob = nullptr;
     Ccap = std::max<int64_t>(C, 1);
     n = n_;
-    const size_t cb = al256((size_t)Ccap * 4), rows = al256((size_t)Ccap * n * 4);
+    const size_t cb = al256((size_t)Ccap * 4), rows_b = rows ? al256((size_t)Ccap * n * 4) : 0;
     const size_t sb = al256(scan_scratch_bytes(Ccap));
-    hipError_t e = stream_alloc((void **)&cblob, 6 * cb + rows + sb, s);
+    hipError_t e = stream_alloc((void **)&cblob, 6 * cb + rows_b + sb, s);
     if (e != hipSuccess) { cblob = nullptr; Ccap = 0; return e; }
     char *p = (char *)cblob;
     w.ujob = (int32_t *)p; p += cb;
@@ -64,7 +64,8 @@ hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
     w.clb = (int32_t *)p; p += cb;
     w.keep = (uint32_t *)p; p += cb;
     w.pos = (uint32_t *)p; p += cb;
-    w.crow = (int32_t *)p; p += rows;
+    w.crow = rows ? (int32_t *)p : nullptr;
+    p += rows_b;
     sums_c = (uint32_t *)p;
     return hipSuccess;
 }
@@ -79,7 +80,7 @@ void StepBuffers::release(hipStream_t s)
 
 size_t StepBuffers::bytes() const
 {
-    return (size_t)Kcap * 8 + (size_t)Ccap * (24 + 4 * (size_t)n) + scan_scratch_bytes(Kcap) +
+    return (size_t)Kcap * 8 + (size_t)Ccap * (24 + (rows ? 4 * (size_t)n : 0)) + scan_scratch_bytes(Kcap) +
            scan_scratch_bytes(Ccap);
 }
 
@@ -230,6 +231,7 @@ hipError_t Search::begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in,
     hipError_t e = stream_alloc((void **)&srows, (size_t)cap_stack * n * 4, s);
     if (e == hipSuccess) e = stream_alloc((void **)&sdep, (size_t)cap_stack * 4, s);
     if (e == hipSuccess) e = stream_alloc((void **)&dinc, (size_t)n * 4, s);
+    B.rows = !kids16_eligible(I);
     if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
     if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
     // the root: an all-zero row of depth 0 at the bottom of the stack
@@ -706,6 +708,7 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
     hipError_t e = bf.alloc(std::max<int64_t>(4096, 8 * pool_cap));
     // step buffers at their usual size up front (a parent with more children
     // than pool_cap grows them later)
+    B.rows = !kids16_eligible(inst);
     if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
     if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
     if (e == hipSuccess) e = bf.ensure_survivors(pool_cap);
@@ -865,6 +868,7 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
         ctx.release();
     };
     const TabLayout L(1, K);
+    B.rows = !kids16_eligible(inst);
     hipError_t e = B.ensure_k(K, s);
     if (e == hipSuccess) e = B.ensure_c(1, inst->n, s);
     if (e == hipSuccess) e = ctx.reserve(L.total);
