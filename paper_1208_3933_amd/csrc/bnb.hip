@@ -109,11 +109,16 @@ __global__ __launch_bounds__(256) void mstep_keep_kernel(const StepReq *__restri
     q->w.keep[c] = (q->w.cdepth[c] < q->a.n && lb >= 0 && lb < ub) ? 1u : 0u;
 }
 
-// Survivors are copied to their compacted slot (kRowLanes lanes per child).
-__global__ __launch_bounds__(256) void mstep_scatter_kernel(const StepReq *__restrict__ reqs)
+// The step's tail after the compaction, in one launch over disjoint block
+// ranges (all four parts only read the compaction and write disjoint outputs):
+//   survivor rows to their compacted slots (kRowLanes lanes per child),
+//   the fingerprint of the survivor order, survivors per parent, and the
+//   incumbent row.
+
+// Block blk of the survivor copies.
+__device__ inline void tail_scatter(ReqP q, int64_t blk)
 {
-    ReqP q = req_of(reqs);
-    const int64_t c = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x / kRowLanes);
+    const int64_t c = blk * kRowsPerBlock + (threadIdx.x / kRowLanes);
     const int sub = threadIdx.x % kRowLanes;
     if (c >= q->nchild) return;
     if (!q->w.keep[c]) return;
@@ -139,19 +144,16 @@ __global__ __launch_bounds__(256) void mstep_scatter_kernel(const StepReq *__res
     }
 }
 
-// Fingerprint of the survivor order: sum over survivors of (S - rank) * (job + 1).
-// A grid-stride loop over at most kPrintBlocks blocks, one block reduction
+// Fingerprint of the survivor order: sum over survivors of (S - rank) *
+// (job + 1); block blk of nblk strides over the children, one block reduction
 // and one atomic per block.
-constexpr int kPrintBlocks = 128;
-__global__ __launch_bounds__(256) void mstep_fingerprint_kernel(const StepReq *__restrict__ reqs)
+__device__ inline void tail_fingerprint(ReqP q, int64_t blk, int64_t nblk, unsigned long long *part)
 {
-    __shared__ unsigned long long part[256];
-    ReqP q = req_of(reqs);
     const int64_t nch = q->nchild;
-    if ((int64_t)blockIdx.x * 256 >= nch) return;  // whole block
+    if (blk * 256 >= nch) return;  // whole block
     unsigned long long v = 0;
     const unsigned long long S = *q->w.nsurv;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < nch; c += (int64_t)gridDim.x * 256)
+    for (int64_t c = blk * 256 + threadIdx.x; c < nch; c += nblk * 256)
         if (q->w.keep[c]) v += (S - q->w.pos[c]) * (unsigned long long)(q->w.ujob[c] + 1);
     part[threadIdx.x] = v;
     __syncthreads();
@@ -164,25 +166,25 @@ __global__ __launch_bounds__(256) void mstep_fingerprint_kernel(const StepReq *_
 
 // Survivors per parent: a parent's children are contiguous in child order, so
 // its survivor count is the difference of the compaction offsets at the ends
-// of its children.
-__global__ __launch_bounds__(256) void mstep_per_parent_kernel(const StepReq *__restrict__ reqs)
+// of its children.  Block blk of nblk strides over the parents.
+__device__ inline void tail_per_parent(ReqP q, int64_t blk, int64_t nblk)
 {
-    ReqP q = req_of(reqs);
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= q->a.K || !q->a.surv_per_parent) return;
-    const uint32_t cnt = q->w.cnt[p];
-    uint32_t v = 0u;
-    if (cnt) {
-        const int64_t lo = q->w.off[p], hi = lo + cnt;
-        const uint32_t end = hi < q->nchild ? q->w.pos[hi] : *q->w.nsurv;
-        v = end - q->w.pos[lo];
+    if (!q->a.surv_per_parent) return;
+    for (int64_t p = blk * 256 + threadIdx.x; p < q->a.K; p += nblk * 256) {
+        const uint32_t cnt = q->w.cnt[p];
+        uint32_t v = 0u;
+        if (cnt) {
+            const int64_t lo = q->w.off[p], hi = lo + cnt;
+            const uint32_t end = hi < q->nchild ? q->w.pos[hi] : *q->w.nsurv;
+            v = end - q->w.pos[lo];
+        }
+        q->a.surv_per_parent[p] = v;
     }
-    q->a.surv_per_parent[p] = v;
 }
 
-__global__ void mstep_incumbent_kernel(const StepReq *__restrict__ reqs)
+// The best complete child, when it lowered the upper bound, becomes the incumbent.
+__device__ inline void tail_incumbent(ReqP q)
 {
-    ReqP q = req_of(reqs);
     const unsigned long long b = *q->w.best;
     const uint32_t idx = (uint32_t)(b & 0xffffffffu);
     int32_t *inc = q->a.incumbent;
@@ -195,6 +197,22 @@ __global__ void mstep_incumbent_kernel(const StepReq *__restrict__ reqs)
     } else {
         for (int t = threadIdx.x; t < n; t += blockDim.x) inc[t] = q->w.crow[(int64_t)idx * n + t];
     }
+}
+
+constexpr int kPrintBlocks = 128, kParentBlocks = 64;
+
+// Blocks [0, bs) copy survivors, [bs, bs + bf) take the fingerprint,
+// [bs + bf, bs + bf + bp) count survivors per parent, the last one writes the
+// incumbent.  Block-uniform branches: every barrier is reached by a whole block.
+__global__ __launch_bounds__(256) void mstep_tail_kernel(const StepReq *__restrict__ reqs, int bs, int bf, int bp)
+{
+    __shared__ unsigned long long part[256];
+    ReqP q = req_of(reqs);
+    const int b = blockIdx.x;
+    if (b < bs) tail_scatter(q, b);
+    else if (b < bs + bf) tail_fingerprint(q, b - bs, bf, part);
+    else if (b < bs + bf + bp) tail_per_parent(q, b - bs - bf, bp);
+    else tail_incumbent(q);
 }
 
 static unsigned blocks_for(int64_t items, int per_block)
@@ -239,12 +257,12 @@ hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t
         if (e != hipSuccess) return e;
         e = exclusive_scan_segments(segs, R, maxC, s);
         if (e != hipSuccess) return e;
-        mstep_scatter_kernel<<<dim3(blocks_for(maxC, kRowsPerBlock), R), 256, 0, s>>>(reqs);
-        mstep_fingerprint_kernel<<<dim3((unsigned)std::min<int64_t>(blocks_for(maxC, 256), kPrintBlocks), R), 256, 0,
-                                   s>>>(reqs);
-        mstep_incumbent_kernel<<<dim3(1, R), 256, 0, s>>>(reqs);
     }
-    if (maxK > 0) mstep_per_parent_kernel<<<dim3(blocks_for(maxK, 256), R), 256, 0, s>>>(reqs);
+    // without children the tail only writes the per-parent counts (all zero)
+    const int bs = maxC > 0 ? (int)blocks_for(maxC, kRowsPerBlock) : 0;
+    const int bf = maxC > 0 ? (int)std::min<int64_t>(blocks_for(maxC, 256), kPrintBlocks) : 0;
+    const int bp = maxK > 0 ? (int)std::min<int64_t>(blocks_for(maxK, 256), kParentBlocks) : 0;
+    mstep_tail_kernel<<<dim3((unsigned)(bs + bf + bp + 1), R), 256, 0, s>>>(reqs, bs, bf, bp);
     return hipGetLastError();
 }
 

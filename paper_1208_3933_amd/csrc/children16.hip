@@ -34,20 +34,19 @@ __device__ inline void stage_p16(int n, const int32_t *p32, uint32_t *p16)
     __syncthreads();
 }
 
-// One lane per parent: completion times of the prefix and the time of the
-// unscheduled jobs per machine.  Parents with no children (invalid, or
+// Chain part, one lane per parent: completion times of the prefix and the
+// time of the unscheduled jobs per machine.  Parents with no children (invalid, or
 // complete) are skipped; the count kernel has validated the others.
+// Block blk of the chain part; p16: LDS for the staged rows.
 template <int MV>
-__global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restrict__ reqs)
+__device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
 {
     constexpr int H = MV / 2;
-    extern __shared__ uint32_t p16[];
-    ReqP q = req_of(reqs);
-    if (!q->w.prow || (int64_t)blockIdx.x * 256 >= q->a.K) return;  // whole block
+    if (!q->w.prow || blk * 256 >= q->a.K) return;  // whole block
     const int n = q->T.n;
     stage_p16<H>(n, q->T.p32, p16);
     int32_t *__restrict__ rec = q->w.krec;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = blk * 256 + threadIdx.x;
     if (p >= q->a.K || q->w.cnt[p] == 0) return;
     const int d = parent_depth(q, p);
     const int32_t *row = parent_row(q, p);
@@ -106,15 +105,14 @@ __global__ __launch_bounds__(256) void kid_chain_kernel(const StepReq *__restric
     }
 }
 
-// One wave per parent: copies the parent row, builds its unscheduled set, and
-// lane k (< m) finds the least and second least tails on machine k over the
+// Tails part, one wave per parent: copies the parent row, builds its
+// unscheduled set, and lane k (< m) finds the least and second least tails on machine k over the
 // unscheduled jobs, taken in increasing id.
-__global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restrict__ reqs)
+// Block blk of the tails part (four parents); mask: 4 x kMaskWords words of LDS.
+__device__ inline void kid_tails(ReqP q, int64_t blk, uint32_t (*mask)[kMaskWords])
 {
-    __shared__ uint32_t mask[4][kMaskWords];
-    ReqP q = req_of(reqs);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t p = blk * 4 + wv;
     if (!q->w.prow) return;        // whole block: the request bounds children from rows
     if (p >= q->a.K) return;       // whole wave
     if (q->w.cnt[p] == 0) return;  // whole wave
@@ -154,6 +152,18 @@ __global__ __launch_bounds__(256) void kid_tails_kernel(const StepReq *__restric
         r[kKidJ1 + lane] = j1;
         r[kKidQ2 + lane] = q2;
     }
+}
+
+// Both per-parent parts in one launch: blocks [0, bc) the chain part, the
+// rest the tails part (block-uniform branch).
+template <int MV>
+__global__ __launch_bounds__(256) void kid_parents_kernel(const StepReq *__restrict__ reqs, int bc)
+{
+    extern __shared__ uint32_t p16[];
+    __shared__ uint32_t mask[4][kMaskWords];
+    ReqP q = req_of(reqs);
+    if ((int)blockIdx.x < bc) kid_chain<MV>(q, blockIdx.x, p16);
+    else kid_tails(q, (int64_t)blockIdx.x - bc, mask);
 }
 
 // One lane per child (and per padding slot up to the group boundary): writes
@@ -225,8 +235,8 @@ hipError_t launch_kids(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, 
 {
     const size_t lds = (size_t)(nmax + 1) * (MV / 2) * 4;
     const int64_t Npad = (maxC + kGroup - 1) / kGroup * kGroup;
-    kid_chain_kernel<MV><<<dim3((unsigned)((maxK + 255) / 256), R), 256, lds, s>>>(dreqs);
-    kid_tails_kernel<<<dim3((unsigned)((maxK + 3) / 4), R), 256, 0, s>>>(dreqs);
+    const int bc = (int)((maxK + 255) / 256), bt = (int)((maxK + 3) / 4);
+    kid_parents_kernel<MV><<<dim3((unsigned)(bc + bt), R), 256, lds, s>>>(dreqs, bc);
     kid_decode_kernel<MV><<<dim3((unsigned)((Npad + 255) / 256), R), 256, lds, s>>>(dreqs);
     return hipGetLastError();
 }
