@@ -49,10 +49,22 @@ __device__ inline void depth_scatter_block(const int32_t *__restrict__ depths, i
     for (int b = t; b < nb; b += blockDim.x) {
         const uint32_t *c = cnt + (int64_t)b * B;
         uint32_t all = 0, before = 0;
-        for (int k = 0; k < B; ++k) {
-            const uint32_t v = c[k];
-            all += v;
-            before += k < blk ? v : 0u;
+        if ((B & 3) == 0) {  // rows of 16-byte multiples (cnt is 256-byte aligned): 16-byte loads
+            const uint4 *c4 = reinterpret_cast<const uint4 *>(c);
+#pragma unroll 4
+            for (int k4 = 0; k4 < (B >> 2); ++k4) {
+                const uint4 v = c4[k4];
+                const int k = 4 * k4;
+                all += v.x + v.y + v.z + v.w;
+                before += (k < blk ? v.x : 0u) + (k + 1 < blk ? v.y : 0u) + (k + 2 < blk ? v.z : 0u) +
+                          (k + 3 < blk ? v.w : 0u);
+            }
+        } else {
+            for (int k = 0; k < B; ++k) {
+                const uint32_t v = c[k];
+                all += v;
+                before += k < blk ? v : 0u;
+            }
         }
         tot[b] = all;
         cur[b] = before;
