@@ -56,7 +56,7 @@ typedef struct fsp_instance_s *fsp_instance;
 
 typedef struct {
     int32_t n, m;          /* jobs, machines */
-    int32_t pairs;         /* m(m-1)/2 machine pairs */
+    int32_t pairs;         /* machine pairs the bound takes: m(m-1)/2, or the subset's size */
     int32_t max_value;     /* (n+m-1) * max p: bound on every intermediate value */
     int32_t packed16;      /* 1 when max_value < 65536: the fast 16-bit path is used */
     int32_t flags;         /* FSP_INSTANCE_* flags it was created with */
@@ -72,6 +72,11 @@ typedef struct {
  * m = 2 and with at most one job left.  Applies to every call on the
  * instance: bounding, batches, steps, solves and served searches. */
 #define FSP_INSTANCE_HEADS 1
+
+/* Reported in fsp_instance_info.flags (not accepted as an input flag): the
+ * instance was created by fsp_create_instance_pairs with fewer pairs than
+ * m(m-1)/2. */
+#define FSP_INSTANCE_PAIR_SUBSET 2
 
 /* Name of a status code (static string). */
 const char *fsp_status_string(fsp_status s);
@@ -95,6 +100,25 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
 /* fsp_create_instance with flags (0 or FSP_INSTANCE_HEADS); other bits:
  * FSP_E_INVAL. */
 fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_t flags, fsp_instance *out);
+
+/*
+ * fsp_create_instance_pairs - an instance whose bound is the maximum of the
+ * pair values of Fig. 2 over a subset of the machine pairs only (the MM list
+ * of Table I replaced by `pairs`).  Each pair's value is unchanged, so the
+ * bound is never above the full one, still valid, and cheaper in proportion
+ * to the pairs dropped.  A search with it bounds more nodes.
+ *   pairs   host, npairs x 2 int32 (k, l), 0 <= k < l < m, no pair twice,
+ *           and at least one pair with l = m - 1 (then a complete schedule's
+ *           bound is its makespan, which the searches rely on); copied.  The
+ *           order does not matter.
+ *   npairs  1 .. m(m-1)/2 (all of them gives the plain instance).
+ *   flags   as for fsp_create_instance_ex.
+ * Errors as for fsp_create_instance_ex, and FSP_E_INVAL for a null list,
+ * an npairs out of range, a pair out of range, a repeated pair or no pair
+ * ending on the last machine.  Every entry point accepts the instance.
+ */
+fsp_status fsp_create_instance_pairs(const int32_t *p, int32_t n, int32_t m, const int32_t *pairs, int32_t npairs,
+                                     int32_t flags, fsp_instance *out);
 
 /* Release an instance (synchronises the device first).  NULL is a no-op. */
 fsp_status fsp_destroy_instance(fsp_instance inst);

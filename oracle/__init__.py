@@ -84,6 +84,14 @@ def lib():
         L.orc_bnb.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _i32p,
                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                               ctypes.POINTER(BnbResult), _i32p, _i64p, ctypes.c_int64, ctypes.c_int]
+        L.orc_bound_pool_pairs.restype = ctypes.c_int64
+        L.orc_bound_pool_pairs.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, _i32p, _i32p,
+                                           ctypes.c_int64, _i32p, ctypes.c_int, _i32p, ctypes.c_int]
+        L.orc_bnb_pairs.restype = ctypes.c_int
+        L.orc_bnb_pairs.argtypes = [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _i32p,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                    ctypes.POINTER(BnbResult), _i32p, _i64p, ctypes.c_int64, ctypes.c_int,
+                                    ctypes.c_int, _i32p, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -157,13 +165,28 @@ def pair_scan(p, prefix, k: int, l: int):
     return int(t2.value), int(q.value)
 
 
-def bound_pool(p, prefixes, depths, heads: bool = False) -> np.ndarray:
+def _pairs(pairs):
+    """The pair subset as a contiguous (P, 2) int32 array, or None for every pair."""
+    if pairs is None:
+        return None
+    a = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    assert a.shape[0] >= 1
+    return a
+
+
+def bound_pool(p, prefixes, depths, heads: bool = False, pairs=None) -> np.ndarray:
+    """Bounds of a pool (heads: the heads variant; pairs: the maximum over
+    these machine pairs (k, l) only, else over every pair)."""
     p, n, m = _mat(p)
     pre = np.ascontiguousarray(prefixes, dtype=np.int32).reshape(-1, n)
     dep = np.ascontiguousarray(depths, dtype=np.int32).reshape(-1)
     assert pre.shape[0] == dep.shape[0]
     out = np.empty(dep.shape[0], np.int32)
-    if heads:
+    pr = _pairs(pairs)
+    if pr is not None:
+        lib().orc_bound_pool_pairs(_p(p), n, m, _p(pre), _p(dep), dep.shape[0], _p(out), int(heads), _p(pr),
+                                   pr.shape[0])
+    elif heads:
         lib().orc_bound_pool_mode(_p(p), n, m, _p(pre), _p(dep), dep.shape[0], _p(out), 1)
     else:
         lib().orc_bound_pool(_p(p), n, m, _p(pre), _p(dep), dep.shape[0], _p(out))
@@ -186,19 +209,24 @@ def neh(p):
 
 
 def bnb(p, ub0: int, incumbent0=None, pool_cap: int = 1 << 18, node_budget: int = 1 << 62,
-        strict_gt: bool = False, steplog_cap: int = 0, heads: bool = False, best_first: bool = False):
+        strict_gt: bool = False, steplog_cap: int = 0, heads: bool = False, best_first: bool = False,
+        pairs=None):
     """Pool-synchronous branch-and-bound, depth-first or best-first (heads:
-    the heads variant of the bound).  Returns a dict; for best-first,
-    max_stack is the largest frontier."""
+    the heads variant of the bound; pairs: the bound over these machine
+    pairs only).  Returns a dict; for best-first, max_stack is the largest
+    frontier."""
     p, n, m = _mat(p)
     res = BnbResult()
     inc = np.empty(n, np.int32)
     inc0 = None if incumbent0 is None else _seq(incumbent0)
     log = np.zeros((max(steplog_cap, 1), 6), np.int64)
-    fn = lib().orc_bnb_best_first if best_first else lib().orc_bnb
-    rc = fn(_p(p), n, m, int(ub0), None if inc0 is None else _p(inc0),
-                       int(pool_cap), int(node_budget), int(strict_gt), ctypes.byref(res),
-                       _p(inc), log.ctypes.data_as(_i64p), int(steplog_cap), int(heads))
+    pr = _pairs(pairs)
+    args = (_p(p), n, m, int(ub0), None if inc0 is None else _p(inc0), int(pool_cap), int(node_budget),
+            int(strict_gt), ctypes.byref(res), _p(inc), log.ctypes.data_as(_i64p), int(steplog_cap), int(heads))
+    if pr is not None:
+        rc = lib().orc_bnb_pairs(*args, int(best_first), _p(pr), pr.shape[0])
+    else:
+        rc = (lib().orc_bnb_best_first if best_first else lib().orc_bnb)(*args)
     if rc != 0:
         raise ValueError("bad arguments")
     return {"ub": int(res.ub), "proven": bool(res.proven), "nodes_bounded": int(res.nodes_bounded),

@@ -32,6 +32,11 @@
  *     and then takes a maximum, which can only be a typo.
  *   - Elimination prunes a node whose bound is >= the upper bound; the
  *     paper's strict ">" is available for the brute-force pins (strict_gt).
+ *   - The pair-subset variant takes the maximum of Fig. 2 over a given
+ *     subset of the machine pairs (the MM list restricted) instead of all
+ *     of them; each pair's value is unchanged, so the bound can only drop.
+ *     The searches need a pair ending on the last machine, so that a
+ *     complete schedule's bound is its makespan.
  *
  * Parity pins live in tests/test_oracle_pins.py (brute force, closed forms,
  * invariants).  Nothing here is "parity unpinned".
@@ -135,6 +140,11 @@ static keyed_job johnson_fields(int32_t j, int64_t a, int64_t b, int64_t L, int6
     return kj;
 }
 
+/* Which bound: heads = the heads variant of RM; pairsel = NULL for every
+ * machine pair, else an m x m matrix with pairsel[k*m + l] = 1 for the pairs
+ * (k,l), k<l, the maximum is taken over. */
+typedef struct { int heads; const unsigned char *pairsel; } orc_variant;
+
 /* The lower bound of Sec. II-D / Fig. 2 for the node (prefix[0..d-1]).
  *
  * For every machine pair (k,l), k<l (the MM list, lexicographic):
@@ -148,8 +158,10 @@ static keyed_job johnson_fields(int32_t j, int64_t a, int64_t b, int64_t L, int6
  * Returns ORC_INVALID for an invalid node. */
 static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix, int d,
                           const int32_t *tiekey, int eq_in_s2, orc_counts *cnt,
-                          int only_k, int only_l, int64_t *pair_t2, int64_t *pair_q, int heads)
+                          int only_k, int only_l, int64_t *pair_t2, int64_t *pair_q, const orc_variant *v)
 {
+    const int heads = v ? v->heads : 0;
+    const unsigned char *pairsel = v ? v->pairsel : NULL;
     unsigned char *scheduled = (unsigned char *)malloc((size_t)n + 1);
     if (!decode_node(n, prefix, d, scheduled)) { free(scheduled); return ORC_INVALID; }
 
@@ -196,6 +208,7 @@ static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix,
     for (int k = 0; k < m; ++k) {
         for (int l = k + 1; l < m; ++l) {
             if (only_k >= 0 && (k != only_k || l != only_l)) continue;
+            if (pairsel && !pairsel[k * m + l]) continue;
             if (cnt) cnt->mm += 2;
             /* Johnson-with-lags order of the unscheduled jobs for (k,l). */
             int cnt_u = 0;
@@ -232,13 +245,14 @@ static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix,
 
 int32_t orc_bound(const int32_t *p, int n, int m, const int32_t *prefix, int d)
 {
-    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL, 0);
+    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL, NULL);
 }
 
 /* The bound with the heads variant of RM (see the header). */
 int32_t orc_bound_heads(const int32_t *p, int n, int m, const int32_t *prefix, int d)
 {
-    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL, 1);
+    const orc_variant v = {1, NULL};
+    return bound_impl(p, n, m, prefix, d, NULL, 0, NULL, -1, -1, NULL, NULL, &v);
 }
 
 /* Same bound with a custom tie-break key per job and a choice of group for
@@ -246,7 +260,7 @@ int32_t orc_bound_heads(const int32_t *p, int n, int m, const int32_t *prefix, i
 int32_t orc_bound_tie(const int32_t *p, int n, int m, const int32_t *prefix, int d,
                       const int32_t *tiekey, int eq_in_s2)
 {
-    return bound_impl(p, n, m, prefix, d, tiekey, eq_in_s2, NULL, -1, -1, NULL, NULL, 0);
+    return bound_impl(p, n, m, prefix, d, tiekey, eq_in_s2, NULL, -1, -1, NULL, NULL, NULL);
 }
 
 /* Same bound, counting accesses to the Table I structures. */
@@ -254,7 +268,7 @@ int32_t orc_bound_counted(const int32_t *p, int n, int m, const int32_t *prefix,
                           orc_counts *cnt)
 {
     memset(cnt, 0, sizeof(*cnt));
-    return bound_impl(p, n, m, prefix, d, NULL, 0, cnt, -1, -1, NULL, NULL, 0);
+    return bound_impl(p, n, m, prefix, d, NULL, 0, cnt, -1, -1, NULL, NULL, NULL);
 }
 
 /* One pair only: *t2 = timeOnM2 after the scan (before the tail), *q = tail
@@ -263,22 +277,52 @@ int32_t orc_pair_scan(const int32_t *p, int n, int m, const int32_t *prefix, int
                       int k, int l, int64_t *t2, int64_t *q)
 {
     if (k < 0 || l <= k || l >= m) return ORC_INVALID;
-    int32_t v = bound_impl(p, n, m, prefix, d, NULL, 0, NULL, k, l, t2, q, 0);
+    int32_t v = bound_impl(p, n, m, prefix, d, NULL, 0, NULL, k, l, t2, q, NULL);
     return v == ORC_INVALID ? ORC_INVALID : 0;
 }
 
 /* Bounds of a pool: prefixes is count x n (row i holds depths[i] scheduled
  * jobs first), out[i] = bound or ORC_INVALID.  Returns the number of invalid
  * rows. */
-int64_t orc_bound_pool_mode(const int32_t *p, int n, int m, const int32_t *prefixes,
-                            const int32_t *depths, int64_t count, int32_t *out, int heads)
+static int64_t bound_pool_v(const int32_t *p, int n, int m, const int32_t *prefixes, const int32_t *depths,
+                            int64_t count, int32_t *out, const orc_variant *v)
 {
     int64_t bad = 0;
     for (int64_t i = 0; i < count; ++i) {
-        out[i] = bound_impl(p, n, m, prefixes + i * (int64_t)n, depths[i], NULL, 0, NULL, -1, -1, NULL, NULL,
-                            heads);
+        out[i] = bound_impl(p, n, m, prefixes + i * (int64_t)n, depths[i], NULL, 0, NULL, -1, -1, NULL, NULL, v);
         if (out[i] == ORC_INVALID) ++bad;
     }
+    return bad;
+}
+
+int64_t orc_bound_pool_mode(const int32_t *p, int n, int m, const int32_t *prefixes,
+                            const int32_t *depths, int64_t count, int32_t *out, int heads)
+{
+    const orc_variant v = {heads, NULL};
+    return bound_pool_v(p, n, m, prefixes, depths, count, out, &v);
+}
+
+/* The pair-subset matrix of npairs pairs (pairs[2i], pairs[2i+1]) = (k, l);
+ * NULL (every pair) when npairs <= 0.  The caller frees it. */
+static unsigned char *pair_matrix(int m, const int32_t *pairs, int npairs)
+{
+    if (!pairs || npairs <= 0) return NULL;
+    unsigned char *sel = (unsigned char *)calloc((size_t)m * (size_t)m, 1);
+    for (int i = 0; i < npairs; ++i) {
+        int k = pairs[2 * i], l = pairs[2 * i + 1];
+        if (k >= 0 && k < l && l < m) sel[k * m + l] = 1;
+    }
+    return sel;
+}
+
+/* Bounds of a pool with the maximum over the given machine pairs only. */
+int64_t orc_bound_pool_pairs(const int32_t *p, int n, int m, const int32_t *prefixes, const int32_t *depths,
+                             int64_t count, int32_t *out, int heads, const int32_t *pairs, int npairs)
+{
+    unsigned char *sel = pair_matrix(m, pairs, npairs);
+    const orc_variant v = {heads, sel};
+    int64_t bad = bound_pool_v(p, n, m, prefixes, depths, count, out, &v);
+    free(sel);
     return bad;
 }
 
@@ -417,10 +461,10 @@ typedef struct {
  *   [3] children pushed, [4] stack size after the step,
  *   [5] sum over pushed children of (position in push order + 1) * (job
  *       appended + 1), a cheap order-sensitive fingerprint of the frontier. */
-int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
-            int64_t pool_cap, int64_t node_budget, int strict_gt,
-            orc_bnb_result *res, int32_t *incumbent_out,
-            int64_t *steplog, int64_t steplog_cap, int heads)
+static int bnb_dfs(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+                   int64_t pool_cap, int64_t node_budget, int strict_gt,
+                   orc_bnb_result *res, int32_t *incumbent_out,
+                   int64_t *steplog, int64_t steplog_cap, const orc_variant *v)
 {
     memset(res, 0, sizeof(*res));
     if (n < 1 || m < 2 || pool_cap < 1) return -1;
@@ -435,7 +479,7 @@ int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
 #define NODE(i) (stack + (int64_t)(i) * (n + 1))
 
     int64_t nodes = 1;
-    int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, heads);
+    int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, v);
     int pruned_root = strict_gt ? (root_lb > UB) : (root_lb >= UB);
     if (!pruned_root) {
         NODE(0)[0] = 0;
@@ -482,7 +526,7 @@ int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
         /* 4. bounding */
         for (int64_t i = 0; i < nchild; ++i) {
             int32_t *ch = children + i * (n + 1);
-            lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, heads);
+            lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, v);
         }
         nodes += nchild;
         /* 5. complete children update the upper bound */
@@ -568,10 +612,10 @@ static int cmp_bf(const void *x, const void *y)
     return a->seq < b->seq ? -1 : (a->seq > b->seq ? 1 : 0);
 }
 
-int orc_bnb_best_first(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
-                       int64_t pool_cap, int64_t node_budget, int strict_gt,
-                       orc_bnb_result *res, int32_t *incumbent_out,
-                       int64_t *steplog, int64_t steplog_cap, int heads)
+static int bnb_best(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+                    int64_t pool_cap, int64_t node_budget, int strict_gt,
+                    orc_bnb_result *res, int32_t *incumbent_out,
+                    int64_t *steplog, int64_t steplog_cap, const orc_variant *v)
 {
     memset(res, 0, sizeof(*res));
     if (n < 1 || m < 2 || pool_cap < 1) return -1;
@@ -583,7 +627,7 @@ int orc_bnb_best_first(const int32_t *p, int n, int m, int32_t ub0, const int32_
     int64_t M = 0, capF = 16, seq = 0;
     bf_node *F = (bf_node *)malloc(sizeof(bf_node) * (size_t)capF);
     int64_t nodes = 1;
-    int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, heads);
+    int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, v);
     if (!(strict_gt ? (root_lb > UB) : (root_lb >= UB))) {
         F[0].lb = root_lb;
         F[0].seq = seq++;
@@ -642,7 +686,7 @@ int orc_bnb_best_first(const int32_t *p, int n, int m, int32_t ub0, const int32_
         /* 4. bounding */
         for (int64_t i = 0; i < nchild; ++i) {
             int32_t *ch = children + i * (n + 1);
-            lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, heads);
+            lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, v);
         }
         nodes += nchild;
         /* 5. complete children update the upper bound */
@@ -699,4 +743,49 @@ int orc_bnb_best_first(const int32_t *p, int n, int m, int32_t ub0, const int32_
     for (int64_t i = 0; i < M; ++i) free(F[i].node);
     free(F); free(sched); free(children); free(lbs); free(inc);
     return 0;
+}
+
+/* The searches with the plain bound (heads = 0) or the heads variant, over
+ * every machine pair. */
+int orc_bnb(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+            int64_t pool_cap, int64_t node_budget, int strict_gt,
+            orc_bnb_result *res, int32_t *incumbent_out,
+            int64_t *steplog, int64_t steplog_cap, int heads)
+{
+    const orc_variant v = {heads, NULL};
+    return bnb_dfs(p, n, m, ub0, inc0, pool_cap, node_budget, strict_gt, res, incumbent_out, steplog,
+                   steplog_cap, &v);
+}
+
+int orc_bnb_best_first(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+                       int64_t pool_cap, int64_t node_budget, int strict_gt,
+                       orc_bnb_result *res, int32_t *incumbent_out,
+                       int64_t *steplog, int64_t steplog_cap, int heads)
+{
+    const orc_variant v = {heads, NULL};
+    return bnb_best(p, n, m, ub0, inc0, pool_cap, node_budget, strict_gt, res, incumbent_out, steplog,
+                    steplog_cap, &v);
+}
+
+/* Either search (best_first = 0: depth first) with the bound over the given
+ * machine pairs only (npairs <= 0: every pair). */
+int orc_bnb_pairs(const int32_t *p, int n, int m, int32_t ub0, const int32_t *inc0,
+                  int64_t pool_cap, int64_t node_budget, int strict_gt,
+                  orc_bnb_result *res, int32_t *incumbent_out,
+                  int64_t *steplog, int64_t steplog_cap, int heads, int best_first,
+                  const int32_t *pairs, int npairs)
+{
+    /* a complete schedule's bound must be its makespan: some pair ends on
+     * the last machine */
+    int last = 0;
+    for (int i = 0; pairs && i < npairs; ++i) last |= pairs[2 * i + 1] == m - 1;
+    if (npairs > 0 && !last) return -1;
+    unsigned char *sel = pair_matrix(m, pairs, npairs);
+    const orc_variant v = {heads, sel};
+    int r = best_first ? bnb_best(p, n, m, ub0, inc0, pool_cap, node_budget, strict_gt, res, incumbent_out,
+                                  steplog, steplog_cap, &v)
+                       : bnb_dfs(p, n, m, ub0, inc0, pool_cap, node_budget, strict_gt, res, incumbent_out,
+                                 steplog, steplog_cap, &v);
+    free(sel);
+    return r;
 }

@@ -27,6 +27,16 @@ std::map<std::pair<int, int>, ScanTuning> g_tune;
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
+namespace {
+// Rule of thumb: about four machine pairs per wave and chain.
+ScanTuning rule_tuning(int P)
+{
+    int w = 1;
+    while (w < kBatchWaves && 4 * 2 * w <= P) w *= 2;
+    return ScanTuning{w, 8, kBatchGrid};
+}
+}  // namespace
+
 ScanTuning scan_tuning(int n, int m)
 {
     {
@@ -34,11 +44,14 @@ ScanTuning scan_tuning(int n, int m)
         auto it = g_tune.find({n, m});
         if (it != g_tune.end()) return it->second;
     }
-    // rule of thumb: about four machine pairs per wave and chain
-    const int P = m * (m - 1) / 2;
-    int w = 1;
-    while (w < kBatchWaves && 4 * 2 * w <= P) w *= 2;
-    return ScanTuning{w, 8, kBatchGrid};
+    return rule_tuning(m * (m - 1) / 2);
+}
+
+ScanTuning scan_tuning_for(const fsp_instance_s *I)
+{
+    // the table is keyed by shape with every pair; a pair subset scans fewer pairs
+    if (I->P != I->m * (I->m - 1) / 2) return rule_tuning(I->P);
+    return scan_tuning(I->n, I->m);
 }
 
 void set_scan_tuning(int n, int m, ScanTuning t)
@@ -108,7 +121,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         P.out_lb = d.out_lb;
         P.N = d.N;
         P.Npad = Npad;
-        P.wpg = wpg_force ? wpg_force : scan_tuning(n, m).waves_per_group;
+        P.wpg = wpg_force ? wpg_force : scan_tuning_for(I).waves_per_group;
         const int gpp = kBatchWaves / P.wpg;
         const int64_t per_wave = (I->P + P.wpg - 1) / P.wpg;
         for (int64_t g0 = 0; g0 < G; g0 += gpp) {
@@ -120,7 +133,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
     }
     bool all_persistent = true;
     for (int i = 0; i < n_pools; ++i)
-        if (pools[i].N > 0 && scan_tuning(pools[i].inst->n, pools[i].inst->m).form != kBatchPersistent)
+        if (pools[i].N > 0 && scan_tuning_for(pools[i].inst).form != kBatchPersistent)
             all_persistent = false;
     pl.form = form_force >= 0 ? form_force : (all_persistent ? kBatchPersistent : kBatchGrid);
     std::stable_sort(items.begin(), items.end(), [](const Cost &x, const Cost &y) { return x.cost > y.cost; });

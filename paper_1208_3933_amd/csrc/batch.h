@@ -61,6 +61,9 @@ struct ScanTuning {
     int form;  // batched-scan launch form preferred for the shape
 };
 ScanTuning scan_tuning(int n, int m);
+// The schedule of an instance: its shape's entry, or for an instance over a
+// subset of the machine pairs the rule of thumb for its pair count.
+ScanTuning scan_tuning_for(const fsp_instance_s *I);
 void set_scan_tuning(int n, int m, ScanTuning t);
 bool has_scan_tuning(int n, int m);
 void scan_tuning_entries(std::vector<std::pair<std::pair<int, int>, ScanTuning>> &out);

@@ -74,12 +74,13 @@ fsp_status fsp_create_instance(const int32_t *p, int32_t n, int32_t m, fsp_insta
     return fsp_create_instance_ex(p, n, m, 0, out);
 }
 
-fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_t flags, fsp_instance *out)
+namespace {
+
+// Builds an instance whose bound takes the maximum over `prs` (pairs (k,l),
+// k < l, lexicographic, no repeats; checked by the callers).
+fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags,
+                           const std::vector<std::pair<int, int>> &prs, fsp_instance *out)
 {
-    if (!out) return FSP_E_INVAL;
-    *out = nullptr;
-    if (!p || n < 1 || m < 2 || n > kMaxJobs || m > kMaxMachines) return FSP_E_INVAL;
-    if (flags & ~FSP_INSTANCE_HEADS) return FSP_E_INVAL;
     int64_t pmax = 0;
     for (int64_t i = 0; i < (int64_t)n * m; ++i) {
         if (p[i] < 0) return FSP_E_INVAL;
@@ -98,7 +99,7 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     if (e != hipSuccess) { set_last_error(e); return FSP_E_DEVICE; }
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FSP_E_NODEVICE;
 
-    const int P = m * (m - 1) / 2;
+    const int P = (int)prs.size();
     const int npad = (n + 3) & ~3;
 
     // host tables
@@ -120,9 +121,9 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
                                                ((uint32_t)tails[(size_t)j * S + 2 * c + 1] << 16);
     std::vector<int> order;
     std::vector<int32_t> lagv;
-    int pr = 0;
-    for (int k = 0; k < m; ++k) {
-        for (int l = k + 1; l < m; ++l, ++pr) {
+    for (int pr = 0; pr < P; ++pr) {
+        {
+            const int k = prs[pr].first, l = prs[pr].second;
             pairs[2 * pr] = k;
             pairs[2 * pr + 1] = l;
             johnson_with_lags(p, n, m, k, l, order, lagv);
@@ -180,7 +181,7 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     I->p_host = new int32_t[(size_t)n * m];
     std::memcpy(I->p_host, p, sizeof(int32_t) * (size_t)n * m);
     unsigned char *b = (unsigned char *)d;
-    I->flags = flags;
+    I->flags = flags | (P < m * (m - 1) / 2 ? FSP_INSTANCE_PAIR_SUBSET : 0);
     I->dt.n = n; I->dt.m = m; I->dt.P = P; I->dt.npad = npad;
     I->dt.heads = (flags & FSP_INSTANCE_HEADS) ? 1 : 0;
     I->dt.p32 = (const int32_t *)(b + off_p);
@@ -194,6 +195,47 @@ fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_
     I->dt.bad = (unsigned long long *)(b + off_bad);
     *out = I;
     return FSP_OK;
+}
+
+fsp_status check_shape(const int32_t *p, int32_t n, int32_t m, int32_t flags, fsp_instance *out)
+{
+    if (!out) return FSP_E_INVAL;
+    *out = nullptr;
+    if (!p || n < 1 || m < 2 || n > kMaxJobs || m > kMaxMachines) return FSP_E_INVAL;
+    if (flags & ~FSP_INSTANCE_HEADS) return FSP_E_INVAL;
+    return FSP_OK;
+}
+
+}  // namespace
+
+fsp_status fsp_create_instance_ex(const int32_t *p, int32_t n, int32_t m, int32_t flags, fsp_instance *out)
+{
+    fsp_status st = check_shape(p, n, m, flags, out);
+    if (st != FSP_OK) return st;
+    std::vector<std::pair<int, int>> prs;
+    for (int k = 0; k < m; ++k)
+        for (int l = k + 1; l < m; ++l) prs.push_back({k, l});
+    return create_instance(p, n, m, flags, prs, out);
+}
+
+fsp_status fsp_create_instance_pairs(const int32_t *p, int32_t n, int32_t m, const int32_t *pairs, int32_t npairs,
+                                     int32_t flags, fsp_instance *out)
+{
+    fsp_status st = check_shape(p, n, m, flags, out);
+    if (st != FSP_OK) return st;
+    if (!pairs || npairs < 1 || npairs > m * (m - 1) / 2) return FSP_E_INVAL;
+    std::vector<std::pair<int, int>> prs;
+    bool last = false;  // a pair ending on the last machine: a complete schedule's bound is its makespan
+    for (int i = 0; i < npairs; ++i) {
+        const int k = pairs[2 * i], l = pairs[2 * i + 1];
+        if (k < 0 || l <= k || l >= m) return FSP_E_INVAL;
+        last = last || l == m - 1;
+        prs.push_back({k, l});
+    }
+    if (!last) return FSP_E_INVAL;
+    std::sort(prs.begin(), prs.end());
+    if (std::adjacent_find(prs.begin(), prs.end()) != prs.end()) return FSP_E_INVAL;  // a repeated pair
+    return create_instance(p, n, m, flags, prs, out);
 }
 
 fsp_status fsp_destroy_instance(fsp_instance inst)

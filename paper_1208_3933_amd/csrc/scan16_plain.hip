@@ -85,13 +85,13 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
     }
 }
 
-static int scan_waves(int n, int m)
+static int scan_waves(const fsp_instance_s *I)
 {
     if (const char *e = getenv("FSPBB_SCAN_WAVES")) {
         const int w = atoi(e);
         if (w == 1 || w == 2 || w == 4 || w == 8 || w == 16) return w;
     }
-    return scan_tuning(n, m).waves_per_group;
+    return scan_tuning_for(I).waves_per_group;
 }
 
 static int scan_unroll()
@@ -147,8 +147,8 @@ static void launch_scan(int unr, dim3 grid, size_t lds_b, hipStream_t s, const D
 hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s)
 {
     if (N <= 0) return hipSuccess;
-    const int n = I->n, m = I->m;
-    const int waves = scan_waves(n, m);
+    const int n = I->n;
+    const int waves = scan_waves(I);
     const size_t lds_b = (size_t)((n + 1) > waves ? (n + 1) : waves) * 256;
     const dim3 grid((unsigned)((N + kGroup - 1) / kGroup));
     const int unr = scan_unroll();

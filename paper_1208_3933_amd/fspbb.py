@@ -29,6 +29,7 @@ PENDING = 2
 LB_INVALID = -1
 
 INSTANCE_HEADS = 1
+INSTANCE_PAIR_SUBSET = 2
 
 UB_NEH = -1
 UB_NONE = 0x7FFFFFFF
@@ -107,6 +108,8 @@ _SIGNATURES = {
     "fsp_create_instance": (ctypes.c_int32, [_i32p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "fsp_create_instance_ex": (ctypes.c_int32, [_i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(_vp)]),
+    "fsp_create_instance_pairs": (ctypes.c_int32, [_i32p, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                                   ctypes.c_int32, ctypes.POINTER(_vp)]),
     "fsp_destroy_instance": (ctypes.c_int32, [_vp]),
     "fsp_get_instance_info": (ctypes.c_int32, [_vp, ctypes.POINTER(InstanceInfo)]),
     "fsp_bound_pool": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
@@ -200,13 +203,17 @@ def _dev_i32(t, name, shape=None):
 class Instance:
     """An instance created by fsp_create_instance (owns the device tables)."""
 
-    def __init__(self, p, heads: bool = False):
+    def __init__(self, p, heads: bool = False, pairs=None):
         p = np.ascontiguousarray(p, dtype=np.int32)
         if p.ndim != 2:
             raise ValueError("p must be an n x m matrix")
         self.n, self.m = int(p.shape[0]), int(p.shape[1])
         h = _vp()
-        if heads:
+        if pairs is not None:
+            pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+            st = lib().fsp_create_instance_pairs(p.ctypes.data_as(_i32p), self.n, self.m, pr.ctypes.data_as(_i32p),
+                                                 int(pr.shape[0]), INSTANCE_HEADS if heads else 0, ctypes.byref(h))
+        elif heads:
             st = lib().fsp_create_instance_ex(p.ctypes.data_as(_i32p), self.n, self.m, INSTANCE_HEADS,
                                               ctypes.byref(h))
         else:
@@ -241,9 +248,11 @@ class Instance:
         self.close()
 
 
-def create_instance(p, heads: bool = False) -> Instance:
-    """heads: releases as the earliest starts of unscheduled jobs (FSP_INSTANCE_HEADS)."""
-    return Instance(p, heads)
+def create_instance(p, heads: bool = False, pairs=None) -> Instance:
+    """heads: releases as the earliest starts of unscheduled jobs (FSP_INSTANCE_HEADS);
+    pairs: (P, 2) machine pairs (k, l), k < l, the bound takes its maximum over
+    (fsp_create_instance_pairs), else every pair."""
+    return Instance(p, heads, pairs)
 
 
 def destroy_instance(inst: Instance) -> None:

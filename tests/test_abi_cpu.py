@@ -96,3 +96,16 @@ def test_rule_of_thumb_schedules():
     assert fspbb.tune_get(50, 10)[0] == 8     # 45 pairs
     assert fspbb.tune_get(20, 5)[0] == 2      # 10 pairs
     assert fspbb.tune_get(9, 2)[0] == 1       # 1 pair
+
+
+def test_create_instance_pairs_rejects_bad_pair_lists():
+    L = fspbb.lib()
+    p = np.ones((6, 4), np.int32)
+    pp = p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    for pairs in [[], [(0, 0)], [(2, 1)], [(0, 4)], [(-1, 2)], [(0, 3), (0, 3)], [(0, 3)] * 7, [(0, 1), (1, 2)]]:
+        a = np.asarray(pairs, np.int32).reshape(-1, 2)
+        h = ctypes.c_void_p()
+        st = L.fsp_create_instance_pairs(pp, 6, 4, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(pairs), 0,
+                                         ctypes.byref(h))
+        assert st == fspbb.E_INVAL and not h.value, pairs
+    assert L.fsp_create_instance_pairs(pp, 6, 4, None, 1, 0, ctypes.byref(ctypes.c_void_p())) == fspbb.E_INVAL

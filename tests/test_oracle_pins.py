@@ -523,3 +523,71 @@ def test_best_first_budget():
     p = inst(12, 5, 331)
     r = oracle.bnb(p, 1 << 30, None, pool_cap=8, node_budget=200, best_first=True)
     assert not r["proven"] and r["nodes_bounded"] >= 200
+
+
+# --- bound over a subset of the machine pairs ---------------------------------------
+
+def pair_subsets(m, seed):
+    """Adjacent pairs, pairs ending on the last machine, and a seeded random
+    subset; each holds a pair ending on the last machine."""
+    every = [(k, l) for k in range(m) for l in range(k + 1, m)]
+    rng = np.random.default_rng(seed)
+    pick = [pr for pr in every if rng.random() < 0.3 and pr[1] < m - 1] + [(int(rng.integers(0, m - 1)), m - 1)]
+    return [[(k, k + 1) for k in range(m - 1)], [(k, m - 1) for k in range(m - 1)], pick]
+
+
+@pytest.mark.parametrize("n,m,seed", [(9, 5, 301), (12, 6, 302), (30, 8, 303)])
+def test_pair_subset_is_max_over_its_pairs(n, m, seed):
+    """The subset bound is the largest pair value of the subset, each value
+    being the one the two-machine pins tie to the exact relaxation."""
+    p = inst(n, m, seed)
+    prefixes, depths = gen.random_pool(n, 12, gen.make_seed(95, seed, 1))
+    for S in pair_subsets(m, seed):
+        got = oracle.bound_pool(p, prefixes, depths, pairs=S)
+        for i, (row, d) in enumerate(zip(prefixes, depths)):
+            pre = tuple(int(x) for x in row[:d])
+            want = max(sum(oracle.pair_scan(p, pre, k, l)) for k, l in S)
+            assert got[i] == max(want, 0), (S, pre)
+
+
+@pytest.mark.parametrize("n,m,seed", [(8, 4, 311), (20, 5, 312), (40, 10, 313)])
+def test_pair_subset_below_full_and_equal_with_every_pair(n, m, seed):
+    p = inst(n, m, seed)
+    prefixes, depths = gen.random_pool(n, 40, gen.make_seed(96, seed, 1))
+    full = oracle.bound_pool(p, prefixes, depths)
+    every = [(k, l) for k in range(m) for l in range(k + 1, m)]
+    assert (oracle.bound_pool(p, prefixes, depths, pairs=every[::-1]) == full).all()
+    for S in pair_subsets(m, seed):
+        assert (oracle.bound_pool(p, prefixes, depths, pairs=S) <= full).all()
+
+
+def test_pair_subset_leaf_bound_is_makespan():
+    """With a pair ending on the last machine, a complete schedule's bound is
+    its makespan; without one it is the completion on an earlier machine,
+    which is why the searches refuse such subsets."""
+    p = inst(7, 4, 321)
+    perm = np.arange(7, dtype=np.int32)
+    ms = oracle.makespan(p, perm)
+    assert oracle.bound_pool(p, perm[None, :], [7], pairs=[(0, 3)])[0] == ms
+    assert oracle.bound_pool(p, perm[None, :], [7], pairs=[(0, 1)])[0] == oracle.makespan(p[:, :2], perm) < ms
+    with pytest.raises(ValueError):
+        oracle.bnb(p, 1 << 30, None, pool_cap=8, pairs=[(0, 1)])
+
+
+@pytest.mark.parametrize("n,m,seed", [(7, 4, 321), (8, 3, 322)])
+def test_pair_subset_search_finds_the_optimum(n, m, seed):
+    """A weaker bound is still valid: the search proves the brute-force
+    optimum.  Started from the optimum it expands a superset of the nodes
+    the full bound expands (no upper-bound change can reorder the pruning),
+    so it bounds at least as many."""
+    p = inst(n, m, seed)
+    opt = oracle.brute(p)
+    full_r = oracle.bnb(p, 1 << 30, None, pool_cap=8)
+    full_opt = oracle.bnb(p, opt, full_r["incumbent"], pool_cap=8)
+    for S in pair_subsets(m, seed):
+        r = oracle.bnb(p, 1 << 30, None, pool_cap=8, pairs=S)
+        assert r["ub"] == opt and r["proven"]
+        assert sorted(int(x) for x in r["incumbent"]) == list(range(n))
+        assert oracle.makespan(p, r["incumbent"]) == opt
+        r_opt = oracle.bnb(p, opt, full_r["incumbent"], pool_cap=8, pairs=S)
+        assert r_opt["proven"] and r_opt["nodes_bounded"] >= full_opt["nodes_bounded"]
