@@ -170,21 +170,31 @@ def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
     return out
 
 
+def adjacent_pairs(m: int) -> list:
+    """Machine pairs (k, k+1) and (0, m-1): m pairs (m - 1 when m = 2) of the
+    m(m-1)/2, including one that ends on the last machine."""
+    return sorted({(k, k + 1) for k in range(m - 1)} | {(0, m - 1)})
+
+
 def variants_leg(p, pre_d, dep_d, steps: int, stream, solve_seeds: int = 6) -> dict:
-    """The next rows of the path: the heads bound variant (releases as the
-    earliest starts of unscheduled jobs) and best-first selection.  Bound
-    throughput with heads on the same 200x20 pool, and solves from NEH of
-    seeded small instances with each strategy (same pool_cap and budget)."""
+    """The next rows of the path: the bound variants (heads: releases as the
+    earliest starts of unscheduled jobs; a subset of the machine pairs: the
+    adjacent ones and (0, m-1)) and best-first selection.  Bound throughput
+    of each variant on the same 200x20 pool, and solves from NEH of seeded
+    small instances with each strategy (same pool_cap and budget)."""
     import torch
 
     from paper_1208_3933_amd import fspbb, serve
     out = {}
-    with fspbb.create_instance(p, heads=True) as inst:
-        o = dep_d.new_empty(dep_d.shape)
-        for _ in range(2):
-            fspbb.bound_pool(inst, pre_d, dep_d, o, stream)
-        t = _time(lambda: fspbb.bound_pool(inst, pre_d, dep_d, o, stream), steps)
-        out["heads_bound_200x20_nodes_per_s"] = int(dep_d.shape[0]) / t
+    m20 = int(p.shape[1])
+    for key, kw in (("heads_bound_200x20_nodes_per_s", {"heads": True}),
+                    ("adjacent_pairs_bound_200x20_nodes_per_s", {"pairs": adjacent_pairs(m20)})):
+        with fspbb.create_instance(p, **kw) as inst:
+            o = dep_d.new_empty(dep_d.shape)
+            for _ in range(2):
+                fspbb.bound_pool(inst, pre_d, dep_d, o, stream)
+            t = _time(lambda: fspbb.bound_pool(inst, pre_d, dep_d, o, stream), steps)
+            out[key] = int(dep_d.shape[0]) / t
     # the three mappings of the bound on the 50 x 10 and 200 x 20 pools
     from paper_1208_3933_amd import gen
     mappings = {}
@@ -211,14 +221,16 @@ def variants_leg(p, pre_d, dep_d, steps: int, stream, solve_seeds: int = 6) -> d
     shapes = [(20, 5), (20, 10), (50, 5), (100, 5)]
     cands = serve.candidates(solve_seeds, shapes)
     budget, cap = 2_000_000, 8192
-    modes = {"dfs": (False, False), "dfs_heads": (True, False), "best_first": (False, True)}
+    modes = {"dfs": (False, False, False), "dfs_heads": (True, False, False), "best_first": (False, True, False),
+             "dfs_adjacent_pairs": (False, False, True)}
     rows = {}
     for c in cands:
         key = "%dx%d" % shapes[c.shape]
         r = rows.setdefault(key, {"instances": 0})
         r["instances"] += 1
-        for mode, (heads, bfirst) in modes.items():
-            with fspbb.create_instance(c.p, heads=heads) as inst:
+        for mode, (heads, bfirst, sub) in modes.items():
+            pairs = adjacent_pairs(int(c.p.shape[1])) if sub else None
+            with fspbb.create_instance(c.p, heads=heads, pairs=pairs) as inst:
                 t0 = time.perf_counter()
                 res = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, 0, stream, best_first=bfirst)
                 dt = time.perf_counter() - t0
