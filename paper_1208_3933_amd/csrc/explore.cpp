@@ -4,16 +4,20 @@
 // the multi-threaded CPU exploration the paper leaves to future work).
 //
 // Each explorer runs its own depth-first search on a host stack: it pops
-// parents while their children fit in pool_cap, writes the children's rows
-// into a host pool, hands the pool to the bounding service and waits; then it
-// updates the shared upper bound with complete children and pushes the others
-// whose bound is below it (reverse child order).  When its stack is empty it
-// takes the next subtree from a shared list: the first levels of the tree,
-// expanded breadth first until there are four subtrees per explorer.
+// parents while their children fit in pool_cap and hands the parents to the
+// bounding service, which returns the bounds of all their children (in
+// parent order, then by increasing appended job).  The explorer then updates
+// the shared upper bound with complete children and pushes the others whose
+// bound is below it (reverse child order), building only those rows.  When
+// its stack is empty it takes the next subtree from a shared list: the first
+// levels of the tree, expanded breadth first until there are four subtrees
+// per explorer.
 //
 // The bounding service is one thread that owns every HIP call: it takes all
-// pools waiting at that moment, packs them into one pinned buffer, copies it
-// to the device, bounds it as one pool and copies the bounds back, so the
+// requests waiting at that moment, copies their parents (not their children:
+// n - d times fewer rows cross PCIe) to the device in one pinned transfer,
+// lists and bounds the children of all of them as one step (children bounded
+// from their parents on the 16-bit path) and copies the bounds back, so the
 // explorers' pools are merged into large launches.  Node counts depend on
 // thread timing; the optimum and the proof do not.
 #include <algorithm>
@@ -33,16 +37,16 @@ using namespace fspbb;
 namespace {
 
 struct PoolReq {
-    const int32_t *rows;  // N x n, host
-    const int32_t *depths;
-    int64_t N;
-    int32_t *lb;          // N, host (written by the service)
+    const int32_t *parents;  // K x n, host: the first depth entries of each row
+    const int32_t *depths;   // K, each < n
+    int64_t K, nch;          // nch = sum over parents of (n - depth)
+    int32_t *lb;             // nch, host (written by the service), child order
     bool done = false;
 };
 
 class BoundService {
 public:
-    BoundService(fsp_instance_s *I, hipStream_t s) : I_(I), s_(s) {}
+    BoundService(fsp_instance_s *I, hipStream_t s) : I_(I), s_(s) { ctx_.s = s; }
 
     hipError_t start()
     {
@@ -61,7 +65,7 @@ public:
         release();
     }
 
-    // Blocks until the pool's bounds are written; false if the device failed.
+    // Blocks until the children's bounds are written; false if the device failed.
     bool bound(PoolReq &r)
     {
         std::unique_lock<std::mutex> lk(mu_);
@@ -100,59 +104,79 @@ private:
         }
     }
 
-    hipError_t reserve(int64_t N)
+    hipError_t reserve(int64_t K, int64_t C)
     {
-        if (N <= cap_) return hipSuccess;
-        release();
-        cap_ = std::max<int64_t>(N, 4096);
-        const size_t rb = (size_t)cap_ * I_->n * 4, db = (size_t)cap_ * 4;
-        hipError_t e = hipHostMalloc((void **)&h_rows_, rb, 0);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&h_dep_, db, 0);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&h_lb_, db, 0);
-        if (e == hipSuccess) e = hipMalloc((void **)&d_rows_, rb);
-        if (e == hipSuccess) e = hipMalloc((void **)&d_dep_, db);
-        if (e == hipSuccess) e = hipMalloc((void **)&d_lb_, db);
-        if (e != hipSuccess) cap_ = 0;
-        return e;
+        if (K > capK_) {
+            if (h_par_) hipHostFree(h_par_);
+            if (h_dep_) hipHostFree(h_dep_);
+            if (d_par_) hipFree(d_par_);
+            if (d_dep_) hipFree(d_dep_);
+            h_par_ = h_dep_ = d_par_ = d_dep_ = nullptr;
+            capK_ = 0;
+            const int64_t c = std::max<int64_t>(K, 1024);
+            const size_t rb = (size_t)c * I_->n * 4, db = (size_t)c * 4;
+            hipError_t e = hipHostMalloc((void **)&h_par_, rb, 0);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&h_dep_, db, 0);
+            if (e == hipSuccess) e = hipMalloc((void **)&d_par_, rb);
+            if (e == hipSuccess) e = hipMalloc((void **)&d_dep_, db);
+            if (e != hipSuccess) return e;
+            capK_ = c;
+        }
+        if (C > capC_) {
+            if (h_lb_) hipHostFree(h_lb_);
+            h_lb_ = nullptr;
+            capC_ = 0;
+            const int64_t c = std::max<int64_t>(C, 4096);
+            hipError_t e = hipHostMalloc((void **)&h_lb_, (size_t)c * 4, 0);
+            if (e != hipSuccess) return e;
+            capC_ = c;
+        }
+        return hipSuccess;
     }
 
     void release()
     {
-        if (h_rows_) hipHostFree(h_rows_);
+        hipStreamSynchronize(s_);
+        if (h_par_) hipHostFree(h_par_);
         if (h_dep_) hipHostFree(h_dep_);
         if (h_lb_) hipHostFree(h_lb_);
-        if (d_rows_) hipFree(d_rows_);
+        if (d_par_) hipFree(d_par_);
         if (d_dep_) hipFree(d_dep_);
-        if (d_lb_) hipFree(d_lb_);
-        h_rows_ = h_dep_ = h_lb_ = d_rows_ = d_dep_ = d_lb_ = nullptr;
-        cap_ = 0;
+        h_par_ = h_dep_ = h_lb_ = d_par_ = d_dep_ = nullptr;
+        capK_ = capC_ = 0;
+        B_.release(s_);
+        kids16_release(kids_, s_);
+        ctx_.release();
     }
 
     hipError_t run(const std::vector<PoolReq *> &batch)
     {
         const int n = I_->n;
-        int64_t N = 0;
-        for (PoolReq *r : batch) N += r->N;
-        hipError_t e = reserve(N);
+        int64_t K = 0, C = 0;
+        for (PoolReq *r : batch) {
+            K += r->K;
+            C += r->nch;
+        }
+        if (C == 0) return hipSuccess;
+        hipError_t e = reserve(K, C);
         if (e != hipSuccess) return e;
         int64_t off = 0;
         for (PoolReq *r : batch) {
-            std::memcpy(h_rows_ + off * n, r->rows, (size_t)r->N * n * 4);
-            std::memcpy(h_dep_ + off, r->depths, (size_t)r->N * 4);
-            off += r->N;
+            for (int64_t k = 0; k < r->K; ++k)
+                std::memcpy(h_par_ + (off + k) * n, r->parents + k * n, (size_t)r->depths[k] * 4);
+            std::memcpy(h_dep_ + off, r->depths, (size_t)r->K * 4);
+            off += r->K;
         }
-        e = hipMemcpyAsync(d_rows_, h_rows_, (size_t)N * n * 4, hipMemcpyHostToDevice, s_);
-        if (e == hipSuccess) e = hipMemcpyAsync(d_dep_, h_dep_, (size_t)N * 4, hipMemcpyHostToDevice, s_);
-        if (e == hipSuccess)
-            e = I_->packed16 ? launch_bound_packed(I_, d_rows_, d_dep_, N, d_lb_, s_)
-                             : launch_bound_lane32(I_, d_rows_, d_dep_, N, d_lb_, s_);
-        if (e == hipSuccess) e = hipMemcpyAsync(h_lb_, d_lb_, (size_t)N * 4, hipMemcpyDeviceToHost, s_);
+        e = hipMemcpyAsync(d_par_, h_par_, (size_t)K * n * 4, hipMemcpyHostToDevice, s_);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_dep_, h_dep_, (size_t)K * 4, hipMemcpyHostToDevice, s_);
+        if (e == hipSuccess) e = bound_children_of(I_, d_par_, d_dep_, K, C, B_, kids_, ctx_, s_);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_lb_, B_.w.clb, (size_t)C * 4, hipMemcpyDeviceToHost, s_);
         if (e == hipSuccess) e = hipStreamSynchronize(s_);
         if (e != hipSuccess) return e;
         off = 0;
         for (PoolReq *r : batch) {
-            std::memcpy(r->lb, h_lb_ + off, (size_t)r->N * 4);
-            off += r->N;
+            std::memcpy(r->lb, h_lb_ + off, (size_t)r->nch * 4);
+            off += r->nch;
         }
         ++launches_;
         return hipSuccess;
@@ -166,9 +190,12 @@ private:
     std::deque<PoolReq *> q_;
     bool stop_ = false;
     hipError_t err_ = hipSuccess;
-    int64_t cap_ = 0, launches_ = 0;
-    int32_t *h_rows_ = nullptr, *h_dep_ = nullptr, *h_lb_ = nullptr;
-    int32_t *d_rows_ = nullptr, *d_dep_ = nullptr, *d_lb_ = nullptr;
+    int64_t capK_ = 0, capC_ = 0, launches_ = 0;
+    int32_t *h_par_ = nullptr, *h_dep_ = nullptr, *h_lb_ = nullptr;
+    int32_t *d_par_ = nullptr, *d_dep_ = nullptr;
+    StepBuffers B_;
+    Kids16 kids_;
+    TickContext ctx_;
 };
 
 // Upper bound and incumbent shared by the explorers.
@@ -195,10 +222,54 @@ struct Shared {
     }
 };
 
+// Bounds the children of `nodes` (entries [depth, jobs...] of n + 1 ints,
+// each with depth < n) through the service: lb receives them in child order.
+bool bound_children(int n, const std::vector<int32_t> &nodes, BoundService &svc, std::vector<int32_t> &prow,
+                    std::vector<int32_t> &pdep, std::vector<int32_t> &lb, int64_t &nch)
+{
+    const int W = n + 1;
+    const int64_t K = (int64_t)nodes.size() / W;
+    prow.resize((size_t)std::max<int64_t>(K, 1) * n);
+    pdep.resize((size_t)std::max<int64_t>(K, 1));
+    nch = 0;
+    for (int64_t k = 0; k < K; ++k) {
+        const int32_t *nd = nodes.data() + k * W;
+        pdep[k] = nd[0];
+        std::memcpy(prow.data() + k * n, nd + 1, (size_t)nd[0] * 4);
+        nch += n - nd[0];
+    }
+    lb.resize((size_t)std::max<int64_t>(nch, 1));
+    PoolReq r{prow.data(), pdep.data(), K, nch, lb.data()};
+    return svc.bound(r);
+}
+
+// Calls f(child index, parent entry, appended job) over the children of
+// `nodes` in child order (reverse: from the last child back).
+template <class F>
+void for_children(int n, const std::vector<int32_t> &nodes, int64_t nch, bool reverse, std::vector<unsigned char> &sched,
+                  F f)
+{
+    const int W = n + 1;
+    const int64_t K = (int64_t)nodes.size() / W;
+    int64_t c = reverse ? nch - 1 : 0;
+    for (int64_t kk = 0; kk < K; ++kk) {
+        const int64_t k = reverse ? K - 1 - kk : kk;
+        const int32_t *nd = nodes.data() + k * W;
+        std::fill(sched.begin(), sched.end(), 0);
+        for (int t = 0; t < nd[0]; ++t) sched[nd[1 + t]] = 1;
+        for (int jj = 0; jj < n; ++jj) {
+            const int j = reverse ? n - 1 - jj : jj;
+            if (sched[j]) continue;
+            f(c, nd, j);
+            c += reverse ? -1 : 1;
+        }
+    }
+}
+
 void explorer(int n, int64_t pool_cap, Shared &sh, BoundService &svc)
 {
     std::vector<int32_t> stack;  // nodes of n + 1 ints: depth, jobs
-    std::vector<int32_t> rows, depths, lbs, parents;
+    std::vector<int32_t> prow, pdep, lbs, parents, row(n);
     std::vector<unsigned char> sched(n);
     const int W = n + 1;
     for (;;) {
@@ -220,41 +291,28 @@ void explorer(int n, int64_t pool_cap, Shared &sh, BoundService &svc)
             stack.resize(stack.size() - W);
             nch += c;
         }
-        const int64_t K = (int64_t)parents.size() / W;
-        rows.assign((size_t)nch * n, 0);
-        depths.resize(nch);
-        lbs.resize(nch);
-        int64_t c = 0;
-        for (int64_t k = 0; k < K; ++k) {
-            const int32_t *par = parents.data() + k * W;
-            const int d = par[0];
-            std::fill(sched.begin(), sched.end(), 0);
-            for (int t = 0; t < d; ++t) sched[par[1 + t]] = 1;
-            for (int j = 0; j < n; ++j) {
-                if (sched[j]) continue;
-                int32_t *row = rows.data() + c * n;
-                std::memcpy(row, par + 1, (size_t)d * 4);
-                row[d] = j;
-                depths[c] = d + 1;
-                ++c;
-            }
-        }
-        PoolReq r{rows.data(), depths.data(), nch, lbs.data()};
-        if (!svc.bound(r)) {
+        if (!bound_children(n, parents, svc, prow, pdep, lbs, nch)) {
             sh.failed = true;
             return;
         }
         if (sh.nodes.fetch_add(nch) + nch >= sh.budget) sh.out_of_budget = true;
-        for (int64_t i = 0; i < nch; ++i)
-            if (depths[i] == n && lbs[i] < sh.ub.load()) sh.offer(lbs[i], rows.data() + i * n, n);
+        // complete children first (they may lower the bound), then the pushes
+        for_children(n, parents, nch, false, sched, [&](int64_t c, const int32_t *nd, int j) {
+            if (nd[0] + 1 == n && lbs[c] < sh.ub.load()) {
+                std::memcpy(row.data(), nd + 1, (size_t)nd[0] * 4);
+                row[nd[0]] = j;
+                sh.offer(lbs[c], row.data(), n);
+            }
+        });
         const int32_t ub = sh.ub.load();
-        for (int64_t i = nch - 1; i >= 0; --i) {
-            if (depths[i] == n || lbs[i] >= ub) continue;
+        for_children(n, parents, nch, true, sched, [&](int64_t c, const int32_t *nd, int j) {
+            if (nd[0] + 1 == n || lbs[c] >= ub) return;
             const size_t at = stack.size();
             stack.resize(at + W);
-            stack[at] = depths[i];
-            std::memcpy(stack.data() + at + 1, rows.data() + i * n, (size_t)n * 4);
-        }
+            stack[at] = nd[0] + 1;
+            std::memcpy(stack.data() + at + 1, nd + 1, (size_t)nd[0] * 4);
+            stack[at + 1 + nd[0]] = j;
+        });
     }
 }
 
@@ -282,53 +340,43 @@ fsp_status fsp_explore(fsp_instance inst, int32_t ub0, int32_t threads, int64_t 
     BoundService svc(inst, (hipStream_t)stream);
     svc.start();
 
-    // root, then the first levels breadth first until there is work for every explorer
-    std::vector<std::vector<int32_t>> level(1, std::vector<int32_t>(n + 1, 0));
+    // the first levels, breadth first from the root, until there is work for
+    // every explorer (the root itself is not bounded: its children are)
+    std::vector<int32_t> level(n + 1, 0);
     int64_t nodes = 0;
     bool ok = true;
     {
-        std::vector<int32_t> lb(1);
-        std::vector<int32_t> row(n, 0), dep(1, 0);
-        PoolReq r{row.data(), dep.data(), 1, lb.data()};
-        ok = svc.bound(r);
-        nodes = 1;
-        if (ok && lb[0] >= sh.ub.load()) level.clear();
-    }
-    for (int depth = 0; ok && !level.empty() && depth < n - 1 && (int64_t)level.size() < 4 * threads; ++depth) {
-        std::vector<int32_t> rows, deps, lbs;
+        std::vector<int32_t> prow, pdep, lbs, next, row(n);
         std::vector<unsigned char> sched(n);
-        for (const auto &par : level) {
-            std::fill(sched.begin(), sched.end(), 0);
-            for (int t = 0; t < par[0]; ++t) sched[par[1 + t]] = 1;
-            for (int j = 0; j < n; ++j) {
-                if (sched[j]) continue;
-                const size_t at = rows.size();
-                rows.resize(at + n, 0);
-                std::memcpy(rows.data() + at, par.data() + 1, (size_t)par[0] * 4);
-                rows[at + par[0]] = j;
-                deps.push_back(par[0] + 1);
-            }
+        for (int depth = 0; ok && !level.empty() && depth < n - 1 && (int64_t)level.size() / (n + 1) < 4 * threads;
+             ++depth) {
+            int64_t nch = 0;
+            ok = bound_children(n, level, svc, prow, pdep, lbs, nch);
+            if (!ok) break;
+            nodes += nch;
+            next.clear();
+            for_children(n, level, nch, false, sched, [&](int64_t c, const int32_t *nd, int j) {
+                if (nd[0] + 1 == n) {
+                    if (lbs[c] < sh.ub.load()) {
+                        std::memcpy(row.data(), nd + 1, (size_t)nd[0] * 4);
+                        row[nd[0]] = j;
+                        sh.offer(lbs[c], row.data(), n);
+                    }
+                    return;
+                }
+                if (lbs[c] >= sh.ub.load()) return;
+                const size_t at = next.size();
+                next.resize(at + n + 1, 0);
+                next[at] = nd[0] + 1;
+                std::memcpy(next.data() + at + 1, nd + 1, (size_t)nd[0] * 4);
+                next[at + 1 + nd[0]] = j;
+            });
+            level.swap(next);
         }
-        lbs.resize(deps.size());
-        PoolReq r{rows.data(), deps.data(), (int64_t)deps.size(), lbs.data()};
-        ok = svc.bound(r);
-        nodes += (int64_t)deps.size();
-        std::vector<std::vector<int32_t>> next;
-        for (size_t i = 0; ok && i < deps.size(); ++i) {
-            if (deps[i] == n) {
-                if (lbs[i] < sh.ub.load()) sh.offer(lbs[i], rows.data() + i * n, n);
-                continue;
-            }
-            if (lbs[i] >= sh.ub.load()) continue;
-            std::vector<int32_t> node(n + 1);
-            node[0] = deps[i];
-            std::memcpy(node.data() + 1, rows.data() + i * n, (size_t)n * 4);
-            next.push_back(std::move(node));
-        }
-        level.swap(next);
     }
     sh.nodes = nodes;
-    for (auto &nd : level) sh.work.push_back(std::move(nd));
+    for (size_t at = 0; at < level.size(); at += n + 1)
+        sh.work.push_back(std::vector<int32_t>(level.begin() + at, level.begin() + at + n + 1));
     if (ok && nodes >= node_budget && !sh.work.empty()) sh.out_of_budget = true;
 
     std::vector<std::thread> ts;

@@ -46,6 +46,14 @@ struct TickContext {
     void release();
 };
 
+// Bounds the children of K parents (device rows and depths, taken in order;
+// each parent valid with depth < n) into B.w.clb: nch children (known to the
+// caller), in parent order and then by increasing appended job.  The table
+// upload goes through ctx's pinned buffer, so the caller synchronizes s
+// before its next call.
+hipError_t bound_children_of(fsp_instance_s *I, const int32_t *parents, const int32_t *pdepth, int64_t K,
+                             int64_t nch, StepBuffers &B, Kids16 &kids, TickContext &ctx, hipStream_t s);
+
 struct Search {
     fsp_instance_s *inst = nullptr;
     int n = 0;

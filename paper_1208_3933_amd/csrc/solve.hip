@@ -412,6 +412,43 @@ void bind_results(StepReq &q, StepReq *dq_entry, int32_t ub_in)
 }
 }  // namespace
 
+// ---------------------------------------------------------------- children of parents
+
+hipError_t bound_children_of(fsp_instance_s *I, const int32_t *parents, const int32_t *pdepth, int64_t K,
+                             int64_t nch, StepBuffers &B, Kids16 &kids, TickContext &ctx, hipStream_t s)
+{
+    if (K <= 0 || nch <= 0) return hipSuccess;
+    const int n = I->n;
+    B.rows = !kids16_eligible(I);
+    hipError_t e = B.ensure_k(K, s);
+    if (e == hipSuccess) e = B.ensure_c(nch, n, s);
+    KidsStep ks(kids);
+    if (e == hipSuccess) e = ks.start(I, K, nch, s);
+    const TabLayout L(1, K);
+    if (e == hipSuccess) e = ctx.reserve(L.total);
+    if (e != hipSuccess) return e;
+    char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
+    StepReq *dentry = (StepReq *)(d + L.req);
+    StepReq q;
+    std::memset(&q, 0, sizeof(q));
+    q.a.n = n;
+    q.a.ub_in = 0x7fffffff;
+    q.a.parents = parents;
+    q.a.pdepth = pdepth;
+    q.a.K = K;
+    q.w = B.w;
+    if (ks.on) kids16_point(q.w, ks.k);
+    q.T = I->dt;
+    q.nchild = nch;
+    bind_results(q, dentry, 0x7fffffff);
+    *(StepReq *)(h + L.req) = q;
+    *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
+    e = hipMemcpyAsync(d, h, L.seg2, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
+    if (e == hipSuccess) e = branch_and_bound1(dentry, I, ks, K, nch, q.w, s, true);
+    return e;
+}
+
 hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
 {
     hipStream_t s = ctx.s;

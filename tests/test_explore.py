@@ -59,6 +59,22 @@ def test_explore_heads_and_budget():
         assert sorted(r["perm"].tolist()) == list(range(20))
 
 
+@pytest.mark.parametrize("n,m,seed", [(10, 6, 41), (12, 20, 42), (25, 3, 43)])
+def test_explore_pair_subset_and_wide(n, m, seed):
+    """Pair subsets (adjacent pairs plus (0, m - 1)) and instances outside the
+    incremental path's limits reach the oracle's optimum."""
+    require_gpu()
+    p = times(n, m, seed)
+    S = [(k, k + 1) for k in range(m - 1)] + ([(0, m - 1)] if m > 2 else [])
+    for pairs in (S, None):
+        want = oracle.bnb(p, *oracle.neh(p), pool_cap=256, pairs=pairs)
+        assert want["proven"]
+        with fspbb.create_instance(p, pairs=pairs) as inst:
+            r = fspbb.explore(inst, fspbb.UB_NEH, 4, 256)
+        assert r["proven"] and r["opt"] == want["ub"]
+        assert oracle.makespan(p, r["perm"]) == r["opt"]
+
+
 def test_explore_rejects_bad_arguments():
     require_gpu()
     with fspbb.create_instance(times(6, 3, 31)) as inst:
