@@ -12,6 +12,10 @@ JSON line.  Further legs:
   batched  the same pool as 64 pools of 4,096 in one graph-captured batch vs
            64 plain launches, and 64 seeded instances of mixed shape with
            log-normal pool sizes, batched vs plain;
+  peaks    probe kernels for the packed 16-bit and 32-bit VALU, LDS reads and
+           an HBM copy: what the chip delivers at its running clock, beside
+           the published peaks (the scan's roofline also gives its fraction
+           of the 16-bit probe's rate);
   variants the three mappings of the bound (lane per two nodes, lane per
            node, wave per node) on the 50 x 10 and 200 x 20 pools; the heads
            bound variant (earliest-start releases) and best-first selection:
@@ -25,8 +29,9 @@ JSON line.  Further legs:
   tables   nodes/s over the shape x pool grid of the paper's Tables II/III,
            device-resident and with the pool's transfers in the timed region;
   cpu_baseline  the plain C oracle on a bounded prefix of the pool on the
-           host cores (its bounds are also compared with the GPU's), and on
-           one core per table shape (the ratio the paper's tables report).
+           host cores (its bounds are also compared with the GPU's), on
+           one core per table shape (the ratio the paper's tables report),
+           and the share of a short sequential oracle search spent bounding.
 """
 from __future__ import annotations
 
@@ -48,6 +53,13 @@ CONFIG = 2
 # Peak of the unit the scan kernel is bound by: packed 16-bit integer VALU ops,
 # 256 CUs x 4 SIMDs x 16 lanes x 2 halves x 2.4 GHz.
 PEAK_U16_OPS = 256 * 4 * 16 * 2 * 2.4e9
+# Published or unit-count peaks the probes are set against: 32-bit VALU (one
+# op per lane per clock), LDS reads at 256 bytes per clock per CU (the LDS
+# probe reaches 1.9x the 128 bytes per clock of the previous generation, so
+# the read path is twice as wide), HBM3E 8 TB/s.
+PEAK_I32_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_LDS_BYTES = 256 * 256 * 2.4e9
+PEAK_HBM_BYTES = 8.0e12
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scan16_200x20_pool262144_hbm_traffic.md")
@@ -98,6 +110,32 @@ def cpu_baseline(p, pre, dep, sample: int, threads: int, gpu_lb: np.ndarray) -> 
     return {"value": len(idx) / dt, "unit": "nodes/s", "cores": threads, "kind": "oracle",
             "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per core",
             "gpu_bounds_equal": bool((gpu_lb[idx] == want).all())}
+
+
+def bound_share(p) -> dict:
+    """Share of the oracle's sequential depth-first search spent bounding, the
+    figure the paper gives for its CPU B&B (Sec. I): 200x20 from the NEH bound,
+    steps of up to 4,096 children, stopped after 4,096 nodes, one thread."""
+    import oracle
+    ms, perm = oracle.neh(p)
+    r = oracle.bnb(p, ms, perm, pool_cap=4096, node_budget=4096)
+    return {"share": r["seconds_bound"] / r["seconds_total"], "seconds": r["seconds_total"],
+            "nodes": r["nodes_bounded"], "steps": r["steps"],
+            "search": "200x20 DFS from NEH, pool_cap 4096, node budget 4096, one thread"}
+
+
+def peaks_leg(stream) -> dict:
+    """What the chip delivers at its running clock: each probe kernel's rate
+    (best of three) and its fraction of the published or unit-count peak."""
+    from paper_1208_3933_amd import fspbb
+    out = {}
+    for name, kind, peak, unit, scale in [("valu_u16", fspbb.PROBE_VALU16, PEAK_U16_OPS, "TOP/s", 1e12),
+                                          ("valu_i32", fspbb.PROBE_VALU32, PEAK_I32_OPS, "TOP/s", 1e12),
+                                          ("lds_read", fspbb.PROBE_LDS, PEAK_LDS_BYTES, "TB/s", 1e12),
+                                          ("hbm_copy", fspbb.PROBE_HBM, PEAK_HBM_BYTES, "TB/s", 1e12)]:
+        rate = max(fspbb.probe_peak(kind, 1 << 30, stream)[0] for _ in range(3))
+        out[name] = {"achieved": rate / scale, "peak": peak / scale, "unit": unit, "frac": rate / peak}
+    return out
 
 
 def _time(fn, reps: int) -> float:
@@ -491,6 +529,10 @@ def main() -> int:
                      "decode_avg_ms": dec_ms / max(launches, 1)},
         "plain_nodes_per_s": value,
     }
+    result["peaks"] = peaks_leg(stream)
+    probe = result["peaks"]["valu_u16"]["achieved"]
+    result["roofline"]["probe_peak"] = probe
+    result["roofline"]["frac_of_probe_peak"] = achieved / probe
     if args.batched_reps > 0:
         result["batched"] = batched_leg(inst, pre_d, dep_d, args.batched_reps, stream)
         print("[bench] batched leg done", file=sys.stderr, flush=True)
@@ -516,6 +558,7 @@ def main() -> int:
         result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads, gpu_lb)
         one = single_core_rates()
         result["cpu_baseline"]["single_core_nodes_per_s"] = one
+        result["cpu_baseline"]["bound_share_of_search"] = bound_share(p)
         if "tables" in result:  # GPU (with transfers) over one oracle core, the form of the paper's tables
             result["tables_ratio_vs_one_core"] = {
                 shape: {N: round(v["with_transfers_nodes_per_s"] / one[shape], 1) for N, v in row.items()}

@@ -439,6 +439,28 @@ fsp_status fsp_server_destroy(fsp_server srv);
 fsp_status fsp_timing_enable(fsp_instance inst, int32_t on);
 fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms, int64_t *launches);
 
+/*
+ * Peak probes (measurement support; not an operation of the method).  Each
+ * runs one kernel built to saturate one unit of the current device, three
+ * times untimed and five times timed with HIP events on `stream`, and returns
+ * the rate and the mean duration (ms, optional) of the timed launches:
+ *   FSP_PROBE_VALU16  chains of packed 16-bit max and add, the arithmetic of
+ *                     the 16-bit pair scan; rate = 16-bit operations per
+ *                     second (a packed instruction counts two);
+ *   FSP_PROBE_VALU32  the same chains in 32-bit lanes; operations per second;
+ *   FSP_PROBE_LDS     conflict-free 16-byte LDS reads; bytes per second;
+ *   FSP_PROBE_HBM     a copy between two device buffers of `bytes` bytes each
+ *                     (a multiple of 16, at least 1 MiB), which the call
+ *                     allocates and frees; bytes read plus written per second.
+ * `bytes` is ignored by the other kinds.  Synchronous on `stream`.  Errors:
+ * FSP_E_INVAL (unknown kind, null rate, bad size), FSP_E_NOMEM, FSP_E_DEVICE.
+ */
+#define FSP_PROBE_VALU16 0
+#define FSP_PROBE_VALU32 1
+#define FSP_PROBE_LDS 2
+#define FSP_PROBE_HBM 3
+fsp_status fsp_probe_peak(int32_t kind, int64_t bytes, void *stream, double *rate, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

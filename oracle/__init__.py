@@ -29,7 +29,8 @@ class Counts(ctypes.Structure):
 class BnbResult(ctypes.Structure):
     _fields_ = [("ub", ctypes.c_int32), ("proven", ctypes.c_int32),
                 ("nodes_bounded", ctypes.c_int64), ("steps", ctypes.c_int64),
-                ("improvements", ctypes.c_int64), ("max_stack", ctypes.c_int64)]
+                ("improvements", ctypes.c_int64), ("max_stack", ctypes.c_int64),
+                ("seconds_total", ctypes.c_double), ("seconds_bound", ctypes.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -232,4 +233,5 @@ def bnb(p, ub0: int, incumbent0=None, pool_cap: int = 1 << 18, node_budget: int 
     return {"ub": int(res.ub), "proven": bool(res.proven), "nodes_bounded": int(res.nodes_bounded),
             "steps": int(res.steps), "improvements": int(res.improvements),
             "max_stack": int(res.max_stack), "incumbent": inc,
+            "seconds_total": float(res.seconds_total), "seconds_bound": float(res.seconds_bound),
             "steplog": log[:min(int(res.steps), steplog_cap)] if steplog_cap else None}

@@ -41,9 +41,11 @@
  * Parity pins live in tests/test_oracle_pins.py (brute force, closed forms,
  * invariants).  Nothing here is "parity unpinned".
  */
+#define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define ORC_INVALID (-1)
 
@@ -454,7 +456,19 @@ typedef struct {
     int64_t steps;
     int64_t improvements;
     int64_t max_stack;
+    /* Wall time of the search and of its bounding (step 4, and the root's
+     * bound) alone: the share of the search spent bounding, which the paper
+     * gives for its sequential B&B (Sec. I).  Depth-first search only. */
+    double seconds_total;
+    double seconds_bound;
 } orc_bnb_result;
+
+static double now_seconds(void)
+{
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
+}
 
 /* steplog, when non-NULL, receives per step (up to steplog_cap steps):
  *   [0] parents popped, [1] children bounded, [2] UB after the step,
@@ -468,6 +482,8 @@ static int bnb_dfs(const int32_t *p, int n, int m, int32_t ub0, const int32_t *i
 {
     memset(res, 0, sizeof(*res));
     if (n < 1 || m < 2 || pool_cap < 1) return -1;
+    const double t_start = now_seconds();
+    double t_bound = 0.0;
     int32_t UB = ub0;
     int32_t *inc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int have_inc = 0;
@@ -479,7 +495,9 @@ static int bnb_dfs(const int32_t *p, int n, int m, int32_t ub0, const int32_t *i
 #define NODE(i) (stack + (int64_t)(i) * (n + 1))
 
     int64_t nodes = 1;
+    double t0 = now_seconds();
     int32_t root_lb = bound_impl(p, n, m, NULL, 0, NULL, 0, NULL, -1, -1, NULL, NULL, v);
+    t_bound += now_seconds() - t0;
     int pruned_root = strict_gt ? (root_lb > UB) : (root_lb >= UB);
     if (!pruned_root) {
         NODE(0)[0] = 0;
@@ -524,10 +542,12 @@ static int bnb_dfs(const int32_t *p, int n, int m, int32_t ub0, const int32_t *i
         }
         top = first;
         /* 4. bounding */
+        t0 = now_seconds();
         for (int64_t i = 0; i < nchild; ++i) {
             int32_t *ch = children + i * (n + 1);
             lbs[i] = bound_impl(p, n, m, ch + 1, ch[0], NULL, 0, NULL, -1, -1, NULL, NULL, v);
         }
+        t_bound += now_seconds() - t0;
         nodes += nchild;
         /* 5. complete children update the upper bound */
         int improved = 0;
@@ -576,6 +596,8 @@ static int bnb_dfs(const int32_t *p, int n, int m, int32_t ub0, const int32_t *i
         else for (int j = 0; j < n; ++j) incumbent_out[j] = -1;
     }
     free(sched); free(children); free(lbs); free(stack); free(inc);
+    res->seconds_total = now_seconds() - t_start;
+    res->seconds_bound = t_bound;
     return 0;
 }
 

@@ -150,6 +150,8 @@ _SIGNATURES = {
     "fsp_timing_enable": (ctypes.c_int32, [_vp, ctypes.c_int32]),
     "fsp_timing_read": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "fsp_probe_peak": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -302,6 +304,18 @@ def timing_read(inst: Instance):
     _check(lib().fsp_timing_read(inst.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "fsp_timing_read")
     return a.value, b.value, int(c.value)
+
+
+PROBE_VALU16, PROBE_VALU32, PROBE_LDS, PROBE_HBM = 0, 1, 2, 3
+
+
+def probe_peak(kind: int, nbytes: int = 1 << 30, stream=None):
+    """(rate, ms) of one peak-probe kernel on the current device: 16-bit or
+    32-bit operations/s, or bytes/s for LDS and HBM (a copy of nbytes)."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fsp_probe_peak(int(kind), int(nbytes), _stream_handle(stream), ctypes.byref(rate), ctypes.byref(ms)),
+           "fsp_probe_peak")
+    return rate.value, ms.value
 
 
 def neh(inst: Instance):
