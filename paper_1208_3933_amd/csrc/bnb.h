@@ -45,6 +45,10 @@ struct StepScratch {
     int32_t *ujob, *upar;        // C: appended job and parent of each child
     int32_t *crow;               // C x n child rows
     int32_t *cdepth, *clb;       // C
+    // Survivors of the compaction, for a step of nch children and W =
+    // ceil(nch / 32): keep[t] (t < W) holds the survivor bits of children
+    // 32t..32t+31, keep[W + t] the survivors of the words before t within its
+    // 256-child block, and pos[b] the survivors before block b.
     uint32_t *keep, *pos;        // C
     uint32_t *nchild, *nsurv;    // device scalars
     unsigned long long *best;    // (bound << 32) | child index of the best complete child
@@ -87,9 +91,10 @@ hipError_t mstep_phase1(const StepReq *reqs, const ScanSeg *segs, int R, int64_t
 hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
 // Branch without rows: the children's appended jobs and parents only.
 hipError_t mstep_list(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
-// Finish (after the children are bounded into w.clb): upper bound, keep,
-// stable compaction, scatter, fingerprint, per-parent counts, incumbent.
-hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, int64_t maxC,
-                        hipStream_t s);
+// Finish (after the children are bounded into w.clb): upper bound, keep and
+// stable compaction (survivor bits and block counts, then one block per
+// search scans the block counts), scatter, fingerprint, per-parent counts,
+// incumbent.
+hipError_t mstep_finish(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
 
 }  // namespace fspbb

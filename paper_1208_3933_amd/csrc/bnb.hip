@@ -16,12 +16,66 @@
 //   6. keeps the non-leaf children whose bound is below the new upper bound
 //      and compacts them stably (prefix sum), optionally in reverse child
 //      order so that pushing them on a stack leaves the first child on top.
+// The compaction of step 6 keeps survivor bits and per-block counts; one
+// small launch scans the block counts, and a survivor's rank is its block's
+// offset plus the bits before it within the block.
 #include <algorithm>
 
 #include "step_dev.h"
 
 namespace fspbb {
 
+// ---- block-level helpers (blocks of 256 threads)
+
+// Inclusive prefix sum of one value per thread over the block: within each
+// wave by shuffles, then the sums of the waves before.  sh holds 4 words.
+__device__ inline uint32_t block_inclusive_sum(uint32_t v, uint32_t *sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    for (int w = 0; w < wv; ++w) x += sh[w];
+    __syncthreads();
+    return x;
+}
+
+// out[i] = in[0] + ... + in[i - 1] for i < count (in and out may be the same
+// array), the sum of all to *total; one block, 4,096 items per round.
+__device__ inline void block_scan_array(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total,
+                                        uint32_t *sh, uint32_t *round_total)
+{
+    constexpr int kItems = 16;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < count; base += 256 * kItems) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * kItems;
+        uint32_t v[kItems], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            v[k] = i0 + k < count ? in[i0 + k] : 0u;
+            sum += v[k];
+        }
+        const uint32_t inc = block_inclusive_sum(sum, sh);
+        uint32_t run = carry + inc - sum;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (i0 + k < count) out[i0 + k] = run;
+            run += v[k];
+        }
+        if (threadIdx.x == 255) *round_total = inc;
+        __syncthreads();
+        carry += *round_total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// One wave per parent: validation and child count.
 __global__ __launch_bounds__(256) void mstep_count_kernel(const StepReq *__restrict__ reqs)
 {
     __shared__ uint32_t mask[4][kMaxJobs / 32];
@@ -99,14 +153,61 @@ __global__ __launch_bounds__(256) void mstep_leaf_kernel(const StepReq *__restri
         atomicMin(q->w.best, ((unsigned long long)(uint32_t)lb << 32) | (unsigned long long)c);
 }
 
+// Keep, one block per 256 children: each wave's ballot gives two words of
+// survivor bits; thread 0 writes the words' offsets within the block and the
+// block's count.
 __global__ __launch_bounds__(256) void mstep_keep_kernel(const StepReq *__restrict__ reqs)
 {
+    __shared__ uint32_t wcnt[8];
     ReqP q = req_of(reqs);
+    const int64_t nch = q->nchild;
+    const int64_t nblk = (nch + 255) >> 8;
+    if ((int64_t)blockIdx.x >= nblk) return;  // whole block
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= q->nchild) return;
-    const int32_t ub = (int32_t)(*q->w.best >> 32);
-    const int32_t lb = q->w.clb[c];
-    q->w.keep[c] = (q->w.cdepth[c] < q->a.n && lb >= 0 && lb < ub) ? 1u : 0u;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t W = (nch + 31) >> 5;
+    uint32_t *kb = q->w.keep;
+    bool k = false;
+    if (c < nch) {
+        const int32_t ub = (int32_t)(*q->w.best >> 32);
+        const int32_t lb = q->w.clb[c];
+        k = q->w.cdepth[c] < q->a.n && lb >= 0 && lb < ub;
+    }
+    const unsigned long long bal = __ballot(k);
+    if ((lane & 31) == 0) {
+        const uint32_t bits = lane ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+        if ((c >> 5) < W) kb[c >> 5] = bits;
+        wcnt[wv * 2 + (lane >> 5)] = __popc(bits);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < 8; ++t) {
+            const int64_t g = (int64_t)blockIdx.x * 8 + t;
+            if (g < W) kb[W + g] = run;
+            run += wcnt[t];
+        }
+        q->w.pos[blockIdx.x] = run;
+    }
+}
+
+// One block per search: block counts -> block offsets, and the survivor count.
+__global__ __launch_bounds__(256) void mstep_blockscan_kernel(const StepReq *__restrict__ reqs)
+{
+    __shared__ uint32_t sh[4];
+    __shared__ uint32_t round_total;
+    ReqP q = req_of(reqs);
+    const int64_t nblk = (q->nchild + 255) >> 8;
+    block_scan_array(q->w.pos, q->w.pos, nblk, q->w.nsurv, sh, &round_total);
+}
+
+// Whether child c survives, and its rank among the survivors (c < nchild).
+__device__ __forceinline__ bool surv_kept(ReqP q, int64_t c) { return (q->w.keep[c >> 5] >> (c & 31)) & 1u; }
+__device__ __forceinline__ uint32_t surv_rank(ReqP q, int64_t c)
+{
+    const int64_t W = (q->nchild + 31) >> 5;
+    const uint32_t *kb = q->w.keep;
+    return q->w.pos[c >> 8] + kb[W + (c >> 5)] + (uint32_t)__popc(kb[c >> 5] & ((1u << (c & 31)) - 1u));
 }
 
 // The step's tail after the compaction, in one launch over disjoint block
@@ -121,10 +222,10 @@ __device__ inline void tail_scatter(ReqP q, int64_t blk)
     const int64_t c = blk * kRowsPerBlock + (threadIdx.x / kRowLanes);
     const int sub = threadIdx.x % kRowLanes;
     if (c >= q->nchild) return;
-    if (!q->w.keep[c]) return;
+    if (!surv_kept(q, c)) return;
     const int n = q->a.n;
     const int64_t S = *q->w.nsurv;
-    const int64_t s = q->w.pos[c];
+    const int64_t s = surv_rank(q, c);
     const int64_t dst = q->a.out_reversed ? q->a.out_base + (S - 1 - s) : q->a.out_base + s;
     if (dst < 0 || dst >= q->a.out_cap) return;  // overflow is reported by the host
     const int d = q->w.cdepth[c];
@@ -154,7 +255,7 @@ __device__ inline void tail_fingerprint(ReqP q, int64_t blk, int64_t nblk, unsig
     unsigned long long v = 0;
     const unsigned long long S = *q->w.nsurv;
     for (int64_t c = blk * 256 + threadIdx.x; c < nch; c += nblk * 256)
-        if (q->w.keep[c]) v += (S - q->w.pos[c]) * (unsigned long long)(q->w.ujob[c] + 1);
+        if (surv_kept(q, c)) v += (S - surv_rank(q, c)) * (unsigned long long)(q->w.ujob[c] + 1);
     part[threadIdx.x] = v;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -175,8 +276,8 @@ __device__ inline void tail_per_parent(ReqP q, int64_t blk, int64_t nblk)
         uint32_t v = 0u;
         if (cnt) {
             const int64_t lo = q->w.off[p], hi = lo + cnt;
-            const uint32_t end = hi < q->nchild ? q->w.pos[hi] : *q->w.nsurv;
-            v = end - q->w.pos[lo];
+            const uint32_t end = hi < q->nchild ? surv_rank(q, hi) : *q->w.nsurv;
+            v = end - surv_rank(q, lo);
         }
         q->a.surv_per_parent[p] = v;
     }
@@ -246,16 +347,14 @@ hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, 
     return hipGetLastError();
 }
 
-hipError_t mstep_finish(const StepReq *reqs, const ScanSeg *segs, int R, int64_t maxK, int64_t maxC,
-                        hipStream_t s)
+hipError_t mstep_finish(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s)
 {
     if (R <= 0) return hipSuccess;
     if (maxC > 0) {
         mstep_leaf_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
         mstep_keep_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
+        mstep_blockscan_kernel<<<dim3(1, R), 256, 0, s>>>(reqs);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = exclusive_scan_segments(segs, R, maxC, s);
         if (e != hipSuccess) return e;
     }
     // without children the tail only writes the per-parent counts (all zero)

@@ -35,10 +35,13 @@ __device__ inline void stage_p16(int n, const int32_t *p32, uint32_t *p16)
 }
 
 // Chain part, one lane per parent: completion times of the prefix and the
-// time of the unscheduled jobs per machine.  Parents with no children (invalid, or
-// complete) are skipped; the count kernel has validated the others.
+// time of the unscheduled jobs per machine.  With COUNT the parents are not
+// validated yet (the tails part of the same launch does it): the depth is
+// clamped to 0..n and a job outside 0..n-1 takes the zero row, so every read
+// stays in bounds and an invalid parent's record, never used, is harmless.
+// Otherwise parents with no children (invalid, or complete) are skipped.
 // Block blk of the chain part; p16: LDS for the staged rows.
-template <int MV>
+template <int MV, bool COUNT>
 __device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
 {
     constexpr int H = MV / 2;
@@ -47,8 +50,9 @@ __device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
     stage_p16<H>(n, q->T.p32, p16);
     int32_t *__restrict__ rec = q->w.krec;
     const int64_t p = blk * 256 + threadIdx.x;
-    if (p >= q->a.K || q->w.cnt[p] == 0) return;
-    const int d = parent_depth(q, p);
+    if (p >= q->a.K) return;
+    if (!COUNT && q->w.cnt[p] == 0) return;
+    const int d = COUNT ? min(max(parent_depth(q, p), 0), n) : parent_depth(q, p);
     const int32_t *row = parent_row(q, p);
     int32_t C[MV];
     u16x2 S2[H];
@@ -62,7 +66,7 @@ __device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
         const int32_t jj[4] = {j0, j1, j2, j3};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int j = t + c < d ? jj[c] : n;
+            const int j = t + c < d && (unsigned)jj[c] < (unsigned)n ? jj[c] : n;
             const uint2 *pr = reinterpret_cast<const uint2 *>(p16 + __mul24(j, H));
             int32_t prev = 0;
 #pragma unroll
@@ -107,24 +111,34 @@ __device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
 
 // Tails part, one wave per parent: copies the parent row, builds its
 // unscheduled set, and lane k (< m) finds the least and second least tails on machine k over the
-// unscheduled jobs, taken in increasing id.
+// unscheduled jobs, taken in increasing id.  With COUNT it also validates the
+// parent and writes its child count (the count kernel's work); otherwise the
+// count kernel has done so.
 // Block blk of the tails part (four parents); mask: 4 x kMaskWords words of LDS.
+template <bool COUNT>
 __device__ inline void kid_tails(ReqP q, int64_t blk, uint32_t (*mask)[kMaskWords])
 {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p = blk * 4 + wv;
     if (!q->w.prow) return;        // whole block: the request bounds children from rows
     if (p >= q->a.K) return;       // whole wave
-    if (q->w.cnt[p] == 0) return;  // whole wave
+    if (!COUNT && q->w.cnt[p] == 0) return;  // whole wave
     int32_t *__restrict__ rec = q->w.krec;
     int32_t *__restrict__ prow = q->w.prow;
     const int32_t *__restrict__ tails32 = q->T.tails32;
     const int n = q->T.n, m = q->T.m, NW = (n + 31) >> 5;
     const int d = parent_depth(q, p);
     const int32_t *row = parent_row(q, p);
+    const bool ok = wave_prefix_set(row, d, n, mask[wv], lane);  // reads the row only for a depth in 0..n
+    if (COUNT) {
+        if (lane == 0) {
+            q->w.cnt[p] = (ok && d < n) ? (uint32_t)(n - d) : 0u;
+            if (!ok) atomicAdd(q->w.bad, 1ull);
+        }
+        if (!ok || d == n) return;  // whole wave: no children
+    }
     int32_t *pr = prow + p * (int64_t)n;
     for (int t = lane; t < d; t += 64) pr[t] = row[t];
-    wave_prefix_set(row, d, n, mask[wv], lane);
     int32_t *r = rec + p * kKidRec;
     if (lane < NW) {
         const int lo = lane * 32;
@@ -156,19 +170,41 @@ __device__ inline void kid_tails(ReqP q, int64_t blk, uint32_t (*mask)[kMaskWord
 
 // Both per-parent parts in one launch: blocks [0, bc) the chain part, the
 // rest the tails part (block-uniform branch).
-template <int MV>
+template <int MV, bool COUNT>
 __global__ __launch_bounds__(256) void kid_parents_kernel(const StepReq *__restrict__ reqs, int bc)
 {
     extern __shared__ uint32_t p16[];
     __shared__ uint32_t mask[4][kMaskWords];
     ReqP q = req_of(reqs);
-    if ((int)blockIdx.x < bc) kid_chain<MV>(q, blockIdx.x, p16);
-    else kid_tails(q, (int64_t)blockIdx.x - bc, mask);
+    if ((int)blockIdx.x < bc) kid_chain<MV, COUNT>(q, blockIdx.x, p16);
+    else kid_tails<COUNT>(q, (int64_t)blockIdx.x - bc, mask);
+}
+
+// Position of the k-th set bit (from 0) of x, which has more than k set bits.
+__device__ __forceinline__ int select_bit(uint32_t x, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int sh = 16; sh > 0; sh >>= 1) {
+        const uint32_t lo = x & ((1u << sh) - 1u);
+        const int c = __popc(lo);
+        if (k >= c) {
+            k -= c;
+            x >>= sh;
+            pos += sh;
+        } else {
+            x = lo;
+        }
+    }
+    return pos;
 }
 
 // One lane per child (and per padding slot up to the group boundary): writes
 // the scan inputs of child i in the decode kernel's layout, and its depth.
-template <int MV>
+// With LIST it also finds the child's parent (the last one whose offset is
+// at most i) and appended job (the (i - offset)-th unscheduled job of the
+// parent, in increasing id) and writes them, the list kernel's work.
+template <int MV, bool LIST>
 __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restrict__ reqs)
 {
     constexpr int H = MV / 2;
@@ -187,8 +223,36 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
     int64_t p = 0;
     int d = 0;
     if (live) {
-        j = q->w.ujob[i];
-        p = q->w.upar[i];
+        if (LIST) {
+            const uint32_t *off = q->w.off;
+            int64_t lo = 0, hi = q->a.K - 1;  // off[0] = 0 <= i
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if ((int64_t)off[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            p = lo;
+            int k = (int)(i - (int64_t)off[p]);
+            const int32_t *rp = rec + p * kKidRec;
+            j = n;
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t bits = (uint32_t)rp[kKidM + w];
+                const int c = __popc(bits);
+                if (k < c) {
+                    j = 32 * w + select_bit(bits, k);
+                    break;
+                }
+                k -= c;
+            }
+            // (a step with an invalid parent has fewer children than listed;
+            // it is reported, and the zero row keeps the reads in bounds)
+            j = min(j, n);
+            q->w.ujob[i] = j;
+            q->w.upar[i] = (int32_t)p;
+        } else {
+            j = q->w.ujob[i];
+            p = q->w.upar[i];
+        }
         d = parent_depth(q, p) + 1;
         q->w.cdepth[i] = d;
     }
@@ -230,14 +294,28 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// segs: null for the plain form (counts, offsets and the child lists done
+// by the step kernels); else the offset scan segments, and the parents'
+// launch counts and the decode lists (the form without the count and list
+// launches).
 template <int MV>
-hipError_t launch_kids(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, hipStream_t s)
+hipError_t launch_kids(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, const ScanSeg *segs,
+                       hipStream_t s)
 {
     const size_t lds = (size_t)(nmax + 1) * (MV / 2) * 4;
     const int64_t Npad = (maxC + kGroup - 1) / kGroup * kGroup;
     const int bc = (int)((maxK + 255) / 256), bt = (int)((maxK + 3) / 4);
-    kid_parents_kernel<MV><<<dim3((unsigned)(bc + bt), R), 256, lds, s>>>(dreqs, bc);
-    kid_decode_kernel<MV><<<dim3((unsigned)((Npad + 255) / 256), R), 256, lds, s>>>(dreqs);
+    const dim3 gp((unsigned)(bc + bt), R), gd((unsigned)((Npad + 255) / 256), R);
+    if (!segs) {
+        kid_parents_kernel<MV, false><<<gp, 256, lds, s>>>(dreqs, bc);
+        kid_decode_kernel<MV, false><<<gd, 256, lds, s>>>(dreqs);
+        return hipGetLastError();
+    }
+    kid_parents_kernel<MV, true><<<gp, 256, lds, s>>>(dreqs, bc);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = exclusive_scan_segments(segs, R, maxK, s);
+    if (e != hipSuccess) return e;
+    kid_decode_kernel<MV, true><<<gd, 256, lds, s>>>(dreqs);
     return hipGetLastError();
 }
 
@@ -355,18 +433,19 @@ void kids16_point(StepScratch &w, const Kids16 &k)
     w.kw = k.W;
 }
 
-hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s)
+hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s,
+                         const ScanSeg *segs)
 {
     if (R <= 0 || maxK <= 0 || maxC <= 0) return hipSuccess;
     switch ((mmax + 3) & ~3) {
-    case 4: return launch_kids<4>(dreqs, R, maxK, maxC, nmax, s);
-    case 8: return launch_kids<8>(dreqs, R, maxK, maxC, nmax, s);
-    case 12: return launch_kids<12>(dreqs, R, maxK, maxC, nmax, s);
-    case 16: return launch_kids<16>(dreqs, R, maxK, maxC, nmax, s);
-    case 20: return launch_kids<20>(dreqs, R, maxK, maxC, nmax, s);
-    case 24: return launch_kids<24>(dreqs, R, maxK, maxC, nmax, s);
-    case 28: return launch_kids<28>(dreqs, R, maxK, maxC, nmax, s);
-    default: return launch_kids<32>(dreqs, R, maxK, maxC, nmax, s);
+    case 4: return launch_kids<4>(dreqs, R, maxK, maxC, nmax, segs, s);
+    case 8: return launch_kids<8>(dreqs, R, maxK, maxC, nmax, segs, s);
+    case 12: return launch_kids<12>(dreqs, R, maxK, maxC, nmax, segs, s);
+    case 16: return launch_kids<16>(dreqs, R, maxK, maxC, nmax, segs, s);
+    case 20: return launch_kids<20>(dreqs, R, maxK, maxC, nmax, segs, s);
+    case 24: return launch_kids<24>(dreqs, R, maxK, maxC, nmax, segs, s);
+    case 28: return launch_kids<28>(dreqs, R, maxK, maxC, nmax, segs, s);
+    default: return launch_kids<32>(dreqs, R, maxK, maxC, nmax, segs, s);
     }
 }
 

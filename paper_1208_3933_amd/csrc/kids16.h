@@ -58,7 +58,12 @@ void kids16_point(StepScratch &w, const Kids16 &k);
 // decodes its parents, then its children into w.kw, and writes the children's
 // depths (w.cdepth).  maxK / maxC bound the requests' parents and children;
 // nmax / mmax their jobs and machines.
-hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s);
+// With segs (the offset scan segments of every request, all of which have
+// w.prow set), it replaces the step's phase 1 and list as well: the parent
+// launch validates and counts the children, the segments are scanned, and
+// the child launch writes each child's parent and appended job.
+hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s,
+                         const ScanSeg *segs = nullptr);
 // The single search in dreq: kids16_decode, then the plain scan of its
 // children, bounds to clb (its w.clb).
 hipError_t kids16_bound(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s);

@@ -23,7 +23,7 @@ inline int64_t initial_stack_rows(int64_t pool_cap) { return pool_cap > 128 ? 8 
 // part (C) grow independently, so the parent outputs survive a child resize.
 struct StepBuffers {
     StepScratch w{};
-    uint32_t *sums_k = nullptr, *sums_c = nullptr;  // scan tile sums
+    uint32_t *sums_k = nullptr;  // tile sums of the separate offset scan
     void *kblob = nullptr, *cblob = nullptr;
     int64_t Kcap = 0, Ccap = 0;
     int n = 0;

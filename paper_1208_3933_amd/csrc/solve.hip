@@ -53,9 +53,10 @@ hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
     cblob = nullptr;
     Ccap = std::max<int64_t>(C, 1);
     n = n_;
+    // (each array holds at least 64 words, so keep also fits the word offsets
+    // of a step with fewer than 64 children)
     const size_t cb = al256((size_t)Ccap * 4), rows_b = rows ? al256((size_t)Ccap * n * 4) : 0;
-    const size_t sb = al256(scan_scratch_bytes(Ccap));
-    hipError_t e = stream_alloc((void **)&cblob, 6 * cb + rows_b + sb, s);
+    hipError_t e = stream_alloc((void **)&cblob, 6 * cb + rows_b, s);
     if (e != hipSuccess) { cblob = nullptr; Ccap = 0; return e; }
     char *p = (char *)cblob;
     w.ujob = (int32_t *)p; p += cb;
@@ -65,8 +66,6 @@ hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
     w.keep = (uint32_t *)p; p += cb;
     w.pos = (uint32_t *)p; p += cb;
     w.crow = rows ? (int32_t *)p : nullptr;
-    p += rows_b;
-    sums_c = (uint32_t *)p;
     return hipSuccess;
 }
 
@@ -80,8 +79,7 @@ void StepBuffers::release(hipStream_t s)
 
 size_t StepBuffers::bytes() const
 {
-    return (size_t)Kcap * 8 + (size_t)Ccap * (24 + (rows ? 4 * (size_t)n : 0)) + scan_scratch_bytes(Kcap) +
-           scan_scratch_bytes(Ccap);
+    return (size_t)Kcap * 8 + (size_t)Ccap * (24 + (rows ? 4 * (size_t)n : 0)) + scan_scratch_bytes(Kcap);
 }
 
 hipError_t TickContext::reserve(size_t bytes)
@@ -379,16 +377,15 @@ static hipError_t prepare_step(Search &S, hipStream_t s)
 }
 
 namespace {
-// Request table of a step: StepReq[R] (with their results), the phase-1 and
-// finish scan segments, then the survivor counts of every popped parent.
+// Request table of a step: StepReq[R] (with their results), the phase-1 scan
+// segments, then the survivor counts of every popped parent.
 struct TabLayout {
-    size_t req, seg1, seg2, surv, total;
+    size_t req, seg1, surv, total;
     TabLayout(int R, int64_t sumK)
     {
         req = 0;
         seg1 = al256(sizeof(StepReq) * R);
-        seg2 = seg1 + al256(sizeof(ScanSeg) * R);
-        surv = seg2 + al256(sizeof(ScanSeg) * R);
+        surv = seg1 + al256(sizeof(ScanSeg) * R);
         total = surv + al256((size_t)std::max<int64_t>(sumK, 1) * 4);
     }
 };
@@ -443,7 +440,7 @@ hipError_t bound_children_of(fsp_instance_s *I, const int32_t *parents, const in
     bind_results(q, dentry, 0x7fffffff);
     *(StepReq *)(h + L.req) = q;
     *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
-    e = hipMemcpyAsync(d, h, L.seg2, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
     if (e == hipSuccess) e = branch_and_bound1(dentry, I, ks, K, nch, q.w, s, true);
     return e;
@@ -495,7 +492,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     }
     char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
     StepReq *hq = (StepReq *)(h + L.req);
-    ScanSeg *hs1 = (ScanSeg *)(h + L.seg1), *hs2 = (ScanSeg *)(h + L.seg2);
+    ScanSeg *hs1 = (ScanSeg *)(h + L.seg1);
     int64_t slot = 0;
     std::vector<int64_t> slots(R);
     for (int r = 0; r < R; ++r) {
@@ -526,17 +523,22 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         slot += S.K;
         hq[r] = q;
         hs1[r] = ScanSeg{q.w.cnt, q.w.off, S.K, q.w.nchild, S.B.sums_k};
-        hs2[r] = ScanSeg{q.w.keep, q.w.pos, S.nch, q.w.nsurv, S.B.sums_c};
     }
     const StepReq *dq = (const StepReq *)(d + L.req);
-    const ScanSeg *ds1 = (const ScanSeg *)(d + L.seg1), *ds2 = (const ScanSeg *)(d + L.seg2);
+    const ScanSeg *ds1 = (const ScanSeg *)(d + L.seg1);
     e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = mstep_phase1(dq, ds1, R, maxK, s);
     if (e != hipSuccess) return e;
-    // branching: job lists for all, child rows for the searches without the
-    // incremental path; the others decode their children from their parents
-    e = any_rows ? mstep_branch(dq, R, maxK, maxC, s) : mstep_list(dq, R, maxK, maxC, s);
-    if (e == hipSuccess && kK > 0) e = kids16_decode(dq, R, kK, kC, knmax, kmmax, s);
+    if (!any_rows) {
+        // every search decodes its children from its parents: validation,
+        // counts and child lists are folded into those launches
+        e = kids16_decode(dq, R, kK, kC, knmax, kmmax, s, ds1);
+    } else {
+        e = mstep_phase1(dq, ds1, R, maxK, s);
+        // branching: job lists for all, child rows for the searches without
+        // the incremental path; the others decode their children from their parents
+        if (e == hipSuccess) e = mstep_branch(dq, R, maxK, maxC, s);
+        if (e == hipSuccess && kK > 0) e = kids16_decode(dq, R, kK, kC, knmax, kmmax, s);
+    }
     if (e != hipSuccess) return e;
     // bounding: one plain launch for a search alone, else one merged batch
     // (decoded workspaces go straight to its scan)
@@ -563,7 +565,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         if (e == hipSuccess && !descs.empty())
             e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s, ready.data());
     }
-    if (e == hipSuccess) e = mstep_finish(dq, ds2, R, maxK, maxC, s);
+    if (e == hipSuccess) e = mstep_finish(dq, R, maxK, maxC, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h, d, L.total, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
@@ -816,13 +818,12 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         bind_results(q, dentry, UB);
         *(StepReq *)(h + L.req) = q;
         *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
-        *(ScanSeg *)(h + L.seg2) = ScanSeg{q.w.keep, q.w.pos, nch, q.w.nsurv, B.sums_c};
         const uint32_t *dnsurv = &dentry->res.nsurv;
         e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
         // parents of mixed depths: the row path sorts its children by depth
         if (e == hipSuccess) e = branch_and_bound1(dentry, inst, ks, K, nch, q.w, s, true);
-        if (e == hipSuccess) e = mstep_finish(dentry, (const ScanSeg *)(d + L.seg2), 1, K, nch, s);
+        if (e == hipSuccess) e = mstep_finish(dentry, 1, K, nch, s);
         if (e == hipSuccess)
             e = bf_sort_survivors(bf.S(1), dnsurv, nch, UB, bf.S(2), bf.S(3), bf.S(4), bf.S(5), &bf.tmp,
                                   &bf.tmp_bytes, s);
@@ -951,10 +952,9 @@ fsp_status fsp_branch_and_prune(fsp_instance inst, const int32_t *parents, const
     q.res = after1;
     q.nchild = nchild;
     *(StepReq *)(h + L.req) = q;
-    *(ScanSeg *)(h + L.seg2) = ScanSeg{q.w.keep, q.w.pos, (int64_t)nchild, q.w.nsurv, B.sums_c};
     e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = branch_and_bound1(dq, inst, ks, K, nchild, q.w, s, true);
-    if (e == hipSuccess) e = mstep_finish(dq, (const ScanSeg *)(d + L.seg2), 1, K, nchild, s);
+    if (e == hipSuccess) e = mstep_finish(dq, 1, K, nchild, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h + L.req, d + L.req, sizeof(StepReq), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { cleanup(); return fail_status(e); }
