@@ -95,6 +95,8 @@ hipError_t mstep_list(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hi
 // stable compaction (survivor bits and block counts, then one block per
 // search scans the block counts), scatter, fingerprint, per-parent counts,
 // incumbent.
-hipError_t mstep_finish(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s);
+// leaves_done: the leaf step was taken by the child decode (see kids16.h).
+hipError_t mstep_finish(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s,
+                        bool leaves_done = false);
 
 }  // namespace fspbb

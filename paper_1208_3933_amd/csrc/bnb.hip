@@ -347,11 +347,11 @@ hipError_t mstep_branch(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, 
     return hipGetLastError();
 }
 
-hipError_t mstep_finish(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s)
+hipError_t mstep_finish(const StepReq *reqs, int R, int64_t maxK, int64_t maxC, hipStream_t s, bool leaves_done)
 {
     if (R <= 0) return hipSuccess;
     if (maxC > 0) {
-        mstep_leaf_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
+        if (!leaves_done) mstep_leaf_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
         mstep_keep_kernel<<<dim3(blocks_for(maxC, 256), R), 256, 0, s>>>(reqs);
         mstep_blockscan_kernel<<<dim3(1, R), 256, 0, s>>>(reqs);
         hipError_t e = hipGetLastError();

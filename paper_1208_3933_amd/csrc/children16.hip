@@ -203,7 +203,8 @@ __device__ __forceinline__ int select_bit(uint32_t x, int k)
 // the scan inputs of child i in the decode kernel's layout, and its depth.
 // With LIST it also finds the child's parent (the last one whose offset is
 // at most i) and appended job (the (i - offset)-th unscheduled job of the
-// parent, in increasing id) and writes them, the list kernel's work.
+// parent, in increasing id) and writes them, the list kernel's work, and
+// takes the leaf step for complete children (the leaf kernel's work).
 template <int MV, bool LIST>
 __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restrict__ reqs)
 {
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
     const int64_t G = i >> 7;
     const int g = (int)(i & 127), lane = g & 63, half = g >> 6;
     uint16_t *d16 = reinterpret_cast<uint16_t *>(Wdec);
-    int32_t prev = 0;
+    int32_t prev = 0, mk = 0;
 #pragma unroll
     for (int q4 = 0; q4 < MV / 4; ++q4) {
         const uint2 v = pj[q4];
@@ -273,6 +274,7 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
             const int k = 4 * q4 + cc;
             const int32_t ck = max(r[kKidC + k], prev) + x[cc];
             prev = ck;
+            if (k == m - 1) mk = ck;
             if (k < m) {
                 const int32_t tk = ck + (r[kKidU + k] - x[cc]);
                 const int32_t qk = r[kKidJ1 + k] == j ? r[kKidQ2 + k] : r[kKidQ1 + k];
@@ -289,6 +291,11 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
             Wflg[(G * NW + w) * 128 + g] = live ? ((uint32_t)r[kKidM + w] & ~drop) : 0u;
         }
     }
+    // With LIST the leaf step is done here too: a complete child's bound is
+    // its makespan (its releases on every pair, no job left, and a pair
+    // ending on the last machine), the last completion time just computed.
+    if (LIST && live && empty && mk < q->a.ub_in)
+        atomicMin(q->w.best, ((unsigned long long)(uint32_t)mk << 32) | (unsigned long long)i);
     Wst[i] = live ? 1u : 0u;
 }
 

@@ -61,7 +61,8 @@ void kids16_point(StepScratch &w, const Kids16 &k);
 // With segs (the offset scan segments of every request, all of which have
 // w.prow set), it replaces the step's phase 1 and list as well: the parent
 // launch validates and counts the children, the segments are scanned, and
-// the child launch writes each child's parent and appended job.
+// the child launch writes each child's parent and appended job and takes the
+// leaf step (mstep_finish then runs with leaves_done).
 hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC, int nmax, int mmax, hipStream_t s,
                          const ScanSeg *segs = nullptr);
 // The single search in dreq: kids16_decode, then the plain scan of its

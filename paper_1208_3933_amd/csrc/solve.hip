@@ -565,7 +565,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         if (e == hipSuccess && !descs.empty())
             e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s, ready.data());
     }
-    if (e == hipSuccess) e = mstep_finish(dq, R, maxK, maxC, s);
+    if (e == hipSuccess) e = mstep_finish(dq, R, maxK, maxC, s, !any_rows);
     if (e == hipSuccess) e = hipMemcpyAsync(h, d, L.total, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
