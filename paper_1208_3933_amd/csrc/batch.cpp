@@ -187,7 +187,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
     pl.meta_bytes = meta;
 }
 
-void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host)
+void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host, char *dmeta)
 {
     for (size_t i = 0; i < pl.pools.size(); ++i) {
         BatchPool &P = pl.pools[i];
@@ -207,7 +207,7 @@ void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host)
             P.W.cnt = (uint32_t *)(w + a + b + c + al256((size_t)P.N * 4));
         }
     }
-    pl.dmeta = base + pl.ws_bytes;
+    pl.dmeta = dmeta ? dmeta : base + pl.ws_bytes;
     host.assign(pl.meta_bytes, 0);
     std::memcpy(host.data() + pl.meta_pools, pl.pools.data(), sizeof(BatchPool) * pl.pools.size());
     if (!pl.items.empty())
@@ -276,6 +276,39 @@ hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStrea
     int d = 0;
     e = hipGetDevice(&d);
     if (e != hipSuccess) return e;
+    return enqueue_batch(plan, plan.form == kBatchPersistent ? batch_grid(d, plan.scan_lds) : 0, s);
+}
+
+hipError_t BatchArena::plan_only(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s,
+                                 const Workspace16 *ready, size_t *meta_bytes)
+{
+    plan_batch(pools, n_pools, 0, false, plan, -1, ready);
+    if (plan.ws_bytes > dev_bytes) {
+        const size_t cap = std::max(plan.ws_bytes, dev_bytes * 2);
+        if (dev) hipFreeAsync(dev, s);
+        dev = nullptr;
+        dev_bytes = 0;
+        hipError_t e = stream_alloc((void **)&dev, cap, s);
+        if (e != hipSuccess) return e;
+        dev_bytes = cap;
+    }
+    *meta_bytes = plan.meta_bytes;
+    return hipSuccess;
+}
+
+void BatchArena::stage(char *dmeta, char *hdst)
+{
+    layout_batch(plan, (char *)dev, meta, dmeta);
+    std::memcpy(hdst, meta.data(), meta.size());
+}
+
+hipError_t BatchArena::launch(hipStream_t s)
+{
+    int d = 0;
+    if (plan.form == kBatchPersistent) {
+        hipError_t e = hipGetDevice(&d);
+        if (e != hipSuccess) return e;
+    }
     return enqueue_batch(plan, plan.form == kBatchPersistent ? batch_grid(d, plan.scan_lds) : 0, s);
 }
 

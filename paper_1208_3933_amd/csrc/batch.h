@@ -110,7 +110,10 @@ fsp_status check_pools(const fsp_pool_desc *pools, int32_t n_pools, int *dev_out
 // sorted nor decoded and takes no workspace of the plan.
 void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, bool sort_depths, BatchPlan &pl,
                 int32_t form_force = -1, const Workspace16 *ready = nullptr);
-void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host_meta);
+// Points the pools' workspaces into `base` (at the plan's offsets) and builds
+// the metadata image for device address dmeta (null: right after the
+// workspaces, at base + ws_bytes).
+void layout_batch(BatchPlan &pl, char *base, std::vector<char> &host_meta, char *dmeta = nullptr);
 hipError_t enqueue_batch(const BatchPlan &pl, int grid, hipStream_t s);
 int batch_grid(int dev, size_t scan_lds);
 
@@ -127,6 +130,14 @@ struct BatchArena {
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
     hipError_t run(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s, const Workspace16 *ready = nullptr);
+    // run in three parts, for a caller that uploads the metadata with its own
+    // copy: plan (and grow the workspace region; *meta_bytes = metadata size),
+    // write the metadata for device address dmeta into host memory hdst, and,
+    // once the copy is enqueued, launch.
+    hipError_t plan_only(const fsp_pool_desc *pools, int32_t n_pools, hipStream_t s, const Workspace16 *ready,
+                         size_t *meta_bytes);
+    void stage(char *dmeta, char *hdst);
+    hipError_t launch(hipStream_t s);
     void release(hipStream_t s);
 };
 

@@ -378,14 +378,17 @@ static hipError_t prepare_step(Search &S, hipStream_t s)
 
 namespace {
 // Request table of a step: StepReq[R] (with their results), the phase-1 scan
-// segments, then the survivor counts of every popped parent.
+// segments, the metadata of a merged bound launch (meta bytes, possibly 0),
+// then the survivor counts of every popped parent.  Everything before surv
+// goes up in one copy.
 struct TabLayout {
-    size_t req, seg1, surv, total;
-    TabLayout(int R, int64_t sumK)
+    size_t req, seg1, meta, surv, total;
+    TabLayout(int R, int64_t sumK, size_t meta_bytes = 0)
     {
         req = 0;
         seg1 = al256(sizeof(StepReq) * R);
-        surv = seg1 + al256(sizeof(ScanSeg) * R);
+        meta = seg1 + al256(sizeof(ScanSeg) * R);
+        surv = meta + al256(meta_bytes);
         total = surv + al256((size_t)std::max<int64_t>(sumK, 1) * 4);
     }
 };
@@ -459,9 +462,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         maxC = std::max(maxC, S->nch);
         sumK += S->K;
     }
-    const TabLayout L(R, sumK);
-    hipError_t e = ctx.reserve(L.total);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     // searches on the 16-bit path with the plain releases bound their
     // children from their parents; the others from child rows
     std::vector<int> kid_of(R, -1);  // index into kv, or -1 (child rows)
@@ -490,7 +491,29 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         e = ctx.kids.layout(kI, kKs, kCs, kv, s);
         if (e != hipSuccess) return e;
     }
+    // a merged step bounds its 16-bit searches in one batched launch, planned
+    // here so that its metadata goes up with the request table
+    std::vector<fsp_pool_desc> descs;
+    std::vector<Workspace16> ready;
+    size_t meta_bytes = 0;
+    if (R > 1) {
+        descs.reserve(R);
+        ready.reserve(R);
+        for (int r = 0; r < R; ++r) {
+            Search *S = act[r];
+            if (!S->inst->packed16) continue;
+            const bool k = kid_of[r] >= 0;
+            descs.push_back(fsp_pool_desc{S->inst, k ? nullptr : S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb});
+            ready.push_back(k ? kv[kid_of[r]].W : Workspace16{});
+        }
+        if (!descs.empty()) e = ctx.arena.plan_only(descs.data(), (int32_t)descs.size(), s, ready.data(), &meta_bytes);
+        if (e != hipSuccess) return e;
+    }
+    const TabLayout L(R, sumK, meta_bytes);
+    e = ctx.reserve(L.total);
+    if (e != hipSuccess) return e;
     char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
+    if (meta_bytes) ctx.arena.stage(d + L.meta, h + L.meta);
     StepReq *hq = (StepReq *)(h + L.req);
     ScanSeg *hs1 = (ScanSeg *)(h + L.seg1);
     int64_t slot = 0;
@@ -547,23 +570,11 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
         e = kid_of[0] >= 0 ? launch_scan16(S.inst, kv[0].W, S.nch, S.B.w.clb, s)
                            : bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s, false);
     } else {
-        std::vector<fsp_pool_desc> descs;
-        std::vector<Workspace16> ready;
-        descs.reserve(R);
-        ready.reserve(R);
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < R && e == hipSuccess; ++r) {
             Search *S = act[r];
-            if (S->inst->packed16) {
-                const bool k = kid_of[r] >= 0;
-                descs.push_back(fsp_pool_desc{S->inst, k ? nullptr : S->B.w.crow, S->B.w.cdepth, S->nch,
-                                              S->B.w.clb});
-                ready.push_back(k ? kv[kid_of[r]].W : Workspace16{});
-            } else if (e == hipSuccess) {
-                e = bound_rows(S->inst, S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb, s);
-            }
+            if (!S->inst->packed16) e = bound_rows(S->inst, S->B.w.crow, S->B.w.cdepth, S->nch, S->B.w.clb, s);
         }
-        if (e == hipSuccess && !descs.empty())
-            e = ctx.arena.run(descs.data(), (int32_t)descs.size(), s, ready.data());
+        if (e == hipSuccess && !descs.empty()) e = ctx.arena.launch(s);
     }
     if (e == hipSuccess) e = mstep_finish(dq, R, maxK, maxC, s, !any_rows);
     if (e == hipSuccess) e = hipMemcpyAsync(h, d, L.total, hipMemcpyDeviceToHost, s);
