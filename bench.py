@@ -430,8 +430,8 @@ def bnb_leg(inst, steps: int, stream, best_first: bool = False) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20, help="untimed pools first (the clocks take some tens to settle)")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bnb-steps", type=int, default=8, help="pool steps of the 200x20 DFS leg (0 = skip)")
