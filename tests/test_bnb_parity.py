@@ -98,6 +98,40 @@ def test_branch_and_prune_step(n, m, K, seed, ub_mode):
         assert list(inc.cpu().numpy()) == want["incumbent"]
 
 
+def test_branch_and_prune_full_pool_sampled():
+    """A full 200 x 20 step (1,324 parents of depth 2: 262,152 children, the
+    DFS leg's pool) with no upper bound: every child survives in child order.
+    Every row is checked, every bound against the row-based plain bound of
+    the same rows, and a sample of bounds against the oracle."""
+    torch = require_gpu()
+    n, m, K = 200, 20, 1324
+    p = gen.processing_times(n, m, gen.make_seed(2, 0, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, K, gen.make_seed(41, 77, 1), 2, 2)
+    nch = K * (n - 2)
+    with fspbb.create_instance(p) as inst:
+        pre_d, dep_d = to_dev(torch, pre, dep)
+        rows = torch.full((nch, n), -9, dtype=torch.int32, device="cuda")
+        cdep = torch.full((nch,), -9, dtype=torch.int32, device="cuda")
+        clb = torch.full((nch,), -9, dtype=torch.int32, device="cuda")
+        res = fspbb.branch_and_prune(inst, pre_d, dep_d, fspbb.UB_NONE, rows, cdep, clb)
+        assert res["status"] == fspbb.OK and res["n_children"] == nch and res["n_survivors"] == nch
+        plain = torch.full((nch,), -7, dtype=torch.int32, device="cuda")
+        fspbb.bound_pool(inst, rows, cdep, plain)
+        torch.cuda.synchronize()
+        rows3, cdep, clb, plain = rows[:, :3].cpu().numpy(), cdep.cpu().numpy(), clb.cpu().numpy(), plain.cpu().numpy()
+    assert (cdep == 3).all() and (clb == plain).all()
+    # child c: parent c // 198, its (c % 198)-th unscheduled job in increasing id
+    par = np.arange(nch) // (n - 2)
+    assert (rows3[:, :2] == pre[par, :2]).all()
+    free = np.sort(pre[:, 2:], axis=1)
+    assert (rows3[:, 2] == free[par, np.arange(nch) % (n - 2)]).all()
+    idx = np.arange(0, nch, nch // 300)
+    want = oracle.bound_pool(p, np.ascontiguousarray(np.concatenate([pre[par[idx], :2], rows3[idx, 2:3],
+                                                                     np.zeros((len(idx), n - 3), np.int32)], axis=1)),
+                             np.full(len(idx), 3, np.int32))
+    assert (clb[idx] == want).all()
+
+
 def test_branch_and_prune_errors():
     torch = require_gpu()
     n, m = 6, 3
