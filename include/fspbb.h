@@ -340,7 +340,7 @@ fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_
 typedef struct {
     int32_t opt;           /* best makespan found (the optimum when proven) */
     int32_t proven;        /* 1 when every subtree was explored within the budget */
-    int64_t nodes_bounded; /* root and children bounded (depends on thread timing) */
+    int64_t nodes_bounded; /* children bounded (depends on thread timing; the root is not bounded) */
     int64_t pools;         /* bounding launches (each merges the pools waiting at the time) */
     int32_t threads;       /* host explorers */
     int32_t ub0;           /* initial upper bound used */
@@ -354,10 +354,13 @@ typedef struct {
  * in Sec. V).  Each of `threads` explorers runs a depth-first search on its
  * own host stack over subtrees taken from a shared list (the first levels of
  * the tree, expanded breadth first until there are 4 per explorer): it pops
- * parents while their children fit in pool_cap, writes the children's rows in
- * host memory and hands them to one bounding thread, which merges the pools
- * waiting at that moment into one host-to-device copy, one bound launch and
- * one copy back.  The upper bound is shared (elimination: bound >= it).
+ * parents while their children fit in pool_cap and hands the parents to one
+ * bounding thread, which merges the requests waiting at that moment into one
+ * host-to-device copy of parent prefixes, one step that lists and bounds all
+ * their children on the device, and one copy back of the bounds (in parent
+ * order, then by increasing appended job).  The explorer builds rows only
+ * for the children it keeps.  The upper bound is shared (elimination: bound
+ * >= it).
  * Node counts depend on thread timing; the optimum does not.  Synchronous.
  *   ub0, pool_cap, node_budget as in fsp_solve; threads 1..256; perm_out host n.
  * Returns FSP_OK (proven), FSP_BUDGET, or an error.
