@@ -293,11 +293,13 @@ def hybrid_leg(inst, p200, stream, threads: int) -> dict:
         t0 = time.perf_counter()
         d = fspbb.solve(i20, fspbb.UB_NEH, 8192, 1 << 40, 0, stream)
         td = time.perf_counter() - t0
+        fspbb.explore(i20, fspbb.UB_NEH, threads, 8192, 10000, stream)  # warm-up
         h = fspbb.explore(i20, fspbb.UB_NEH, threads, 8192, 1 << 40, stream)
     out["20x5_proof"] = {"device_dfs_s": td, "device_dfs_nodes": d["nodes_bounded"], "hybrid_s": h["seconds"],
                          "hybrid_nodes": h["nodes_bounded"], "hybrid_launches": h["pools"],
                          "same_optimum": bool(d["proven"] and h["proven"] and d["opt"] == h["opt"])}
-    budget = 4 * POOL
+    budget = 16 * POOL
+    fspbb.explore(inst, fspbb.UB_NEH, threads, POOL // threads, POOL, stream)  # warm-up
     h = fspbb.explore(inst, fspbb.UB_NEH, threads, POOL // threads, budget, stream)
     out["200x20_budget"] = {"hybrid_nodes_per_s": h["nodes_bounded"] / h["seconds"], "nodes": h["nodes_bounded"],
                             "launches": h["pools"], "pool_cap_per_explorer": POOL // threads}

@@ -48,6 +48,21 @@ class BoundService {
 public:
     BoundService(fsp_instance_s *I, hipStream_t s) : I_(I), s_(s) { ctx_.s = s; }
 
+    // Sizes every buffer for K parents and C children before the thread
+    // starts (the buffers only grow; growing pinned memory mid-search costs
+    // milliseconds per step early on).
+    hipError_t presize(int64_t K, int64_t C)
+    {
+        hipError_t e = reserve(K, C);
+        B_.rows = !kids16_eligible(I_);
+        if (e == hipSuccess) e = B_.ensure_k(K, s_);
+        if (e == hipSuccess) e = B_.ensure_c(C, I_->n, s_);
+        if (e == hipSuccess && !B_.rows) e = kids16_ensure(kids_, I_, K, C, s_);
+        if (e == hipSuccess) e = ctx_.reserve((size_t)K * 4 + (64 << 10));
+        if (e == hipSuccess) e = hipStreamSynchronize(s_);
+        return e;
+    }
+
     hipError_t start()
     {
         th_ = std::thread([this] { loop(); });
@@ -208,7 +223,7 @@ struct Shared {
     std::atomic<bool> failed{false};
     int64_t budget = 0;
     std::mutex work_mu;
-    std::deque<std::vector<int32_t>> work;  // subtree roots: [depth, job_0 .. job_{n-1}]
+    std::deque<std::vector<int32_t>> work;  // subtree roots: depth, then its prefix
 
     // A complete schedule of makespan lb: the new upper bound and incumbent
     // when it is below the current one (ub is also read without the lock).
@@ -222,96 +237,124 @@ struct Shared {
     }
 };
 
-// Bounds the children of `nodes` (entries [depth, jobs...] of n + 1 ints,
-// each with depth < n) through the service: lb receives them in child order.
-bool bound_children(int n, const std::vector<int32_t> &nodes, BoundService &svc, std::vector<int32_t> &prow,
-                    std::vector<int32_t> &pdep, std::vector<int32_t> &lb, int64_t &nch)
+// Bounds the children of the K parents in prow (K x n, the first pdep[k]
+// entries of row k) through the service: lb receives them in child order.
+bool bound_children(int n, int64_t K, const std::vector<int32_t> &prow, const std::vector<int32_t> &pdep,
+                    BoundService &svc, std::vector<int32_t> &lb, int64_t &nch)
 {
-    const int W = n + 1;
-    const int64_t K = (int64_t)nodes.size() / W;
-    prow.resize((size_t)std::max<int64_t>(K, 1) * n);
-    pdep.resize((size_t)std::max<int64_t>(K, 1));
     nch = 0;
-    for (int64_t k = 0; k < K; ++k) {
-        const int32_t *nd = nodes.data() + k * W;
-        pdep[k] = nd[0];
-        std::memcpy(prow.data() + k * n, nd + 1, (size_t)nd[0] * 4);
-        nch += n - nd[0];
-    }
+    for (int64_t k = 0; k < K; ++k) nch += n - pdep[k];
     lb.resize((size_t)std::max<int64_t>(nch, 1));
     PoolReq r{prow.data(), pdep.data(), K, nch, lb.data()};
     return svc.bound(r);
 }
 
-// Calls f(child index, parent entry, appended job) over the children of
-// `nodes` in child order (reverse: from the last child back).
+// Calls f(child index, parent k, appended job) over the children of the K
+// parents in child order (reverse: from the last child back).
 template <class F>
-void for_children(int n, const std::vector<int32_t> &nodes, int64_t nch, bool reverse, std::vector<unsigned char> &sched,
-                  F f)
+void for_children(int n, int64_t K, const std::vector<int32_t> &prow, const std::vector<int32_t> &pdep, int64_t nch,
+                  bool reverse, std::vector<unsigned char> &sched, F f)
 {
-    const int W = n + 1;
-    const int64_t K = (int64_t)nodes.size() / W;
     int64_t c = reverse ? nch - 1 : 0;
     for (int64_t kk = 0; kk < K; ++kk) {
         const int64_t k = reverse ? K - 1 - kk : kk;
-        const int32_t *nd = nodes.data() + k * W;
+        const int32_t *row = prow.data() + k * n;
         std::fill(sched.begin(), sched.end(), 0);
-        for (int t = 0; t < nd[0]; ++t) sched[nd[1 + t]] = 1;
+        for (int t = 0; t < pdep[k]; ++t) sched[row[t]] = 1;
         for (int jj = 0; jj < n; ++jj) {
             const int j = reverse ? n - 1 - jj : jj;
             if (sched[j]) continue;
-            f(c, nd, j);
+            f(c, k, j);
             c += reverse ? -1 : 1;
         }
     }
 }
 
+// An explorer's stack holds compact entries: a child is its parent (an
+// expanded node of the explorer's arena), its appended job and its depth.
+// A prefix is rebuilt only when its node is popped as a parent, by walking
+// the arena up to the subtree root, so a pushed child costs 12 bytes instead
+// of a row of n + 1 ints.
+struct Entry {
+    int32_t parent;  // arena index; kRootEntry: the subtree root itself
+    int32_t job;
+    int32_t depth;
+};
+constexpr int32_t kRootEntry = -2;
+
+struct Arena {
+    std::vector<int32_t> root;                     // the subtree root: depth, then its prefix
+    std::vector<std::pair<int32_t, int32_t>> rec;  // expanded nodes: (parent index, job); -1 = the root
+
+    // Appends the expanded node of stack entry e; returns its index.
+    int32_t expand(const Entry &e)
+    {
+        rec.push_back(e.parent == kRootEntry ? std::make_pair(-1, -1) : std::make_pair(e.parent, e.job));
+        return (int32_t)rec.size() - 1;
+    }
+    // Writes the prefix (depth d) of expanded node a into out.
+    void prefix(int32_t a, int d, int32_t *out) const
+    {
+        int t = d;
+        while (rec[a].first >= 0) {
+            out[--t] = rec[a].second;
+            a = rec[a].first;
+        }
+        std::memcpy(out, root.data() + 1, (size_t)t * 4);  // t is the root's depth
+    }
+};
+
 void explorer(int n, int64_t pool_cap, Shared &sh, BoundService &svc)
 {
-    std::vector<int32_t> stack;  // nodes of n + 1 ints: depth, jobs
-    std::vector<int32_t> prow, pdep, lbs, parents, row(n);
+    std::vector<Entry> stack;
+    Arena ar;
+    std::vector<int32_t> prow, pdep, pidx, lbs, row(n);
     std::vector<unsigned char> sched(n);
-    const int W = n + 1;
     for (;;) {
         if (stack.empty()) {
             std::lock_guard<std::mutex> lk(sh.work_mu);
             if (sh.work.empty()) return;
-            stack = std::move(sh.work.front());
+            ar.root = std::move(sh.work.front());
             sh.work.pop_front();
+            ar.rec.clear();
+            stack.push_back(Entry{kRootEntry, -1, ar.root[0]});
         }
         if (sh.failed.load() || sh.out_of_budget.load()) return;
         // pop parents while their children fit (the first always)
-        int64_t nch = 0;
-        parents.clear();
+        int64_t K = 0, nch = 0;
+        pdep.clear();
+        pidx.clear();
         while (!stack.empty()) {
-            const int32_t *top = stack.data() + stack.size() - W;
-            const int64_t c = n - top[0];
-            if (!parents.empty() && nch + c > pool_cap) break;
-            parents.insert(parents.end(), top, top + W);
-            stack.resize(stack.size() - W);
+            const Entry e = stack.back();
+            const int64_t c = n - e.depth;
+            if (K > 0 && nch + c > pool_cap) break;
+            stack.pop_back();
+            const int32_t a = ar.expand(e);
+            prow.resize((size_t)(K + 1) * n);
+            ar.prefix(a, e.depth, prow.data() + K * n);
+            pdep.push_back(e.depth);
+            pidx.push_back(a);
+            ++K;
             nch += c;
         }
-        if (!bound_children(n, parents, svc, prow, pdep, lbs, nch)) {
+        if (!bound_children(n, K, prow, pdep, svc, lbs, nch)) {
             sh.failed = true;
             return;
         }
         if (sh.nodes.fetch_add(nch) + nch >= sh.budget) sh.out_of_budget = true;
         // complete children first (they may lower the bound), then the pushes
-        for_children(n, parents, nch, false, sched, [&](int64_t c, const int32_t *nd, int j) {
-            if (nd[0] + 1 == n && lbs[c] < sh.ub.load()) {
-                std::memcpy(row.data(), nd + 1, (size_t)nd[0] * 4);
-                row[nd[0]] = j;
+        for_children(n, K, prow, pdep, nch, false, sched, [&](int64_t c, int64_t k, int j) {
+            const int d = pdep[k];
+            if (d + 1 == n && lbs[c] < sh.ub.load()) {
+                std::memcpy(row.data(), prow.data() + k * n, (size_t)d * 4);
+                row[d] = j;
                 sh.offer(lbs[c], row.data(), n);
             }
         });
         const int32_t ub = sh.ub.load();
-        for_children(n, parents, nch, true, sched, [&](int64_t c, const int32_t *nd, int j) {
-            if (nd[0] + 1 == n || lbs[c] >= ub) return;
-            const size_t at = stack.size();
-            stack.resize(at + W);
-            stack[at] = nd[0] + 1;
-            std::memcpy(stack.data() + at + 1, nd + 1, (size_t)nd[0] * 4);
-            stack[at + 1 + nd[0]] = j;
+        for_children(n, K, prow, pdep, nch, true, sched, [&](int64_t c, int64_t k, int j) {
+            if (pdep[k] + 1 == n || lbs[c] >= ub) return;
+            stack.push_back(Entry{pidx[k], j, pdep[k] + 1});
         });
     }
 }
@@ -338,45 +381,55 @@ fsp_status fsp_explore(fsp_instance inst, int32_t ub0, int32_t threads, int64_t 
     sh.budget = node_budget;
     res->ub0 = UB;
     BoundService svc(inst, (hipStream_t)stream);
+    // every explorer's pool at once, with about 64 parents each (up to half a
+    // million children; beyond, the buffers grow when needed)
+    const hipError_t pe = svc.presize((int64_t)threads * 64,
+                                      std::min<int64_t>((int64_t)threads * std::max<int64_t>(pool_cap, n), 1 << 19));
+    if (pe != hipSuccess) {
+        svc.stop();
+        return fail_status(pe);
+    }
     svc.start();
 
     // the first levels, breadth first from the root, until there is work for
     // every explorer (the root itself is not bounded: its children are)
-    std::vector<int32_t> level(n + 1, 0);
-    int64_t nodes = 0;
+    std::vector<int32_t> prow(n), pdep(1, 0);  // the level's nodes: rows and depths
+    int64_t nodes = 0, K = 1;
     bool ok = true;
     {
-        std::vector<int32_t> prow, pdep, lbs, next, row(n);
+        std::vector<int32_t> lbs, nrow, ndep, row(n);
         std::vector<unsigned char> sched(n);
-        for (int depth = 0; ok && !level.empty() && depth < n - 1 && (int64_t)level.size() / (n + 1) < 4 * threads;
-             ++depth) {
+        for (int depth = 0; ok && K > 0 && depth < n - 1 && K < 4 * threads; ++depth) {
             int64_t nch = 0;
-            ok = bound_children(n, level, svc, prow, pdep, lbs, nch);
+            ok = bound_children(n, K, prow, pdep, svc, lbs, nch);
             if (!ok) break;
             nodes += nch;
-            next.clear();
-            for_children(n, level, nch, false, sched, [&](int64_t c, const int32_t *nd, int j) {
-                if (nd[0] + 1 == n) {
-                    if (lbs[c] < sh.ub.load()) {
-                        std::memcpy(row.data(), nd + 1, (size_t)nd[0] * 4);
-                        row[nd[0]] = j;
-                        sh.offer(lbs[c], row.data(), n);
-                    }
+            nrow.clear();
+            ndep.clear();
+            for_children(n, K, prow, pdep, nch, false, sched, [&](int64_t c, int64_t k, int j) {
+                const int d = pdep[k];
+                if (lbs[c] >= sh.ub.load()) return;
+                std::memcpy(row.data(), prow.data() + k * n, (size_t)d * 4);
+                row[d] = j;
+                if (d + 1 == n) {
+                    sh.offer(lbs[c], row.data(), n);
                     return;
                 }
-                if (lbs[c] >= sh.ub.load()) return;
-                const size_t at = next.size();
-                next.resize(at + n + 1, 0);
-                next[at] = nd[0] + 1;
-                std::memcpy(next.data() + at + 1, nd + 1, (size_t)nd[0] * 4);
-                next[at + 1 + nd[0]] = j;
+                nrow.insert(nrow.end(), row.begin(), row.end());
+                ndep.push_back(d + 1);
             });
-            level.swap(next);
+            prow.swap(nrow);
+            pdep.swap(ndep);
+            K = (int64_t)pdep.size();
         }
     }
     sh.nodes = nodes;
-    for (size_t at = 0; at < level.size(); at += n + 1)
-        sh.work.push_back(std::vector<int32_t>(level.begin() + at, level.begin() + at + n + 1));
+    for (int64_t k = 0; k < K; ++k) {  // subtree roots: depth, then the prefix
+        std::vector<int32_t> r(1 + pdep[k]);
+        r[0] = pdep[k];
+        std::memcpy(r.data() + 1, prow.data() + k * n, (size_t)pdep[k] * 4);
+        sh.work.push_back(std::move(r));
+    }
     if (ok && nodes >= node_budget && !sh.work.empty()) sh.out_of_budget = true;
 
     std::vector<std::thread> ts;
