@@ -215,6 +215,25 @@ static hipError_t branch_and_bound1(const StepReq *dreq, fsp_instance_s *I, Kids
     return e;
 }
 
+// Phase 1, branching and bounding of the single search in dreq, whose nch
+// children the host has counted: on the incremental path with validation,
+// counts, lists and the leaf step folded into the child launches (the finish
+// then runs with leaves_done), else phase 1 and branch_and_bound1.
+static hipError_t phase1_and_bound1(const StepReq *dreq, const ScanSeg *seg1, fsp_instance_s *I, KidsStep &ks,
+                                    int64_t K, int64_t nch, const StepScratch &w, hipStream_t s, bool *leaves_done)
+{
+    *leaves_done = false;
+    if (ks.on) {
+        hipError_t e = kids16_decode(dreq, 1, K, nch, I->n, I->m, s, seg1);
+        if (e == hipSuccess) e = launch_scan16(I, ks.k.W, nch, w.clb, s);
+        *leaves_done = true;
+        return e;
+    }
+    hipError_t e = mstep_phase1(dreq, seg1, 1, K, s);
+    if (e == hipSuccess) e = branch_and_bound1(dreq, I, ks, K, nch, w, s, true);
+    return e;
+}
+
 hipError_t Search::begin(fsp_instance_s *I, int32_t ub0_in, int64_t pool_cap_in, int64_t node_budget_in,
                          hipStream_t s)
 {
@@ -444,8 +463,9 @@ hipError_t bound_children_of(fsp_instance_s *I, const int32_t *parents, const in
     *(StepReq *)(h + L.req) = q;
     *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
     e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
-    if (e == hipSuccess) e = branch_and_bound1(dentry, I, ks, K, nch, q.w, s, true);
+    bool leaves_done = false;
+    if (e == hipSuccess)
+        e = phase1_and_bound1(dentry, (const ScanSeg *)(d + L.seg1), I, ks, K, nch, q.w, s, &leaves_done);
     return e;
 }
 
@@ -832,10 +852,11 @@ fsp_status best_first_solve(fsp_instance_s *inst, int32_t ub0, int64_t pool_cap,
         *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, K, q.w.nchild, B.sums_k};
         const uint32_t *dnsurv = &dentry->res.nsurv;
         e = hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = mstep_phase1(dentry, (const ScanSeg *)(d + L.seg1), 1, K, s);
+        bool leaves_done = false;
         // parents of mixed depths: the row path sorts its children by depth
-        if (e == hipSuccess) e = branch_and_bound1(dentry, inst, ks, K, nch, q.w, s, true);
-        if (e == hipSuccess) e = mstep_finish(dentry, 1, K, nch, s);
+        if (e == hipSuccess)
+            e = phase1_and_bound1(dentry, (const ScanSeg *)(d + L.seg1), inst, ks, K, nch, q.w, s, &leaves_done);
+        if (e == hipSuccess) e = mstep_finish(dentry, 1, K, nch, s, leaves_done);
         if (e == hipSuccess)
             e = bf_sort_survivors(bf.S(1), dnsurv, nch, UB, bf.S(2), bf.S(3), bf.S(4), bf.S(5), &bf.tmp,
                                   &bf.tmp_bytes, s);
