@@ -62,6 +62,48 @@ hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s)
     return hipMallocFromPoolAsync(ptr, bytes, pool, s);
 }
 
+namespace {
+std::mutex g_pinned_mu;
+std::vector<std::pair<void *, size_t>> g_pinned;  // kept buffers and their capacities
+constexpr size_t kPinnedKeep = 16;
+}  // namespace
+
+hipError_t pinned_get(void **ptr, size_t *cap, size_t bytes)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        size_t best = g_pinned.size();
+        for (size_t i = 0; i < g_pinned.size(); ++i)
+            if (g_pinned[i].second >= bytes && (best == g_pinned.size() || g_pinned[i].second < g_pinned[best].second))
+                best = i;
+        if (best < g_pinned.size()) {
+            *ptr = g_pinned[best].first;
+            *cap = g_pinned[best].second;
+            g_pinned.erase(g_pinned.begin() + (std::ptrdiff_t)best);
+            return hipSuccess;
+        }
+    }
+    *ptr = nullptr;
+    *cap = 0;
+    hipError_t e = hipHostMalloc(ptr, bytes, 0);
+    if (e == hipSuccess) *cap = bytes;
+    else *ptr = nullptr;
+    return e;
+}
+
+void pinned_put(void *ptr, size_t cap)
+{
+    if (!ptr) return;
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        if (g_pinned.size() < kPinnedKeep) {
+            g_pinned.emplace_back(ptr, cap);
+            return;
+        }
+    }
+    hipHostFree(ptr);
+}
+
 void timing_mark(fsp_instance_s *I, int which, hipStream_t s)
 {
     if (!I->timing) return;

@@ -263,12 +263,11 @@ hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStrea
     }
     layout_batch(plan, (char *)dev, meta);
     if (meta.size() > pinned_bytes) {
-        if (pinned) hipHostFree(pinned);
+        pinned_put(pinned, pinned_bytes);
         pinned = nullptr;
         pinned_bytes = 0;
-        hipError_t e = hipHostMalloc(&pinned, meta.size() * 2, 0);
+        hipError_t e = pinned_get(&pinned, &pinned_bytes, meta.size() * 2);
         if (e != hipSuccess) return e;
-        pinned_bytes = meta.size() * 2;
     }
     std::memcpy(pinned, meta.data(), meta.size());
     hipError_t e = hipMemcpyAsync(plan.dmeta, pinned, meta.size(), hipMemcpyHostToDevice, s);
@@ -319,7 +318,7 @@ void BatchArena::release(hipStream_t s)
     dev_bytes = 0;
     if (pinned) {
         hipStreamSynchronize(s);
-        hipHostFree(pinned);
+        pinned_put(pinned, pinned_bytes);
     }
     pinned = nullptr;
     pinned_bytes = 0;

@@ -122,27 +122,30 @@ private:
     hipError_t reserve(int64_t K, int64_t C)
     {
         if (K > capK_) {
-            if (h_par_) hipHostFree(h_par_);
-            if (h_dep_) hipHostFree(h_dep_);
-            if (d_par_) hipFree(d_par_);
-            if (d_dep_) hipFree(d_dep_);
+            // the previous batch ended with a stream synchronization
+            pinned_put(h_par_, hb_par_);
+            pinned_put(h_dep_, hb_dep_);
+            if (d_par_) hipFreeAsync(d_par_, s_);
+            if (d_dep_) hipFreeAsync(d_dep_, s_);
             h_par_ = h_dep_ = d_par_ = d_dep_ = nullptr;
+            hb_par_ = hb_dep_ = 0;
             capK_ = 0;
             const int64_t c = std::max<int64_t>(K, 1024);
             const size_t rb = (size_t)c * I_->n * 4, db = (size_t)c * 4;
-            hipError_t e = hipHostMalloc((void **)&h_par_, rb, 0);
-            if (e == hipSuccess) e = hipHostMalloc((void **)&h_dep_, db, 0);
-            if (e == hipSuccess) e = hipMalloc((void **)&d_par_, rb);
-            if (e == hipSuccess) e = hipMalloc((void **)&d_dep_, db);
+            hipError_t e = pinned_get((void **)&h_par_, &hb_par_, rb);
+            if (e == hipSuccess) e = pinned_get((void **)&h_dep_, &hb_dep_, db);
+            if (e == hipSuccess) e = stream_alloc((void **)&d_par_, rb, s_);
+            if (e == hipSuccess) e = stream_alloc((void **)&d_dep_, db, s_);
             if (e != hipSuccess) return e;
             capK_ = c;
         }
         if (C > capC_) {
-            if (h_lb_) hipHostFree(h_lb_);
+            pinned_put(h_lb_, hb_lb_);
             h_lb_ = nullptr;
+            hb_lb_ = 0;
             capC_ = 0;
             const int64_t c = std::max<int64_t>(C, 4096);
-            hipError_t e = hipHostMalloc((void **)&h_lb_, (size_t)c * 4, 0);
+            hipError_t e = pinned_get((void **)&h_lb_, &hb_lb_, (size_t)c * 4);
             if (e != hipSuccess) return e;
             capC_ = c;
         }
@@ -152,12 +155,13 @@ private:
     void release()
     {
         hipStreamSynchronize(s_);
-        if (h_par_) hipHostFree(h_par_);
-        if (h_dep_) hipHostFree(h_dep_);
-        if (h_lb_) hipHostFree(h_lb_);
-        if (d_par_) hipFree(d_par_);
-        if (d_dep_) hipFree(d_dep_);
+        pinned_put(h_par_, hb_par_);
+        pinned_put(h_dep_, hb_dep_);
+        pinned_put(h_lb_, hb_lb_);
+        if (d_par_) hipFreeAsync(d_par_, s_);
+        if (d_dep_) hipFreeAsync(d_dep_, s_);
         h_par_ = h_dep_ = h_lb_ = d_par_ = d_dep_ = nullptr;
+        hb_par_ = hb_dep_ = hb_lb_ = 0;
         capK_ = capC_ = 0;
         B_.release(s_);
         kids16_release(kids_, s_);
@@ -207,6 +211,7 @@ private:
     hipError_t err_ = hipSuccess;
     int64_t capK_ = 0, capC_ = 0, launches_ = 0;
     int32_t *h_par_ = nullptr, *h_dep_ = nullptr, *h_lb_ = nullptr;
+    size_t hb_par_ = 0, hb_dep_ = 0, hb_lb_ = 0;  // their capacities in bytes
     int32_t *d_par_ = nullptr, *d_dep_ = nullptr;
     StepBuffers B_;
     Kids16 kids_;

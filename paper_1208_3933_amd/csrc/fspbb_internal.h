@@ -95,6 +95,15 @@ void set_last_error(hipError_t e);
 // its peak size until the process ends.
 hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s);
 
+// Pinned host buffers from a small process-wide cache: allocating and freeing
+// pinned memory maps and unmaps pages and can wait for the device (a
+// millisecond or more per call), so released buffers are kept for reuse.
+// pinned_get returns a buffer of at least `bytes` and its capacity in *cap;
+// pinned_put takes it back (the caller has synchronized every copy that
+// reads or writes it).
+hipError_t pinned_get(void **ptr, size_t *cap, size_t bytes);
+void pinned_put(void *ptr, size_t cap);
+
 // Records event `which` (0 = start, 1 = after decode, 2 = after scan) of the
 // current launch when timing is on.  which = 0 opens a new record.
 void timing_mark(fsp_instance_s *I, int which, hipStream_t s);

@@ -95,13 +95,11 @@ hipError_t TickContext::reserve(size_t bytes)
     }
     if (bytes > hcap) {
         // the previous tick ended with a stream synchronization: no copy reads htab
-        if (htab) hipHostFree(htab);
+        pinned_put(htab, hcap);
         htab = nullptr;
         hcap = 0;
-        const size_t c = std::max(bytes, (size_t)64 * 1024);
-        hipError_t e = hipHostMalloc(&htab, c, 0);
+        hipError_t e = pinned_get(&htab, &hcap, std::max(bytes, (size_t)64 * 1024));
         if (e != hipSuccess) return e;
-        hcap = c;
     }
     return hipSuccess;
 }
@@ -112,7 +110,7 @@ void TickContext::release()
     arena.release(s);
     kids.release(s);
     hipStreamSynchronize(s);
-    if (htab) hipHostFree(htab);
+    pinned_put(htab, hcap);
     dtab = htab = nullptr;
     dcap = hcap = 0;
 }
