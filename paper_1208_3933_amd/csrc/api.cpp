@@ -1,6 +1,7 @@
 // C ABI entry points of the bound path (include/fspbb.h).
 #include <cstdint>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 
 #include "fspbb_internal.h"
@@ -29,7 +30,76 @@ struct DeviceGuard {
 
 namespace fspbb {
 
+namespace {
+// Blocks released by stream_free, kept for reuse by a later stream_alloc on
+// the same device and stream (stream order then guarantees that the earlier
+// work on a block is done before the new work starts).  Freeing a block back
+// to the driver's pool costs tens of microseconds to milliseconds of host
+// time per call; a search's set-up and tear-down make about twenty of them.
+struct CachedBlock {
+    void *ptr;
+    size_t cap;
+    int dev;
+    hipStream_t s;
+};
+std::mutex g_blk_mu;
+std::unordered_map<void *, std::pair<size_t, int>> g_live;  // block -> (capacity, device)
+std::vector<CachedBlock> g_cached;
+size_t g_cached_bytes = 0;
+constexpr size_t kCacheBytes = (size_t)16 << 30, kCacheBlocks = 256;
+}  // namespace
+
 hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s)
+{
+    int cdev = 0;
+    hipError_t ce = hipGetDevice(&cdev);
+    if (ce != hipSuccess) return ce;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        size_t best = g_cached.size();
+        for (size_t i = 0; i < g_cached.size(); ++i) {
+            const CachedBlock &c = g_cached[i];
+            if (c.dev != cdev || c.s != s || c.cap < bytes || c.cap > 2 * bytes + ((size_t)1 << 20)) continue;
+            if (best == g_cached.size() || c.cap < g_cached[best].cap) best = i;
+        }
+        if (best < g_cached.size()) {
+            const CachedBlock c = g_cached[best];
+            g_cached.erase(g_cached.begin() + (std::ptrdiff_t)best);
+            g_cached_bytes -= c.cap;
+            g_live[c.ptr] = {c.cap, c.dev};
+            *ptr = c.ptr;
+            return hipSuccess;
+        }
+    }
+    hipError_t e = pool_alloc(ptr, bytes, s);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        g_live[*ptr] = {bytes, cdev};
+    }
+    return e;
+}
+
+hipError_t stream_free(void *ptr, hipStream_t s)
+{
+    if (!ptr) return hipSuccess;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        auto it = g_live.find(ptr);
+        if (it != g_live.end()) {
+            const size_t cap = it->second.first;
+            const int dev = it->second.second;
+            g_live.erase(it);
+            if (g_cached_bytes + cap <= kCacheBytes && g_cached.size() < kCacheBlocks) {
+                g_cached.push_back(CachedBlock{ptr, cap, dev, s});
+                g_cached_bytes += cap;
+                return hipSuccess;
+            }
+        }
+    }
+    return hipFreeAsync(ptr, s);
+}
+
+hipError_t pool_alloc(void **ptr, size_t bytes, hipStream_t s)
 {
     static std::mutex mu;
     static std::map<int, hipMemPool_t> pools;

@@ -254,7 +254,7 @@ hipError_t BatchArena::run(const fsp_pool_desc *pools, int32_t n_pools, hipStrea
     const size_t need = plan.ws_bytes + plan.meta_bytes;
     if (need > dev_bytes) {
         const size_t cap = std::max(need, dev_bytes * 2);
-        if (dev) hipFreeAsync(dev, s);
+        if (dev) stream_free(dev, s);
         dev = nullptr;
         dev_bytes = 0;
         hipError_t e = stream_alloc((void **)&dev, cap, s);
@@ -284,7 +284,7 @@ hipError_t BatchArena::plan_only(const fsp_pool_desc *pools, int32_t n_pools, hi
     plan_batch(pools, n_pools, 0, false, plan, -1, ready);
     if (plan.ws_bytes > dev_bytes) {
         const size_t cap = std::max(plan.ws_bytes, dev_bytes * 2);
-        if (dev) hipFreeAsync(dev, s);
+        if (dev) stream_free(dev, s);
         dev = nullptr;
         dev_bytes = 0;
         hipError_t e = stream_alloc((void **)&dev, cap, s);
@@ -313,7 +313,7 @@ hipError_t BatchArena::launch(hipStream_t s)
 
 void BatchArena::release(hipStream_t s)
 {
-    if (dev) hipFreeAsync(dev, s);
+    if (dev) stream_free(dev, s);
     dev = nullptr;
     dev_bytes = 0;
     if (pinned) {

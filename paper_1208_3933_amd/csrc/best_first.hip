@@ -170,7 +170,7 @@ hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t c
                                            s);
     if (e != hipSuccess) return e;
     if (need > *tmp_bytes) {
-        if (*tmp) hipFreeAsync(*tmp, s);
+        if (*tmp) stream_free(*tmp, s);
         *tmp = nullptr;
         *tmp_bytes = 0;
         e = stream_alloc(tmp, need, s);

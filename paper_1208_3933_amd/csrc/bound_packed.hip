@@ -587,7 +587,7 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
     timing_mark(I, 1, s);
     if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s);
     timing_mark(I, 2, s);
-    hipError_t e2 = hipFreeAsync(ws, s);
+    hipError_t e2 = stream_free(ws, s);
     return e != hipSuccess ? e : e2;
 }
 

@@ -102,7 +102,7 @@ hipError_t launch_wp(fsp_instance_s *I, const int32_t *prefixes, const int32_t *
     wp_scan_kernel<MV><<<(unsigned)((N + 3) / 4), 256, 0, s>>>(I->dt, N, rtq, act, okf, out_lb);
     timing_mark(I, 2, s);
     e = hipGetLastError();
-    hipError_t e2 = hipFreeAsync(ws, s);
+    hipError_t e2 = stream_free(ws, s);
     return e != hipSuccess ? e : e2;
 }
 

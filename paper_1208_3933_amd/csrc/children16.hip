@@ -335,7 +335,7 @@ hipError_t kids16_ensure(Kids16 &k, const fsp_instance_s *I, int64_t K, int64_t 
     k.K = K;
     k.nch = nch;
     if (k.blob && K <= k.capK && nch <= k.capC && I->n == k.n && I->m == k.m) return hipSuccess;
-    if (k.blob) hipFreeAsync(k.blob, s);
+    if (k.blob) stream_free(k.blob, s);
     k.blob = nullptr;
     const int n = I->n, m = I->m, NW = (n + 31) >> 5;
     // both grow by doubling: a search's steps vary by a few children
@@ -401,7 +401,7 @@ hipError_t KidsArena::layout(const std::vector<const fsp_instance_s *> &I, const
     for (size_t i = 0; i < I.size(); ++i) need += KidsSizes(I[i]->n, I[i]->m, K[i], nch[i]).total();
     if (need > cap) {
         const size_t c = std::max(need, 2 * cap);
-        if (blob) hipFreeAsync(blob, s);
+        if (blob) stream_free(blob, s);
         blob = nullptr;
         cap = 0;
         hipError_t e = stream_alloc(&blob, c, s);
@@ -422,14 +422,14 @@ hipError_t KidsArena::layout(const std::vector<const fsp_instance_s *> &I, const
 
 void KidsArena::release(hipStream_t s)
 {
-    if (blob) hipFreeAsync(blob, s);
+    if (blob) stream_free(blob, s);
     blob = nullptr;
     cap = 0;
 }
 
 void kids16_release(Kids16 &k, hipStream_t s)
 {
-    if (k.blob) hipFreeAsync(k.blob, s);
+    if (k.blob) stream_free(k.blob, s);
     k = Kids16{};
 }
 

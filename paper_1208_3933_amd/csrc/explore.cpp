@@ -125,8 +125,8 @@ private:
             // the previous batch ended with a stream synchronization
             pinned_put(h_par_, hb_par_);
             pinned_put(h_dep_, hb_dep_);
-            if (d_par_) hipFreeAsync(d_par_, s_);
-            if (d_dep_) hipFreeAsync(d_dep_, s_);
+            if (d_par_) stream_free(d_par_, s_);
+            if (d_dep_) stream_free(d_dep_, s_);
             h_par_ = h_dep_ = d_par_ = d_dep_ = nullptr;
             hb_par_ = hb_dep_ = 0;
             capK_ = 0;
@@ -158,8 +158,8 @@ private:
         pinned_put(h_par_, hb_par_);
         pinned_put(h_dep_, hb_dep_);
         pinned_put(h_lb_, hb_lb_);
-        if (d_par_) hipFreeAsync(d_par_, s_);
-        if (d_dep_) hipFreeAsync(d_dep_, s_);
+        if (d_par_) stream_free(d_par_, s_);
+        if (d_dep_) stream_free(d_dep_, s_);
         h_par_ = h_dep_ = h_lb_ = d_par_ = d_dep_ = nullptr;
         hb_par_ = hb_dep_ = hb_lb_ = 0;
         capK_ = capC_ = 0;

@@ -88,12 +88,15 @@ hipError_t launch_bound_wavepair(fsp_instance_s *I, const int32_t *prefixes, con
 
 void set_last_error(hipError_t e);
 
-// Stream-ordered device allocation from a library-owned memory pool of the
-// current device whose release threshold is unbounded: memory freed with
-// hipFreeAsync stays in the pool across stream synchronizations and is
-// reused by later calls instead of going back to the driver.  The pool keeps
-// its peak size until the process ends.
+// Stream-ordered device allocation.  stream_free keeps released blocks (up to
+// 16 GiB) for a later stream_alloc on the same device and stream; other
+// requests come from a library-owned memory pool of the current device whose
+// release threshold is unbounded (pool_alloc; memory freed to it stays in it
+// across stream synchronizations).  Every block from stream_alloc is released
+// with stream_free, on the stream whose work last used it.
 hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s);
+hipError_t stream_free(void *ptr, hipStream_t s);
+hipError_t pool_alloc(void **ptr, size_t bytes, hipStream_t s);
 
 // Pinned host buffers from a small process-wide cache: allocating and freeing
 // pinned memory maps and unmaps pages and can wait for the device (a

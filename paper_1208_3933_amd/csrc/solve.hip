@@ -33,7 +33,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 hipError_t StepBuffers::ensure_k(int64_t K, hipStream_t s)
 {
     if (kblob && K <= Kcap) return hipSuccess;
-    if (kblob) hipFreeAsync(kblob, s);
+    if (kblob) stream_free(kblob, s);
     kblob = nullptr;
     Kcap = std::max<int64_t>(K, 1);
     const size_t kb = al256((size_t)Kcap * 4), sb = al256(scan_scratch_bytes(Kcap));
@@ -49,7 +49,7 @@ hipError_t StepBuffers::ensure_k(int64_t K, hipStream_t s)
 hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
 {
     if (cblob && C <= Ccap && n_ == n) return hipSuccess;
-    if (cblob) hipFreeAsync(cblob, s);
+    if (cblob) stream_free(cblob, s);
     cblob = nullptr;
     Ccap = std::max<int64_t>(C, 1);
     n = n_;
@@ -71,8 +71,8 @@ hipError_t StepBuffers::ensure_c(int64_t C, int n_, hipStream_t s)
 
 void StepBuffers::release(hipStream_t s)
 {
-    if (kblob) hipFreeAsync(kblob, s);
-    if (cblob) hipFreeAsync(cblob, s);
+    if (kblob) stream_free(kblob, s);
+    if (cblob) stream_free(cblob, s);
     kblob = cblob = nullptr;
     Kcap = Ccap = 0;
 }
@@ -85,7 +85,7 @@ size_t StepBuffers::bytes() const
 hipError_t TickContext::reserve(size_t bytes)
 {
     if (bytes > dcap) {
-        if (dtab) hipFreeAsync(dtab, s);
+        if (dtab) stream_free(dtab, s);
         dtab = nullptr;
         dcap = 0;
         const size_t c = std::max(bytes, (size_t)64 * 1024);
@@ -106,7 +106,7 @@ hipError_t TickContext::reserve(size_t bytes)
 
 void TickContext::release()
 {
-    if (dtab) hipFreeAsync(dtab, s);
+    if (dtab) stream_free(dtab, s);
     arena.release(s);
     kids.release(s);
     hipStreamSynchronize(s);
@@ -322,9 +322,9 @@ hipError_t start_many(std::vector<Search *> &ss, const std::vector<StartArgs> &a
 
 void Search::release(hipStream_t s)
 {
-    if (srows) hipFreeAsync(srows, s);
-    if (sdep) hipFreeAsync(sdep, s);
-    if (dinc) hipFreeAsync(dinc, s);
+    if (srows) stream_free(srows, s);
+    if (sdep) stream_free(sdep, s);
+    if (dinc) stream_free(dinc, s);
     srows = sdep = dinc = nullptr;
     B.release(s);
 }
@@ -378,12 +378,12 @@ static hipError_t prepare_step(Search &S, hipStream_t s)
         if (e == hipSuccess) e = hipMemcpyAsync(r2, S.srows, (size_t)S.top * S.n * 4, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(d2, S.sdep, (size_t)S.top * 4, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) {
-            if (r2) hipFreeAsync(r2, s);
-            if (d2) hipFreeAsync(d2, s);
+            if (r2) stream_free(r2, s);
+            if (d2) stream_free(d2, s);
             return e;
         }
-        hipFreeAsync(S.srows, s);
-        hipFreeAsync(S.sdep, s);
+        stream_free(S.srows, s);
+        stream_free(S.sdep, s);
         S.srows = r2;
         S.sdep = d2;
         S.cap_stack = nc;
@@ -707,10 +707,10 @@ struct BestFirst {
         if (e == hipSuccess && M > 0) e = hipMemcpyAsync(b.depth, a.depth, (size_t)M * 4, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && M > 0) e = hipMemcpyAsync(b.slot, a.slot, (size_t)M * 4, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
-        hipFreeAsync(slab, s);
-        hipFreeAsync(fl, s);
-        hipFreeAsync(rec[0], s);
-        hipFreeAsync(rec[1], s);
+        stream_free(slab, s);
+        stream_free(fl, s);
+        stream_free(rec[0], s);
+        stream_free(rec[1], s);
         slab = slab2;
         fl = fl2;
         rec[cur] = r0;
@@ -723,7 +723,7 @@ struct BestFirst {
     hipError_t ensure_survivors(int64_t cap)
     {
         if (cap <= Scap) return hipSuccess;
-        if (sbuf) hipFreeAsync(sbuf, s);
+        if (sbuf) stream_free(sbuf, s);
         sbuf = nullptr;
         Scap = std::max<int64_t>(cap, 1024);
         hipError_t e = stream_alloc((void **)&sbuf, (size_t)Scap * 6 * 4, s);
@@ -735,7 +735,7 @@ struct BestFirst {
     {
         for (void *ptr : {(void *)slab, (void *)fl, (void *)rec[0], (void *)rec[1], (void *)sbuf, tmp, (void *)sel,
                           (void *)dinc})
-            if (ptr) hipFreeAsync(ptr, s);
+            if (ptr) stream_free(ptr, s);
         slab = fl = nullptr;
         rec[0] = rec[1] = sbuf = dinc = nullptr;
         tmp = nullptr;
