@@ -443,6 +443,18 @@ fsp_status fsp_timing_enable(fsp_instance inst, int32_t on);
 fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms, int64_t *launches);
 
 /*
+ * fsp_release_cached - memory management (not an operation of the method).
+ * Device scratch that calls release is kept for reuse by later calls on the
+ * same device and stream (at most 16 GiB), and freed memory stays in the
+ * library's pool.  This call waits for every device that holds such memory,
+ * frees the kept blocks and trims the pools, returning the memory to the
+ * driver.  Calls that run concurrently may keep new blocks afterwards.  A
+ * stream whose work used library scratch should be synchronized before it is
+ * destroyed.  Returns FSP_OK or FSP_E_DEVICE.
+ */
+fsp_status fsp_release_cached(void);
+
+/*
  * Peak probes (measurement support; not an operation of the method).  Each
  * runs one kernel built to saturate one unit of the current device, three
  * times untimed and five times timed with HIP events on `stream`, and returns

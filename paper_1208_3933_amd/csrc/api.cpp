@@ -99,10 +99,15 @@ hipError_t stream_free(void *ptr, hipStream_t s)
     return hipFreeAsync(ptr, s);
 }
 
+namespace {
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;  // per device
+}  // namespace
+
 hipError_t pool_alloc(void **ptr, size_t bytes, hipStream_t s)
 {
-    static std::mutex mu;
-    static std::map<int, hipMemPool_t> pools;
+    std::mutex &mu = g_pool_mu;
+    std::map<int, hipMemPool_t> &pools = g_pools;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -275,6 +280,42 @@ fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms
     if (scan_ms) *scan_ms = ssum;
     if (launches) *launches = cnt;
     if (err != hipSuccess) { set_last_error(err); return FSP_E_DEVICE; }
+    return FSP_OK;
+}
+
+fsp_status fsp_release_cached(void)
+{
+    std::vector<CachedBlock> blocks;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        blocks.swap(g_cached);
+        g_cached_bytes = 0;
+    }
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return FSP_E_DEVICE;
+    hipError_t err = hipSuccess;
+    std::map<int, bool> synced;
+    for (const CachedBlock &c : blocks) {
+        hipError_t e = hipSetDevice(c.dev);
+        if (e == hipSuccess && !synced[c.dev]) e = hipDeviceSynchronize();  // the blocks' streams may be gone
+        synced[c.dev] = true;
+        if (e == hipSuccess) e = hipFreeAsync(c.ptr, nullptr);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (auto &dp : g_pools) {
+            hipError_t e = hipSetDevice(dp.first);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = hipMemPoolTrimTo(dp.second, 0);
+            if (e != hipSuccess && err == hipSuccess) err = e;
+        }
+    }
+    hipSetDevice(cur);
+    if (err != hipSuccess) {
+        set_last_error(err);
+        return FSP_E_DEVICE;
+    }
     return FSP_OK;
 }
 

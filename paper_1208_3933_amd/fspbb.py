@@ -152,6 +152,7 @@ _SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_int64)]),
     "fsp_probe_peak": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
+    "fsp_release_cached": (ctypes.c_int32, []),
 }
 
 
@@ -304,6 +305,11 @@ def timing_read(inst: Instance):
     _check(lib().fsp_timing_read(inst.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "fsp_timing_read")
     return a.value, b.value, int(c.value)
+
+
+def release_cached() -> None:
+    """Returns the device scratch the library keeps for reuse to the driver."""
+    _check(lib().fsp_release_cached(), "fsp_release_cached")
 
 
 PROBE_VALU16, PROBE_VALU32, PROBE_LDS, PROBE_HBM = 0, 1, 2, 3

@@ -210,3 +210,21 @@ def test_solve_root_pruned_and_budget():
         assert (r["perm"] == -1).all()
         r = fspbb.solve(inst, fspbb.UB_NONE, 4, 30)
         assert r["status"] == fspbb.BUDGET and not r["proven"] and r["nodes_bounded"] >= 30
+
+
+def test_release_cached_returns_memory_and_keeps_results():
+    """Scratch kept for reuse goes back to the driver, and searches after it
+    give the same results."""
+    torch = require_gpu()
+    p = gen.processing_times(200, 20, gen.make_seed(2, 0, gen.PURPOSE_TIMES))
+    with fspbb.create_instance(p) as inst:
+        a = fspbb.solve(inst, fspbb.UB_NEH, 262144, 1 + 2 * 262144)  # keeps a 1.6 GB stack among others
+        torch.cuda.synchronize()
+        free0, _ = torch.cuda.mem_get_info()
+        fspbb.release_cached()
+        free1, _ = torch.cuda.mem_get_info()
+        b = fspbb.solve(inst, fspbb.UB_NEH, 262144, 1 + 2 * 262144)
+        fspbb.release_cached()
+    assert free1 >= free0 + (1 << 30)
+    for f in ("opt", "nodes_bounded", "steps", "improvements", "max_stack", "status"):
+        assert a[f] == b[f], f
