@@ -7,7 +7,9 @@
 //     record finds its output position by a binary search in the other one
 //     (earlier insertion first on equal bounds).
 // Only 12-byte records move; rows stay in their slab slots.
-#include <hipcub/hipcub.hpp>
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "best_first.h"
 #include "fspbb_internal.h"
@@ -164,10 +166,15 @@ hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t c
     bf_keys_kernel<<<blocks256(cap), 256, 0, s>>>(lb, nsurv, cap, pad, keys, ranks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // a stable LSD radix sort (onesweep) at every size: the library default
+    // below a million items is a merge sort, whose log2(cap / 2048) passes
+    // cost about 80 us at 262,144 items against a few passes of 8 bits
+    using Cfg = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                           rocprim::default_config, 0>;
     size_t need = 0;
-    e = hipcub::DeviceRadixSort::SortPairs(nullptr, need, reinterpret_cast<const uint32_t *>(keys),
-                                           reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int)cap, 0, bits,
-                                           s);
+    e = rocprim::radix_sort_pairs<Cfg>(nullptr, need, reinterpret_cast<const uint32_t *>(keys),
+                                       reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int64_t)cap, 0u,
+                                       (unsigned)bits, s);
     if (e != hipSuccess) return e;
     if (need > *tmp_bytes) {
         if (*tmp) stream_free(*tmp, s);
@@ -177,9 +184,9 @@ hipError_t bf_sort_survivors(const int32_t *lb, const uint32_t *nsurv, int64_t c
         if (e != hipSuccess) return e;
         *tmp_bytes = need;
     }
-    return hipcub::DeviceRadixSort::SortPairs(*tmp, need, reinterpret_cast<const uint32_t *>(keys),
-                                              reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int)cap, 0,
-                                              bits, s);
+    return rocprim::radix_sort_pairs<Cfg>(*tmp, need, reinterpret_cast<const uint32_t *>(keys),
+                                          reinterpret_cast<uint32_t *>(keys_out), ranks, rank_out, (int64_t)cap, 0u,
+                                          (unsigned)bits, s);
 }
 
 hipError_t bf_merge(const Frontier &F, int64_t a0, int64_t nA, const int32_t *kb, const int32_t *rk,
