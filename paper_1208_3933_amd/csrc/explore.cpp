@@ -92,7 +92,7 @@ public:
     }
 
     hipError_t error() const { return err_; }
-    int64_t launches() const { return launches_; }
+    int64_t launches() const { return launches_.load(); }
 
 private:
     void loop()
@@ -209,7 +209,8 @@ private:
     std::deque<PoolReq *> q_;
     bool stop_ = false;
     hipError_t err_ = hipSuccess;
-    int64_t capK_ = 0, capC_ = 0, launches_ = 0;
+    int64_t capK_ = 0, capC_ = 0;
+    std::atomic<int64_t> launches_{0};  // read by the caller while the thread may run
     int32_t *h_par_ = nullptr, *h_dep_ = nullptr, *h_lb_ = nullptr;
     size_t hb_par_ = 0, hb_dep_ = 0, hb_lb_ = 0;  // their capacities in bytes
     int32_t *d_par_ = nullptr, *d_dep_ = nullptr;
