@@ -450,7 +450,8 @@ fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms
  * frees the kept blocks and trims the pools, returning the memory to the
  * driver.  Calls that run concurrently may keep new blocks afterwards.  A
  * stream whose work used library scratch should be synchronized before it is
- * destroyed.  Returns FSP_OK or FSP_E_DEVICE.
+ * destroyed.  Returns FSP_OK (at once when the process has allocated
+ * nothing) or FSP_E_DEVICE.
  */
 fsp_status fsp_release_cached(void);
 

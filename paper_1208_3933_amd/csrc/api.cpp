@@ -291,6 +291,10 @@ fsp_status fsp_release_cached(void)
         blocks.swap(g_cached);
         g_cached_bytes = 0;
     }
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (blocks.empty() && g_pools.empty()) return FSP_OK;  // nothing was ever allocated
+    }
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess) return FSP_E_DEVICE;
     hipError_t err = hipSuccess;

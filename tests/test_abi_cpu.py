@@ -67,6 +67,7 @@ def test_null_arguments():
     assert L.fsp_destroy_instance(None) == fspbb.OK
     assert L.fsp_get_instance_info(None, None) == fspbb.E_INVAL
     assert L.fsp_pool_status(None, None, None) == fspbb.E_INVAL
+    assert L.fsp_release_cached() == fspbb.OK  # nothing allocated in this process
     rate = ctypes.c_double()
     assert L.fsp_probe_peak(fspbb.PROBE_VALU16, 0, None, None, None) == fspbb.E_INVAL
     for kind, nbytes in [(-1, 1 << 20), (4, 1 << 20), (fspbb.PROBE_HBM, 1 << 19), (fspbb.PROBE_HBM, (1 << 20) + 8)]:
