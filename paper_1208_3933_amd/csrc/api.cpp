@@ -72,6 +72,30 @@ hipError_t stream_alloc(void **ptr, size_t bytes, hipStream_t s)
         }
     }
     hipError_t e = pool_alloc(ptr, bytes, s);
+    if (e == hipErrorOutOfMemory) {
+        // kept blocks of this device go back to the pool, then one more try
+        std::vector<CachedBlock> mine;
+        {
+            std::lock_guard<std::mutex> lk(g_blk_mu);
+            for (size_t i = 0; i < g_cached.size();) {
+                if (g_cached[i].dev == cdev) {
+                    mine.push_back(g_cached[i]);
+                    g_cached_bytes -= g_cached[i].cap;
+                    g_cached.erase(g_cached.begin() + (std::ptrdiff_t)i);
+                } else {
+                    ++i;
+                }
+            }
+        }
+        if (!mine.empty()) {
+            hipGetLastError();  // clear the failed allocation's error
+            hipError_t se = hipDeviceSynchronize();  // their streams may be gone
+            for (const CachedBlock &c : mine)
+                if (se == hipSuccess) se = hipFreeAsync(c.ptr, nullptr);
+            if (se == hipSuccess) se = hipDeviceSynchronize();
+            e = se == hipSuccess ? pool_alloc(ptr, bytes, s) : se;
+        }
+    }
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(g_blk_mu);
         g_live[*ptr] = {bytes, cdev};
