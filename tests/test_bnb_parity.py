@@ -19,7 +19,8 @@ def inst_times(n, m, seed, lo=1, hi=99):
 
 # --- NEH ----------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,m,seed", [(5, 3, 1), (12, 5, 2), (20, 20, 3), (50, 10, 4), (100, 20, 5), (200, 20, 6)])
+@pytest.mark.parametrize("n,m,seed", [(5, 3, 1), (12, 5, 2), (20, 20, 3), (50, 10, 4), (100, 20, 5), (200, 20, 6),
+                                      (512, 32, 7)])
 def test_neh_matches_oracle(n, m, seed):
     require_gpu()
     p = inst_times(n, m, seed)
@@ -67,10 +68,25 @@ def expected_step(p, parents, depths, ub_in):
                                                 (20, 5, 64, 3, "neh"), (50, 10, 40, 4, "neh"),
                                                 (12, 6, 50, 5, "deep"), (200, 20, 120, 6, "none"),
                                                 (50, 19, 150, 7, "none"), (300, 32, 16, 8, "none"),
-                                                (30, 7, 400, 9, "deep")])
+                                                (30, 7, 400, 9, "deep"), (512, 32, 4, 10, "none"),
+                                                (512, 32, 3, 11, "deep")])
 def test_branch_and_prune_step(n, m, K, seed, ub_mode):
+    check_step(inst_times(n, m, seed), K, seed, ub_mode)
+
+
+# Processing times up to 100,000 put the instance on the 32-bit path, whose
+# children are bounded from their rows; the largest shape is the limit of
+# both jobs and machines.
+@pytest.mark.parametrize("n,m,K,seed,ub_mode", [(20, 5, 30, 12, "neh"), (50, 10, 40, 13, "none"),
+                                                (512, 32, 3, 14, "none"), (40, 6, 200, 15, "deep")])
+def test_branch_and_prune_step_32bit(n, m, K, seed, ub_mode):
+    p = inst_times(n, m, seed, 1, 100000)
+    check_step(p, K, seed, ub_mode, packed16=0)
+
+
+def check_step(p, K, seed, ub_mode, packed16=1):
     torch = require_gpu()
-    p = inst_times(n, m, seed)
+    n = p.shape[0]
     if ub_mode == "deep":
         pre, dep = gen.random_pool(n, K, gen.make_seed(41, seed, 1), n - 2, n)
     else:
@@ -81,6 +97,7 @@ def test_branch_and_prune_step(n, m, K, seed, ub_mode):
     want = expected_step(p, pre, dep, ub_in)
     cap = max(want["n_children"], 1)
     with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == packed16
         pre_d, dep_d = to_dev(torch, pre, dep)
         rows = torch.full((cap, n), -9, dtype=torch.int32, device="cuda")
         cdep = torch.full((cap,), -9, dtype=torch.int32, device="cuda")

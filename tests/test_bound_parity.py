@@ -109,13 +109,27 @@ def test_two_machines_is_exact(variant):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("n,m,lo,hi", [(1, 2, 1, 99), (1, 32, 1, 99), (33, 32, 1, 99), (64, 3, 1, 3),
-                                       (65, 17, 1, 99), (512, 4, 1, 30), (96, 20, 1, 2)])
+                                       (65, 17, 1, 99), (512, 4, 1, 30), (96, 20, 1, 2), (512, 32, 1, 99)])
 def test_shape_and_value_edges(variant, n, m, lo, hi):
     torch = require_gpu()
     p = gen.processing_times(n, m, gen.make_seed(14, n * 100 + m, 0), lo, hi)
     pre, dep = gen.random_pool(n, 400, gen.make_seed(14, n * 100 + m, 1), 0, n)
     want = oracle_bounds(p, pre, dep)
     with fspbb.create_instance(p) as inst:
+        assert (gpu_bounds(torch, inst, pre, dep, variant) == want).all()
+
+
+@pytest.mark.parametrize("variant", [fspbb.VARIANT_AUTO, fspbb.VARIANT_WAVEPAIR])
+def test_largest_shape_on_the_32bit_kernel(variant):
+    """512 jobs and 32 machines, the limits of both, with values that need
+    32-bit arithmetic (max_value 543 x 100,000)."""
+    torch = require_gpu()
+    n, m = 512, 32
+    p = gen.processing_times(n, m, gen.make_seed(15, 1, 0), 1, 100000)
+    pre, dep = gen.random_pool(n, 300, gen.make_seed(15, 1, 1), 0, n)
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 0
         assert (gpu_bounds(torch, inst, pre, dep, variant) == want).all()
 
 
