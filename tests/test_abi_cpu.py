@@ -114,3 +114,13 @@ def test_create_instance_pairs_rejects_bad_pair_lists():
                                          ctypes.byref(h))
         assert st == fspbb.E_INVAL and not h.value, pairs
     assert L.fsp_create_instance_pairs(pp, 6, 4, None, 1, 0, ctypes.byref(ctypes.c_void_p())) == fspbb.E_INVAL
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """With no built library every call raises: there is no fallback path."""
+    monkeypatch.setattr(fspbb, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libfspbb.so"))
+    monkeypatch.setattr(fspbb, "_lib", None)
+    with pytest.raises(RuntimeError, match="is missing"):
+        fspbb.lib()
+    with pytest.raises(RuntimeError, match="is missing"):
+        fspbb.create_instance(np.ones((5, 3), np.int32))
