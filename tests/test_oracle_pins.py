@@ -353,6 +353,165 @@ def test_bnb_steplog_consistency():
     assert int(log[-1, 4]) == 0
 
 
+# --- depth-first order rules and NEH ties, worked by hand ------------------------
+
+# Three jobs on two machines, p[j] = (time on machine 0, time on machine 1).
+DFS_P = np.array([[3, 2], [1, 4], [2, 3]], np.int32)
+
+
+def test_dfs_hand_worked_bounds():
+    """The bounds the hand-worked traces below use.  With two machines the
+    bound of a node is the least makespan over its completions (one pair,
+    no lag, no tail), so every value is a minimum over the six schedules:
+
+        012: machine 0 ends 3,4,6; machine 1 ends 5, max(5,4)+4=9,  max(9,6)+3=12
+        021: 3,5,6; 5, max(5,5)+3=8,  max(8,6)+4=12
+        102: 1,4,6; 5, max(5,4)+2=7,  max(7,6)+3=10
+        120: 1,3,6; 5, max(5,3)+3=8,  max(8,6)+2=10
+        201: 2,5,6; 5, max(5,5)+2=7,  max(7,6)+4=11
+        210: 2,3,6; 5, max(5,3)+4=9,  max(9,6)+2=11
+
+    root 10 (Johnson: 1, 2 with a <= b by a, then 0); (0) 12, (1) 10, (2) 11;
+    (0,1) (0,2) 12; (1,0) (1,2) 10; (2,0) (2,1) 11."""
+    want = {(): 10, (0,): 12, (1,): 10, (2,): 11, (0, 1): 12, (0, 2): 12, (1, 0): 10,
+            (1, 2): 10, (2, 0): 11, (2, 1): 11, (0, 1, 2): 12, (0, 2, 1): 12, (1, 0, 2): 10,
+            (1, 2, 0): 10, (2, 0, 1): 11, (2, 1, 0): 11}
+    for pre, v in want.items():
+        assert oracle.bound(DFS_P, pre) == v, pre
+
+
+def test_dfs_hand_worked_trace_pool_cap_1():
+    """UB0 = 100 (no incumbent), pool_cap 1: one parent per step.
+
+    Step log columns: parents, children, UB after the step, pushed, stack
+    size, fingerprint (sum over pushes of push number x (appended job + 1)).
+    Survivors are pushed last child first, so the first child is on top, and
+    a popped node is expanded without a second test against the bound.
+
+     1. root -> (0) 12, (1) 10, (2) 11; all < 100; push (2), (1), (0):
+        fp 1*3 + 2*2 + 3*1 = 10; stack [(2) (1) (0)]
+     2. (0) -> (0,1) 12, (0,2) 12; push (0,2), (0,1): fp 1*3 + 2*2 = 7; stack 4
+     3. (0,1) -> leaf (0,1,2) = 12 < 100: UB 12, incumbent 012; stack 3
+     4. (0,2) -> leaf (0,2,1) = 12, not < 12; stack 2
+     5. (1) -> (1,0) 10, (1,2) 10, both < 12; push (1,2), (1,0): fp 1*3 + 2*1 = 5
+     6. (1,0) -> leaf (1,0,2) = 10 < 12: UB 10, incumbent 102; stack 2
+     7. (1,2) -> leaf (1,2,0) = 10, not < 10; stack 1
+     8. (2) -> (2,0) 11, (2,1) 11, both >= 10: none pushed; stack 0, proven.
+    Nodes: 1 + 3 + 2 + 1 + 1 + 2 + 1 + 1 + 2 = 14."""
+    r = oracle.bnb(DFS_P, 100, None, pool_cap=1, steplog_cap=64)
+    assert r["steplog"].tolist() == [
+        [1, 3, 100, 3, 3, 10], [1, 2, 100, 2, 4, 7], [1, 1, 12, 0, 3, 0], [1, 1, 12, 0, 2, 0],
+        [1, 2, 12, 2, 3, 5], [1, 1, 10, 0, 2, 0], [1, 1, 10, 0, 1, 0], [1, 2, 10, 0, 0, 0]]
+    assert (r["ub"], r["proven"], r["nodes_bounded"], r["steps"]) == (10, True, 14, 8)
+    assert (r["improvements"], r["max_stack"]) == (2, 4)
+    assert r["incumbent"].tolist() == [1, 0, 2]
+
+
+def test_dfs_hand_worked_trace_pool_cap_2():
+    """UB0 = 100, pool_cap 2: parents are popped while the children so far
+    plus the next parent's fit in 2 (the first parent always).
+
+     1. root (3 children, first) -> as with pool_cap 1; stack [(2) (1) (0)]
+     2. (0): 2 children; (1) would make 4 > 2, stop -> (0,1) 12, (0,2) 12,
+        pushed (0,2), (0,1): fp 7; stack 4
+     3. (0,1) then (0,2): 1 + 1 = 2 fits; (1) would make 4 -> leaves 012 = 12
+        (first in child order: UB 12, incumbent 012) and 021 = 12; stack 2
+     4. (1) alone -> (1,0) 10, (1,2) 10, pushed (1,2), (1,0): fp 5; stack 3
+     5. (1,0) then (1,2) -> leaves 102 = 10 (UB 10, incumbent 102), 120 = 10;
+        stack 1
+     6. (2) -> (2,0) 11, (2,1) 11, eliminated; stack 0.
+    Nodes 1 + 3 + 2 + 2 + 2 + 2 + 2 = 14 in 6 steps."""
+    r = oracle.bnb(DFS_P, 100, None, pool_cap=2, steplog_cap=64)
+    assert r["steplog"].tolist() == [
+        [1, 3, 100, 3, 3, 10], [1, 2, 100, 2, 4, 7], [2, 2, 12, 0, 2, 0],
+        [1, 2, 12, 2, 3, 5], [2, 2, 10, 0, 1, 0], [1, 2, 10, 0, 0, 0]]
+    assert (r["ub"], r["proven"], r["nodes_bounded"], r["steps"]) == (10, True, 14, 6)
+    assert r["incumbent"].tolist() == [1, 0, 2]
+
+
+def test_dfs_hand_worked_trace_tight_ub():
+    """UB0 = 11 with the incumbent 201, pool_cap 1.
+
+     1. root 10 < 11 -> (0) 12, (1) 10, (2) 11: only (1) is below 11;
+        pushed (1): fp 1*2 = 2; stack 1
+     2. (1) -> (1,0) 10, (1,2) 10, pushed (1,2), (1,0): fp 1*3 + 2*1 = 5
+     3. (1,0) -> leaf 102 = 10 < 11: UB 10, incumbent 102; stack 1
+     4. (1,2) -> leaf 120 = 10, not < 10; stack 0.
+    A forward push would pop (1,2) first and keep the incumbent 120."""
+    r = oracle.bnb(DFS_P, 11, [2, 0, 1], pool_cap=1, steplog_cap=64)
+    assert r["steplog"].tolist() == [
+        [1, 3, 11, 1, 1, 2], [1, 2, 11, 2, 2, 5], [1, 1, 10, 0, 1, 0], [1, 1, 10, 0, 0, 0]]
+    assert (r["ub"], r["proven"], r["nodes_bounded"], r["steps"]) == (10, True, 8, 4)
+    assert r["incumbent"].tolist() == [1, 0, 2]
+    # the root pruned at once: UB0 equal to its bound (elimination is bound >= UB)
+    r = oracle.bnb(DFS_P, 10, [1, 0, 2], pool_cap=1, steplog_cap=64)
+    assert (r["nodes_bounded"], r["steps"], r["proven"]) == (1, 0, True)
+    assert r["incumbent"].tolist() == [1, 0, 2]
+
+
+def test_dfs_hand_worked_mixed_step():
+    """A step holding a leaf and an inner node: survivors are tested against
+    the upper bound after the step's leaves have lowered it.
+
+    p: job 0 (4,5), job 1 (3,5), job 2 (5,4), job 3 (5,2) on two machines.
+    Johnson: a <= b jobs 1, 0 by a, then a > b jobs 2, 3 by decreasing b, so
+    the optimum is 1023: machine 0 ends 3,7,12,17, machine 1 ends 8, 13,
+    max(13,12)+4 = 17, max(17,17)+2 = 19.  A node's bound is its best
+    completion, i.e. the node's prefix followed by the rest in that order:
+    (0) 0123 = 20 (m1: 9,14,18,20); (1) 19; (2) 2103 = 21 (m0 5,8,12,17;
+    m1 9,14,19,21); (3) 3102 = 22 (m1 7,13,18,22); (1,0) 19; (1,2) 1203 = 19
+    (m1 8,12,17,19); (1,3) 1302 = 21 (m1 8,10,17,21); (1,0,2) 19; (1,0,3)
+    1032 = 21 (m1 8,13,15,21); (1,2,0) 19; (1,2,3) 1230 = 22 (m1 8,12,15,22).
+
+    UB0 = 20, pool_cap 3:
+     1. root -> (0) 20, (1) 19, (2) 21, (3) 22: only (1) < 20; fp 1*2
+     2. (1) -> (1,0) 19, (1,2) 19, (1,3) 21: push (1,2), (1,0); fp 1*3 + 2*1
+     3. (1,0) (the next would make 4 > 3) -> (1,0,2) 19, (1,0,3) 21:
+        push (1,0,2); fp 1*3
+     4. (1,0,2) then (1,2) (1 + 2 = 3 fits) -> leaf 1023 = 19 < 20 sets UB
+        19, so (1,2,0) 19 and (1,2,3) 22 are eliminated; stack empty.
+    Testing survivors against the bound from before the step would keep
+    (1,2,0) and take a fifth step."""
+    p = np.array([[4, 5], [3, 5], [5, 4], [5, 2]], np.int32)
+    r = oracle.bnb(p, 20, None, pool_cap=3, steplog_cap=64)
+    assert r["steplog"].tolist() == [
+        [1, 4, 20, 1, 1, 2], [1, 3, 20, 2, 2, 5], [1, 2, 20, 1, 2, 3], [2, 3, 19, 0, 0, 0]]
+    assert (r["ub"], r["proven"], r["nodes_bounded"], r["steps"]) == (19, True, 13, 4)
+    assert r["incumbent"].tolist() == [1, 0, 2, 3]
+
+
+def test_neh_hand_worked_ties():
+    """NEH on four jobs and three machines, worked by hand.
+
+    p: job 0 (5,1,5), job 1 (2,5,4), job 2 (2,6,5), job 3 (5,1,4).  Totals
+    11, 11, 13, 10, so the insertion order is 2, 0, 1, 3 (jobs 0 and 1 tie on
+    11 and go by increasing id).  Completion times (machines 0,1,2) per job:
+
+    - insert 0 into [2]: [0,2] -> (5,6,11), (7,13,18) = 18; [2,0] -> (2,8,13),
+      (7,9,18) = 18.  A tie: the earliest position gives [0,2].
+    - insert 1 into [0,2]: [1,0,2] -> (2,7,11) (7,8,16) (9,15,21) = 21;
+      [0,1,2] -> (5,6,11) (7,12,16) (9,18,23) = 23; [0,2,1] -> (5,6,11)
+      (7,13,18) (9,18,22) = 22.  Best [1,0,2].
+    - insert 3 into [1,0,2]: [3,1,0,2] -> (5,6,10) (7,12,16) (12,13,21)
+      (14,20,26) = 26; [1,3,0,2] -> (2,7,11) (7,8,15) (12,13,20) (14,20,25) =
+      25; [1,0,3,2] -> (2,7,11) (7,8,16) (12,13,20) (14,20,25) = 25;
+      [1,0,2,3] -> (2,7,11) (7,8,16) (9,15,21) (14,16,25) = 25.  A three-way
+      tie: the earliest position gives [1,3,0,2], makespan 25.
+
+    Taking the latest position on ties instead starts from [2,0] and ends at
+    makespan 26, and so does ordering tied totals by decreasing id (insertion
+    order 2, 1, 0, 3); the schedule found here is optimal (brute force 25)."""
+    p = np.array([[5, 1, 5], [2, 5, 4], [2, 6, 5], [5, 1, 4]], np.int32)
+    ms, perm = oracle.neh(p)
+    assert ms == 25
+    assert perm.tolist() == [1, 3, 0, 2]
+    assert oracle.makespan(p, [0, 2]) == oracle.makespan(p, [2, 0]) == 18
+    assert [oracle.makespan(p, s) for s in ([1, 0, 2], [0, 1, 2], [0, 2, 1])] == [21, 23, 22]
+    assert [oracle.makespan(p, s) for s in ([3, 1, 0, 2], [1, 3, 0, 2], [1, 0, 3, 2], [1, 0, 2, 3])] \
+        == [26, 25, 25, 25]
+    assert oracle.brute(p) == 25
+
+
 # --- heads variant: machine releases as earliest starting times (Table I RM) ----
 
 def test_heads_hand_worked_example():
