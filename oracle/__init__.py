@@ -154,7 +154,7 @@ def bound_counted(p, prefix):
 
 
 def pair_scan(p, prefix, k: int, l: int):
-    """(timeOnM2 after the scan of pair (k,l), tail of machine l)."""
+    """(finishing time on machine l after the scan of pair (k,l), tail of machine l)."""
     p, n, m = _mat(p)
     s = _seq(prefix)
     buf = np.zeros(max(n, 1), np.int32)

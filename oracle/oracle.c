@@ -147,17 +147,18 @@ static keyed_job johnson_fields(int32_t j, int64_t a, int64_t b, int64_t L, int6
  * (k,l), k<l, the maximum is taken over. */
 typedef struct { int heads; const unsigned char *pairsel; } orc_variant;
 
-/* The lower bound of Sec. II-D / Fig. 2 for the node (prefix[0..d-1]).
+/* The lower bound of Sec. II-D (Fig. 2) for the node (prefix[0..d-1]).
  *
- * For every machine pair (k,l), k<l (the MM list, lexicographic):
- *   timeOnM1 = release of k, timeOnM2 = release of l (RM);
- *   for the unscheduled jobs in Johnson-with-lags order for (k,l) (JM
- *   restricted to the unscheduled set, here obtained by sorting that set):
- *     timeOnM1 += p[j][k];
- *     if timeOnM2 > timeOnM1 + lag  then timeOnM2 += p[j][l]
- *     else                               timeOnM2 = timeOnM1 + lag + p[j][l];
- *   timeOnM2 += tail of l (QM);  LB = max(LB, timeOnM2).
- * Returns ORC_INVALID for an invalid node. */
+ * Each machine pair (k,l), k<l, is relaxed to two machines in series with
+ * a lag: every other machine is taken to have unlimited capacity, so a job
+ * leaving k reaches l after its time on the machines in between.  The
+ * unscheduled jobs run through that two-machine system in Johnson-with-lags
+ * order, which minimises its makespan; both machines start at their
+ * release.  A job finishes on k when k has finished the job before it, and
+ * starts on l once l is free and the job has left k and served its lag.
+ * The pair's value is l's finishing time plus the tail of l (the least time
+ * any unscheduled job still needs after l); the bound is the largest value
+ * over the pairs.  Returns ORC_INVALID for an invalid node. */
 static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix, int d,
                           const int32_t *tiekey, int eq_in_s2, orc_counts *cnt,
                           int only_k, int only_l, int64_t *pair_t2, int64_t *pair_q, const orc_variant *v)
@@ -222,23 +223,22 @@ static int32_t bound_impl(const int32_t *p, int n, int m, const int32_t *prefix,
             }
             qsort(order, (size_t)cnt_u, sizeof(keyed_job), cmp_keyed);
 
-            int64_t timeOnM1 = r[k], timeOnM2 = r[l];
+            /* finishing times of the last job so far on k and on l */
+            int64_t fin_k = r[k], fin_l = r[l];
             if (cnt) cnt->rm += 2;
             for (int i = 0; i < cnt_u; ++i) {
                 int j = order[i].job;
-                int64_t L = lag(p, m, j, k, l);
-                timeOnM1 += p[(int64_t)j * m + k];
-                if (timeOnM2 > timeOnM1 + L)
-                    timeOnM2 += p[(int64_t)j * m + l];
-                else
-                    timeOnM2 = timeOnM1 + L + p[(int64_t)j * m + l];
+                fin_k += p[(int64_t)j * m + k];
+                int64_t arrive = fin_k + lag(p, m, j, k, l);
+                int64_t start = arrive > fin_l ? arrive : fin_l;
+                fin_l = start + p[(int64_t)j * m + l];
                 if (cnt) { cnt->ptm += 2; cnt->lm += 1; }
             }
-            if (pair_t2) *pair_t2 = timeOnM2;
+            if (pair_t2) *pair_t2 = fin_l;
             if (pair_q) *pair_q = q[l];
-            timeOnM2 += q[l];
+            int64_t value = fin_l + q[l];
             if (cnt) cnt->qm += 1;
-            if (timeOnM2 > LB) LB = timeOnM2;
+            if (value > LB) LB = value;
         }
     }
     free(order); free(q); free(r); free(scheduled);
@@ -273,7 +273,7 @@ int32_t orc_bound_counted(const int32_t *p, int n, int m, const int32_t *prefix,
     return bound_impl(p, n, m, prefix, d, NULL, 0, cnt, -1, -1, NULL, NULL, NULL);
 }
 
-/* One pair only: *t2 = timeOnM2 after the scan (before the tail), *q = tail
+/* One pair only: *t2 = finishing time on l after the scan (before the tail), *q = tail
  * of machine l.  Returns ORC_INVALID for an invalid node, else 0. */
 int32_t orc_pair_scan(const int32_t *p, int n, int m, const int32_t *prefix, int d,
                       int k, int l, int64_t *t2, int64_t *q)
