@@ -44,13 +44,19 @@ ScanTuning scan_tuning(int n, int m)
         auto it = g_tune.find({n, m});
         if (it != g_tune.end()) return it->second;
     }
-    return rule_tuning(m * (m - 1) / 2);
+    ScanTuning t = rule_tuning(m * (m - 1) / 2);
+    t.waves_per_group = fit_waves_per_group(t.waves_per_group, n);
+    return t;
 }
 
 ScanTuning scan_tuning_for(const fsp_instance_s *I)
 {
     // the table is keyed by shape with every pair; a pair subset scans fewer pairs
-    if (I->P != I->m * (I->m - 1) / 2) return rule_tuning(I->P);
+    if (I->P != I->m * (I->m - 1) / 2) {
+        ScanTuning t = rule_tuning(I->P);
+        t.waves_per_group = fit_waves_per_group(t.waves_per_group, I->n);
+        return t;
+    }
     return scan_tuning(I->n, I->m);
 }
 
@@ -121,7 +127,7 @@ void plan_batch(const fsp_pool_desc *pools, int32_t n_pools, int32_t wpg_force, 
         P.out_lb = d.out_lb;
         P.N = d.N;
         P.Npad = Npad;
-        P.wpg = wpg_force ? wpg_force : scan_tuning_for(I).waves_per_group;
+        P.wpg = fit_waves_per_group(wpg_force ? wpg_force : scan_tuning_for(I).waves_per_group, n);
         const int gpp = kBatchWaves / P.wpg;
         const int64_t per_wave = (I->P + P.wpg - 1) / P.wpg;
         for (int64_t g0 = 0; g0 < G; g0 += gpp) {
@@ -283,7 +289,7 @@ hipError_t BatchArena::plan_only(const fsp_pool_desc *pools, int32_t n_pools, hi
 {
     plan_batch(pools, n_pools, 0, false, plan, -1, ready);
     if (plan.ws_bytes > dev_bytes) {
-        const size_t cap = std::max(plan.ws_bytes, dev_bytes * 2);
+        const size_t cap = bytes_after(plan.ws_bytes);
         if (dev) stream_free(dev, s);
         dev = nullptr;
         dev_bytes = 0;

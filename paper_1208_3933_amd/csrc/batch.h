@@ -1,6 +1,7 @@
 // Batched bounding of many pools in one persistent launch (host/device shared).
 #pragma once
 
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -20,6 +21,17 @@ constexpr int kSortMaxBlocks = 64;
 inline size_t decode16_lds_words(int n, int MV) { return (size_t)((n + 31) >> 5) * 256 + (size_t)(n + 1) * (MV / 2); }
 
 constexpr int kBatchWaves = 16;  // waves per workgroup of the persistent scan
+// LDS a workgroup may allocate on gfx950 (160 KB per compute unit).
+constexpr size_t kLdsLimit = 160 * 1024;
+
+// A work item stages 16 / wpg groups of (n + 1) mask rows of 256 bytes.  The
+// tuned or rule-of-thumb wpg is raised (fewer groups per item, more waves on
+// each) until that fits LDS; n <= 512 always fits with one group per item.
+inline int fit_waves_per_group(int wpg, int n)
+{
+    while (wpg < kBatchWaves && (size_t)(kBatchWaves / wpg) * (size_t)(n + 1) * 256 > kLdsLimit) wpg *= 2;
+    return wpg;
+}
 constexpr int64_t kSortMinNodes = 512;  // smaller pools are decoded in pool order
 
 // One pool of a batch.  wpg = waves per 128-node group (divides 16); a work
@@ -139,6 +151,8 @@ struct BatchArena {
     void stage(char *dmeta, char *hdst);
     hipError_t launch(hipStream_t s);
     void release(hipStream_t s);
+    // The region's size once a plan has needed ws bytes of workspace.
+    size_t bytes_after(size_t ws) const { return ws > dev_bytes ? std::max(ws, dev_bytes * 2) : dev_bytes; }
 };
 
 }  // namespace fspbb

@@ -85,7 +85,7 @@ fsp_status fsp_autotune(fsp_instance inst, int64_t sample_nodes, int32_t reps, f
     for (int c = 0; c < 5 && st == FSP_OK; ++c) {
         const int wpg = cands[c];
         const int64_t gpp = kBatchWaves / wpg;
-        if ((size_t)gpp * (n + 1) * 256 > 160 * 1024) continue;  // the tile must fit LDS
+        if ((size_t)gpp * (n + 1) * 256 > kLdsLimit) continue;  // the tile must fit LDS
         double us = 0;
         st = time_batch(inst, dpre, ddep, dout, N, wpg, kBatchGrid, reps, s, e0, e1, &us);
         if (st != FSP_OK) break;

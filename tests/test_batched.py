@@ -3,6 +3,7 @@ the plain per-pool launch and the oracle, element by element."""
 import numpy as np
 import pytest
 
+import oracle
 from helpers import oracle_bounds, require_gpu, to_dev
 from paper_1208_3933_amd import fspbb, gen
 
@@ -163,3 +164,46 @@ def test_autotune_picks_a_measured_schedule(n, m):
         fspbb.bound_pool(inst, pre_d, dep_d, out)
         idx = np.arange(0, 3000, 10)
         assert (out.cpu().numpy()[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
+
+
+# Shapes whose rule-of-thumb tile (16 / wpg groups of (n + 1) x 256 bytes of
+# masks) would exceed the 160 KB of LDS: 100 x 5 (8 groups, 206,848 B),
+# 500 x 10 (4 groups, 256 KB), 200 x 10 and 200 x 20 over the 19 adjacent
+# pairs (4 groups, 205,824 B).  The planner raises the waves per group until
+# the tile fits.
+BIG_TILE_SHAPES = [(100, 5, None), (500, 10, None), (200, 10, None), (200, 20, "adjacent")]
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_shapes_whose_rule_tile_exceeds_lds(graph):
+    torch = require_gpu()
+    pools, host, insts = [], [], []
+    for s, (n, m, sub) in enumerate(BIG_TILE_SHAPES):
+        p = gen.processing_times(n, m, gen.make_seed(3, 700 + s, gen.PURPOSE_TIMES))
+        pairs = [(k, k + 1) for k in range(m - 1)] if sub else None
+        inst = fspbb.create_instance(p, pairs=pairs)
+        insts.append(inst)
+        wpg, tuned = fspbb.tune_get(n, m)
+        if not sub and not tuned:
+            assert (16 // wpg) * (n + 1) * 256 <= 160 * 1024, (n, m, wpg)
+        for N in (2048, 2047, 900):
+            pre, dep = gen.random_pool(n, N, gen.make_seed(3, 710 + 10 * s + N % 7, gen.PURPOSE_POOL))
+            pre_d, dep_d = to_dev(torch, pre, dep)
+            out = torch.full((N,), -7, dtype=torch.int32, device="cuda")
+            pools.append((inst, pre_d, dep_d, out))
+            host.append((p, pre, dep, pairs))
+    want_plain = plain_bounds(torch, pools)
+    with fspbb.batch_create(pools, graph=graph) as b:
+        b.run()
+        b.run()
+        torch.cuda.synchronize()
+    for i, (inst, _, _, out) in enumerate(pools):
+        got = out.cpu().numpy()
+        assert (got == want_plain[i]).all(), i
+        p, pre, dep, pairs = host[i]
+        idx = np.arange(len(dep)) if p.shape[0] <= 100 else np.arange(0, len(dep), 7)
+        want = oracle.bound_pool(p, pre[idx], dep[idx], pairs=pairs)
+        assert (got[idx] == want).all(), i
+    for inst in insts:
+        assert fspbb.pool_status(inst) == 0
+        inst.close()
