@@ -387,8 +387,19 @@ fsp_status fsp_neh(fsp_instance inst, int32_t *perm_out, int32_t *makespan);
 typedef struct fsp_server_s *fsp_server;
 
 typedef struct {
-    int64_t mem_budget_bytes;  /* device bytes for admitted searches' stacks and
-                                  step scratch, at their initial size (> 0) */
+    int64_t mem_budget_bytes;  /* device bytes for the admitted searches' stacks
+                                  and step buffers plus the server's shared step
+                                  scratch (> 0).  Admission counts a search at
+                                  its initial size; a step that would grow a
+                                  search (stack doubling, larger step buffers)
+                                  or the shared scratch past the budget holds
+                                  that search back to a later call, and when
+                                  every admitted search is held back the one
+                                  holding the most device memory ends with
+                                  FSP_E_NOMEM.
+                                  Per-launch workspace that a bound of child
+                                  rows takes and returns within the call is
+                                  not counted. */
     int32_t max_active;        /* most searches admitted at once (>= 1) */
     int64_t tick_children;     /* cap on children bounded per step call, summed
                                   over searches (0 = none); searches left out
@@ -398,7 +409,8 @@ typedef struct {
 
 typedef struct {
     int32_t active, pending;   /* admitted searches, searches waiting for admission */
-    int64_t mem_used;          /* device bytes held by admitted searches now */
+    int64_t mem_used;          /* device bytes held by admitted searches and the
+                                  shared step scratch now (<= mem_budget_bytes) */
     int64_t ticks;             /* step calls that advanced at least one search */
     int64_t nodes_bounded;     /* over all searches so far */
     int64_t last_children;     /* children bounded by the last step call */
@@ -424,7 +436,8 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
                            fsp_server_stats *stats);
 
 /* fsp_server_poll - FSP_PENDING while search id runs or waits; then its
- * fsp_solve status (FSP_OK, FSP_BUDGET or an error) with res and perm_out
+ * fsp_solve status (FSP_OK, FSP_BUDGET, FSP_E_NOMEM when the memory budget
+ * could not hold its next step, or another error) with res and perm_out
  * (host n, may be NULL) filled, once: the result is then forgotten, and
  * later polls of the id give FSP_E_INVAL. */
 fsp_status fsp_server_poll(fsp_server srv, int64_t id, fsp_solve_result *res, int32_t *perm_out);

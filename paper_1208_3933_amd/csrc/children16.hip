@@ -394,13 +394,18 @@ struct KidsSizes {
 };
 }  // namespace
 
+size_t KidsArena::step_bytes(const fsp_instance_s *I, int64_t K, int64_t nch)
+{
+    return KidsSizes(I->n, I->m, K, nch).total();
+}
+
 hipError_t KidsArena::layout(const std::vector<const fsp_instance_s *> &I, const std::vector<int64_t> &K,
                              const std::vector<int64_t> &nch, std::vector<Kids16> &out, hipStream_t s)
 {
     size_t need = 0;
-    for (size_t i = 0; i < I.size(); ++i) need += KidsSizes(I[i]->n, I[i]->m, K[i], nch[i]).total();
+    for (size_t i = 0; i < I.size(); ++i) need += step_bytes(I[i], K[i], nch[i]);
     if (need > cap) {
-        const size_t c = std::max(need, 2 * cap);
+        const size_t c = cap_after(need);
         if (blob) stream_free(blob, s);
         blob = nullptr;
         cap = 0;

@@ -2,6 +2,7 @@
 // instances on the 16-bit path with the plain releases.
 #pragma once
 
+#include <algorithm>
 #include <vector>
 
 #include "batch.h"
@@ -44,6 +45,10 @@ struct KidsArena {
     hipError_t layout(const std::vector<const fsp_instance_s *> &I, const std::vector<int64_t> &K,
                       const std::vector<int64_t> &nch, std::vector<Kids16> &out, hipStream_t s);
     void release(hipStream_t s);
+    // Bytes of one search's scratch in the region, and the region's size
+    // once a layout has needed `need` bytes.
+    static size_t step_bytes(const fsp_instance_s *I, int64_t K, int64_t nch);
+    size_t cap_after(size_t need) const { return need > cap ? std::max(need, 2 * cap) : cap; }
 };
 
 // Whether children of this instance are bounded from their parents.

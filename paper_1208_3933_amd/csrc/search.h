@@ -32,6 +32,7 @@ struct StepBuffers {
     hipError_t ensure_c(int64_t C, int n, hipStream_t s);
     void release(hipStream_t s);
     size_t bytes() const;
+    static size_t bytes_for(int64_t Kcap, int64_t Ccap, int n, bool rows);
 };
 
 // Per-tick device table and its pinned host image: StepReq[R], the phase-1
@@ -44,6 +45,7 @@ struct TickContext {
     KidsArena kids;  // the incremental scratch of a step's searches
     hipError_t reserve(size_t bytes);
     void release();
+    size_t device_bytes() const;  // the request table and both arenas
 };
 
 // Bounds the children of K parents (device rows and depths, taken in order;
@@ -96,6 +98,19 @@ struct StartArgs {
 // Starts several searches with their root bounds in one merged launch and one
 // copy back (Search::start for each, with one synchronization).
 hipError_t start_many(std::vector<Search *> &ss, const std::vector<StartArgs> &args, TickContext &ctx);
+// ctx.device_bytes() after start_many of these searches.
+size_t start_scratch_after(const std::vector<StartArgs> &args, const TickContext &ctx);
+
+// The parents a search's next step pops (its K parents and nch children),
+// without popping them.
+struct StepSel {
+    int64_t K = 0, nch = 0;
+};
+StepSel select_step(const Search &S);
+// S.device_bytes() once the step q has made room for its children.
+size_t bytes_after_step(const Search &S, const StepSel &q);
+// ctx.device_bytes() after a tick of these searches, whose steps are qs.
+size_t tick_scratch_after(const std::vector<Search *> &sel, const std::vector<StepSel> &qs, const TickContext &ctx);
 
 // Advances every search in `active` (not done, same device) by one step.
 // Synchronous on ctx.s.  A search whose step fails gets done = true and a

@@ -44,23 +44,6 @@ size_t initial_bytes(int n, int64_t pool_cap, bool rows)
     return S.device_bytes();
 }
 
-// Children of the search's next step (the selection of prepare_step, read only).
-int64_t next_children(const Search &S)
-{
-    int64_t K = 0, nch = 0;
-    for (auto it = S.runs.rbegin(); it != S.runs.rend(); ++it) {
-        const int64_t c = S.n - it->first;
-        int64_t x = (S.pool_cap - nch) / c;
-        if (K == 0) x = std::max<int64_t>(x, 1);
-        x = std::min(x, it->second);
-        if (x <= 0) break;
-        K += x;
-        nch += x * c;
-        if (x < it->second) break;
-    }
-    return nch;
-}
-
 }  // namespace
 
 struct fsp_server_s {
@@ -73,13 +56,16 @@ struct fsp_server_s {
     std::map<int64_t, Done> done;
     fsp_server_stats st{};
 
-    size_t mem_used() const
+    // Device bytes of the admitted searches, without and with the shared
+    // step scratch.
+    size_t search_bytes() const
     {
         size_t b = 0;
         for (const auto &j : active)
             if (j->S) b += j->S->device_bytes();
         return b;
     }
+    size_t mem_used() const { return search_bytes() + ctx.device_bytes(); }
 
     void finish(Job &j, fsp_status status)
     {
@@ -142,24 +128,32 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
     };
 
     // admission, first come first served; the admitted searches' roots are
-    // bounded together
-    size_t used = srv->mem_used();
+    // bounded together.  With nothing admitted, the shared step scratch is
+    // handed back if it alone would keep the next search out.
+    const size_t budget = (size_t)srv->cfg.mem_budget_bytes;
+    if (srv->active.empty() && !srv->pending.empty() &&
+        srv->ctx.device_bytes() + srv->pending.front()->est > budget)
+        srv->ctx.release();
+    size_t used = srv->search_bytes();
     std::vector<std::unique_ptr<Job>> admit;
+    std::vector<StartArgs> args;
     while (!srv->pending.empty() && srv->active.size() + admit.size() < (size_t)srv->cfg.max_active) {
         Job &j = *srv->pending.front();
         const bool first = srv->active.empty() && admit.empty();
-        if (used + j.est > (size_t)srv->cfg.mem_budget_bytes && !first) break;
+        args.push_back(StartArgs{j.inst, j.ub0, j.pool_cap, j.node_budget});
+        if (used + j.est + start_scratch_after(args, srv->ctx) > budget && !first) {
+            args.pop_back();
+            break;
+        }
         used += j.est;
         admit.push_back(std::move(srv->pending.front()));
         srv->pending.pop_front();
     }
     if (!admit.empty()) {
         std::vector<Search *> ss;
-        std::vector<StartArgs> args;
         for (auto &jp : admit) {
             jp->S = std::make_unique<Search>();
             ss.push_back(jp->S.get());
-            args.push_back(StartArgs{jp->inst, jp->ub0, jp->pool_cap, jp->node_budget});
         }
         hipError_t e = start_many(ss, args, srv->ctx);
         for (auto &jp : admit) {
@@ -174,16 +168,43 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
         }
     }
 
-    // the searches of this step: all, or those that waited longest up to the cap
+    // the searches of this step: all, or those that waited longest up to the
+    // children cap.  A search whose step would take the searches' memory and
+    // the shared step scratch past the budget (its stack doubling, larger
+    // step buffers) is held back; it keeps its place at the front.  When
+    // every search is held back, nothing would free memory: the search that
+    // holds the most device memory ends with FSP_E_NOMEM (the one that
+    // waited longest among equals).
     std::vector<Search *> sel;
-    size_t nsel = 0;
+    std::vector<StepSel> qs;
+    std::vector<char> picked(srv->active.size(), 0);
     int64_t children = 0;
-    for (auto &jp : srv->active) {
-        const int64_t c = next_children(*jp->S);
-        if (srv->cfg.tick_children > 0 && !sel.empty() && children + c > srv->cfg.tick_children) break;
-        sel.push_back(jp->S.get());
-        children += c;
-        ++nsel;
+    size_t grown = srv->search_bytes();
+    for (size_t i = 0; i < srv->active.size(); ++i) {
+        Search &S = *srv->active[i]->S;
+        const StepSel q = select_step(S);
+        if (srv->cfg.tick_children > 0 && !sel.empty() && children + q.nch > srv->cfg.tick_children) break;
+        const size_t after = grown - S.device_bytes() + bytes_after_step(S, q);
+        sel.push_back(&S);
+        qs.push_back(q);
+        if (after + tick_scratch_after(sel, qs, srv->ctx) > budget) {
+            sel.pop_back();
+            qs.pop_back();
+            continue;
+        }
+        grown = after;
+        picked[i] = 1;
+        children += q.nch;
+    }
+    if (sel.empty() && !srv->active.empty()) {
+        size_t victim = 0;
+        for (size_t i = 1; i < srv->active.size(); ++i)
+            if (srv->active[i]->S->device_bytes() > srv->active[victim]->S->device_bytes()) victim = i;
+        std::unique_ptr<Job> jp = std::move(srv->active[victim]);
+        srv->active.erase(srv->active.begin() + (std::ptrdiff_t)victim);
+        srv->finish(*jp, FSP_E_NOMEM);
+        report(jp->id);
+        picked.erase(picked.begin() + (std::ptrdiff_t)victim);
     }
     fsp_status ret = FSP_OK;
     if (!sel.empty()) {
@@ -202,8 +223,10 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
             ++srv->st.ticks;
             // stepped searches go to the back in their order; finished ones leave
             std::deque<std::unique_ptr<Job>> rest;
-            for (size_t i = nsel; i < srv->active.size(); ++i) rest.push_back(std::move(srv->active[i]));
-            for (size_t i = 0; i < nsel; ++i) {
+            for (size_t i = 0; i < srv->active.size(); ++i)
+                if (!picked[i]) rest.push_back(std::move(srv->active[i]));
+            for (size_t i = 0; i < srv->active.size(); ++i) {
+                if (!picked[i]) continue;
                 std::unique_ptr<Job> &jp = srv->active[i];
                 if (jp->S->done) {
                     srv->finish(*jp, jp->S->status);

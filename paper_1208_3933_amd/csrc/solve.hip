@@ -77,10 +77,12 @@ void StepBuffers::release(hipStream_t s)
     Kcap = Ccap = 0;
 }
 
-size_t StepBuffers::bytes() const
+size_t StepBuffers::bytes_for(int64_t Kc, int64_t Cc, int n_, bool rows_)
 {
-    return (size_t)Kcap * 8 + (size_t)Ccap * (24 + (rows ? 4 * (size_t)n : 0)) + scan_scratch_bytes(Kcap);
+    return (size_t)Kc * 8 + (size_t)Cc * (24 + (rows_ ? 4 * (size_t)n_ : 0)) + scan_scratch_bytes(Kc);
 }
+
+size_t StepBuffers::bytes() const { return bytes_for(Kcap, Ccap, n, rows); }
 
 hipError_t TickContext::reserve(size_t bytes)
 {
@@ -103,6 +105,8 @@ hipError_t TickContext::reserve(size_t bytes)
     }
     return hipSuccess;
 }
+
+size_t TickContext::device_bytes() const { return dcap + arena.dev_bytes + kids.cap; }
 
 void TickContext::release()
 {
@@ -320,6 +324,23 @@ hipError_t start_many(std::vector<Search *> &ss, const std::vector<StartArgs> &a
     return hipSuccess;
 }
 
+size_t start_scratch_after(const std::vector<StartArgs> &args, const TickContext &ctx)
+{
+    if (args.size() <= 1) return ctx.device_bytes();  // one root is bounded on its own
+    const size_t tab = al256(args.size() * 4);
+    const size_t dcap = tab > ctx.dcap ? std::max(tab, (size_t)64 * 1024) : ctx.dcap;
+    std::vector<fsp_pool_desc> descs;
+    for (const StartArgs &a : args)
+        if (a.inst->packed16) descs.push_back(fsp_pool_desc{a.inst, nullptr, nullptr, 1, nullptr});
+    size_t arena = ctx.arena.dev_bytes;
+    if (!descs.empty()) {
+        BatchPlan pl;
+        plan_batch(descs.data(), (int32_t)descs.size(), 0, false, pl);
+        arena = ctx.arena.bytes_after(pl.ws_bytes + pl.meta_bytes);
+    }
+    return dcap + arena + ctx.kids.cap;
+}
+
 void Search::release(hipStream_t s)
 {
     if (srows) stream_free(srows, s);
@@ -345,6 +366,35 @@ void Search::result(fsp_solve_result *res, int32_t *perm_out) const
     res->improvements = improvements;
     res->max_stack = max_stack;
     if (perm_out) std::copy(inc.begin(), inc.end(), perm_out);
+}
+
+StepSel select_step(const Search &S)
+{
+    StepSel q;
+    for (auto it = S.runs.rbegin(); it != S.runs.rend(); ++it) {
+        const int64_t c = S.n - it->first;
+        int64_t x = (S.pool_cap - q.nch) / c;
+        if (q.K == 0) x = std::max<int64_t>(x, 1);
+        x = std::min(x, it->second);
+        if (x <= 0) break;
+        q.K += x;
+        q.nch += x * c;
+        if (x < it->second) break;
+    }
+    return q;
+}
+
+// The stack and step buffers prepare_step leaves for the step q (the same
+// growth rules: the stack doubles, the buffers take the requested size).
+size_t bytes_after_step(const Search &S, const StepSel &q)
+{
+    int64_t cs = S.cap_stack;
+    const int64_t base = S.top - q.K;
+    while (base + q.nch > cs) cs *= 2;
+    const int64_t k = std::max(S.pool_cap, q.K), c = std::max(S.pool_cap, q.nch);
+    const int64_t Kc = (S.B.kblob && k <= S.B.Kcap) ? S.B.Kcap : std::max<int64_t>(k, 1);
+    const int64_t Cc = (S.B.cblob && c <= S.B.Ccap && S.B.n == S.n) ? S.B.Ccap : std::max<int64_t>(c, 1);
+    return (size_t)cs * (S.n + 1) * 4 + (size_t)S.n * 4 + StepBuffers::bytes_for(Kc, Cc, S.n, S.B.rows);
 }
 
 // Pops parents for one step and makes room for their children.
@@ -465,6 +515,38 @@ hipError_t bound_children_of(fsp_instance_s *I, const int32_t *parents, const in
     if (e == hipSuccess)
         e = phase1_and_bound1(dentry, (const ScanSeg *)(d + L.seg1), I, ks, K, nch, q.w, s, &leaves_done);
     return e;
+}
+
+size_t tick_scratch_after(const std::vector<Search *> &sel, const std::vector<StepSel> &qs, const TickContext &ctx)
+{
+    const int R = (int)sel.size();
+    size_t kids_need = 0;
+    int64_t sumK = 0;
+    std::vector<fsp_pool_desc> descs;
+    std::vector<Workspace16> ready;
+    for (int r = 0; r < R; ++r) {
+        const Search &S = *sel[r];
+        sumK += qs[r].K;
+        const bool k = kids16_eligible(S.inst) && qs[r].nch > 0;
+        if (k) kids_need += KidsArena::step_bytes(S.inst, qs[r].K, qs[r].nch);
+        if (R > 1 && S.inst->packed16) {
+            // only sizes matter to the plan; a non-null dec marks a decoded pool
+            descs.push_back(fsp_pool_desc{S.inst, nullptr, nullptr, qs[r].nch, nullptr});
+            Workspace16 w{};
+            if (k) w.dec = reinterpret_cast<uint32_t *>(uintptr_t(256));
+            ready.push_back(w);
+        }
+    }
+    size_t arena = ctx.arena.dev_bytes, meta = 0;
+    if (!descs.empty()) {
+        BatchPlan pl;
+        plan_batch(descs.data(), (int32_t)descs.size(), 0, false, pl, -1, ready.data());
+        arena = ctx.arena.bytes_after(pl.ws_bytes);
+        meta = pl.meta_bytes;
+    }
+    const size_t tab = TabLayout(R, sumK, meta).total;
+    const size_t dcap = tab > ctx.dcap ? std::max(tab, (size_t)64 * 1024) : ctx.dcap;
+    return dcap + arena + (kids_need ? ctx.kids.cap_after(kids_need) : ctx.kids.cap);
 }
 
 hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
