@@ -2,6 +2,8 @@
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
+import json
 import os
 
 import numpy as np
@@ -51,3 +53,75 @@ def require_gpu():
 
 def to_dev(torch, *arrays):
     return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in arrays]
+
+
+def host_dfs_steps(p, ub0, pool_cap, nsteps):
+    """The first nsteps pool steps of the depth-first search of the oracle's
+    order rules, built on the host with every child bounded by the oracle
+    (fanned out over host threads).  Returns per step the step-log row
+    [parents, children, UB, pushed, stack, fingerprint], the parents in pop
+    order and the survivors (rows, bounds) in child order."""
+    n = p.shape[0]
+    ub = int(ub0)
+    root = int(oracle.bound(p, []))
+    stack_rows = [np.zeros(n, np.int32)] if root < ub else []
+    stack_dep = [0] if root < ub else []
+    nodes, out = 1, []
+    for _ in range(nsteps):
+        if not stack_rows:
+            break
+        par_rows, par_dep, nchild = [], [], 0
+        while stack_rows:
+            c = n - stack_dep[-1]
+            if par_rows and nchild + c > pool_cap:
+                break
+            nchild += c
+            par_rows.append(stack_rows.pop())
+            par_dep.append(stack_dep.pop())
+        kids, kdep, kjob = [], [], []
+        for row, d in zip(par_rows, par_dep):
+            sched = np.zeros(n, bool)
+            sched[row[:d]] = True
+            free = np.nonzero(~sched)[0]
+            block = np.zeros((len(free), n), np.int32)
+            block[:, :d] = row[:d]
+            block[:, d] = free
+            kids.append(block)
+            kdep.append(np.full(len(free), d + 1, np.int32))
+            kjob.append(free.astype(np.int64))
+        kids, kdep, kjob = np.concatenate(kids), np.concatenate(kdep), np.concatenate(kjob)
+        lbs = oracle_bounds(p, kids, kdep)
+        nodes += len(kdep)
+        leaf = np.nonzero((kdep == n) & (lbs < ub))[0]
+        if len(leaf):
+            best = leaf[np.argmin(lbs[leaf])]  # argmin takes the first of equal values
+            ub = int(lbs[best])
+        keep = np.nonzero((kdep < n) & (lbs < ub))[0]
+        S = len(keep)
+        fp = int(((S - np.arange(S)) * (kjob[keep] + 1)).sum())
+        for i in keep[::-1]:
+            stack_rows.append(kids[i])
+            stack_dep.append(int(kdep[i]))
+        out.append({"log": [len(par_rows), len(kdep), ub, S, len(stack_rows), fp],
+                    "parents": (np.array(par_rows), np.array(par_dep, np.int32)),
+                    "ub_in": None, "survivors": (kids[keep], kdep[keep], lbs[keep]), "nodes": nodes})
+    ubs = [int(ub0)] + [s["log"][2] for s in out]
+    for s, u in zip(out, ubs):
+        s["ub_in"] = u
+    return out
+
+
+def survivors_digest(rows, depths, lbs) -> str:
+    """SHA-256 of a step's survivors in order: each survivor's prefix (up to
+    the largest depth), depth and bound as little-endian int32."""
+    d = int(depths.max()) if len(depths) else 0
+    a = np.concatenate([np.asarray(rows)[:, :d], np.asarray(depths)[:, None], np.asarray(lbs)[:, None]], axis=1)
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i4").tobytes()).hexdigest()
+
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name: str):
+    with open(os.path.join(GOLDEN_DIR, name)) as f:
+        return json.load(f)

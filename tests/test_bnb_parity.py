@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import oracle_bounds, require_gpu, to_dev
+from helpers import load_golden, oracle_bounds, require_gpu, survivors_digest, to_dev
 from paper_1208_3933_amd import fspbb, gen
 
 pytestmark = pytest.mark.gpu
@@ -245,3 +245,49 @@ def test_release_cached_returns_memory_and_keeps_results():
     assert free1 >= free0 + (1 << 30)
     for f in ("opt", "nodes_bounded", "steps", "improvements", "max_stack", "status"):
         assert a[f] == b[f], f
+
+
+# --- the benchmarked search: 200 x 20 from NEH with 262,144-child pools --------
+
+def test_solve_200x20_neh_benchmarked_pool_cap():
+    """The benchmarked search (the 200 x 20 instance of the bound pool, NEH
+    upper bound, pool_cap 262,144) for three steps (1 + 200 + 39,800 +
+    261,954 nodes).  tests/golden/make_bnb_200x20.py built these steps on the
+    host with every child bounded by the oracle.  Every step-log entry
+    (parents, children, UB, pushed, stack, fingerprint) must equal it.  The
+    third step is then run alone through fsp_branch_and_prune on the same
+    parents and upper bound: the survivors in order (rows, depths, bounds)
+    must hash to the oracle's, and a sample of them is compared one by one."""
+    torch = require_gpu()
+    g = load_golden("bnb_200x20_neh_cap262144.json")
+    n, cap = g["n"], g["pool_cap"]
+    p = gen.processing_times(n, g["m"], gen.make_seed(*g["seed"]))
+    steps = g["steps"]
+    with fspbb.create_instance(p) as inst:
+        budget = steps[1]["nodes_after"] + 1  # the search stops after its third step
+        got = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, steplog_cap=8)
+        assert got["ub0"] == g["neh"]
+        assert got["steps"] == 3 and got["nodes_bounded"] == steps[2]["nodes_after"]
+        for k in range(3):
+            assert got["steplog"][k].tolist() == steps[k]["log"], k
+        last = steps[2]
+        pre = np.zeros((len(last["parents"]), n), np.int32)
+        pre[:, :last["parents_depth"]] = np.array(last["parents"], np.int32)
+        dep = np.full(len(pre), last["parents_depth"], np.int32)
+        pre_d, dep_d = to_dev(torch, pre, dep)
+        nch = last["log"][1]
+        rows = torch.full((nch, n), -9, dtype=torch.int32, device="cuda")
+        cdep = torch.full((nch,), -9, dtype=torch.int32, device="cuda")
+        clb = torch.full((nch,), -9, dtype=torch.int32, device="cuda")
+        res = fspbb.branch_and_prune(inst, pre_d, dep_d, last["ub_in"], rows, cdep, clb)
+        torch.cuda.synchronize()
+    assert res["status"] == fspbb.OK
+    S = last["log"][3]
+    assert (res["n_children"], res["n_survivors"], res["ub_out"], res["fingerprint"]) == \
+        (nch, S, last["log"][2], last["log"][5])
+    d = last["parents_depth"] + 1
+    rows, cdep, clb = rows[:S, :d].cpu().numpy(), cdep[:S].cpu().numpy(), clb[:S].cpu().numpy()
+    for row in last["survivor_sample"]:
+        i = row[0]
+        assert rows[i].tolist() == row[1:1 + d] and cdep[i] == d and clb[i] == row[-1], i
+    assert survivors_digest(rows, cdep, clb) == last["survivors_sha256"]

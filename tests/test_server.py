@@ -114,19 +114,22 @@ def test_mix_identical_to_alone(setup):
 
 def test_memory_admission_limits_active_searches(setup):
     reqs, insts, alone = setup
-    # the largest initial footprint among the requests, measured by admitting it alone
+    # the largest footprint among the requests (the search's buffers and the
+    # server's step scratch), measured over each search run alone
     foot = 0
     for inst, r in zip(insts, reqs):
         with fspbb.server_create(1 << 34, 1) as srv:
             i = srv.submit(inst, r["ub0"], r["pool_cap"], r["budget"])
-            _, st = srv.step()
-            foot = max(foot, st["mem_used"])
-            while srv.poll(i) is None:
-                srv.step()
+            while True:
+                _, st = srv.step()
+                foot = max(foot, st["mem_used"])
+                if srv.poll(i) is not None:
+                    break
     budget = int(1.2 * foot)  # below the sum of the footprints, above the largest
     seen = []
 
     def check(stats):
+        assert stats["mem_used"] <= budget
         seen.append((stats["active"], stats["pending"]))
 
     served = run_served(insts, reqs, budget, 64, 0, arrivals_per_step=12, check=check)
@@ -172,3 +175,89 @@ def test_poll_and_submit_errors(setup):
         assert same(r, alone[0])
         with pytest.raises(fspbb.FspError):
             srv.poll(i)  # a result is returned once
+
+
+def test_memory_budget_holds_growth_back():
+    """A search whose stack must double past the budget (60 jobs, no upper
+    bound, pool_cap 128: its stack outgrows the initial 1,024 rows) ends with
+    FSP_E_NOMEM instead of taking the memory, alone and in a mix; the small
+    search beside it gives the same result as alone; the memory in use never
+    passes the budget."""
+    require_gpu()
+    big = fspbb.create_instance(times(60, 5, 201))
+    small_p = times(8, 4, 0)
+    small = fspbb.create_instance(small_p)
+    try:
+        alone_small = fspbb.solve(small, fspbb.UB_NEH, 16, 1 << 40)
+        with fspbb.server_create(1 << 34, 4) as srv:
+            srv.submit(big, fspbb.UB_NONE, 128, 1 << 40)
+            _, st = srv.step()
+        start_big = st["mem_used"]
+        for budget, with_small in ((int(start_big * 1.05), False), (int(start_big * 1.05) + (4 << 20), True)):
+            ids = {}
+            with fspbb.server_create(budget, 4) as srv:
+                ids[srv.submit(big, fspbb.UB_NONE, 128, 1 << 40)] = "big"
+                if with_small:
+                    ids[srv.submit(small, fspbb.UB_NEH, 16, 1 << 40)] = "small"
+                got = {}
+                for _ in range(100000):
+                    done, st = srv.step()
+                    assert st["mem_used"] <= budget
+                    for i in done:
+                        if ids[i] == "big":
+                            with pytest.raises(fspbb.FspError) as ei:
+                                srv.poll(i)
+                            got["big"] = ei.value.status
+                        else:
+                            got["small"] = srv.poll(i)
+                    if len(got) == len(ids):
+                        break
+            assert got["big"] == fspbb.E_NOMEM
+            if with_small:
+                assert same(got["small"], alone_small)
+    finally:
+        big.close()
+        small.close()
+
+
+# Large shapes of the served stream, each stopped by its node budget: 200 x 20,
+# 500 x 20 (whose tables do not fit LDS and are read from HBM), and 100 x 5
+# and 100 x 10, whose merged bound launches need the tile sized to LDS.
+LARGE = [(200, 20, 301, 1024, 20000), (500, 20, 302, 1024, 12000), (100, 5, 303, 2048, 30000),
+         (100, 10, 304, 2048, 30000)]
+
+
+def test_large_shapes_served_match_alone_and_oracle():
+    """Each large search's first two steps (parents, children, UB, pushed,
+    stack, fingerprint) equal the host build of the steps with every child
+    bounded by the oracle, from the oracle's NEH bound; served in a mix with
+    three small searches, every search gives the same result as alone."""
+    require_gpu()
+    from helpers import host_dfs_steps
+    insts, reqs = [], []
+    try:
+        for n, m, idx, cap, budget in LARGE:
+            p = times(n, m, idx)
+            inst = fspbb.create_instance(p)
+            insts.append(inst)
+            reqs.append(dict(p=p, pool_cap=cap, budget=budget, ub0=fspbb.UB_NEH))
+            got = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, steplog_cap=2)
+            ms, _ = oracle.neh(p)
+            assert got["ub0"] == ms and got["status"] == fspbb.BUDGET
+            want = host_dfs_steps(p, ms, cap, 2)
+            assert [s["log"] for s in want] == got["steplog"].tolist(), (n, m)
+        for k in (0, 6, 9):
+            n, m, idx, cap, budget, mode, hi = REQUESTS[k]
+            p = times(n, m, idx, 1, hi)
+            insts.append(fspbb.create_instance(p))
+            reqs.append(dict(p=p, pool_cap=cap, budget=budget, ub0=fspbb.UB_NEH if mode == "neh" else fspbb.UB_NONE))
+        alone = solve_alone(insts, reqs)
+        served = run_served(insts, reqs, 1 << 34, 64, 0, arrivals_per_step=2)
+        for k, (a, s) in enumerate(zip(alone, served)):
+            assert same(a, s), (k, a, s)
+        served = run_served(insts, reqs, 1 << 34, 3, 3000, arrivals_per_step=1)
+        for k, (a, s) in enumerate(zip(alone, served)):
+            assert same(a, s), (k, a, s)
+    finally:
+        for inst in insts:
+            inst.close()
