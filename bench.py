@@ -96,6 +96,32 @@ def algorithmic_scan_ops(n: int, m: int, depths: np.ndarray) -> float:
     return float(P * (n * len(depths) + 4 * nprime + 2 * len(depths)))
 
 
+def host_cores() -> dict:
+    """Host CPUs this process may use: the count the OS reports, the CPUs of
+    its affinity mask, and the cgroup CPU quota (a container's share), with
+    the least of them as the cores to run on."""
+    visible = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = visible
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(per)
+    except (OSError, ValueError):
+        try:
+            q = int(open("/sys/fs/cgroup/cpu/cpu.cfs_quota_us").read())
+            per = int(open("/sys/fs/cgroup/cpu/cpu.cfs_period_us").read())
+            if q > 0:
+                quota = q / per
+        except (OSError, ValueError):
+            pass
+    usable = min(visible, affinity, int(quota) if quota else visible)
+    return {"os_cpu_count": visible, "affinity": affinity, "cgroup_quota": quota, "usable": max(1, usable)}
+
+
 def cpu_baseline(p, pre, dep, sample: int, threads: int, gpu_lb: np.ndarray) -> dict:
     import concurrent.futures as cf
 
@@ -108,7 +134,8 @@ def cpu_baseline(p, pre, dep, sample: int, threads: int, gpu_lb: np.ndarray) -> 
     dt = time.perf_counter() - t0
     want = np.concatenate(parts)
     return {"value": len(idx) / dt, "unit": "nodes/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per core",
+            "sample": f"first {len(idx)} nodes of the same 200x20 pool, plain C oracle, one thread per usable "
+                      f"host core",
             "gpu_bounds_equal": bool((gpu_lb[idx] == want).all())}
 
 
@@ -367,15 +394,18 @@ def single_core_rates() -> dict:
     return out
 
 
-def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: int, stream) -> dict:
-    """Poisson stream of solves at 0.7 x the measured saturation rate."""
+def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: int, large_budget: int,
+                stream) -> dict:
+    """Poisson stream of solves at 0.7 x the measured saturation rate.  The
+    200x20 and 500x20 requests are searches stopped after large_budget nodes;
+    the latency of proven solves and of those is reported apart."""
     from paper_1208_3933_amd import gen, serve
-    cands = serve.candidates(seeds_per_shape)
+    cands = serve.candidates(seeds_per_shape, budgeted_budget=large_budget)
     serve.screen(cands[:4], pool_cap, budget, stream)  # warm-up
     serve.screen(cands, pool_cap, budget, stream)
     unsolved = {}
     for c in cands:
-        if not c.alone["proven"]:
+        if not c.alone["proven"] and not c.budgeted:
             key = "%dx%d" % serve.SHAPES[c.shape]
             unsolved[key] = unsolved.get(key, 0) + 1
     mem = 32 << 30
@@ -387,11 +417,22 @@ def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: in
     rate = 0.7 * sat_rate
     arr = serve.poisson_arrivals(n_requests, rate, gen.make_seed(serve.CONFIG, 3, gen.PURPOSE_ARRIVALS))
     r = serve.run(cands, reqs, arr, pool_cap, budget, mem, 256, 0, stream)
-    lat_ms = r["latency_s"] * 1e3
+    lat_all = r["latency_s"] * 1e3
+    proven = np.array([not cands[k].budgeted for k in reqs], bool)
+    lat_ms = lat_all[proven]
+    stopped = {}
+    for key in sorted({"%dx%d" % serve.SHAPES[cands[k].shape] for k in reqs if cands[k].budgeted}):
+        sel = np.array(["%dx%d" % serve.SHAPES[cands[k].shape] == key and cands[k].budgeted for k in reqs], bool)
+        x = lat_all[sel]
+        stopped[key] = {"requests": int(sel.sum()), "node_budget": large_budget,
+                        "p50_ms": serve.percentile(x, 50), "p99_ms": serve.percentile(x, 99),
+                        "mean_ms": float(x.mean())}
     for c in cands:
         c.inst.close()
-    return {"requests": n_requests, "rate_per_s": rate, "p50_ms": serve.percentile(lat_ms, 50),
+    return {"requests": n_requests, "rate_per_s": rate, "proven_requests": int(proven.sum()),
+            "p50_ms": serve.percentile(lat_ms, 50),
             "p99_ms": serve.percentile(lat_ms, 99), "mean_ms": float(lat_ms.mean()),
+            "budget_stopped_by_shape": stopped,
             "nodes_per_s": r["nodes_bounded"] / r["wall_s"], "solves_per_s": n_requests / r["wall_s"],
             "wall_s": r["wall_s"], "mean_searches_per_step": r["mean_searches_per_tick"],
             "mismatches_vs_alone": r["mismatches"] + sat["mismatches"],
@@ -442,6 +483,8 @@ def main() -> int:
     ap.add_argument("--serve-seeds", type=int, default=10, help="screened instances per shape")
     ap.add_argument("--serve-pool-cap", type=int, default=8192)
     ap.add_argument("--serve-budget", type=int, default=2000000)
+    ap.add_argument("--serve-large-budget", type=int, default=131072,
+                    help="node budget of the served 200x20 and 500x20 searches (0 = serve proven instances only)")
     ap.add_argument("--tables-reps", type=int, default=10,
                     help="repetitions per point of the shape x pool grid of the paper's tables (0 = skip)")
     ap.add_argument("--variant-solves", type=int, default=6,
@@ -524,7 +567,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "plain bounding, 200 jobs x 20 machines (190 pairs), U[1,99] times, "
                                "pool of 262144 nodes, depths U{0..199}",
-                   "n": N_JOBS, "m": N_MACH, "pool": POOL, "kernel": "decode16 + scan16 (8 waves/group)"},
+                   "n": N_JOBS, "m": N_MACH, "pool": POOL,
+                   "kernel": "decode16 + scan16 (%d waves per 128-node group)" % fspbb.tune_get(N_JOBS, N_MACH)[0]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(), "traffic_unit": "bytes/launch",
                      "kernel": "bound_scan16_kernel", "kernel_avg_ms": scan_avg_s * 1e3,
@@ -548,7 +592,7 @@ def main() -> int:
         print("[bench] bnb leg done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         result["serving"] = serving_leg(args.serve_requests, args.serve_seeds, args.serve_pool_cap,
-                                        args.serve_budget, stream)
+                                        args.serve_budget, args.serve_large_budget, stream)
         s = result["serving"]
         result["p50_ms"], result["p99_ms"] = s["p50_ms"], s["p99_ms"]
         print("[bench] serving leg done", file=sys.stderr, flush=True)
@@ -556,8 +600,9 @@ def main() -> int:
         result["tables"] = tables_leg(stream, args.tables_reps)
         print("[bench] tables leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1))
-        result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, threads, gpu_lb)
+        cores = host_cores()
+        result["cpu_baseline"] = cpu_baseline(p, pre, dep, args.cpu_sample, cores["usable"], gpu_lb)
+        result["cpu_baseline"]["host"] = cores
         one = single_core_rates()
         result["cpu_baseline"]["single_core_nodes_per_s"] = one
         result["cpu_baseline"]["bound_share_of_search"] = bound_share(p)

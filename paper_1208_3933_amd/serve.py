@@ -8,9 +8,13 @@ from arrival to result on the host.  Instances are created once and stay
 resident on the device (their tables are reused by every request on them).
 
 Requests are drawn from instances screened beforehand by solving each alone
-(fsp_solve, same pool_cap and budget): only instances proven optimal within
-the budget enter the stream; the others are reported by shape.  The screened
-alone results are also the reference each served result must equal.
+(fsp_solve, same pool_cap and budget): instances proven optimal within the
+budget enter the stream; the others are reported by shape.  The largest
+shapes (200 x 20, and 500 x 20 whose tables do not fit LDS) rarely close
+within any budget on random U[1,99] instances; they enter the stream as
+searches stopped by a smaller node budget of their own, whose results are as
+deterministic as a proof, and their latency is reported apart.  The
+screened alone results are also the reference each served result must equal.
 """
 from __future__ import annotations
 
@@ -27,6 +31,8 @@ from . import fspbb, gen
 SHAPES = [(20, 5), (20, 10), (50, 5), (50, 10), (100, 5), (100, 10), (200, 10), (200, 20), (500, 20)]
 WEIGHTS = [6, 5, 4, 3, 3, 2, 2, 1, 1]
 CONFIG = 4
+# Shapes served as budget-stopped searches (node budget of their own).
+BUDGETED = {(200, 20), (500, 20)}
 RESULT_FIELDS = ("opt", "proven", "nodes_bounded", "steps", "ub0", "improvements", "max_stack", "status")
 
 
@@ -38,14 +44,21 @@ class Candidate:
     inst: object = None
     alone: dict = field(default_factory=dict)
     alone_s: float = 0.0
+    budgeted: bool = False  # served as a budget-stopped search
+    budget: int = 0         # its node budget (0: the stream's)
 
 
-def candidates(seeds_per_shape: int, shapes=SHAPES) -> list:
+def candidates(seeds_per_shape: int, shapes=SHAPES, budgeted_budget: int = 0) -> list:
+    """Seeded instances per shape.  With budgeted_budget > 0, the shapes of
+    BUDGETED are served as searches stopped after that many nodes."""
     out = []
     for si, (n, m) in enumerate(shapes):
         for i in range(seeds_per_shape):
             p = gen.processing_times(n, m, gen.make_seed(CONFIG, si * 1000 + i, gen.PURPOSE_TIMES))
-            out.append(Candidate(si, i, p))
+            c = Candidate(si, i, p)
+            if budgeted_budget > 0 and (n, m) in BUDGETED:
+                c.budgeted, c.budget = True, budgeted_budget
+            out.append(c)
     return out
 
 
@@ -55,18 +68,21 @@ def screen(cands, pool_cap: int, budget: int, stream=None) -> None:
     for c in cands:
         if c.inst is None:
             c.inst = fspbb.create_instance(c.p)
+        if not c.budget:
+            c.budget = budget
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        c.alone = fspbb.solve(c.inst, fspbb.UB_NEH, pool_cap, budget, 0, stream)
+        c.alone = fspbb.solve(c.inst, fspbb.UB_NEH, pool_cap, c.budget, 0, stream)
         c.alone_s = time.perf_counter() - t0
 
 
 def sample_requests(cands, count: int, seed: int) -> list:
     """count candidates drawn with replacement: a shape by WEIGHTS among the
-    shapes with proven candidates, then a proven candidate of it uniformly."""
+    shapes with servable candidates (proven, or budget-stopped by design),
+    then one of its servable candidates uniformly."""
     proven = {}
     for k, c in enumerate(cands):
-        if c.alone.get("proven"):
+        if c.alone.get("proven") or c.budgeted:
             proven.setdefault(c.shape, []).append(k)
     shapes = sorted(proven)
     if not shapes:
@@ -108,7 +124,8 @@ def run(cands, reqs, arrivals, pool_cap: int, budget: int, mem_budget: int, max_
         while done < n:
             now = time.perf_counter() - t0
             while nxt < n and arr[nxt] <= now:
-                ids[srv.submit(cands[reqs[nxt]].inst, fspbb.UB_NEH, pool_cap, budget)] = nxt
+                c = cands[reqs[nxt]]
+                ids[srv.submit(c.inst, fspbb.UB_NEH, pool_cap, c.budget or budget)] = nxt
                 nxt += 1
             if len(ids) == done and nxt < n:
                 # idle until the next arrival
