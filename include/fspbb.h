@@ -415,6 +415,9 @@ typedef struct {
     int64_t nodes_bounded;     /* over all searches so far */
     int64_t last_children;     /* children bounded by the last step call */
     int32_t last_searches;     /* searches advanced by the last step call */
+    int64_t swap_outs;         /* stacks moved to host memory to let another
+                                  search step within the budget, so far */
+    int64_t swap_ins;          /* stacks brought back, so far */
 } fsp_server_stats;
 
 /* fsp_server_create - cfg host; stream: every launch and copy of the server
@@ -428,7 +431,10 @@ fsp_status fsp_server_submit(fsp_server srv, fsp_instance inst, int32_t ub0, int
                              int64_t node_budget, int64_t *id_out);
 
 /* fsp_server_step - admit what fits, then one step of every admitted search
- * (synchronous on the stream).  done_ids host (done_cap entries, may be NULL):
+ * whose step fits the memory budget (synchronous on the stream).  When no
+ * admitted search fits, the stacks of the others are moved to host memory,
+ * largest first, until the one that waited longest does; a moved search comes
+ * back when its step fits again.  Moving changes no result.  done_ids host (done_cap entries, may be NULL):
  * ids of the searches that finished in this call, *n_done their count (ids
  * beyond done_cap are not listed but can still be polled).  stats may be NULL.
  * An error here leaves every admitted search failed with that status. */
@@ -437,7 +443,8 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
 
 /* fsp_server_poll - FSP_PENDING while search id runs or waits; then its
  * fsp_solve status (FSP_OK, FSP_BUDGET, FSP_E_NOMEM when the memory budget
- * could not hold its next step, or another error) with res and perm_out
+ * could not hold its next step even with every other search's stack moved
+ * to host memory, or another error) with res and perm_out
  * (host n, may be NULL) filled, once: the result is then forgotten, and
  * later polls of the id give FSP_E_INVAL. */
 fsp_status fsp_server_poll(fsp_server srv, int64_t id, fsp_solve_result *res, int32_t *perm_out);

@@ -76,6 +76,10 @@ struct Search {
     int64_t K = 0, nch = 0, base = 0;                  // the step in flight
     bool done = false;
     fsp_status status = FSP_OK;
+    // A search moved out of device memory (swap_out) keeps its live stack
+    // rows here; its stack and step buffers are freed, the incumbent stays.
+    bool swapped = false;
+    std::vector<int32_t> host_rows, host_dep;
 
     // NEH or the given upper bound, device state, and the root bound.
     // Synchronous on s.
@@ -87,6 +91,14 @@ struct Search {
     void release(hipStream_t s);
     size_t device_bytes() const;
     void result(fsp_solve_result *res, int32_t *perm_out) const;
+    // Copies the live stack rows to host memory, then frees the stack and the
+    // step buffers.  Synchronous on s.  The search's state is otherwise kept,
+    // so its later steps are those it would have taken without the move.
+    hipError_t swap_out(hipStream_t s);
+    // Reallocates the stack (cap_stack rows) and pool-sized step buffers and
+    // copies the rows back.  Synchronous on s; on failure the search stays
+    // swapped out and holds no stack.
+    hipError_t swap_in(hipStream_t s);
 };
 
 struct StartArgs {

@@ -171,10 +171,11 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
     // the searches of this step: all, or those that waited longest up to the
     // children cap.  A search whose step would take the searches' memory and
     // the shared step scratch past the budget (its stack doubling, larger
-    // step buffers) is held back; it keeps its place at the front.  When
-    // every search is held back, nothing would free memory: the search that
-    // holds the most device memory ends with FSP_E_NOMEM (the one that
-    // waited longest among equals).
+    // step buffers, or bringing a moved-out stack back) is held back; it
+    // keeps its place at the front.  When every search is held back, the
+    // others' stacks go to host memory, largest first, until the search that
+    // waited longest fits with a fresh step scratch; only a search that does
+    // not fit even alone ends with FSP_E_NOMEM.
     std::vector<Search *> sel;
     std::vector<StepSel> qs;
     std::vector<char> picked(srv->active.size(), 0);
@@ -196,17 +197,62 @@ fsp_status fsp_server_step(fsp_server srv, int64_t *done_ids, int32_t done_cap, 
         picked[i] = 1;
         children += q.nch;
     }
-    if (sel.empty() && !srv->active.empty()) {
-        size_t victim = 0;
-        for (size_t i = 1; i < srv->active.size(); ++i)
-            if (srv->active[i]->S->device_bytes() > srv->active[victim]->S->device_bytes()) victim = i;
-        std::unique_ptr<Job> jp = std::move(srv->active[victim]);
-        srv->active.erase(srv->active.begin() + (std::ptrdiff_t)victim);
-        srv->finish(*jp, FSP_E_NOMEM);
-        report(jp->id);
-        picked.erase(picked.begin() + (std::ptrdiff_t)victim);
-    }
     fsp_status ret = FSP_OK;
+    if (sel.empty() && !srv->active.empty()) {
+        Search &F = *srv->active[0]->S;
+        const StepSel q0 = select_step(F);
+        TickContext fresh;
+        std::vector<Search *> one{&F};
+        std::vector<StepSel> oq{q0};
+        const size_t need = bytes_after_step(F, q0) + tick_scratch_after(one, oq, fresh);
+        size_t others = srv->search_bytes() - F.device_bytes();
+        std::vector<size_t> order;
+        for (size_t i = 1; i < srv->active.size(); ++i) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+            return srv->active[a]->S->device_bytes() > srv->active[b]->S->device_bytes();
+        });
+        for (size_t i : order) {
+            if (need + others <= budget) break;
+            Search &O = *srv->active[i]->S;
+            if (O.swapped) continue;
+            const size_t b0 = O.device_bytes();
+            hipError_t e = O.swap_out(srv->ctx.s);
+            if (e != hipSuccess) {
+                ret = fail_status(e);
+                break;
+            }
+            others = others - b0 + O.device_bytes();
+            ++srv->st.swap_outs;
+        }
+        if (ret == FSP_OK && need + others <= budget) {
+            srv->ctx.release();
+            sel.push_back(&F);
+            qs.push_back(q0);
+            picked[0] = 1;
+            children = q0.nch;
+        } else if (ret == FSP_OK) {
+            std::unique_ptr<Job> jp = std::move(srv->active[0]);
+            srv->active.erase(srv->active.begin());
+            srv->finish(*jp, FSP_E_NOMEM);
+            report(jp->id);
+            picked.erase(picked.begin());
+        }
+    }
+    // moved-out stacks of the stepped searches come back first
+    for (size_t i = 0; ret == FSP_OK && i < sel.size(); ++i) {
+        if (!sel[i]->swapped) continue;
+        hipError_t e = sel[i]->swap_in(srv->ctx.s);
+        if (e != hipSuccess) ret = fail_status(e);
+        else ++srv->st.swap_ins;
+    }
+    if (ret != FSP_OK) {
+        for (auto &jp : srv->active) {
+            srv->finish(*jp, ret);
+            report(jp->id);
+        }
+        srv->active.clear();
+        sel.clear();
+    }
     if (!sel.empty()) {
         std::vector<int64_t> before(sel.size());
         for (size_t i = 0; i < sel.size(); ++i) before[i] = sel[i]->nodes;

@@ -352,7 +352,52 @@ void Search::release(hipStream_t s)
 
 size_t Search::device_bytes() const
 {
-    return (size_t)cap_stack * (n + 1) * 4 + (size_t)n * 4 + B.bytes();
+    return (swapped ? 0 : (size_t)cap_stack * (n + 1) * 4) + (size_t)n * 4 + B.bytes();
+}
+
+hipError_t Search::swap_out(hipStream_t s)
+{
+    if (swapped) return hipSuccess;
+    host_rows.resize((size_t)top * n);
+    host_dep.resize((size_t)top);
+    hipError_t e = hipSuccess;
+    if (top > 0) {
+        e = hipMemcpyAsync(host_rows.data(), srows, (size_t)top * n * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(host_dep.data(), sdep, (size_t)top * 4, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    stream_free(srows, s);
+    stream_free(sdep, s);
+    srows = sdep = nullptr;
+    B.release(s);
+    swapped = true;
+    return hipSuccess;
+}
+
+hipError_t Search::swap_in(hipStream_t s)
+{
+    if (!swapped) return hipSuccess;
+    hipError_t e = stream_alloc((void **)&srows, (size_t)cap_stack * n * 4, s);
+    if (e == hipSuccess) e = stream_alloc((void **)&sdep, (size_t)cap_stack * 4, s);
+    if (e == hipSuccess) e = B.ensure_k(pool_cap, s);
+    if (e == hipSuccess) e = B.ensure_c(pool_cap, n, s);
+    if (e == hipSuccess && top > 0) {
+        e = hipMemcpyAsync(srows, host_rows.data(), (size_t)top * n * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(sdep, host_dep.data(), (size_t)top * 4, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        if (srows) stream_free(srows, s);
+        if (sdep) stream_free(sdep, s);
+        srows = sdep = nullptr;
+        B.release(s);
+        return e;
+    }
+    std::vector<int32_t>().swap(host_rows);
+    std::vector<int32_t>().swap(host_dep);
+    swapped = false;
+    return hipSuccess;
 }
 
 void Search::result(fsp_solve_result *res, int32_t *perm_out) const

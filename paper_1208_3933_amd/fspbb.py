@@ -98,7 +98,7 @@ class ServerConfig(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int32), ("pending", ctypes.c_int32), ("mem_used", ctypes.c_int64),
                 ("ticks", ctypes.c_int64), ("nodes_bounded", ctypes.c_int64), ("last_children", ctypes.c_int64),
-                ("last_searches", ctypes.c_int32)]
+                ("last_searches", ctypes.c_int32), ("swap_outs", ctypes.c_int64), ("swap_ins", ctypes.c_int64)]
 
 
 _lib = None

@@ -125,19 +125,66 @@ def test_memory_admission_limits_active_searches(setup):
                 foot = max(foot, st["mem_used"])
                 if srv.poll(i) is not None:
                     break
-    budget = int(1.2 * foot)  # below the sum of the footprints, above the largest
+    budget = int(1.2 * foot)  # above the largest footprint
+    # the memory of every request admitted at once, after their roots; enough
+    # copies of the request list, all arriving at once, that their initial
+    # footprints alone exceed the budget
+    with fspbb.server_create(1 << 34, 64) as srv:
+        for inst, r in zip(insts, reqs):
+            srv.submit(inst, r["ub0"], r["pool_cap"], r["budget"])
+        _, st = srv.step()
+        first = st["mem_used"]
+    copies = min(8, max(2, -(-3 * budget // first)))
     seen = []
 
     def check(stats):
         assert stats["mem_used"] <= budget
         seen.append((stats["active"], stats["pending"]))
 
-    served = run_served(insts, reqs, budget, 64, 0, arrivals_per_step=12, check=check)
+    served = run_served(insts * copies, reqs * copies, budget, 64, 0, arrivals_per_step=len(reqs) * copies,
+                        check=check)
     assert max(a for a, _ in seen) >= 2
     # with 64 slots free, only the memory budget holds searches back
-    assert any(p > 0 for _, p in seen)
-    for k, (a, s) in enumerate(zip(alone, served)):
+    assert any(p > 0 for _, p in seen), (budget, first, copies)
+    for k, (a, s) in enumerate(zip(alone * copies, served)):
         assert same(a, s), k
+
+
+def test_tight_budget_moves_stacks_to_host():
+    """Three copies of a search whose stack grows eightfold (100 jobs, no upper
+    bound, pool_cap 64, stopped by a node budget) under a budget just above
+    its largest footprint alone: admitted together on their initial
+    footprints, they cannot all grow, so held-back searches' stacks go to host
+    memory and come back later.  Every result is still the search's alone."""
+    require_gpu()
+    inst = fspbb.create_instance(times(100, 5, 202))
+    try:
+        alone = fspbb.solve(inst, fspbb.UB_NONE, 64, 60000)
+        assert alone["status"] == fspbb.BUDGET and alone["max_stack"] > 4096
+        with fspbb.server_create(1 << 34, 1) as srv:
+            i = srv.submit(inst, fspbb.UB_NONE, 64, 60000)
+            foot = 0
+            while True:
+                _, st = srv.step()
+                foot = max(foot, st["mem_used"])
+                if srv.poll(i) is not None:
+                    break
+        budget = int(1.05 * foot)
+        results, last, most = {}, None, 0
+        with fspbb.server_create(budget, 8) as srv:
+            ids = [srv.submit(inst, fspbb.UB_NONE, 64, 60000) for _ in range(3)]
+            while len(results) < 3:
+                done, last = srv.step()
+                most = max(most, last["active"])
+                assert last["mem_used"] <= budget
+                for j in done:
+                    results[j] = srv.poll(j)
+        for j in ids:
+            assert same(alone, results[j]), results[j]
+        assert most >= 2
+        assert last["swap_outs"] >= 1 and last["swap_ins"] >= 1
+    finally:
+        inst.close()
 
 
 def test_children_cap_and_slots(setup):
@@ -178,13 +225,14 @@ def test_poll_and_submit_errors(setup):
 
 
 def test_memory_budget_holds_growth_back():
-    """A search whose stack must double past the budget (60 jobs, no upper
-    bound, pool_cap 128: its stack outgrows the initial 1,024 rows) ends with
-    FSP_E_NOMEM instead of taking the memory, alone and in a mix; the small
-    search beside it gives the same result as alone; the memory in use never
-    passes the budget."""
+    """A search whose stack must double past the budget (200 jobs, no upper
+    bound, pool_cap 128: its stack outgrows the initial 1,024 rows within a
+    few steps, and each doubling adds more than the shared step scratch could
+    give back) ends with FSP_E_NOMEM instead of taking the memory, alone and
+    in a mix; the small search beside it gives the same result as alone; the
+    memory in use never passes the budget."""
     require_gpu()
-    big = fspbb.create_instance(times(60, 5, 201))
+    big = fspbb.create_instance(times(200, 5, 201))
     small_p = times(8, 4, 0)
     small = fspbb.create_instance(small_p)
     try:
