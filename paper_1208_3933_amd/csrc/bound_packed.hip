@@ -111,6 +111,14 @@ __global__ __launch_bounds__(256) void depth_scatter_kernel(const int32_t *__res
     depth_scatter_block(depths, N, n, chunk, B, cnt, order, blockIdx.x, sh);
 }
 
+void launch_depth_sort(const int32_t *depths, int64_t N, int n, int B, int64_t chunk, uint32_t *cnt, int32_t *order,
+                       hipStream_t s)
+{
+    const size_t hb = (size_t)(n + 2) * 4, sb = ((size_t)(n + 2) * 2 + 256) * 4;
+    depth_count_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, cnt);
+    depth_scatter_kernel<<<B, 256, sb, s>>>(depths, N, n, chunk, B, cnt, order);
+}
+
 // ---- decode: one lane per node, nodes taken in depth order
 //
 // Computes for each node its scheduled set (rejecting out-of-range and
@@ -315,6 +323,225 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
 {
     extern __shared__ uint32_t sm[];
     decode16_block<MV>(T, prefixes, depths, N, Npad, W, out_lb, blockIdx.x, sm);
+}
+
+// ---- decode with four lanes per node, for pools too small to fill the chip
+//
+// The one-lane decode above is latency-bound on a small pool: each lane walks
+// its whole prefix through all m machines one job at a time.  Here the four
+// lanes of a node (an aligned quad) split the machines, lane q holding
+// machines [q*MQ, (q+1)*MQ), and the completion-time recurrence of the prefix
+// runs as a pipeline across them: at step s lane q takes job s - q, with the
+// completion time on the machine before its first one handed over by lane
+// q - 1 (a one-lane DPP shift).  The jobs travel down the quad the same way;
+// lane 0 reads them from the prefix row, checks their range, and sets the
+// scheduled bits (LDS ORs that return nothing; a repeated job shows at the
+// end as fewer set bits than the depth).  A step past the prefix, or before a lane's first job, takes
+// the zero row: it leaves the completion times unchanged, because they never
+// decrease along the machines.  The tails split the jobs instead (job j to
+// lane j mod 4), with packed 16-bit minima combined across the quad.
+//
+// Writes the scan workspace in the layout of the one-lane decode (nodes in
+// pool order), and out_lb = 0 for every valid node so that a scan split over
+// several workgroups can combine by atomic max; FSP_LB_INVALID otherwise.
+// One block of 256 threads per 64 nodes; Npad is a multiple of 64.
+template <int MV>
+__global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const int32_t *__restrict__ prefixes,
+                                                             const int32_t *__restrict__ depths, int64_t N,
+                                                             Workspace16 W, int32_t *__restrict__ out_lb)
+{
+    constexpr int MQ = MV / 4;  // machines per lane
+    constexpr int H = MV / 2;   // packed tail pairs per job
+    extern __shared__ uint32_t sm[];
+    const int n = T.n, m = T.m, NW = (n + 31) >> 5;
+    int32_t *pl = reinterpret_cast<int32_t *>(sm);   // (n + 1) x MV times; row n is zero
+    uint32_t *tq = sm + (n + 1) * MV;                 // n x H packed tails
+    uint32_t *bits = tq + n * H;                      // 64 nodes x NW scheduled-job words
+    const int tid = threadIdx.x, q = tid & 3, nl = tid >> 2;
+    for (int e = tid; e < (n + 1) * MV; e += 256) {
+        const int j = e / MV, k = e - j * MV;
+        pl[e] = j < n ? T.p32[(size_t)j * kMaxMachines + k] : 0;
+    }
+    for (int e = tid; e < n * H; e += 256) {
+        const int j = e / H, c = e - j * H;
+        tq[e] = T.tails16[(size_t)j * (kMaxMachines / 2) + c];
+    }
+    for (int e = tid; e < 64 * NW; e += 256) bits[e] = 0u;
+    __syncthreads();
+
+    const int64_t node = (int64_t)blockIdx.x * 64 + nl;
+    const bool live = node < N;
+    int d = live ? depths[node] : 0;
+    bool ok = live && d >= 0 && d <= n;
+    if (!ok) d = 0;
+    const int32_t *row = prefixes + (live ? node : 0) * (int64_t)n;
+    uint32_t *mybits = bits + nl * NW;
+
+    int32_t C[MQ], S[MQ];
+#pragma unroll
+    for (int kk = 0; kk < MQ; ++kk) { C[kk] = 0; S[kk] = 0; }
+    // wave-uniform step count: the deepest prefix of the wave plus the pipeline fill
+    int smax = d + 3;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) smax = max(smax, __shfl_xor(smax, off));
+
+    // lane 0's job at step s is row[s] (s < d), else the zero row; prefix
+    // entries come four at a time with the next four in flight
+    auto fetch4 = [&](int s0, int32_t (&v)[4]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = row[min(s0 + c, n - 1)];
+    };
+    auto inject = [&](int s, int32_t jraw) -> int32_t {
+        int32_t j = n;
+        if (q == 0 && s < d) {
+            if ((unsigned)jraw < (unsigned)n) {
+                atomicOr(&mybits[jraw >> 5], 1u << (jraw & 31));  // no return: nothing waits on it
+                j = jraw;
+            } else {
+                ok = false;
+            }
+        }
+        return j;
+    };
+    int32_t cur[4], nxt[4];
+    fetch4(0, cur);
+    fetch4(4, nxt);
+    // job of this lane for the coming step and its times (loaded one step
+    // ahead, so that the LDS reads overlap the step before)
+    int32_t job = inject(0, cur[0]);
+    int32_t x[MQ];
+#pragma unroll
+    for (int kk = 0; kk < MQ; ++kk) x[kk] = pl[job * MV + q * MQ + kk];
+    int32_t last = 0;  // completion on this lane's last machine of its previous job
+    for (int s4 = 0; s4 < smax; s4 += 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int s = s4 + c;
+            // next step: lane q takes the job lane q-1 does now
+            const int32_t jl = __builtin_amdgcn_mov_dpp(job, 0x111, 0xf, 0xf, true);  // row_shr:1
+            const int32_t ji = inject(s + 1, c < 3 ? cur[c + 1] : nxt[0]);
+            const int32_t jn = q == 0 ? ji : jl;
+            int32_t xn[MQ];
+#pragma unroll
+            for (int kk = 0; kk < MQ; ++kk) xn[kk] = pl[jn * MV + q * MQ + kk];
+            // completion on the machine before this lane's first, for this job
+            const int32_t fromleft = __builtin_amdgcn_mov_dpp(last, 0x111, 0xf, 0xf, true);
+            int32_t prev = q == 0 ? 0 : fromleft;
+#pragma unroll
+            for (int kk = 0; kk < MQ; ++kk) {
+                const int32_t ck = max(C[kk], prev) + x[kk];
+                C[kk] = ck;
+                prev = ck;
+                S[kk] += x[kk];
+            }
+            last = prev;
+            job = jn;
+#pragma unroll
+            for (int kk = 0; kk < MQ; ++kk) x[kk] = xn[kk];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
+        fetch4(s4 + 8, nxt);
+    }
+    __syncthreads();
+
+    // a repeated job shows as fewer scheduled bits than the depth; validity
+    // (with lane 0's range checks) is broadcast over the quad
+    int nset = 0;
+    for (int w = 0; w < NW; ++w) nset += __popc(mybits[w]);
+    ok = ok && nset == d;
+    ok = __builtin_amdgcn_mov_dpp((int)ok, 0x00, 0xf, 0xf, false) != 0;  // quad_perm [0,0,0,0]
+
+    // tails: lane q takes jobs j = 32w + q + 4i, packed 16-bit minima over (Q | off)
+    uint32_t q2[H];
+#pragma unroll
+    for (int c = 0; c < H; ++c) q2[c] = 0xffffffffu;
+    for (int w = 0; w < NW; ++w) {
+        const int lo = w * 32;
+        const uint32_t valid = n >= lo + 32 ? 0xffffffffu : ((1u << (n - lo)) - 1u);
+        const uint32_t un = ~mybits[w] & valid;
+        for (int b = q; b < 32 && lo + b < n; b += 4) {
+            const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)un, b, 1);
+            const uint32_t *tr = tq + (lo + b) * H;
+#pragma unroll
+            for (int c = 0; c < H; ++c) q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(tr[c] | off)));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+        q2[c] = as32(__builtin_elementwise_min(as16(q2[c]),
+                                               as16((uint32_t)__builtin_amdgcn_mov_dpp((int)q2[c], 0xb1, 0xf, 0xf,
+                                                                                      false))));  // [1,0,3,2]
+        q2[c] = as32(__builtin_elementwise_min(as16(q2[c]),
+                                               as16((uint32_t)__builtin_amdgcn_mov_dpp((int)q2[c], 0x4e, 0xf, 0xf,
+                                                                                      false))));  // [2,3,0,1]
+    }
+
+    const bool empty = d == n;  // no unscheduled job: every tail is 0
+    const int64_t G = node >> 7;
+    const int g = (int)(node & 127), lane = g & 63, half = g >> 6;
+    uint16_t *d16 = reinterpret_cast<uint16_t *>(W.dec);
+    cptr<int32_t> cs = as_const(T.colsum32);
+#pragma unroll
+    for (int kk = 0; kk < MQ; ++kk) {
+        const int k = q * MQ + kk;
+        if (k < m) {
+            const uint32_t qk = (q2[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+            d16[((G * 3 + 0) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[kk] : 0);
+            d16[((G * 3 + 1) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok ? C[kk] + (cs[k] - S[kk]) : 0);
+            d16[((G * 3 + 2) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok && !empty ? qk : 0u);
+        }
+    }
+    for (int w = q; w < NW; w += 4) {
+        const int lo = w * 32;
+        const uint32_t valid = n >= lo + 32 ? 0xffffffffu : ((1u << (n - lo)) - 1u);
+        W.flg[(G * NW + w) * 128 + g] = ok ? (~mybits[w] & valid) : 0u;
+    }
+    if (q == 0) {
+        W.st[node] = ok ? 1u : 0u;
+        if (live) {
+            out_lb[node] = ok ? 0 : FSP_LB_INVALID;
+            if (!ok) atomicAdd(T.bad, 1ull);
+        }
+    }
+}
+
+// LDS bytes of decode16_lanes_kernel for n jobs and MV machine slots.
+inline size_t decode16_lanes_lds(int n, int MV)
+{
+    return ((size_t)(n + 1) * MV + (size_t)n * (MV / 2) + (size_t)64 * ((n + 31) >> 5)) * 4;
+}
+
+// How a pool is decoded and scanned.  Below one serial-decode wave per SIMD
+// the one-lane decode is latency-bound, so smaller pools take the four-lane
+// decode (nodes in pool order, no depth sort); a pool of fewer
+// groups than two per compute unit also splits each group's machine pairs
+// over several workgroups (at least four pairs per wave and chain), which
+// needs the four-lane decode's zeroed bounds.
+struct PoolPlan {
+    bool lanes;  // four-lane decode
+    int splits;  // pair splits of the scan
+};
+
+static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+            cus = c;
+        else
+            cus = 256;
+    }
+    int cap = 16;
+    if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: the regular path only
+    int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
+    if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
+    if (I->dt.heads || cap <= 1 || N >= lanes_below) return PoolPlan{false, 1};
+    int sp = 1;
+    while (sp < cap && G * sp < 2 * cus && 4 * 2 * sp <= I->P) sp *= 2;
+    return PoolPlan{true, sp};
 }
 
 // ---- batched bounding: many pools in one decode launch per machine-count
@@ -544,37 +771,76 @@ int batch_scan_blocks_per_cu(size_t lds_bytes)
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
-                               int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths)
+namespace {
+// Section sizes of the 16-bit workspace for N nodes, each rounded up to 256 bytes.
+struct PackedWsLayout {
+    size_t dec, flg, st, ord, cnt;
+    size_t total() const { return dec + flg + st + ord + cnt; }
+};
+
+PackedWsLayout packed_ws_layout(const fsp_instance_s *I, int64_t N)
 {
-    if (N <= 0) return hipSuccess;
     const int n = I->n, m = I->m, NW = (n + 31) >> 5;
     const int64_t G = (N + kGroup - 1) / kGroup, Npad = G * kGroup;
     const int B = (int)std::min<int64_t>(kSortMaxBlocks, (N + 4095) / 4096);
-    const int64_t chunk = (N + B - 1) / B;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t dec_b = al((size_t)G * 3 * m * 64 * 4), flg_b = al((size_t)G * NW * 128 * 4),
-                 st_b = al((size_t)Npad * 4), ord_b = al((size_t)N * 4), cnt_b = al((size_t)(n + 2) * B * 4);
-    void *ws = nullptr;
-    hipError_t e = stream_alloc((void **)&ws, dec_b + flg_b + st_b + ord_b + cnt_b, s);
-    if (e != hipSuccess) return e;
+    return PackedWsLayout{al((size_t)G * 3 * m * 64 * 4), al((size_t)G * NW * 128 * 4), al((size_t)Npad * 4),
+                          al((size_t)N * 4), al((size_t)(n + 2) * B * 4)};
+}
+}  // namespace
+
+size_t packed_workspace_bytes(const fsp_instance_s *I, int64_t N)
+{
+    return N > 0 ? packed_ws_layout(I, N).total() : 0;
+}
+
+hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths, int64_t N,
+                                  int32_t *out_lb, hipStream_t s, bool sort_depths, void *ws, bool marks)
+{
+    if (N <= 0) return hipSuccess;
+    const int n = I->n, m = I->m;
+    const int64_t G = (N + kGroup - 1) / kGroup, Npad = G * kGroup;
+    const int B = (int)std::min<int64_t>(kSortMaxBlocks, (N + 4095) / 4096);
+    const int64_t chunk = (N + B - 1) / B;
+    const PackedWsLayout L = packed_ws_layout(I, N);
+    // every section is written in full before it is read (the count kernel
+    // writes all n + 2 buckets of its block, the decode every node slot of
+    // the padded pool), so the workspace needs no clearing
     char *w = (char *)ws;
     Workspace16 W;
     W.dec = (uint32_t *)w;
-    W.flg = (uint32_t *)(w + dec_b);
-    W.st = (uint32_t *)(w + dec_b + flg_b);
-    W.order = sort_depths ? (int32_t *)(w + dec_b + flg_b + st_b) : nullptr;
-    W.cnt = (uint32_t *)(w + dec_b + flg_b + st_b + ord_b);
+    W.flg = (uint32_t *)(w + L.dec);
+    W.st = (uint32_t *)(w + L.dec + L.flg);
+    W.order = sort_depths ? (int32_t *)(w + L.dec + L.flg + L.st) : nullptr;
+    W.cnt = (uint32_t *)(w + L.dec + L.flg + L.st + L.ord);
 
-    timing_mark(I, 0, s);
-    if (sort_depths) {
-        const size_t hb = (size_t)(n + 2) * 4, sb = ((size_t)(n + 2) * 2 + 256) * 4;
-        depth_count_kernel<<<B, 256, hb, s>>>(depths, N, n, chunk, B, W.cnt);
-        depth_scatter_kernel<<<B, 256, sb, s>>>(depths, N, n, chunk, B, W.cnt, W.order);
+    const int MV = (m + 3) & ~3;
+    const PoolPlan plan = pool_plan(I, N, G);
+    if (plan.lanes) {
+        // four lanes per node in pool order, then the pairs of each group,
+        // split over several workgroups when the groups are few
+        W.order = nullptr;
+        if (marks) timing_mark(I, 0, s);
+        const dim3 lgrid((unsigned)(Npad / 64));
+        const size_t llds = decode16_lanes_lds(n, MV);
+#define FSP_LDECODE(MVV) \
+    case MVV: decode16_lanes_kernel<MVV><<<lgrid, 256, llds, s>>>(I->dt, prefixes, depths, N, W, out_lb); break;
+        switch (MV) {
+            FSP_LDECODE(4) FSP_LDECODE(8) FSP_LDECODE(12) FSP_LDECODE(16)
+            FSP_LDECODE(20) FSP_LDECODE(24) FSP_LDECODE(28) FSP_LDECODE(32)
+        }
+#undef FSP_LDECODE
+        hipError_t e = hipGetLastError();
+        if (marks) timing_mark(I, 1, s);
+        if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s, plan.splits);
+        if (marks) timing_mark(I, 2, s);
+        return e;
     }
 
+    if (marks) timing_mark(I, 0, s);
+    if (sort_depths) launch_depth_sort(depths, N, n, B, chunk, W.cnt, W.order, s);
+
     const dim3 dgrid((unsigned)((Npad + 255) / 256)), dblock(256);
-    const int MV = (m + 3) & ~3;
     const size_t dlds = decode16_lds_words(n, MV) * 4;
 #define FSP_DECODE(MVV) \
     case MVV: bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb); break;
@@ -583,10 +849,21 @@ hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const
         FSP_DECODE(20) FSP_DECODE(24) FSP_DECODE(28) FSP_DECODE(32)
     }
 #undef FSP_DECODE
-    e = hipGetLastError();
-    timing_mark(I, 1, s);
+    hipError_t e = hipGetLastError();
+    if (marks) timing_mark(I, 1, s);
     if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s);
-    timing_mark(I, 2, s);
+    if (marks) timing_mark(I, 2, s);
+    return e;
+}
+
+hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
+                               int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths)
+{
+    if (N <= 0) return hipSuccess;
+    void *ws = nullptr;
+    hipError_t e = stream_alloc(&ws, packed_workspace_bytes(I, N), s);
+    if (e != hipSuccess) return e;
+    e = launch_bound_packed_ws(I, prefixes, depths, N, out_lb, s, sort_depths, ws, true);
     hipError_t e2 = stream_free(ws, s);
     return e != hipSuccess ? e : e2;
 }

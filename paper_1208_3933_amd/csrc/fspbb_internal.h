@@ -82,6 +82,12 @@ hipError_t launch_bound_lane32(fsp_instance_s *I, const int32_t *prefixes, const
 // evens out the per-lane prefix loops of pools of mixed depths.
 hipError_t launch_bound_packed(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
                                int64_t N, int32_t *out_lb, hipStream_t s, bool sort_depths = true);
+// The same over a caller-provided workspace (256-byte aligned, at least
+// packed_workspace_bytes(I, N) bytes); allocates nothing when marks is false
+// (the timing marks create events).
+size_t packed_workspace_bytes(const fsp_instance_s *I, int64_t N);
+hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths, int64_t N,
+                                  int32_t *out_lb, hipStream_t s, bool sort_depths, void *ws, bool marks);
 
 hipError_t launch_bound_wavepair(fsp_instance_s *I, const int32_t *prefixes, const int32_t *depths,
                                  int64_t N, int32_t *out_lb, hipStream_t s);

@@ -10,6 +10,7 @@
 // maxima through LDS at the end.  The Johnson-with-lags order of a pair is the
 // same for every node, so the per-slot records (mask-row offset, lag + a,
 // b - a) are wave-uniform scalar loads; only the mask is per lane.
+#include <algorithm>
 #include <cstdlib>
 
 #include "batch.h"
@@ -17,9 +18,13 @@
 
 namespace fspbb {
 
+// Grid (groups, splits): workgroup (G, y) scans pairs [y * pps, (y+1) * pps)
+// of group G.  With one split it writes each bound; with several, each split
+// takes its partial maximum into out_lb with an atomic max (out_lb holds 0
+// for every valid node beforehand, written by the decode).
 template <int WAVES, int UNR, bool ADDTID, int NCH>
 __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, Workspace16 W, int64_t N,
-                                                                  int32_t *__restrict__ out_lb)
+                                                                  int32_t *__restrict__ out_lb, int pps)
 {
     extern __shared__ uint32_t lds[];  // (n + 1) rows x 64 lanes; row n stays zero
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
@@ -27,15 +32,18 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t G = blockIdx.x;
 
-    for (int j = wave; j <= n; j += WAVES) {
-        uint32_t m2 = 0;
-        if (j < n) {
-            const uint32_t *fw = W.flg + (G * NW + (j >> 5)) * 128;
-            const uint32_t a = (fw[lane] >> (j & 31)) & 1u, b = (fw[64 + lane] >> (j & 31)) & 1u;
-            m2 = (a ? 0x0000ffffu : 0u) | (b ? 0xffff0000u : 0u);
+    // the mask rows from the unscheduled bits: each lane reads its two nodes'
+    // bit words once per 32 jobs (all loads first), then expands them
+    for (int w = wave; w < NW; w += WAVES) {
+        const uint32_t *fw = W.flg + (G * NW + w) * 128;
+        const uint32_t a = fw[lane], b = fw[64 + lane];
+        const int jn = min(32, n - 32 * w);
+        for (int t = 0; t < jn; ++t) {
+            const uint32_t m2 = (((a >> t) & 1u) ? 0x0000ffffu : 0u) | (((b >> t) & 1u) ? 0xffff0000u : 0u);
+            lds[(32 * w + t) * 64 + lane] = m2;
         }
-        lds[j * 64 + lane] = m2;
     }
+    if (wave == WAVES - 1) lds[n * 64 + lane] = 0u;  // the zero row of padding slots
     __syncthreads();
 
     const unsigned char *lds_lane = reinterpret_cast<const unsigned char *>(lds) + lane * 4;
@@ -47,8 +55,9 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
     const uint32_t *dQ = dT + m * 64;
     cptr<int32_t> pairs = as_const(T.pairs);
     u16x2 lb = {0, 0};
-    int pr = wave;
-    for (; pr + (NCH - 1) * WAVES < T.P; pr += NCH * WAVES) {
+    const int p0 = (int)blockIdx.y * pps, p1 = min(T.P, p0 + pps);
+    int pr = p0 + wave;
+    for (; pr + (NCH - 1) * WAVES < p1; pr += NCH * WAVES) {
         int prs[NCH];
         u16x2 s[NCH];
         uint32_t tk[NCH], ql[NCH];
@@ -64,7 +73,7 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) lb = __builtin_elementwise_max(lb, as16(tk[ch]) + s[ch] + as16(ql[ch]));
     }
-    for (; pr < T.P; pr += WAVES) {  // fewer than NCH pairs left for this wave
+    for (; pr < p1; pr += WAVES) {  // fewer than NCH pairs left for this wave
         const int prs[1] = {pr};
         const int k = pairs[2 * pr], l = pairs[2 * pr + 1];
         u16x2 s[1] = {as16(dR[l * 64]) - as16(dR[k * 64])};
@@ -80,8 +89,13 @@ __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, W
 #pragma unroll
         for (int w = 1; w < WAVES; ++w) best = __builtin_elementwise_max(best, as16(lds[w * 64 + lane]));
         const int64_t a = G * 128 + lane, b = a + 64;
-        if (a < N && W.st[a]) out_lb[W.order ? W.order[a] : a] = (int32_t)best.x;
-        if (b < N && W.st[b]) out_lb[W.order ? W.order[b] : b] = (int32_t)best.y;
+        if (gridDim.y == 1) {
+            if (a < N && W.st[a]) out_lb[W.order ? W.order[a] : a] = (int32_t)best.x;
+            if (b < N && W.st[b]) out_lb[W.order ? W.order[b] : b] = (int32_t)best.y;
+        } else {
+            if (a < N && W.st[a]) atomicMax(&out_lb[W.order ? W.order[a] : a], (int32_t)best.x);
+            if (b < N && W.st[b]) atomicMax(&out_lb[W.order ? W.order[b] : b], (int32_t)best.y);
+        }
     }
 }
 
@@ -120,44 +134,59 @@ static bool scan_addtid()
 
 template <int WAVES, bool ADDTID>
 static void launch_scan_u(int unr, dim3 grid, size_t lds_b, hipStream_t s, const DevTables &dt,
-                          const Workspace16 &W, int64_t N, int32_t *out_lb)
+                          const Workspace16 &W, int64_t N, int32_t *out_lb, int pps)
 {
     const dim3 block(64 * WAVES);
     const int nch = scan_chains();
     if (unr == 16 && nch == 2)
-        bound_scan16_kernel<WAVES, 16, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+        bound_scan16_kernel<WAVES, 16, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
     else if (unr == 16)
-        bound_scan16_kernel<WAVES, 16, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+        bound_scan16_kernel<WAVES, 16, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
     else if (nch == 2)
-        bound_scan16_kernel<WAVES, 8, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+        bound_scan16_kernel<WAVES, 8, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
     else
-        bound_scan16_kernel<WAVES, 8, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb);
+        bound_scan16_kernel<WAVES, 8, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
 }
 
 template <int WAVES>
 static void launch_scan(int unr, dim3 grid, size_t lds_b, hipStream_t s, const DevTables &dt, const Workspace16 &W,
-                        int64_t N, int32_t *out_lb)
+                        int64_t N, int32_t *out_lb, int pps)
 {
     if (scan_addtid())
-        launch_scan_u<WAVES, true>(unr, grid, lds_b, s, dt, W, N, out_lb);
+        launch_scan_u<WAVES, true>(unr, grid, lds_b, s, dt, W, N, out_lb, pps);
     else
-        launch_scan_u<WAVES, false>(unr, grid, lds_b, s, dt, W, N, out_lb);
+        launch_scan_u<WAVES, false>(unr, grid, lds_b, s, dt, W, N, out_lb, pps);
 }
 
-hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s)
+hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s,
+                         int splits)
 {
     if (N <= 0) return hipSuccess;
-    const int n = I->n;
-    const int waves = scan_waves(I);
+    const int n = I->n, P = I->P;
+    if (splits < 1) splits = 1;
+    if (splits > P) splits = P;
+    const int pps = (P + splits - 1) / splits;
+    splits = (P + pps - 1) / pps;
+    // one group per workgroup: the tuned waves; a split: about four pairs per
+    // wave and chain of its share (the rule of thumb), at most the tuned waves
+    int waves = scan_waves(I);
+    if (splits > 1) {
+        // about ppw pairs per wave (two chains each) of the split's share
+        int ppw = 4;
+        if (const char *e = getenv("FSPBB_SPLIT_PAIRS_PER_WAVE")) ppw = std::max(1, atoi(e));
+        int w = 1;
+        while (w < 16 && ppw * w < pps) w *= 2;
+        waves = w;
+    }
     const size_t lds_b = (size_t)((n + 1) > waves ? (n + 1) : waves) * 256;
-    const dim3 grid((unsigned)((N + kGroup - 1) / kGroup));
+    const dim3 grid((unsigned)((N + kGroup - 1) / kGroup), (unsigned)splits);
     const int unr = scan_unroll();
     switch (waves) {
-    case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-    case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-    case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-    case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
-    default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb); break;
+    case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
+    case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
+    case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
+    case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
+    default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
     }
     return hipGetLastError();
 }

@@ -14,8 +14,18 @@ struct Workspace16 {
     uint32_t *cnt;    // (n + 2) x B: per-block depth counts, then scatter offsets
 };
 
+// Counting sort of a pool's node indices by depth (invalid depths last):
+// B blocks of `chunk` nodes, per-block counts in cnt ((n + 2) x B words),
+// the sorted indices in order (N).  Two launches.
+void launch_depth_sort(const int32_t *depths, int64_t N, int n, int B, int64_t chunk, uint32_t *cnt, int32_t *order,
+                       hipStream_t s);
+
 // The 16-bit scan alone over a decoded workspace of N nodes (identity order
-// unless W.order is set), bounds to out_lb.
-hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s);
+// unless W.order is set), bounds to out_lb.  splits > 1 divides the machine
+// pairs of each group between that many workgroups, which combine their
+// maxima into out_lb by atomic max: out_lb must then hold 0 for every valid
+// node beforehand.
+hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s,
+                         int splits = 1);
 
 }  // namespace fspbb

@@ -1,0 +1,101 @@
+"""Pools too small to fill the chip (fewer 128-node groups than compute
+units) take the four-lanes-per-node decode and a scan whose machine pairs are
+split over several workgroups, combined by atomic max.  Bounds are integers:
+every one is compared bit-exactly with the oracle, and with the regular
+one-lane decode and one-workgroup-per-group scan (FSPBB_SMALL_SPLITS=1) on the
+same pool.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import oracle_bounds, require_gpu, to_dev
+from paper_1208_3933_amd import fspbb, gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _bounds(torch, inst, pre, dep, regular=False):
+    pre_d, dep_d = to_dev(torch, pre, dep)
+    out = torch.full((dep.shape[0],), -7, dtype=torch.int32, device="cuda")
+    old = os.environ.get("FSPBB_SMALL_SPLITS")
+    if regular:
+        os.environ["FSPBB_SMALL_SPLITS"] = "1"
+    try:
+        fspbb.bound_pool(inst, pre_d, dep_d, out)
+        torch.cuda.synchronize()
+    finally:
+        if regular:
+            if old is None:
+                del os.environ["FSPBB_SMALL_SPLITS"]
+            else:
+                os.environ["FSPBB_SMALL_SPLITS"] = old
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,m", [(20, 5), (50, 10), (200, 20), (100, 5), (1, 2), (7, 32), (33, 3), (64, 17)])
+@pytest.mark.parametrize("N", [1, 63, 64, 129, 1000, 4096])
+def test_small_pool_parity(n, m, N):
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(19, n * 100 + m, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(19, n * 100 + m + N, gen.PURPOSE_POOL), 0, n)
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 1
+        got = _bounds(torch, inst, pre, dep)
+        reg = _bounds(torch, inst, pre, dep, regular=True)
+        assert fspbb.pool_status(inst) == 0
+    bad = np.nonzero(got != reg)[0]
+    assert bad.size == 0, f"{bad.size} differ from the regular path, first {bad[:5]}: {got[bad[:5]]} vs {reg[bad[:5]]}"
+    if n * N <= 200 * 1000:
+        want = oracle_bounds(p, pre, dep)
+    else:
+        idx = np.arange(0, N, 7)
+        want, got = oracle_bounds(p, pre[idx], dep[idx]), got[idx]
+    assert (got == want).all()
+
+
+@pytest.mark.parametrize("n,m,N", [(200, 20, 4096), (500, 20, 2048), (512, 32, 700), (200, 20, 32000)])
+def test_small_pool_large_shapes_sampled(n, m, N):
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(20, n * 100 + m, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(20, n * 100 + m, gen.PURPOSE_POOL), 0, n)
+    with fspbb.create_instance(p) as inst:
+        got = _bounds(torch, inst, pre, dep)
+        reg = _bounds(torch, inst, pre, dep, regular=True)
+    assert (got == reg).all()
+    idx = np.unique(gen.splitmix64(gen.make_seed(20, n, 9), 400) % np.uint64(N)).astype(np.int64)
+    assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
+
+
+def test_small_pool_invalid_nodes_and_leaves():
+    torch = require_gpu()
+    n, m, N = 30, 6, 300
+    p = gen.processing_times(n, m, gen.make_seed(21, 0, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(21, 0, gen.PURPOSE_POOL), 0, n)
+    pre, dep = pre.copy(), dep.copy()
+    dep[0] = n + 1                          # depth out of range
+    dep[1] = -2
+    dep[2] = 6; pre[2, 5] = pre[2, 1]        # repeated job
+    dep[3] = 4; pre[3, 3] = n                # job out of range
+    dep[4] = 3; pre[4, 0] = -1               # negative job
+    dep[5] = n                               # complete schedule: the makespan
+    dep[6] = 0                               # the root
+    want = oracle_bounds(p, pre, dep)
+    assert (want[:5] == oracle.INVALID).all()
+    with fspbb.create_instance(p) as inst:
+        got = _bounds(torch, inst, pre, dep)
+        assert fspbb.pool_status(inst) == 5
+    assert (got == want).all()
+    assert got[5] == oracle.makespan(p, pre[5]) and got[6] == oracle.bound(p, [])
+
+
+def test_small_pool_heads_instance_takes_the_regular_path():
+    torch = require_gpu()
+    n, m, N = 20, 10, 1500
+    p = gen.processing_times(n, m, gen.make_seed(22, 0, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(22, 0, gen.PURPOSE_POOL), 0, n)
+    with fspbb.create_instance(p, heads=True) as inst:
+        got = _bounds(torch, inst, pre, dep)
+    assert (got == oracle.bound_pool(p, pre, dep, heads=True)).all()
