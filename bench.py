@@ -274,12 +274,28 @@ def variants_leg(p, pre_d, dep_d, steps: int, stream, solve_seeds: int = 6) -> d
         with fspbb.create_instance(pp) as inst:
             o = b.new_empty(b.shape)
             for name, v in (("lane_per_two_nodes_u16", fspbb.VARIANT_PACKED16),
+                            ("lane_per_node_i32_lds_masks", fspbb.VARIANT_WIDE),
                             ("lane_per_node_i32", fspbb.VARIANT_LANE32), ("wave_per_node_i32", fspbb.VARIANT_WAVEPAIR)):
                 fspbb.bound_pool(inst, a, b, o, stream, variant=v)
                 t = _time(lambda: fspbb.bound_pool(inst, a, b, o, stream, variant=v), max(2, steps // 4))
                 row[name] = N / t
         mappings["%dx%d_pool%d" % (n, m, N)] = row
     out["mappings_nodes_per_s"] = mappings
+    # an instance past the 16-bit guard: 200 x 20 with times U[1,300] takes the
+    # 32-bit kernels; every bound of the default one equals the other's
+    pw = gen.processing_times(200, 20, gen.make_seed(18, 200, gen.PURPOSE_TIMES), 1, 300)
+    wrow = {}
+    with fspbb.create_instance(pw) as inst:
+        assert not inst.info()["packed16"]
+        o1, o2 = dep_d.new_empty(dep_d.shape), dep_d.new_empty(dep_d.shape)
+        for name, v, o in (("default_lane_per_node_i32_lds_masks", fspbb.VARIANT_AUTO, o1),
+                           ("lane_per_node_i32", fspbb.VARIANT_LANE32, o2)):
+            fspbb.bound_pool(inst, pre_d, dep_d, o, stream, variant=v)
+            t = _time(lambda: fspbb.bound_pool(inst, pre_d, dep_d, o, stream, variant=v), max(2, steps // 4))
+            wrow[name] = int(dep_d.shape[0]) / t
+        torch.cuda.synchronize()
+        wrow["same_bounds"] = bool((o1 == o2).all().item())
+    out["wide_values_200x20_pool262144_nodes_per_s"] = wrow
 
     if solve_seeds <= 0:
         return out

@@ -152,11 +152,13 @@ fsp_status fsp_pool_status(fsp_instance inst, void *stream, int64_t *n_bad);
 
 /*
  * fsp_bound_pool_variant - like fsp_bound_pool with an explicit kernel
- * variant (0 = automatic, 1 = general 32-bit lane-per-node kernel,
- * 2 = 16-bit packed decode+scan kernels, lane per two nodes, 3 = 32-bit
- * wave-per-node kernels, lane per machine pair).  Used by tests and the
- * benchmark to compare the mappings on the same pool.  FSP_E_INVAL for a
- * variant the instance cannot run (2 needs max_value < 65536).
+ * variant (0 = automatic: 2 when max_value < 65536, else 4; 1 = general
+ * 32-bit lane-per-node kernel with register bit sets, 2 = 16-bit packed
+ * decode+scan kernels, lane per two nodes, 3 = 32-bit wave-per-node kernels,
+ * lane per machine pair, 4 = 32-bit decode+scan kernels, lane per node, masks
+ * in LDS).  Used by tests and the benchmark to compare the mappings on the
+ * same pool.  FSP_E_INVAL for a variant the instance cannot run (2 needs
+ * max_value < 65536).
  */
 fsp_status fsp_bound_pool_variant(fsp_instance inst, const int32_t *prefixes,
                                   const int32_t *depths, int64_t N, int32_t *out_lb,

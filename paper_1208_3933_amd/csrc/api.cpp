@@ -5,6 +5,7 @@
 #include <mutex>
 
 #include "fspbb_internal.h"
+#include "bound_wide.h"
 
 using namespace fspbb;
 
@@ -224,16 +225,17 @@ fsp_status dispatch(fsp_instance inst, const int32_t *prefixes, const int32_t *d
     if (!inst || N < 0) return FSP_E_INVAL;
     if (N == 0) return FSP_OK;
     if (!prefixes || !depths || !out_lb) return FSP_E_INVAL;
-    if (variant == 0) variant = inst->packed16 ? 2 : 1;
+    if (variant == 0) variant = inst->packed16 ? 2 : 4;
     if (variant == 2 && !inst->packed16) return FSP_E_INVAL;
-    if (variant < 1 || variant > 3) return FSP_E_INVAL;
+    if (variant < 1 || variant > 4) return FSP_E_INVAL;
     DeviceGuard g(inst->device);
     if (!g.ok) return FSP_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;
     fsp_instance_s *I = const_cast<fsp_instance_s *>(inst);
     hipError_t e = variant == 1   ? launch_bound_lane32(I, prefixes, depths, N, out_lb, s)
                    : variant == 2 ? launch_bound_packed(I, prefixes, depths, N, out_lb, s)
-                                  : launch_bound_wavepair(I, prefixes, depths, N, out_lb, s);
+                   : variant == 3 ? launch_bound_wavepair(I, prefixes, depths, N, out_lb, s)
+                                  : launch_bound_wide(I, prefixes, depths, N, out_lb, s);
     if (e != hipSuccess) {
         set_last_error(e);
         return e == hipErrorOutOfMemory ? FSP_E_NOMEM : FSP_E_DEVICE;

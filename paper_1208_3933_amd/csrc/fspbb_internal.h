@@ -34,12 +34,20 @@ struct Rec16 {
     uint32_t ce;
 };
 
+// Per-slot record of the 32-bit scan with masks in LDS: the job's mask-row
+// offset (j * 256) and E, C as in Rec32.  npad slots per pair; padding slots
+// point at the all-zero row n with E = C = 0.
+struct RecW {
+    uint32_t joff;
+    int32_t E, C;
+};
+
 // Kernel-side view of an instance (passed by value).
 struct DevTables {
     int32_t n, m, P;
     int32_t npad;             // slots per pair in rec16 (n rounded up to 4)
     int32_t heads;            // 1: releases are the earliest starts of unscheduled jobs
-    int32_t pad0;
+    int32_t tails16ok;        // 1: every tail is below 65536, so tails16 is exact
     const int32_t *p32;       // (n+1) x 32, zero-padded; row n is zero (PTM)
     const int32_t *colsum32;  // 32: sum over all jobs of p[j][k], zero-padded
     const int32_t *tails32;   // n x 32: Q[j][l] = sum_{h>l} p[j][h], zero-padded
@@ -48,6 +56,7 @@ struct DevTables {
     const Rec32 *rec32;       // P x n
     const Rec32 *rec32sm;     // n x P: the same records slot-major (wave-per-node kernel)
     const Rec16 *rec16;       // P x npad
+    const RecW *recw;         // P x npad (32-bit scan with LDS masks)
     unsigned long long *bad;  // invalid-node counter
 };
 

@@ -107,6 +107,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     std::vector<int32_t> hp((size_t)(n + 1) * S, 0), colsum(S, 0), tails((size_t)n * S, 0), pairs(2 * P);
     std::vector<Rec32> rec32((size_t)P * n), rec32sm((size_t)n * P);
     std::vector<Rec16> rec16((size_t)P * npad);
+    std::vector<RecW> recw((size_t)P * npad);
     for (int j = 0; j < n; ++j)
         for (int k = 0; k < m; ++k) hp[(size_t)j * S + k] = p[j * m + k];
     for (int j = 0; j < n; ++j)
@@ -129,6 +130,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
             johnson_with_lags(p, n, m, k, l, order, lagv);
             for (int i = 0; i < npad; ++i) {
                 Rec16 r16{(uint32_t)n * 256u, 0u};  // padding: the all-zero mask row
+                RecW rw{(uint32_t)n * 256u, 0, 0};
                 if (i < n) {
                     int j = order[i];
                     int32_t a = p[j * m + k], b = p[j * m + l];
@@ -136,8 +138,10 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
                     rec32[(size_t)pr * n + i] = Rec32{(uint32_t)(j >> 5), (uint32_t)(j & 31), E, C};
                     rec32sm[(size_t)i * P + pr] = rec32[(size_t)pr * n + i];
                     r16 = Rec16{(uint32_t)j * 256u, ((uint32_t)E << 16) | ((uint32_t)C & 0xffffu)};
+                    rw = RecW{(uint32_t)j * 256u, E, C};
                 }
                 rec16[(size_t)pr * npad + i] = r16;
+                recw[(size_t)pr * npad + i] = rw;
             }
         }
     }
@@ -152,7 +156,8 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     size_t off_r32 = align(off_pr + pairs.size() * 4);
     size_t off_rsm = align(off_r32 + rec32.size() * sizeof(Rec32));
     size_t off_r16 = align(off_rsm + rec32sm.size() * sizeof(Rec32));
-    size_t off_bad = align(off_r16 + rec16.size() * sizeof(Rec16));
+    size_t off_rw = align(off_r16 + rec16.size() * sizeof(Rec16));
+    size_t off_bad = align(off_rw + recw.size() * sizeof(RecW));
     size_t total = align(off_bad + sizeof(unsigned long long));
     std::vector<unsigned char> blob(total, 0);
     std::memcpy(blob.data() + off_p, hp.data(), hp.size() * 4);
@@ -163,6 +168,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     std::memcpy(blob.data() + off_r32, rec32.data(), rec32.size() * sizeof(Rec32));
     std::memcpy(blob.data() + off_rsm, rec32sm.data(), rec32sm.size() * sizeof(Rec32));
     std::memcpy(blob.data() + off_r16, rec16.data(), rec16.size() * sizeof(Rec16));
+    std::memcpy(blob.data() + off_rw, recw.data(), recw.size() * sizeof(RecW));
 
     void *d = nullptr;
     e = hipMalloc(&d, total);
@@ -184,6 +190,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     I->flags = flags | (P < m * (m - 1) / 2 ? FSP_INSTANCE_PAIR_SUBSET : 0);
     I->dt.n = n; I->dt.m = m; I->dt.P = P; I->dt.npad = npad;
     I->dt.heads = (flags & FSP_INSTANCE_HEADS) ? 1 : 0;
+    I->dt.tails16ok = *std::max_element(tails.begin(), tails.end()) < 65536 ? 1 : 0;
     I->dt.p32 = (const int32_t *)(b + off_p);
     I->dt.colsum32 = (const int32_t *)(b + off_cs);
     I->dt.tails32 = (const int32_t *)(b + off_t);
@@ -192,6 +199,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     I->dt.rec32 = (const Rec32 *)(b + off_r32);
     I->dt.rec32sm = (const Rec32 *)(b + off_rsm);
     I->dt.rec16 = (const Rec16 *)(b + off_r16);
+    I->dt.recw = (const RecW *)(b + off_rw);
     I->dt.bad = (unsigned long long *)(b + off_bad);
     *out = I;
     return FSP_OK;

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "best_first.h"
+#include "bound_wide.h"
 #include "kids16.h"
 #include "search.h"
 
@@ -184,7 +185,7 @@ static hipError_t bound_rows(fsp_instance_s *I, const int32_t *rows, const int32
 {
     if (N <= 0) return hipSuccess;
     return I->packed16 ? launch_bound_packed(I, rows, depths, N, lb, s, sort_depths)
-                       : launch_bound_lane32(I, rows, depths, N, lb, s);
+                       : launch_bound_wide(I, rows, depths, N, lb, s, sort_depths);
 }
 
 // Whether one step bounds its children from their parents, with the

@@ -38,6 +38,7 @@ VARIANT_AUTO = 0
 VARIANT_LANE32 = 1
 VARIANT_PACKED16 = 2
 VARIANT_WAVEPAIR = 3
+VARIANT_WIDE = 4
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p

@@ -15,7 +15,7 @@ from paper_1208_3933_amd import fspbb, gen
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16, fspbb.VARIANT_WAVEPAIR]
+VARIANTS = [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16, fspbb.VARIANT_WAVEPAIR, fspbb.VARIANT_WIDE]
 
 
 def gpu_bounds(torch, inst, pre, dep, variant=fspbb.VARIANT_AUTO):
@@ -49,8 +49,9 @@ def test_200x20_full_pool_sampled_parity():
         got = gpu_bounds(torch, inst, pre, dep)                           # the benchmarked launch
         got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)   # the other kernel families
         gotwp = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WAVEPAIR)
+        gotw = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WIDE)
         assert fspbb.pool_status(inst) == 0
-    assert (got == got32).all() and (got == gotwp).all()
+    assert (got == got32).all() and (got == gotwp).all() and (got == gotw).all()
     idx = np.unique(gen.splitmix64(gen.make_seed(2, 0, 9), 3000) % np.uint64(N)).astype(np.int64)
     want = oracle_bounds(p, pre[idx], dep[idx])
     assert (got[idx] == want).all()
@@ -119,7 +120,7 @@ def test_shape_and_value_edges(variant, n, m, lo, hi):
         assert (gpu_bounds(torch, inst, pre, dep, variant) == want).all()
 
 
-@pytest.mark.parametrize("variant", [fspbb.VARIANT_AUTO, fspbb.VARIANT_WAVEPAIR])
+@pytest.mark.parametrize("variant", [fspbb.VARIANT_AUTO, fspbb.VARIANT_LANE32, fspbb.VARIANT_WAVEPAIR])
 def test_largest_shape_on_the_32bit_kernel(variant):
     """512 jobs and 32 machines, the limits of both, with values that need
     32-bit arithmetic (max_value 543 x 100,000)."""
@@ -143,6 +144,7 @@ def test_large_values_use_the_32bit_kernel():
         assert inst.info()["packed16"] == 0
         assert (gpu_bounds(torch, inst, pre, dep) == want).all()
         assert (gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WAVEPAIR) == want).all()
+        assert (gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32) == want).all()
         with pytest.raises(fspbb.FspError):
             gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_PACKED16)
 
@@ -178,7 +180,8 @@ def test_500x20_sampled():
         got = gpu_bounds(torch, inst, pre, dep)
         got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)
         gotwp = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WAVEPAIR)
-    assert (got == got32).all() and (got == gotwp).all()
+        gotw = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_WIDE)
+    assert (got == got32).all() and (got == gotwp).all() and (got == gotw).all()
     idx = np.arange(0, N, 16)
     assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
 
@@ -192,3 +195,23 @@ def test_ties_heavy_instance():
     with fspbb.create_instance(p) as inst:
         for v in VARIANTS:
             assert (gpu_bounds(torch, inst, pre, dep, v) == want).all()
+
+
+@pytest.mark.parametrize("n,m,N", [(200, 20, 262144), (500, 20, 8192)])
+def test_wide_values_full_pool(n, m, N):
+    """Processing times U[1,300] put 200 x 20 past the 16-bit guard
+    ((n+m-1) * 300 >= 65536), so the pool takes the 32-bit decode + scan with
+    masks in LDS: every node against the register-bit-set 32-bit kernel, a
+    seeded sample against the oracle (the 200 x 20 pool is the benchmark's
+    size and launch for this case)."""
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(18, n, gen.PURPOSE_TIMES), 1, 300)
+    pre, dep = gen.random_pool(n, N, gen.make_seed(18, n, gen.PURPOSE_POOL))
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 0
+        got = gpu_bounds(torch, inst, pre, dep)
+        got32 = gpu_bounds(torch, inst, pre, dep, fspbb.VARIANT_LANE32)
+        assert fspbb.pool_status(inst) == 0
+    assert (got == got32).all()
+    idx = np.unique(gen.splitmix64(gen.make_seed(18, n, 9), 1500) % np.uint64(N)).astype(np.int64)
+    assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()

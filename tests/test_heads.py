@@ -16,7 +16,7 @@ def oracle_heads(p, pre, dep):
     return oracle.bound_pool(p, pre, dep, heads=True)
 
 
-@pytest.mark.parametrize("variant", [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16])
+@pytest.mark.parametrize("variant", [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16, fspbb.VARIANT_WIDE])
 @pytest.mark.parametrize("n,m,N", [(20, 5, 4096), (20, 10, 3000), (50, 10, 2000), (7, 32, 700), (1, 4, 5)])
 def test_heads_pool_parity(variant, n, m, N):
     torch = require_gpu()

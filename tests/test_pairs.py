@@ -21,7 +21,8 @@ def subsets(m, seed):
     return [[(k, k + 1) for k in range(m - 1)], [(k, m - 1) for k in range(m - 1)], pick]
 
 
-@pytest.mark.parametrize("variant", [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16, fspbb.VARIANT_WAVEPAIR])
+@pytest.mark.parametrize("variant", [fspbb.VARIANT_LANE32, fspbb.VARIANT_PACKED16, fspbb.VARIANT_WAVEPAIR,
+                                     fspbb.VARIANT_WIDE])
 @pytest.mark.parametrize("n,m,N", [(20, 5, 4096), (50, 10, 3000), (30, 20, 2000), (9, 32, 700)])
 def test_pair_subset_pool_parity(variant, n, m, N):
     torch = require_gpu()
