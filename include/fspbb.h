@@ -164,6 +164,32 @@ fsp_status fsp_bound_pool_variant(fsp_instance inst, const int32_t *prefixes,
                                   const int32_t *depths, int64_t N, int32_t *out_lb,
                                   int32_t variant, void *stream);
 
+/*
+ * fsp_bound_pool_noalloc - fsp_bound_pool for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid allocation.  The arguments, layout, results,
+ * invalid-node handling and stream semantics are those of fsp_bound_pool.
+ * The call makes no device or host allocation.  The decode's workspace
+ * (about 156 bytes per node at 200 x 20 on the 16-bit path, 276 on the 32-bit
+ * path) is a fixed array of FSP_NOALLOC_SCRATCH_BYTES inside the library.
+ * Each device the library runs on holds its own copy until the process ends;
+ * its address is looked up on the first call on that device.
+ * Every call on a device shares that device's array, and a call leaves its
+ * contents behind.  Calls that overlap on one device (on different streams,
+ * or from several host threads without ordering) therefore race and give
+ * wrong bounds: order them on one stream.
+ * Errors: as fsp_bound_pool, plus FSP_E_RANGE (nothing launched) when the
+ * workspace of N nodes would exceed the array, i.e. N > fsp_noalloc_max_nodes.
+ */
+#define FSP_NOALLOC_SCRATCH_BYTES (48u << 20)
+fsp_status fsp_bound_pool_noalloc(fsp_instance inst, const int32_t *prefixes,
+                                  const int32_t *depths, int64_t N, int32_t *out_lb,
+                                  void *stream);
+
+/* Largest N fsp_bound_pool_noalloc accepts for this instance (-1 for a null
+ * instance).  Host only. */
+int64_t fsp_noalloc_max_nodes(fsp_instance inst);
+
 /* ---- batched bounding --------------------------------------------------- */
 
 /* One pool of a batch: an instance and its pool buffers (as fsp_bound_pool). */

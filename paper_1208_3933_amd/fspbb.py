@@ -115,6 +115,8 @@ _SIGNATURES = {
     "fsp_get_instance_info": (ctypes.c_int32, [_vp, ctypes.POINTER(InstanceInfo)]),
     "fsp_bound_pool": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
     "fsp_bound_pool_variant": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.c_int32, _vp]),
+    "fsp_bound_pool_noalloc": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "fsp_noalloc_max_nodes": (ctypes.c_int64, [_vp]),
     "fsp_pool_status": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "fsp_neh": (ctypes.c_int32, [_vp, _i32p, ctypes.POINTER(ctypes.c_int32)]),
     "fsp_branch_and_prune": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp,
@@ -281,6 +283,22 @@ def bound_pool(inst: Instance, prefixes, depths, out_lb, stream=None, variant: i
     else:
         st = lib().fsp_bound_pool_variant(inst.handle, a, b, N, c, int(variant), s)
     _check(st, "fsp_bound_pool")
+
+
+def bound_pool_noalloc(inst: Instance, prefixes, depths, out_lb, stream=None) -> None:
+    """fsp_bound_pool_noalloc: the bound of every node of a pool with no
+    allocation (the workspace is the library's fixed per-device array; calls
+    that overlap on one device race)."""
+    N = int(depths.shape[0])
+    a = _dev_i32(prefixes, "prefixes", (N, inst.n))
+    b = _dev_i32(depths, "depths", (N,))
+    c = _dev_i32(out_lb, "out_lb", (N,))
+    _check(lib().fsp_bound_pool_noalloc(inst.handle, a, b, N, c, _stream_handle(stream)), "fsp_bound_pool_noalloc")
+
+
+def noalloc_max_nodes(inst: Instance) -> int:
+    """Largest pool fsp_bound_pool_noalloc accepts for this instance."""
+    return int(lib().fsp_noalloc_max_nodes(inst.handle))
 
 
 def bound_pool_variant(inst: Instance, prefixes, depths, out_lb, variant: int, stream=None) -> None:

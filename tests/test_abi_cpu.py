@@ -124,3 +124,10 @@ def test_binding_fails_loudly_without_the_library(monkeypatch):
         fspbb.lib()
     with pytest.raises(RuntimeError, match="is missing"):
         fspbb.create_instance(np.ones((5, 3), np.int32))
+
+
+def test_noalloc_entry_points_reject_a_null_instance():
+    # argument checks only: nothing reaches a device
+    L = fspbb.lib()
+    assert L.fsp_noalloc_max_nodes(None) == -1
+    assert L.fsp_bound_pool_noalloc(None, None, None, 1, None, None) == fspbb.E_INVAL
