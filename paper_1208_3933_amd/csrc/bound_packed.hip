@@ -333,18 +333,21 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
 // machines [q*MQ, (q+1)*MQ), and the completion-time recurrence of the prefix
 // runs as a pipeline across them: at step s lane q takes job s - q, with the
 // completion time on the machine before its first one handed over by lane
-// q - 1 (a one-lane DPP shift).  The jobs travel down the quad the same way;
-// lane 0 reads them from the prefix row, checks their range, and sets the
-// scheduled bits (LDS ORs that return nothing; a repeated job shows at the
-// end as fewer set bits than the depth).  A step past the prefix, or before a lane's first job, takes
-// the zero row: it leaves the completion times unchanged, because they never
-// decrease along the machines.  The tails split the jobs instead (job j to
-// lane j mod 4), with packed 16-bit minima combined across the quad.
+// q - 1 (a one-lane DPP shift), the only value that crosses lanes.  The
+// block's prefix rows are staged in LDS, so each lane reads its own jobs and
+// their time rows two and one steps ahead.  A step before a lane's first job
+// or past the prefix takes the zero row: it leaves the completion times
+// unchanged, because they never decrease along the machines.  Range checks
+// and the scheduled bits (LDS ORs; a repeated job shows at the end as fewer
+// set bits than the depth) are a separate pass with the prefix split over the
+// quad.  The tails split the jobs too (job j to lane j mod 4), with packed
+// 16-bit minima combined across the quad.
 //
 // Writes the scan workspace in the layout of the one-lane decode (nodes in
 // pool order), and out_lb = 0 for every valid node so that a scan split over
 // several workgroups can combine by atomic max; FSP_LB_INVALID otherwise.
-// One block of 256 threads per 64 nodes; Npad is a multiple of 64.
+// One block of 256 threads per 64 nodes; Npad is a multiple of 64; n <= 256
+// (the rows' LDS).
 template <int MV>
 __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const int32_t *__restrict__ prefixes,
                                                              const int32_t *__restrict__ depths, int64_t N,
@@ -357,7 +360,9 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     int32_t *pl = reinterpret_cast<int32_t *>(sm);   // (n + 1) x MV times; row n is zero
     uint32_t *tq = sm + (n + 1) * MV;                 // n x H packed tails
     uint32_t *bits = tq + n * H;                      // 64 nodes x NW scheduled-job words
+    int32_t *rows = reinterpret_cast<int32_t *>(bits + 64 * NW);  // 64 nodes x n prefix rows
     const int tid = threadIdx.x, q = tid & 3, nl = tid >> 2;
+    const int64_t node0 = (int64_t)blockIdx.x * 64;
     for (int e = tid; e < (n + 1) * MV; e += 256) {
         const int j = e / MV, k = e - j * MV;
         pl[e] = j < n ? T.p32[(size_t)j * kMaxMachines + k] : 0;
@@ -367,15 +372,28 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
         tq[e] = T.tails16[(size_t)j * (kMaxMachines / 2) + c];
     }
     for (int e = tid; e < 64 * NW; e += 256) bits[e] = 0u;
+    {
+        // the block's 64 rows are contiguous: one coalesced copy, clamped at the pool's end
+        const int64_t lim = max<int64_t>(0, min<int64_t>(64, N - node0)) * n;
+        const int32_t *src = prefixes + node0 * (int64_t)n;
+        for (int e = tid; e < 64 * n; e += 256) rows[e] = e < lim ? src[e] : 0;
+    }
     __syncthreads();
 
-    const int64_t node = (int64_t)blockIdx.x * 64 + nl;
+    const int64_t node = node0 + nl;
     const bool live = node < N;
     int d = live ? depths[node] : 0;
     bool ok = live && d >= 0 && d <= n;
     if (!ok) d = 0;
-    const int32_t *row = prefixes + (live ? node : 0) * (int64_t)n;
+    const int32_t *myrow = rows + nl * n;
     uint32_t *mybits = bits + nl * NW;
+
+    // range checks and scheduled bits, the prefix split over the quad
+    for (int t = q; t < d; t += 4) {
+        const int32_t j = myrow[t];
+        if ((unsigned)j < (unsigned)n) atomicOr(&mybits[j >> 5], 1u << (j & 31));
+        else ok = false;
+    }
 
     int32_t C[MQ], S[MQ];
 #pragma unroll
@@ -385,72 +403,58 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) smax = max(smax, __shfl_xor(smax, off));
 
-    // lane 0's job at step s is row[s] (s < d), else the zero row; prefix
-    // entries come four at a time with the next four in flight
-    auto fetch4 = [&](int s0, int32_t (&v)[4]) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = row[min(s0 + c, n - 1)];
+    // lane q's job at step s is prefix entry s - q, or the zero row.  Entries
+    // are read (always in bounds) four steps ahead and resolved two steps
+    // ahead, when the job's time row is read; rings of four registers, indexed
+    // by the step modulo 4 in a loop unrolled four times, keep every read two
+    // steps from its use.
+    auto raw_at = [&](int s) -> int32_t { return myrow[min(max(s - q, 0), n - 1)]; };
+    auto resolve = [&](int s, int32_t raw) -> int32_t {
+        const int t = s - q;
+        return (t >= 0 && t < d && (unsigned)raw < (unsigned)n) ? raw : n;
     };
-    auto inject = [&](int s, int32_t jraw) -> int32_t {
-        int32_t j = n;
-        if (q == 0 && s < d) {
-            if ((unsigned)jraw < (unsigned)n) {
-                atomicOr(&mybits[jraw >> 5], 1u << (jraw & 31));  // no return: nothing waits on it
-                j = jraw;
-            } else {
-                ok = false;
-            }
-        }
-        return j;
-    };
-    int32_t cur[4], nxt[4];
-    fetch4(0, cur);
-    fetch4(4, nxt);
-    // job of this lane for the coming step and its times (loaded one step
-    // ahead, so that the LDS reads overlap the step before)
-    int32_t job = inject(0, cur[0]);
-    int32_t x[MQ];
+    int32_t xr[4][MQ], rr[4];
 #pragma unroll
-    for (int kk = 0; kk < MQ; ++kk) x[kk] = pl[job * MV + q * MQ + kk];
+    for (int k = 0; k < 4; ++k) rr[k] = raw_at(k);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int32_t j = resolve(k, rr[k]);
+#pragma unroll
+        for (int kk = 0; kk < MQ; ++kk) xr[k][kk] = pl[j * MV + q * MQ + kk];
+    }
     int32_t last = 0;  // completion on this lane's last machine of its previous job
+    // a multiple of four steps: a step past the prefix reads the zero row
     for (int s4 = 0; s4 < smax; s4 += 4) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int s = s4 + c;
-            // next step: lane q takes the job lane q-1 does now
-            const int32_t jl = __builtin_amdgcn_mov_dpp(job, 0x111, 0xf, 0xf, true);  // row_shr:1
-            const int32_t ji = inject(s + 1, c < 3 ? cur[c + 1] : nxt[0]);
-            const int32_t jn = q == 0 ? ji : jl;
-            int32_t xn[MQ];
+            rr[c] = raw_at(s + 4);
+            const int32_t j2 = resolve(s + 2, rr[(c + 2) & 3]);
 #pragma unroll
-            for (int kk = 0; kk < MQ; ++kk) xn[kk] = pl[jn * MV + q * MQ + kk];
+            for (int kk = 0; kk < MQ; ++kk) xr[(c + 2) & 3][kk] = pl[j2 * MV + q * MQ + kk];
             // completion on the machine before this lane's first, for this job
-            const int32_t fromleft = __builtin_amdgcn_mov_dpp(last, 0x111, 0xf, 0xf, true);
+            const int32_t fromleft = __builtin_amdgcn_mov_dpp(last, 0x111, 0xf, 0xf, true);  // row_shr:1
             int32_t prev = q == 0 ? 0 : fromleft;
 #pragma unroll
             for (int kk = 0; kk < MQ; ++kk) {
-                const int32_t ck = max(C[kk], prev) + x[kk];
+                const int32_t ck = max(C[kk], prev) + xr[c][kk];
                 C[kk] = ck;
                 prev = ck;
-                S[kk] += x[kk];
+                S[kk] += xr[c][kk];
             }
             last = prev;
-            job = jn;
-#pragma unroll
-            for (int kk = 0; kk < MQ; ++kk) x[kk] = xn[kk];
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
-        fetch4(s4 + 8, nxt);
     }
     __syncthreads();
 
-    // a repeated job shows as fewer scheduled bits than the depth; validity
-    // (with lane 0's range checks) is broadcast over the quad
+    // a repeated job shows as fewer scheduled bits than the depth; every lane
+    // of the quad sees the same bits, and the range checks are combined
     int nset = 0;
     for (int w = 0; w < NW; ++w) nset += __popc(mybits[w]);
-    ok = ok && nset == d;
-    ok = __builtin_amdgcn_mov_dpp((int)ok, 0x00, 0xf, 0xf, false) != 0;  // quad_perm [0,0,0,0]
+    int bad = !ok;
+    bad |= __builtin_amdgcn_mov_dpp(bad, 0xb1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+    bad |= __builtin_amdgcn_mov_dpp(bad, 0x4e, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    ok = !bad && live && nset == d;
 
     // tails: lane q takes jobs j = 32w + q + 4i, packed 16-bit minima over (Q | off)
     uint32_t q2[H];
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 // LDS bytes of decode16_lanes_kernel for n jobs and MV machine slots.
 inline size_t decode16_lanes_lds(int n, int MV)
 {
-    return ((size_t)(n + 1) * MV + (size_t)n * (MV / 2) + (size_t)64 * ((n + 31) >> 5)) * 4;
+    return ((size_t)(n + 1) * MV + (size_t)n * (MV / 2) + (size_t)64 * ((n + 31) >> 5) + (size_t)64 * n) * 4;
 }
 
 // How a pool is decoded and scanned.  Below one serial-decode wave per SIMD
@@ -522,6 +526,8 @@ struct PoolPlan {
     bool lanes;  // four-lane decode
     int splits;  // pair splits of the scan
 };
+
+constexpr int kLanesMaxJobs = 256;  // the four-lane decode stages 64 prefix rows in LDS
 
 static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
 {
@@ -538,7 +544,7 @@ static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
     if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: the regular path only
     int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
     if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
-    if (I->dt.heads || cap <= 1 || N >= lanes_below) return PoolPlan{false, 1};
+    if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1};
     int sp = 1;
     while (sp < cap && G * sp < 2 * cus && 4 * 2 * sp <= I->P) sp *= 2;
     return PoolPlan{true, sp};
@@ -840,16 +846,20 @@ hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, co
     if (marks) timing_mark(I, 0, s);
     if (sort_depths) launch_depth_sort(depths, N, n, B, chunk, W.cnt, W.order, s);
 
-    const dim3 dgrid((unsigned)((Npad + 255) / 256)), dblock(256);
     const size_t dlds = decode16_lds_words(n, MV) * 4;
+    // decode of sorted positions [0, Np) of a part whose workspace starts at W
+    auto decode = [&](const Workspace16 &Wp, int64_t Np, int64_t Nppad, hipStream_t st) {
+        const dim3 dgrid((unsigned)((Nppad + 255) / 256)), dblock(256);
 #define FSP_DECODE(MVV) \
-    case MVV: bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, s>>>(I->dt, prefixes, depths, N, Npad, W, out_lb); break;
-    switch (MV) {
-        FSP_DECODE(4) FSP_DECODE(8) FSP_DECODE(12) FSP_DECODE(16)
-        FSP_DECODE(20) FSP_DECODE(24) FSP_DECODE(28) FSP_DECODE(32)
-    }
+    case MVV: bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, st>>>(I->dt, prefixes, depths, Np, Nppad, Wp, out_lb); break;
+        switch (MV) {
+            FSP_DECODE(4) FSP_DECODE(8) FSP_DECODE(12) FSP_DECODE(16)
+            FSP_DECODE(20) FSP_DECODE(24) FSP_DECODE(28) FSP_DECODE(32)
+        }
 #undef FSP_DECODE
-    hipError_t e = hipGetLastError();
+        return hipGetLastError();
+    };
+    hipError_t e = decode(W, N, Npad, s);
     if (marks) timing_mark(I, 1, s);
     if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s);
     if (marks) timing_mark(I, 2, s);

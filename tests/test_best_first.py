@@ -43,10 +43,14 @@ def compare(p, ub_mode, cap, budget=1 << 62, heads=False):
 @pytest.mark.parametrize("cap", [1, 3, 16, 1 << 20])
 @pytest.mark.parametrize("ub_mode", ["neh", "none"])
 def test_best_first_small_matches_oracle(n, m, seed, cap, ub_mode):
-    if ub_mode == "none" and n == 10 and cap <= 3:
-        pytest.skip("tens of thousands of one-parent steps: covered at larger pool caps")
     require_gpu()
     p = times(n, m, seed)
+    if ub_mode == "none" and n == 10 and cap <= 3:
+        # the full search takes tens of thousands of one- to three-parent
+        # steps: stopped by a node budget, the first 6,000 nodes still match
+        got = compare(p, ub_mode, cap, budget=6000)
+        assert got["status"] == fspbb.BUDGET and not got["proven"]
+        return
     got = compare(p, ub_mode, cap)
     assert got["proven"]
     if n <= 8:
