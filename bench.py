@@ -232,6 +232,21 @@ def batched_leg(inst, pre_d, dep_d, reps: int, stream) -> dict:
     compare("mixed_64_instances", pools)
     for ins in insts:
         ins.close()
+    # the tuner's timing of both scan launch forms (one workgroup per work item,
+    # persistent) for each shape of the mixed batch, on its seeded sample pool;
+    # the tuning table is put back afterwards so that later legs run as before
+    forms = {}
+    for n, m in shapes:
+        w0, _ = fspbb.tune_get(n, m)
+        f0 = fspbb.tune_get_form(n, m)
+        with fspbb.create_instance(gen.processing_times(n, m, gen.make_seed(3, 100 + n, gen.PURPOSE_TIMES))) as ins:
+            t = fspbb.autotune(ins, 16384, 3)
+        fspbb.tune_set(n, m, w0)
+        fspbb.tune_set_form(n, m, f0)
+        forms["%dx%d" % (n, m)] = {"waves_per_group": t["waves_per_group"], "grid_us": t["grid_us"],
+                                   "persistent_us": t["persistent_us"],
+                                   "persistent_vs_grid": t["grid_us"] / t["persistent_us"]}
+    out["tuner_forms_16384_nodes"] = forms
     return out
 
 
@@ -302,18 +317,19 @@ def variants_leg(p, pre_d, dep_d, steps: int, stream, solve_seeds: int = 6) -> d
     shapes = [(20, 5), (20, 10), (50, 5), (100, 5)]
     cands = serve.candidates(solve_seeds, shapes)
     budget, cap = 2_000_000, 8192
-    modes = {"dfs": (False, False, False), "dfs_heads": (True, False, False), "best_first": (False, True, False),
-             "dfs_adjacent_pairs": (False, False, True)}
+    modes = {"dfs": (False, False, False, False), "dfs_device_steps": (False, False, False, True),
+             "dfs_heads": (True, False, False, False), "best_first": (False, True, False, False),
+             "dfs_adjacent_pairs": (False, False, True, False)}
     rows = {}
     for c in cands:
         key = "%dx%d" % shapes[c.shape]
         r = rows.setdefault(key, {"instances": 0})
         r["instances"] += 1
-        for mode, (heads, bfirst, sub) in modes.items():
+        for mode, (heads, bfirst, sub, dev) in modes.items():
             pairs = adjacent_pairs(int(c.p.shape[1])) if sub else None
             with fspbb.create_instance(c.p, heads=heads, pairs=pairs) as inst:
                 t0 = time.perf_counter()
-                res = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, 0, stream, best_first=bfirst)
+                res = fspbb.solve(inst, fspbb.UB_NEH, cap, budget, 0, stream, best_first=bfirst, device_steps=dev)
                 dt = time.perf_counter() - t0
             r[mode + "_proven"] = r.get(mode + "_proven", 0) + int(res["proven"])
             r[mode + "_nodes"] = r.get(mode + "_nodes", 0) + int(res["nodes_bounded"])
@@ -461,7 +477,7 @@ def serving_leg(n_requests: int, seeds_per_shape: int, pool_cap: int, budget: in
             "unsolved_by_shape": unsolved}
 
 
-def bnb_leg(inst, steps: int, stream, best_first: bool = False) -> dict:
+def bnb_leg(inst, steps: int, stream, best_first: bool = False, device_steps: bool = False) -> dict:
     """Branch-and-bound from the NEH upper bound on the same instance, pool
     steps of 262,144 children (the paper's largest pool), search state resident
     on the device: depth first (stack) or best first (frontier by bound).  The
@@ -474,10 +490,11 @@ def bnb_leg(inst, steps: int, stream, best_first: bool = False) -> dict:
     t0 = time.perf_counter()
     ub0, _ = fspbb.neh(inst)
     neh_ms = (time.perf_counter() - t0) * 1e3
-    fspbb.solve(inst, ub0, POOL, 1 + steps * POOL, 0, stream, best_first=best_first)  # warm-up: the same search
+    kw = {"best_first": best_first, "device_steps": device_steps}
+    fspbb.solve(inst, ub0, POOL, 1 + steps * POOL, 0, stream, **kw)  # warm-up: the same search
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = fspbb.solve(inst, ub0, POOL, 1 + steps * POOL, 0, stream, best_first=best_first)
+    r = fspbb.solve(inst, ub0, POOL, 1 + steps * POOL, 0, stream, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"nodes_per_s": r["nodes_bounded"] / dt, "nodes_bounded": r["nodes_bounded"], "steps": r["steps"],
@@ -603,6 +620,7 @@ def main() -> int:
         print("[bench] variants leg done", file=sys.stderr, flush=True)
     if args.bnb_steps > 0:
         result["bnb"] = bnb_leg(inst, args.bnb_steps, stream)
+        result["bnb_device_steps"] = bnb_leg(inst, args.bnb_steps, stream, device_steps=True)
         result["bnb_best_first"] = bnb_leg(inst, args.bnb_steps, stream, best_first=True)
         result["hybrid"] = hybrid_leg(inst, p, stream, max(1, min(16, os.cpu_count() or 1)))
         print("[bench] bnb leg done", file=sys.stderr, flush=True)

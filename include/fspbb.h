@@ -360,7 +360,17 @@ fsp_status fsp_solve(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t n
  * frontier size after each step. */
 #define FSP_SOLVE_BEST_FIRST 1
 
-/* fsp_solve with flags (0 = depth first as fsp_solve, or FSP_SOLVE_BEST_FIRST). */
+/* Depth first with the steps chosen on the device: the parents of each step
+ * are taken from the depths at the top of the device stack, and the counters,
+ * upper bound, stack top, step log and stop rule are kept on the device, so
+ * the host enqueues several steps (1, 2, 4, ... up to 16) per
+ * synchronisation.  The steps, results and step log are those of fsp_solve.
+ * Applies to instances whose children are bounded from their parents
+ * (max_value < 65536, no FSP_INSTANCE_HEADS); others run host-driven. */
+#define FSP_SOLVE_DEVICE_STEPS 2
+
+/* fsp_solve with flags (0 = depth first as fsp_solve, FSP_SOLVE_BEST_FIRST,
+ * or FSP_SOLVE_DEVICE_STEPS; the last two are exclusive: FSP_E_INVAL). */
 fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_t node_budget, int32_t flags,
                         fsp_solve_result *res, int32_t *perm_out, int64_t *steplog, int64_t steplog_cap,
                         void *stream);

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libfspbb.so")
 ARCH = "gfx950"
 SOURCES = ["instance.cpp", "api.cpp", "bound_lane32.hip", "bound_packed.hip", "scan16_plain.hip", "bound_wavepair.hip", "children16.hip", "scan.hip", "bnb.hip",
            "solve.hip", "best_first.hip", "batch.cpp", "tune.cpp", "server.cpp",
-           "explore.cpp", "peaks.hip", "noalloc.hip", "bound_wide.hip"]
+           "explore.cpp", "peaks.hip", "noalloc.hip", "bound_wide.hip", "dsteps.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -21,16 +21,23 @@ namespace fspbb {
 // Grid (groups, splits): workgroup (G, y) scans pairs [y * pps, (y+1) * pps)
 // of group G.  With one split it writes each bound; with several, each split
 // takes its partial maximum into out_lb with an atomic max (out_lb holds 0
-// for every valid node beforehand, written by the decode).
+// for every valid node beforehand, written by the decode).  With Ndev the
+// node count is read from the device (a grid sized for a bound on it; groups
+// past it leave at once).
 template <int WAVES, int UNR, bool ADDTID, int NCH>
 __global__ __launch_bounds__(64 * WAVES) void bound_scan16_kernel(DevTables T, Workspace16 W, int64_t N,
-                                                                  int32_t *__restrict__ out_lb, int pps)
+                                                                  int32_t *__restrict__ out_lb, int pps,
+                                                                  const int64_t *__restrict__ Ndev)
 {
     extern __shared__ uint32_t lds[];  // (n + 1) rows x 64 lanes; row n stays zero
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int64_t G = blockIdx.x;
+    if (Ndev) {
+        N = *Ndev;
+        if (G * kGroup >= N) return;  // the whole workgroup
+    }
 
     // the mask rows from the unscheduled bits: each lane reads its two nodes'
     // bit words once per 32 jobs (all loads first), then expands them
@@ -134,32 +141,32 @@ static bool scan_addtid()
 
 template <int WAVES, bool ADDTID>
 static void launch_scan_u(int unr, dim3 grid, size_t lds_b, hipStream_t s, const DevTables &dt,
-                          const Workspace16 &W, int64_t N, int32_t *out_lb, int pps)
+                          const Workspace16 &W, int64_t N, int32_t *out_lb, int pps, const int64_t *Ndev)
 {
     const dim3 block(64 * WAVES);
     const int nch = scan_chains();
     if (unr == 16 && nch == 2)
-        bound_scan16_kernel<WAVES, 16, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
+        bound_scan16_kernel<WAVES, 16, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps, Ndev);
     else if (unr == 16)
-        bound_scan16_kernel<WAVES, 16, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
+        bound_scan16_kernel<WAVES, 16, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps, Ndev);
     else if (nch == 2)
-        bound_scan16_kernel<WAVES, 8, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
+        bound_scan16_kernel<WAVES, 8, ADDTID, 2><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps, Ndev);
     else
-        bound_scan16_kernel<WAVES, 8, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps);
+        bound_scan16_kernel<WAVES, 8, ADDTID, 1><<<grid, block, lds_b, s>>>(dt, W, N, out_lb, pps, Ndev);
 }
 
 template <int WAVES>
 static void launch_scan(int unr, dim3 grid, size_t lds_b, hipStream_t s, const DevTables &dt, const Workspace16 &W,
-                        int64_t N, int32_t *out_lb, int pps)
+                        int64_t N, int32_t *out_lb, int pps, const int64_t *Ndev)
 {
     if (scan_addtid())
-        launch_scan_u<WAVES, true>(unr, grid, lds_b, s, dt, W, N, out_lb, pps);
+        launch_scan_u<WAVES, true>(unr, grid, lds_b, s, dt, W, N, out_lb, pps, Ndev);
     else
-        launch_scan_u<WAVES, false>(unr, grid, lds_b, s, dt, W, N, out_lb, pps);
+        launch_scan_u<WAVES, false>(unr, grid, lds_b, s, dt, W, N, out_lb, pps, Ndev);
 }
 
 hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s,
-                         int splits)
+                         int splits, const int64_t *Ndev)
 {
     if (N <= 0) return hipSuccess;
     const int n = I->n, P = I->P;
@@ -182,11 +189,11 @@ hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t 
     const dim3 grid((unsigned)((N + kGroup - 1) / kGroup), (unsigned)splits);
     const int unr = scan_unroll();
     switch (waves) {
-    case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
-    case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
-    case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
-    case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
-    default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps); break;
+    case 16: launch_scan<16>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps, Ndev); break;
+    case 8: launch_scan<8>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps, Ndev); break;
+    case 4: launch_scan<4>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps, Ndev); break;
+    case 2: launch_scan<2>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps, Ndev); break;
+    default: launch_scan<1>(unr, grid, lds_b, s, I->dt, W, N, out_lb, pps, Ndev); break;
     }
     return hipGetLastError();
 }

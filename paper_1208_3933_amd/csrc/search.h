@@ -101,6 +101,31 @@ struct Search {
     hipError_t swap_in(hipStream_t s);
 };
 
+constexpr int kDevSelChunk = 1024;  // stack entries per block of the device selection
+
+// Device-side state of a depth-first search stepped on the device
+// (dsteps.hip): the host's counters and stack top, and the step in flight.
+struct DevSearch {
+    int64_t top, nodes, steps, max_stack;
+    int64_t node_budget, pool_cap, maxK, steplog_cap;
+    int64_t K, nch, base;
+    int32_t UB, improvements, done, status;
+    int32_t n, pad;
+};
+
+// The two host-side parts of a step as kernels: choose the step's parents
+// from the stack's top depths (writing the request's sizes and initial
+// results), and account for the step once its kernels ran.  sums holds
+// nchunks = ceil(maxK / 1024) words.
+hipError_t launch_device_step_select(DevSearch *ds, const int32_t *sdep, int64_t *sums, int nchunks, StepReq *req,
+                                     ScanSeg *seg, hipStream_t s);
+hipError_t launch_device_step_update(DevSearch *ds, const StepReq *req, int64_t *steplog, hipStream_t s);
+
+// Runs a started depth-first search (16-bit instance with the plain
+// releases) to its end with steps chosen on the device, several steps per
+// host synchronisation.  Synchronous on ctx.s.
+hipError_t run_device_steps(Search &S, TickContext &ctx);
+
 struct StartArgs {
     fsp_instance_s *inst;
     int32_t ub0;

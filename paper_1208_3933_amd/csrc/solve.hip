@@ -778,6 +778,134 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     return e;
 }
 
+// ---------------------------------------------------------------- device-chosen steps
+
+hipError_t run_device_steps(Search &S, TickContext &ctx)
+{
+    hipStream_t s = ctx.s;
+    fsp_instance_s *I = S.inst;
+    const int n = S.n;
+    // grids for the largest step: at most pool_cap parents, and pool_cap
+    // children unless one parent alone has more (at most n)
+    const int64_t maxK = S.pool_cap, maxC = std::max<int64_t>(S.pool_cap, n);
+    hipError_t e = S.B.ensure_k(maxK, s);
+    if (e == hipSuccess) e = S.B.ensure_c(maxC, n, s);
+    std::vector<Kids16> kv;
+    if (e == hipSuccess) e = ctx.kids.layout({I}, {maxK}, {maxC}, kv, s);
+    if (e != hipSuccess) return e;
+    // the request table of one search, then the device state, the selection's
+    // chunk sums and the step log
+    const TabLayout L(1, maxK, 0);
+    const int nchunks = (int)((maxK + kDevSelChunk - 1) / kDevSelChunk);
+    const size_t off_ds = L.total, off_sums = off_ds + al256(sizeof(DevSearch)),
+                 off_log = off_sums + al256((size_t)nchunks * 8);
+    const int64_t logcap = S.steplog ? S.steplog_cap : 0;
+    e = ctx.reserve(off_log + al256((size_t)std::max<int64_t>(logcap, 1) * 6 * 8));
+    if (e != hipSuccess) return e;
+    char *h = (char *)ctx.htab, *d = (char *)ctx.dtab;
+    StepReq *dq = (StepReq *)(d + L.req);
+    ScanSeg *ds1 = (ScanSeg *)(d + L.seg1);
+    DevSearch *dds = (DevSearch *)(d + off_ds);
+    int64_t *dsums = (int64_t *)(d + off_sums);
+    int64_t *dlog = logcap ? (int64_t *)(d + off_log) : nullptr;
+
+    // the table's fixed fields (the selection writes the sizes of each step)
+    auto upload_table = [&]() -> hipError_t {
+        StepReq q;
+        std::memset(&q, 0, sizeof(q));
+        q.a.n = n;
+        q.a.ub_in = S.UB;
+        q.a.parents = S.srows;
+        q.a.pdepth = S.sdep;
+        q.a.parents_reversed = 1;
+        q.a.parent_top = S.top;
+        q.a.out_rows = S.srows;
+        q.a.out_depth = S.sdep;
+        q.a.out_cap = S.cap_stack;
+        q.a.out_reversed = 1;
+        q.a.surv_per_parent = (uint32_t *)(d + L.surv);
+        q.a.incumbent = S.dinc;
+        q.w = S.B.w;
+        kids16_point(q.w, kv[0]);
+        q.T = I->dt;
+        bind_results(q, dq, S.UB);
+        *(StepReq *)(h + L.req) = q;
+        *(ScanSeg *)(h + L.seg1) = ScanSeg{q.w.cnt, q.w.off, 0, q.w.nchild, S.B.sums_k};
+        return hipMemcpyAsync(d, h, L.surv, hipMemcpyHostToDevice, s);
+    };
+    DevSearch st{};
+    st.top = S.top;
+    st.nodes = S.nodes;
+    st.steps = S.steps;
+    st.max_stack = S.max_stack;
+    st.node_budget = S.node_budget;
+    st.pool_cap = S.pool_cap;
+    st.maxK = maxK;
+    st.steplog_cap = logcap;
+    st.UB = S.UB;
+    st.improvements = S.improvements;
+    st.done = S.done ? 1 : 0;
+    st.status = S.status;
+    st.n = n;
+    std::memcpy(h + off_ds, &st, sizeof(st));
+    e = hipMemcpyAsync(dds, h + off_ds, sizeof(st), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = upload_table();
+    // steps per synchronisation: 1, 2, 4, ... up to 16, so that short
+    // searches do not run many empty steps after their end
+    int chunk = 1;
+    while (e == hipSuccess && !st.done) {
+        // room on the stack for the chunk: a step adds at most maxC - 1 rows
+        if (st.top + chunk * maxC > S.cap_stack) {
+            int64_t nc = S.cap_stack;
+            while (st.top + chunk * maxC > nc) nc *= 2;
+            int32_t *r2 = nullptr, *d2 = nullptr;
+            e = stream_alloc((void **)&r2, (size_t)nc * n * 4, s);
+            if (e == hipSuccess) e = stream_alloc((void **)&d2, (size_t)nc * 4, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(r2, S.srows, (size_t)st.top * n * 4, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(d2, S.sdep, (size_t)st.top * 4, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) {
+                if (r2) stream_free(r2, s);
+                if (d2) stream_free(d2, s);
+                break;
+            }
+            stream_free(S.srows, s);
+            stream_free(S.sdep, s);
+            S.srows = r2;
+            S.sdep = d2;
+            S.cap_stack = nc;
+            e = upload_table();
+            if (e != hipSuccess) break;
+        }
+        for (int k = 0; k < chunk && e == hipSuccess; ++k) {
+            e = launch_device_step_select(dds, S.sdep, dsums, nchunks, dq, ds1, s);
+            if (e == hipSuccess) e = kids16_decode(dq, 1, maxK, maxC, n, I->m, s, ds1);
+            if (e == hipSuccess) e = launch_scan16(I, kv[0].W, maxC, S.B.w.clb, s, 1, &dq->nchild);
+            if (e == hipSuccess) e = mstep_finish(dq, 1, maxK, maxC, s, true);
+            if (e == hipSuccess) e = launch_device_step_update(dds, dq, dlog, s);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(h + off_ds, dds, sizeof(st), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) std::memcpy(&st, h + off_ds, sizeof(st));
+        if (chunk < 16) chunk *= 2;
+    }
+    if (e != hipSuccess) return e;
+    S.top = st.top;
+    S.nodes = st.nodes;
+    S.steps = st.steps;
+    S.max_stack = st.max_stack;
+    S.UB = st.UB;
+    S.improvements = st.improvements;
+    S.done = true;
+    S.status = st.status;
+    S.runs.clear();  // the host view of the stack is not kept in this mode
+    if (S.improvements > 0) e = hipMemcpyAsync(S.inc.data(), S.dinc, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+    const int64_t nlog = std::min(S.steps, logcap);
+    if (e == hipSuccess && nlog > 0)
+        e = hipMemcpyAsync(S.steplog, dlog, (size_t)nlog * 6 * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
 // ---------------------------------------------------------------- best first
 
 namespace {
@@ -1142,7 +1270,8 @@ fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_
                         void *stream)
 {
     if (!inst || !res || pool_cap < 1 || node_budget < 1 || (ub0 < 0 && ub0 != FSP_UB_NEH)) return FSP_E_INVAL;
-    if (flags & ~FSP_SOLVE_BEST_FIRST) return FSP_E_INVAL;
+    if (flags & ~(FSP_SOLVE_BEST_FIRST | FSP_SOLVE_DEVICE_STEPS)) return FSP_E_INVAL;
+    if ((flags & FSP_SOLVE_BEST_FIRST) && (flags & FSP_SOLVE_DEVICE_STEPS)) return FSP_E_INVAL;
     std::memset(res, 0, sizeof(*res));
     DeviceGuard g(inst->device);
     if (!g.ok) return FSP_E_DEVICE;
@@ -1162,6 +1291,10 @@ fsp_status fsp_solve_ex(fsp_instance inst, int32_t ub0, int64_t pool_cap, int64_
     S.steplog = steplog;
     S.steplog_cap = steplog ? steplog_cap : 0;
     std::vector<Search *> act{&S};
+    if ((flags & FSP_SOLVE_DEVICE_STEPS) && kids16_eligible(inst) && !S.done) {
+        e = run_device_steps(S, ctx);
+        if (e != hipSuccess) { cleanup(); return fail_status(e); }
+    }
     while (!S.done) {
         e = tick(act, ctx);
         if (e != hipSuccess) { cleanup(); return fail_status(e); }

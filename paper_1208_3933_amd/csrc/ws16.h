@@ -24,8 +24,9 @@ void launch_depth_sort(const int32_t *depths, int64_t N, int n, int B, int64_t c
 // unless W.order is set), bounds to out_lb.  splits > 1 divides the machine
 // pairs of each group between that many workgroups, which combine their
 // maxima into out_lb by atomic max: out_lb must then hold 0 for every valid
-// node beforehand.
+// node beforehand.  With Ndev, N only bounds the node count, which the
+// kernel reads from Ndev on the device.
 hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t N, int32_t *out_lb, hipStream_t s,
-                         int splits = 1);
+                         int splits = 1, const int64_t *Ndev = nullptr);
 
 }  // namespace fspbb

@@ -374,17 +374,20 @@ def branch_and_prune(inst: Instance, parents, parent_depths, ub_in: int, childre
 
 
 SOLVE_BEST_FIRST = 1
+SOLVE_DEVICE_STEPS = 2
 
 
 def solve(inst: Instance, ub0: int = UB_NEH, pool_cap: int = 1 << 18, node_budget: int = 1 << 62,
-          steplog_cap: int = 0, stream=None, best_first: bool = False) -> dict:
+          steplog_cap: int = 0, stream=None, best_first: bool = False, device_steps: bool = False) -> dict:
     """Branch-and-bound with the search state on the device: depth first
-    (stack), or best first (frontier ordered by bound and insertion)."""
+    (stack), or best first (frontier ordered by bound and insertion);
+    device_steps: depth first with the steps chosen on the device
+    (FSP_SOLVE_DEVICE_STEPS)."""
     res = SolveResult()
     perm = np.empty(inst.n, np.int32)
     log = np.zeros((max(steplog_cap, 1), 6), np.int64)
-    st = lib().fsp_solve_ex(inst.handle, int(ub0), int(pool_cap), int(node_budget),
-                            SOLVE_BEST_FIRST if best_first else 0, ctypes.byref(res),
+    flags = (SOLVE_BEST_FIRST if best_first else 0) | (SOLVE_DEVICE_STEPS if device_steps else 0)
+    st = lib().fsp_solve_ex(inst.handle, int(ub0), int(pool_cap), int(node_budget), flags, ctypes.byref(res),
                             perm.ctypes.data_as(_i32p), log.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                             int(steplog_cap), _stream_handle(stream))
     if st not in (OK, BUDGET):
