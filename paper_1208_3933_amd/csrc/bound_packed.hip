@@ -13,6 +13,7 @@
 #include <cstdlib>
 
 #include "batch.h"
+#include "lds_stage.h"
 #include "scan16.h"
 
 namespace fspbb {
@@ -20,6 +21,8 @@ namespace fspbb {
 // ---- counting sort of node indices by depth (bucket n+1 holds invalid depths)
 
 __device__ __forceinline__ int depth_bucket(int d, int n) { return (d >= 0 && d <= n) ? d : n + 1; }
+
+constexpr int kSortPer = 16;  // depths in flight per thread
 
 // Block `blk` of B: histogram of the depths of nodes [blk*chunk, (blk+1)*chunk)
 // into cnt[bucket * B + blk].  h: n + 2 words of LDS.
@@ -29,7 +32,15 @@ __device__ inline void depth_count_block(const int32_t *__restrict__ depths, int
     for (int b = threadIdx.x; b < n + 2; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const int64_t lo = blk * chunk, hi = min(N, lo + chunk);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[depth_bucket(depths[i], n)], 1u);
+    // each thread's depths are loaded kSortPer at a time before their counts
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (int64_t)kSortPer * blockDim.x) {
+        int32_t dv[kSortPer];
+#pragma unroll
+        for (int k = 0; k < kSortPer; ++k) dv[k] = depths[min(i0 + (int64_t)k * blockDim.x, hi - 1)];
+#pragma unroll
+        for (int k = 0; k < kSortPer; ++k)
+            if (i0 + (int64_t)k * blockDim.x < hi) atomicAdd(&h[depth_bucket(dv[k], n)], 1u);
+    }
     __syncthreads();
     for (int b = threadIdx.x; b < n + 2; b += blockDim.x) cnt[(int64_t)b * B + blk] = h[b];
 }
@@ -90,9 +101,18 @@ __device__ inline void depth_scatter_block(const int32_t *__restrict__ depths, i
     }
     __syncthreads();
     const int64_t lo_i = blk * chunk, hi_i = min(N, lo_i + chunk);
-    for (int64_t i = lo_i + t; i < hi_i; i += blockDim.x) {
-        const uint32_t pos = atomicAdd(&cur[depth_bucket(depths[i], n)], 1u);
-        order[pos] = (int32_t)i;
+    for (int64_t i0 = lo_i + t; i0 < hi_i; i0 += (int64_t)kSortPer * blockDim.x) {
+        int32_t dv[kSortPer];
+#pragma unroll
+        for (int k = 0; k < kSortPer; ++k) dv[k] = depths[min(i0 + (int64_t)k * blockDim.x, hi_i - 1)];
+#pragma unroll
+        for (int k = 0; k < kSortPer; ++k) {
+            const int64_t i = i0 + (int64_t)k * blockDim.x;
+            if (i < hi_i) {
+                const uint32_t pos = atomicAdd(&cur[depth_bucket(dv[k], n)], 1u);
+                order[pos] = (int32_t)i;
+            }
+        }
     }
 }
 
@@ -148,10 +168,10 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     uint32_t *bits = sm;             // NW words x 256 lanes
     uint32_t *p16 = sm + NW * 256;   // (n + 1) x H; row n is zero
     const int tid = threadIdx.x;
-    for (int e = tid; e < (n + 1) * H; e += 256) {
-        const int32_t *r = T.p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H);
-        p16[e] = ((uint32_t)r[0] & 0xffffu) | ((uint32_t)r[1] << 16);
-    }
+    stage_lds<8>(p16, (n + 1) * H, [&](int e) {
+        const int2 r = *reinterpret_cast<const int2 *>(T.p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H));
+        return ((uint32_t)r.x & 0xffffu) | ((uint32_t)r.y << 16);
+    });
     __syncthreads();
 
     const int64_t i = blk * 256 + tid;
@@ -333,21 +353,29 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
 // machines [q*MQ, (q+1)*MQ), and the completion-time recurrence of the prefix
 // runs as a pipeline across them: at step s lane q takes job s - q, with the
 // completion time on the machine before its first one handed over by lane
-// q - 1 (a one-lane DPP shift), the only value that crosses lanes.  The
-// block's prefix rows are staged in LDS, so each lane reads its own jobs and
-// their time rows two and one steps ahead.  A step before a lane's first job
-// or past the prefix takes the zero row: it leaves the completion times
-// unchanged, because they never decrease along the machines.  Range checks
-// and the scheduled bits (LDS ORs; a repeated job shows at the end as fewer
-// set bits than the depth) are a separate pass with the prefix split over the
-// quad.  The tails split the jobs too (job j to lane j mod 4), with packed
-// 16-bit minima combined across the quad.
+// q - 1 (a one-lane DPP shift), the only value that crosses lanes.
+//
+// The block's 64 prefix rows are staged in LDS, each in a slot row of
+// n + 16 words with four words of padding before it.  A first pass, with the
+// prefix split over the quad, checks every job's range, sets the scheduled
+// bits (LDS ORs; a repeated job shows at the end as fewer set bits than the
+// depth) and replaces each entry by the offset of the job's time row, or of
+// the zero row for an invalid job or an entry past the depth; the padding
+// holds the zero row too.  A step before a lane's first job or past the
+// prefix thus reads the zero row, which leaves the completion times
+// unchanged, because they never decrease along the machines.  Step s of lane
+// q reads entry s - q at a fixed distance from its own base: the offsets are
+// read four steps ahead, the time rows two steps ahead, and a step spends one
+// address add on them.  The tails split the jobs over the quad (job j to lane
+// j mod 4), with packed 16-bit minima combined across the quad.
 //
 // Writes the scan workspace in the layout of the one-lane decode (nodes in
 // pool order), and out_lb = 0 for every valid node so that a scan split over
 // several workgroups can combine by atomic max; FSP_LB_INVALID otherwise.
 // One block of 256 threads per 64 nodes; Npad is a multiple of 64; n <= 256
-// (the rows' LDS).
+// (the slot rows' LDS).
+constexpr int kLanesPad = 16;  // slot row = 4 words before the prefix, n entries, 12 after
+
 template <int MV>
 __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const int32_t *__restrict__ prefixes,
                                                              const int32_t *__restrict__ depths, int64_t N,
@@ -356,28 +384,56 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     constexpr int MQ = MV / 4;  // machines per lane
     constexpr int H = MV / 2;   // packed tail pairs per job
     extern __shared__ uint32_t sm[];
-    const int n = T.n, m = T.m, NW = (n + 31) >> 5;
-    int32_t *pl = reinterpret_cast<int32_t *>(sm);   // (n + 1) x MV times; row n is zero
-    uint32_t *tq = sm + (n + 1) * MV;                 // n x H packed tails
-    uint32_t *bits = tq + n * H;                      // 64 nodes x NW scheduled-job words
-    int32_t *rows = reinterpret_cast<int32_t *>(bits + 64 * NW);  // 64 nodes x n prefix rows
+    const int n = T.n, m = T.m, NW = (n + 31) >> 5, RS = n + kLanesPad;
+    int32_t *slots = reinterpret_cast<int32_t *>(sm);  // 64 nodes x RS: padding, prefix entries, padding
+    int32_t *pl = slots + 64 * RS;                     // (n + 1) x MV times; row n is zero
+    uint32_t *tq = reinterpret_cast<uint32_t *>(pl + (n + 1) * MV);  // n x H packed tails
+    uint32_t *bits = tq + n * H;                       // 64 nodes x NW scheduled-job words
     const int tid = threadIdx.x, q = tid & 3, nl = tid >> 2;
+    const int zrow = n * MV;  // offset of the zero row in pl
     const int64_t node0 = (int64_t)blockIdx.x * 64;
-    for (int e = tid; e < (n + 1) * MV; e += 256) {
-        const int j = e / MV, k = e - j * MV;
-        pl[e] = j < n ? T.p32[(size_t)j * kMaxMachines + k] : 0;
-    }
-    for (int e = tid; e < n * H; e += 256) {
-        const int j = e / H, c = e - j * H;
-        tq[e] = T.tails16[(size_t)j * (kMaxMachines / 2) + c];
-    }
-    for (int e = tid; e < 64 * NW; e += 256) bits[e] = 0u;
     {
-        // the block's 64 rows are contiguous: one coalesced copy, clamped at the pool's end
-        const int64_t lim = max<int64_t>(0, min<int64_t>(64, N - node0)) * n;
+        // the block's 64 rows are contiguous in the pool: entry e of the copy
+        // is job e mod n of node e / n (the grid never starts a block past
+        // the pool's end, so lim >= n)
+        const int lim = (int)max<int64_t>(0, min<int64_t>(64, N - node0)) * n;
         const int32_t *src = prefixes + node0 * (int64_t)n;
-        for (int e = tid; e < 64 * n; e += 256) rows[e] = e < lim ? src[e] : 0;
+        if (lim > 0 && (n & 3) == 0 && ((uintptr_t)src & 15) == 0) {
+            // a 16-byte load never crosses a row; slot rows keep 16-byte alignment
+            const int4 *s4 = reinterpret_cast<const int4 *>(src);
+            const int lim4 = lim >> 2;
+            stage_lds_with<16, int4>(
+                16 * n,
+                [&](int e) {
+                    const int4 v = s4[min(e, lim4 - 1)];
+                    return e < lim4 ? v : int4{0, 0, 0, 0};
+                },
+                [&](int e, int4 v) {
+                    const int w = 4 * e, r = w / n;
+                    *reinterpret_cast<int4 *>(slots + r * RS + 4 + (w - r * n)) = v;
+                });
+        } else if (lim > 0) {
+            stage_lds_with<16, int32_t>(
+                64 * n,
+                [&](int e) {
+                    const int32_t v = src[min(e, lim - 1)];
+                    return e < lim ? v : 0;
+                },
+                [&](int e, int32_t v) {
+                    const int r = e / n;
+                    slots[r * RS + 4 + (e - r * n)] = v;
+                });
+        }
     }
+    stage_lds<16>(pl, (n + 1) * MV, [&](int e) {  // row n of p32 is zero
+        const int j = e / MV, k = e - j * MV;
+        return T.p32[(size_t)j * kMaxMachines + k];
+    });
+    stage_lds<8>(tq, n * H, [&](int e) {
+        const int j = e / H, c = e - j * H;
+        return T.tails16[(size_t)j * (kMaxMachines / 2) + c];
+    });
+    for (int e = tid; e < 64 * NW; e += 256) bits[e] = 0u;
     __syncthreads();
 
     const int64_t node = node0 + nl;
@@ -385,15 +441,32 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     int d = live ? depths[node] : 0;
     bool ok = live && d >= 0 && d <= n;
     if (!ok) d = 0;
-    const int32_t *myrow = rows + nl * n;
+    int32_t *myslot = slots + nl * RS;
     uint32_t *mybits = bits + nl * NW;
 
-    // range checks and scheduled bits, the prefix split over the quad
-    for (int t = q; t < d; t += 4) {
-        const int32_t j = myrow[t];
-        if ((unsigned)j < (unsigned)n) atomicOr(&mybits[j >> 5], 1u << (j & 31));
-        else ok = false;
+    // range checks, scheduled bits and time-row offsets, the prefix split
+    // over the quad; the padding takes the zero row
+    if (q == 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) myslot[t] = zrow;
     }
+    for (int t = 4 + n + q; t < RS; t += 4) myslot[t] = zrow;
+    for (int t = q; t < n; t += 16) {
+        int32_t raw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) raw[u] = myslot[4 + min(t + 4 * u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int tt = t + 4 * u;
+            if (tt < n) {
+                const bool in = tt < d, good = (unsigned)raw[u] < (unsigned)n;
+                if (in && good) atomicOr(&mybits[raw[u] >> 5], 1u << (raw[u] & 31));
+                if (in && !good) ok = false;
+                myslot[4 + tt] = in && good ? raw[u] * MV : zrow;
+            }
+        }
+    }
+    __syncthreads();
 
     int32_t C[MQ], S[MQ];
 #pragma unroll
@@ -403,35 +476,28 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) smax = max(smax, __shfl_xor(smax, off));
 
-    // lane q's job at step s is prefix entry s - q, or the zero row.  Entries
-    // are read (always in bounds) four steps ahead and resolved two steps
-    // ahead, when the job's time row is read; rings of four registers, indexed
-    // by the step modulo 4 in a loop unrolled four times, keep every read two
-    // steps from its use.
-    auto raw_at = [&](int s) -> int32_t { return myrow[min(max(s - q, 0), n - 1)]; };
-    auto resolve = [&](int s, int32_t raw) -> int32_t {
-        const int t = s - q;
-        return (t >= 0 && t < d && (unsigned)raw < (unsigned)n) ? raw : n;
-    };
-    int32_t xr[4][MQ], rr[4];
+    // step s of lane q takes entry s - q: base[s] (base[0] is padding for
+    // q > 0).  Rings of four registers, indexed by the step modulo 4 in a loop
+    // unrolled four times: offsets read four steps ahead, rows two steps ahead.
+    const int32_t *base = myslot + 4 - q;
+    const int lq = q * MQ;  // this lane's first machine in a time row
+    int32_t xr[4][MQ], o[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) rr[k] = raw_at(k);
+    for (int k = 0; k < 4; ++k) o[k] = base[k];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int32_t j = resolve(k, rr[k]);
+    for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int kk = 0; kk < MQ; ++kk) xr[k][kk] = pl[j * MV + q * MQ + kk];
-    }
+        for (int kk = 0; kk < MQ; ++kk) xr[k][kk] = pl[o[k] + lq + kk];
     int32_t last = 0;  // completion on this lane's last machine of its previous job
     // a multiple of four steps: a step past the prefix reads the zero row
     for (int s4 = 0; s4 < smax; s4 += 4) {
+        const int32_t *b4 = base + s4;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int s = s4 + c;
-            rr[c] = raw_at(s + 4);
-            const int32_t j2 = resolve(s + 2, rr[(c + 2) & 3]);
+            const int a2 = o[(c + 2) & 3] + lq;  // step s + 2, read two steps ago
+            o[c] = b4[c + 4];                    // step s + 4
 #pragma unroll
-            for (int kk = 0; kk < MQ; ++kk) xr[(c + 2) & 3][kk] = pl[j2 * MV + q * MQ + kk];
+            for (int kk = 0; kk < MQ; ++kk) xr[(c + 2) & 3][kk] = pl[a2 + kk];
             // completion on the machine before this lane's first, for this job
             const int32_t fromleft = __builtin_amdgcn_mov_dpp(last, 0x111, 0xf, 0xf, true);  // row_shr:1
             int32_t prev = q == 0 ? 0 : fromleft;
@@ -513,15 +579,16 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 // LDS bytes of decode16_lanes_kernel for n jobs and MV machine slots.
 inline size_t decode16_lanes_lds(int n, int MV)
 {
-    return ((size_t)(n + 1) * MV + (size_t)n * (MV / 2) + (size_t)64 * ((n + 31) >> 5) + (size_t)64 * n) * 4;
+    return ((size_t)(n + 1) * MV + (size_t)n * (MV / 2) + (size_t)64 * ((n + 31) >> 5) +
+            (size_t)64 * (n + kLanesPad)) * 4;
 }
 
 // How a pool is decoded and scanned.  Below one serial-decode wave per SIMD
 // the one-lane decode is latency-bound, so smaller pools take the four-lane
 // decode (nodes in pool order, no depth sort); a pool of fewer
 // groups than two per compute unit also splits each group's machine pairs
-// over several workgroups (at least four pairs per wave and chain), which
-// needs the four-lane decode's zeroed bounds.
+// over several workgroups (at least four pairs per split, about one per
+// wave), which needs the four-lane decode's zeroed bounds.
 struct PoolPlan {
     bool lanes;  // four-lane decode
     int splits;  // pair splits of the scan
@@ -545,8 +612,11 @@ static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
     int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
     if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
     if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1};
+    int fill = 2, minp = 4;  // workgroups per compute unit; least pairs per split
+    if (const char *e = getenv("FSPBB_SPLIT_FILL")) fill = std::max(1, atoi(e));
+    if (const char *e = getenv("FSPBB_SPLIT_MIN_PAIRS")) minp = std::max(1, atoi(e));
     int sp = 1;
-    while (sp < cap && G * sp < 2 * cus && 4 * 2 * sp <= I->P) sp *= 2;
+    while (sp < cap && G * sp < (int64_t)fill * cus && minp * 2 * sp <= I->P) sp *= 2;
     return PoolPlan{true, sp};
 }
 

@@ -20,6 +20,7 @@
 
 #include "batch.h"
 #include "bound_wide.h"
+#include "lds_stage.h"
 #include "scan16.h"
 
 namespace fspbb {
@@ -46,10 +47,10 @@ __global__ __launch_bounds__(256) void bound_decodew_kernel(DevTables T, const i
     uint32_t *bits = sm;                                         // NW words x 256 lanes
     int32_t *pl = reinterpret_cast<int32_t *>(sm + NW * 256);   // (n + 1) x MV; row n is zero
     const int tid = threadIdx.x;
-    for (int e = tid; e < (n + 1) * MV; e += 256) {
+    stage_lds<16>(pl, (n + 1) * MV, [&](int e) {  // row n of p32 is zero
         const int j = e / MV, k = e - j * MV;
-        pl[e] = j < n ? T.p32[(size_t)j * kMaxMachines + k] : 0;
-    }
+        return T.p32[(size_t)j * kMaxMachines + k];
+    });
     __syncthreads();
 
     const int64_t i = (int64_t)blockIdx.x * 256 + tid;

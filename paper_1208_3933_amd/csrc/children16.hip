@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "kids16.h"
+#include "lds_stage.h"
 #include "scan16.h"
 #include "step_dev.h"
 
@@ -27,10 +28,10 @@ namespace {
 template <int H>
 __device__ inline void stage_p16(int n, const int32_t *p32, uint32_t *p16)
 {
-    for (int e = threadIdx.x; e < (n + 1) * H; e += blockDim.x) {
-        const int32_t *r = p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H);
-        p16[e] = ((uint32_t)r[0] & 0xffffu) | ((uint32_t)r[1] << 16);
-    }
+    stage_lds<8>(p16, (n + 1) * H, [&](int e) {
+        const int2 r = *reinterpret_cast<const int2 *>(p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H));
+        return ((uint32_t)r.x & 0xffffu) | ((uint32_t)r.y << 16);
+    });
     __syncthreads();
 }
 

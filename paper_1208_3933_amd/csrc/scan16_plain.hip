@@ -174,12 +174,11 @@ hipError_t launch_scan16(const fsp_instance_s *I, const Workspace16 &W, int64_t 
     if (splits > P) splits = P;
     const int pps = (P + splits - 1) / splits;
     splits = (P + pps - 1) / pps;
-    // one group per workgroup: the tuned waves; a split: about four pairs per
-    // wave and chain of its share (the rule of thumb), at most the tuned waves
+    // one group per workgroup: the tuned waves; a split: about one pair per
+    // wave of its share (small pools are latency-bound), at most 16 waves
     int waves = scan_waves(I);
     if (splits > 1) {
-        // about ppw pairs per wave (two chains each) of the split's share
-        int ppw = 4;
+        int ppw = 1;
         if (const char *e = getenv("FSPBB_SPLIT_PAIRS_PER_WAVE")) ppw = std::max(1, atoi(e));
         int w = 1;
         while (w < 16 && ppw * w < pps) w *= 2;

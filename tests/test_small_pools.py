@@ -99,3 +99,51 @@ def test_small_pool_heads_instance_takes_the_regular_path():
     with fspbb.create_instance(p, heads=True) as inst:
         got = _bounds(torch, inst, pre, dep)
     assert (got == oracle.bound_pool(p, pre, dep, heads=True)).all()
+
+
+@pytest.mark.parametrize("n,m,N", [(200, 20, 1000), (64, 8, 4096)])
+def test_small_pool_rows_off_16_byte_boundary(n, m, N):
+    """Prefix rows that do not start on a 16-byte boundary are staged word by
+    word instead of 16 bytes at a time; the bounds are the same."""
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(23, n, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(23, n, gen.PURPOSE_POOL), 0, n)
+    buf = torch.zeros(N * n + 1, dtype=torch.int32, device="cuda")
+    buf[1:] = torch.from_numpy(np.ascontiguousarray(pre).reshape(-1)).to("cuda")
+    pre_off = buf[1:].view(N, n)
+    assert pre_off.data_ptr() % 16 == 4
+    dep_d = torch.from_numpy(dep).to("cuda")
+    out = torch.full((N,), -7, dtype=torch.int32, device="cuda")
+    with fspbb.create_instance(p) as inst:
+        fspbb.bound_pool(inst, pre_off, dep_d, out)
+        torch.cuda.synchronize()
+        aligned = _bounds(torch, inst, pre, dep)
+    got = out.cpu().numpy()
+    assert (got == aligned).all()
+    idx = np.arange(0, N, 5)
+    assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
+
+
+@pytest.mark.parametrize("fill,minp,ppw", [(8, 2, 1), (4, 4, 2), (2, 1, 1)])
+def test_small_pool_split_shapes(fill, minp, ppw):
+    """Other shapes of the split scan (workgroups per compute unit, least pairs
+    per split, pairs per wave) give the same bounds."""
+    torch = require_gpu()
+    n, m, N = 200, 20, 4096
+    p = gen.processing_times(n, m, gen.make_seed(24, 0, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(24, 0, gen.PURPOSE_POOL), 0, n)
+    keys = {"FSPBB_SPLIT_FILL": fill, "FSPBB_SPLIT_MIN_PAIRS": minp, "FSPBB_SPLIT_PAIRS_PER_WAVE": ppw}
+    with fspbb.create_instance(p) as inst:
+        want = _bounds(torch, inst, pre, dep, regular=True)
+        old = {k: os.environ.get(k) for k in keys}
+        try:
+            for k, v in keys.items():
+                os.environ[k] = str(v)
+            got = _bounds(torch, inst, pre, dep)
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+    assert (got == want).all()
