@@ -224,10 +224,11 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     const int32_t *row = prefixes + node * (int64_t)n;
     if ((n & 3) == 0 && ((uintptr_t)prefixes & 15) == 0) {
         // rows of a multiple of 4 jobs are 16-byte aligned: one vector load
-        // per 4 jobs, two loads in flight (indices clamped into the row)
+        // per 4 jobs, two loads in flight (indices clamped into the prefix,
+        // so no line past the depth is fetched)
         const int4 *r4 = reinterpret_cast<const int4 *>(row);
-        const int last = (n >> 2) - 1;
-        int4 a = r4[0];
+        const int last = max(0, (d - 1) >> 2);
+        int4 a = d > 0 ? r4[0] : int4{0, 0, 0, 0};
         for (int t = 0; t < d; t += 8) {
             const int4 b = r4[min((t >> 2) + 1, last)];
             step4(a.x, a.y, a.z, a.w, t);
@@ -236,7 +237,7 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
         }
     } else {
         for (int t = 0; t < d; t += 4)
-            step4(row[min(t, n - 1)], row[min(t + 1, n - 1)], row[min(t + 2, n - 1)], row[min(t + 3, n - 1)], t);
+            step4(row[t], row[min(t + 1, d - 1)], row[min(t + 2, d - 1)], row[min(t + 3, d - 1)], t);
     }
 
     u32v<kMaskWords> act;
@@ -355,8 +356,8 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
 // completion time on the machine before its first one handed over by lane
 // q - 1 (a one-lane DPP shift), the only value that crosses lanes.
 //
-// The block's 64 prefix rows are staged in LDS, each in a slot row of
-// n + 16 words with four words of padding before it.  A first pass, with the
+// The block's 64 prefix rows are staged in LDS, each in a slot row of at
+// least n + 16 words with four words of padding before it.  A first pass, with the
 // prefix split over the quad, checks every job's range, sets the scheduled
 // bits (LDS ORs; a repeated job shows at the end as fewer set bits than the
 // depth) and replaces each entry by the offset of the job's time row, or of
@@ -374,7 +375,24 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
 // several workgroups can combine by atomic max; FSP_LB_INVALID otherwise.
 // One block of 256 threads per 64 nodes; Npad is a multiple of 64; n <= 256
 // (the slot rows' LDS).
-constexpr int kLanesPad = 16;  // slot row = 4 words before the prefix, n entries, 12 after
+constexpr int kLanesPad = 16;  // slot row: 4 words before the prefix, n entries, at least 12 after
+
+// LDS bytes of decode16_lanes_kernel outside the slot rows.
+__host__ __device__ inline int lanes_lds_rest(int n, int MV)
+{
+    return ((n + 1) * MV + n * (MV / 2) + 64 * ((n + 31) >> 5)) * 4;
+}
+
+// Words per slot row: n + kLanesPad rounded up to 4, and one more 16-byte
+// unit when that makes the row an odd number of them, which puts the eight
+// nodes of a half-wave (read by their quads at four consecutive words) on
+// different LDS banks; but only while two blocks still fit a compute unit.
+__host__ __device__ inline int lanes_slot_row(int n, int MV)
+{
+    const int r = (n + kLanesPad + 3) & ~3;
+    const int rc = ((r >> 2) & 1) ? r : r + 4;
+    return 64 * rc * 4 + lanes_lds_rest(n, MV) <= 80 * 1024 ? rc : r;
+}
 
 template <int MV>
 __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const int32_t *__restrict__ prefixes,
@@ -384,7 +402,7 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     constexpr int MQ = MV / 4;  // machines per lane
     constexpr int H = MV / 2;   // packed tail pairs per job
     extern __shared__ uint32_t sm[];
-    const int n = T.n, m = T.m, NW = (n + 31) >> 5, RS = n + kLanesPad;
+    const int n = T.n, m = T.m, NW = (n + 31) >> 5, RS = lanes_slot_row(n, MV);
     int32_t *slots = reinterpret_cast<int32_t *>(sm);  // 64 nodes x RS: padding, prefix entries, padding
     int32_t *pl = slots + 64 * RS;                     // (n + 1) x MV times; row n is zero
     uint32_t *tq = reinterpret_cast<uint32_t *>(pl + (n + 1) * MV);  // n x H packed tails
@@ -392,26 +410,48 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     const int tid = threadIdx.x, q = tid & 3, nl = tid >> 2;
     const int zrow = n * MV;  // offset of the zero row in pl
     const int64_t node0 = (int64_t)blockIdx.x * 64;
+    const int64_t node = node0 + nl;
+    const bool live = node < N;
+    int d;
     {
-        // the block's 64 rows are contiguous in the pool: entry e of the copy
-        // is job e mod n of node e / n (the grid never starts a block past
-        // the pool's end, so lim >= n)
+        // Every global load of the staging is issued before the first store:
+        // the time rows (row n of p32 is zero), the packed tails, the depth
+        // and the block's 64 prefix rows, which are contiguous in the pool
+        // (entry e of the copy is job e mod n of node e / n; the grid never
+        // starts a block past the pool's end, so lim >= n).
+        constexpr int PP = MV + 1, TP = H;  // (n + 1) * MV <= 256 * PP, n * H <= 256 * TP
+        const int cp = (n + 1) * MV, ct = n * H;
+        int32_t pv[PP];
+        uint32_t tv[TP];
+#pragma unroll
+        for (int k = 0; k < PP; ++k) {
+            const int e = min(k * 256 + tid, cp - 1), j = e / MV;
+            pv[k] = T.p32[(size_t)j * kMaxMachines + (e - j * MV)];
+        }
+#pragma unroll
+        for (int k = 0; k < TP; ++k) {
+            const int e = min(k * 256 + tid, ct - 1), j = e / H;
+            tv[k] = T.tails16[(size_t)j * (kMaxMachines / 2) + (e - j * H)];
+        }
+        d = live ? depths[node] : 0;
         const int lim = (int)max<int64_t>(0, min<int64_t>(64, N - node0)) * n;
         const int32_t *src = prefixes + node0 * (int64_t)n;
         if (lim > 0 && (n & 3) == 0 && ((uintptr_t)src & 15) == 0) {
-            // a 16-byte load never crosses a row; slot rows keep 16-byte alignment
+            // 16-byte loads (16 n of them, at most 16 per thread) never cross
+            // a row; slot rows keep 16-byte alignment
             const int4 *s4 = reinterpret_cast<const int4 *>(src);
-            const int lim4 = lim >> 2;
-            stage_lds_with<16, int4>(
-                16 * n,
-                [&](int e) {
-                    const int4 v = s4[min(e, lim4 - 1)];
-                    return e < lim4 ? v : int4{0, 0, 0, 0};
-                },
-                [&](int e, int4 v) {
+            const int lim4 = lim >> 2, c4 = 16 * n;
+            int4 rv[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) rv[k] = s4[min(k * 256 + tid, lim4 - 1)];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int e = k * 256 + tid;
+                if (e < c4) {
                     const int w = 4 * e, r = w / n;
-                    *reinterpret_cast<int4 *>(slots + r * RS + 4 + (w - r * n)) = v;
-                });
+                    *reinterpret_cast<int4 *>(slots + r * RS + 4 + (w - r * n)) = e < lim4 ? rv[k] : int4{0, 0, 0, 0};
+                }
+            }
         } else if (lim > 0) {
             stage_lds_with<16, int32_t>(
                 64 * n,
@@ -424,21 +464,16 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
                     slots[r * RS + 4 + (e - r * n)] = v;
                 });
         }
+#pragma unroll
+        for (int k = 0; k < PP; ++k)
+            if (k * 256 + tid < cp) pl[k * 256 + tid] = pv[k];
+#pragma unroll
+        for (int k = 0; k < TP; ++k)
+            if (k * 256 + tid < ct) tq[k * 256 + tid] = tv[k];
     }
-    stage_lds<16>(pl, (n + 1) * MV, [&](int e) {  // row n of p32 is zero
-        const int j = e / MV, k = e - j * MV;
-        return T.p32[(size_t)j * kMaxMachines + k];
-    });
-    stage_lds<8>(tq, n * H, [&](int e) {
-        const int j = e / H, c = e - j * H;
-        return T.tails16[(size_t)j * (kMaxMachines / 2) + c];
-    });
     for (int e = tid; e < 64 * NW; e += 256) bits[e] = 0u;
     __syncthreads();
 
-    const int64_t node = node0 + nl;
-    const bool live = node < N;
-    int d = live ? depths[node] : 0;
     bool ok = live && d >= 0 && d <= n;
     if (!ok) d = 0;
     int32_t *myslot = slots + nl * RS;
@@ -530,11 +565,24 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
         const int lo = w * 32;
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : ((1u << (n - lo)) - 1u);
         const uint32_t un = ~mybits[w] & valid;
-        for (int b = q; b < 32 && lo + b < n; b += 4) {
-            const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)un, b, 1);
-            const uint32_t *tr = tq + (lo + b) * H;
+        // four jobs per pass, their rows read before their minima; a job past
+        // n reads row n - 1 with every half masked off
+        for (int b = q; b < 32 && lo + b < n; b += 16) {
+            uint32_t off[4], r[4][H];
 #pragma unroll
-            for (int c = 0; c < H; ++c) q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(tr[c] | off)));
+            for (int u = 0; u < 4; ++u) {
+                const int bb = b + 4 * u;
+                const bool in = bb < 32 && lo + bb < n;
+                off[u] = in ? ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)un, bb, 1) : 0xffffffffu;
+                const uint32_t *tr = tq + min(lo + bb, n - 1) * H;
+#pragma unroll
+                for (int c = 0; c < H; ++c) r[u][c] = tr[c];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < H; ++c)
+                    q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(r[u][c] | off[u])));
         }
     }
 #pragma unroll
@@ -579,8 +627,7 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 // LDS bytes of decode16_lanes_kernel for n jobs and MV machine slots.
 inline size_t decode16_lanes_lds(int n, int MV)
 {
-    return ((size_t)(n + 1) * MV + (size_t)n * (MV / 2) + (size_t)64 * ((n + 31) >> 5) +
-            (size_t)64 * (n + kLanesPad)) * 4;
+    return (size_t)lanes_lds_rest(n, MV) + (size_t)64 * lanes_slot_row(n, MV) * 4;
 }
 
 // How a pool is decoded and scanned.  Below one serial-decode wave per SIMD

@@ -87,10 +87,10 @@ __device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
         }
     };
     if ((n & 3) == 0 && ((uintptr_t)row & 15) == 0) {
-        // 16-byte row loads, two in flight (indices clamped into the row)
+        // 16-byte row loads, two in flight (indices clamped into the prefix)
         const int4 *r4 = reinterpret_cast<const int4 *>(row);
-        const int last = (n >> 2) - 1;
-        int4 a = r4[0];
+        const int last = max(0, (d - 1) >> 2);
+        int4 a = d > 0 ? r4[0] : int4{0, 0, 0, 0};
         for (int t = 0; t < d; t += 8) {
             const int4 b = r4[min((t >> 2) + 1, last)];
             step4(a.x, a.y, a.z, a.w, t);
@@ -99,7 +99,7 @@ __device__ inline void kid_chain(ReqP q, int64_t blk, uint32_t *p16)
         }
     } else {
         for (int t = 0; t < d; t += 4)
-            step4(row[min(t, n - 1)], row[min(t + 1, n - 1)], row[min(t + 2, n - 1)], row[min(t + 3, n - 1)], t);
+            step4(row[t], row[min(t + 1, d - 1)], row[min(t + 2, d - 1)], row[min(t + 3, d - 1)], t);
     }
     int32_t *r = rec + p * kKidRec;
     cptr<int32_t> cs = as_const(q->T.colsum32);

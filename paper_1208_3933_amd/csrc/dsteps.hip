@@ -53,58 +53,81 @@ __device__ __forceinline__ int64_t kids_from_top(const DevSearch *ds, const int3
     return (i < ds->maxK && idx >= 0) ? (int64_t)(ds->n - sdep[idx]) : 0;
 }
 
+// No step runs: the search ended, or the stack has no room for the next
+// step's worst case.
+__device__ __forceinline__ bool idle(const DevSearch *ds) { return ds->done || ds->paused; }
+
 __global__ __launch_bounds__(kSelThreads) void dsel_sums_kernel(const DevSearch *__restrict__ ds,
                                                                 const int32_t *__restrict__ sdep,
                                                                 int64_t *__restrict__ sums)
 {
     __shared__ int64_t sh[kSelThreads];
     const int64_t i = (int64_t)blockIdx.x * kSelThreads + threadIdx.x;
-    const int64_t v = ds->done ? 0 : kids_from_top(ds, sdep, i);
+    const int64_t v = idle(ds) ? 0 : kids_from_top(ds, sdep, i);
     const int64_t tot = block_scan_incl(v, sh);
     if (threadIdx.x == kSelThreads - 1) sums[blockIdx.x] = tot;
 }
 
 // One block: the step's parents K and children nch, and the request's sizes
-// and initial results.
+// and initial results.  Pauses the search first when the stack has no room
+// for the step's worst case.
 __global__ __launch_bounds__(kSelThreads) void dsel_finish_kernel(DevSearch *__restrict__ ds,
                                                                   const int32_t *__restrict__ sdep,
                                                                   const int64_t *__restrict__ sums, int nchunks,
                                                                   StepReq *__restrict__ req, ScanSeg *__restrict__ seg)
 {
     __shared__ int64_t sh[kSelThreads];
-    __shared__ int64_t s_chunk, s_before, s_K, s_nch;
+    __shared__ unsigned long long s_chunk, s_K;
+    __shared__ int64_t s_before, s_tile, s_nch;
+    __shared__ int s_off;
     const int t = threadIdx.x;
     const int64_t cap = ds->pool_cap;
     if (t == 0) {
-        // the first chunk whose sum would pass pool_cap, and the children before it
-        int64_t before = 0, c = 0;
-        for (; c < nchunks; ++c) {
-            if (before + sums[c] > cap) break;
-            before += sums[c];
-        }
-        s_chunk = c;
-        s_before = before;
-        // every entry of the chunks before fits; when every chunk fits, so
-        // does every entry within reach
-        s_K = c < nchunks ? c * kSelThreads : min(ds->top, ds->maxK);
-        s_nch = before;
+        if (!ds->done && !ds->paused && ds->top + ds->maxC > ds->cap_stack) ds->paused = 1;
+        s_off = idle(ds) ? 1 : 0;
+        s_chunk = (unsigned long long)nchunks;
+        s_before = 0;
+        s_tile = 0;
     }
     __syncthreads();
-    const int64_t c = s_chunk;
-    if (!ds->done && c < nchunks) {
+    const bool off = s_off != 0;
+    // the first chunk whose running sum passes pool_cap (chunk sums scanned a
+    // block-width at a time), and the children in the chunks before it
+    int64_t base = 0;
+    for (int c0 = 0; c0 < nchunks && !off; c0 += kSelThreads) {
+        const int c = c0 + t;
+        const int64_t v = c < nchunks ? sums[c] : 0;
+        const int64_t incl = base + block_scan_incl(v, sh);
+        if (t == kSelThreads - 1) s_tile = incl;  // the running sum through this tile
+        if (c < nchunks && incl > cap) atomicMin(&s_chunk, (unsigned long long)c);
+        __syncthreads();
+        if ((unsigned long long)c == s_chunk) s_before = incl - v;
+        base = s_tile;
+        __syncthreads();
+        if (s_chunk < (unsigned long long)nchunks) break;
+    }
+    const int64_t c = (int64_t)s_chunk;
+    if (t == 0) {
+        // every entry of the chunks before the cut fits; when no chunk passes
+        // pool_cap, so does every entry within reach, with all their children
+        s_K = c < nchunks ? (unsigned long long)(c * kSelThreads) : (unsigned long long)min(ds->top, ds->maxK);
+        s_nch = c < nchunks ? s_before : s_tile;
+    }
+    __syncthreads();
+    if (!off && c < nchunks) {
         const int64_t i = c * kSelThreads + t;
         const int64_t v = kids_from_top(ds, sdep, i);
         const int64_t pre = s_before + block_scan_incl(v, sh);  // children up to and including entry i
         // entries of the chunk that fit: those with prefix <= cap (and a parent)
         const int fits = (v > 0 && pre <= cap) ? 1 : 0;
-        if (fits) atomicMax((unsigned long long *)&s_K, (unsigned long long)(i + 1));
+        if (fits) atomicMax(&s_K, (unsigned long long)(i + 1));
         __syncthreads();
-        if (fits && i + 1 == s_K) s_nch = pre;
+        if (fits && (unsigned long long)(i + 1) == s_K) s_nch = pre;
         __syncthreads();
     }
     if (t == 0) {
-        int64_t K = ds->done ? 0 : s_K, nch = ds->done ? 0 : s_nch;
-        if (!ds->done && K == 0 && ds->top > 0) {  // the first parent alone passes pool_cap: it is taken
+        int64_t K = off ? 0 : (int64_t)s_K, nch = off ? 0 : s_nch;
+        if (!off && K == 0 && ds->top > 0) {  // the first parent alone passes pool_cap: it is taken
             K = 1;
             nch = ds->n - sdep[ds->top - 1];
         }
@@ -128,7 +151,7 @@ __global__ __launch_bounds__(kSelThreads) void dsel_finish_kernel(DevSearch *__r
 __global__ void dstep_update_kernel(DevSearch *__restrict__ ds, const StepReq *__restrict__ req,
                                     int64_t *__restrict__ steplog)
 {
-    if (threadIdx.x != 0 || ds->done || ds->K == 0) return;
+    if (threadIdx.x != 0 || idle(ds) || ds->K == 0) return;
     const StepResultDev o = req->res;
     if (o.bad || (int64_t)o.nchild != ds->nch) {
         ds->done = 1;

@@ -105,12 +105,16 @@ constexpr int kDevSelChunk = 1024;  // stack entries per block of the device sel
 
 // Device-side state of a depth-first search stepped on the device
 // (dsteps.hip): the host's counters and stack top, and the step in flight.
+// A step whose worst case (maxC more rows) would not fit the stack's
+// cap_stack rows is not started: the search pauses until the host grows the
+// stack and clears `paused`.
 struct DevSearch {
     int64_t top, nodes, steps, max_stack;
     int64_t node_budget, pool_cap, maxK, steplog_cap;
     int64_t K, nch, base;
+    int64_t cap_stack, maxC;
     int32_t UB, improvements, done, status;
-    int32_t n, pad;
+    int32_t n, paused;
 };
 
 // The two host-side parts of a step as kernels: choose the step's parents

@@ -841,39 +841,54 @@ hipError_t run_device_steps(Search &S, TickContext &ctx)
     st.node_budget = S.node_budget;
     st.pool_cap = S.pool_cap;
     st.maxK = maxK;
+    st.maxC = maxC;
+    st.cap_stack = S.cap_stack;
     st.steplog_cap = logcap;
     st.UB = S.UB;
     st.improvements = S.improvements;
     st.done = S.done ? 1 : 0;
     st.status = S.status;
     st.n = n;
-    std::memcpy(h + off_ds, &st, sizeof(st));
-    e = hipMemcpyAsync(dds, h + off_ds, sizeof(st), hipMemcpyHostToDevice, s);
+    st.paused = 0;
+    auto upload_state = [&]() -> hipError_t {
+        std::memcpy(h + off_ds, &st, sizeof(st));
+        return hipMemcpyAsync(dds, h + off_ds, sizeof(st), hipMemcpyHostToDevice, s);
+    };
+    e = upload_state();
     if (e == hipSuccess) e = upload_table();
-    // steps per synchronisation: 1, 2, 4, ... up to 16, so that short
-    // searches do not run many empty steps after their end
+    // steps per synchronisation: 1, 2, 4, ... up to 16, and fewer when the
+    // steps are large (at most about 2^20 children per synchronisation), so
+    // that a search does not run many empty steps after its end
+    const int chunk_max = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 20) / maxC));
     int chunk = 1;
     while (e == hipSuccess && !st.done) {
-        // room on the stack for the chunk: a step adds at most maxC - 1 rows
-        if (st.top + chunk * maxC > S.cap_stack) {
+        // the device pauses a search whose next step might not fit the stack
+        // (maxC more rows): grow it, doubling, and resume
+        if (st.paused || st.top + maxC > S.cap_stack) {
             int64_t nc = S.cap_stack;
-            while (st.top + chunk * maxC > nc) nc *= 2;
-            int32_t *r2 = nullptr, *d2 = nullptr;
-            e = stream_alloc((void **)&r2, (size_t)nc * n * 4, s);
-            if (e == hipSuccess) e = stream_alloc((void **)&d2, (size_t)nc * 4, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(r2, S.srows, (size_t)st.top * n * 4, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(d2, S.sdep, (size_t)st.top * 4, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) {
-                if (r2) stream_free(r2, s);
-                if (d2) stream_free(d2, s);
-                break;
+            while (st.top + maxC > nc) nc *= 2;
+            if (nc > S.cap_stack) {
+                int32_t *r2 = nullptr, *d2 = nullptr;
+                e = stream_alloc((void **)&r2, (size_t)nc * n * 4, s);
+                if (e == hipSuccess) e = stream_alloc((void **)&d2, (size_t)nc * 4, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(r2, S.srows, (size_t)st.top * n * 4, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(d2, S.sdep, (size_t)st.top * 4, hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) {
+                    if (r2) stream_free(r2, s);
+                    if (d2) stream_free(d2, s);
+                    break;
+                }
+                stream_free(S.srows, s);
+                stream_free(S.sdep, s);
+                S.srows = r2;
+                S.sdep = d2;
+                S.cap_stack = nc;
+                e = upload_table();
+                if (e != hipSuccess) break;
             }
-            stream_free(S.srows, s);
-            stream_free(S.sdep, s);
-            S.srows = r2;
-            S.sdep = d2;
-            S.cap_stack = nc;
-            e = upload_table();
+            st.cap_stack = S.cap_stack;
+            st.paused = 0;
+            e = upload_state();
             if (e != hipSuccess) break;
         }
         for (int k = 0; k < chunk && e == hipSuccess; ++k) {
@@ -886,7 +901,7 @@ hipError_t run_device_steps(Search &S, TickContext &ctx)
         if (e == hipSuccess) e = hipMemcpyAsync(h + off_ds, dds, sizeof(st), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess) std::memcpy(&st, h + off_ds, sizeof(st));
-        if (chunk < 16) chunk *= 2;
+        chunk = std::min(2 * chunk, chunk_max);
     }
     if (e != hipSuccess) return e;
     S.top = st.top;
