@@ -346,77 +346,85 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
     decode16_block<MV>(T, prefixes, depths, N, Npad, W, out_lb, blockIdx.x, sm);
 }
 
-// ---- decode with four lanes per node, for pools too small to fill the chip
+// ---- decode with four or eight lanes per node, for pools too small to fill the chip
 //
 // The one-lane decode above is latency-bound on a small pool: each lane walks
-// its whole prefix through all m machines one job at a time.  Here the four
-// lanes of a node (an aligned quad) split the machines, lane q holding
+// its whole prefix through all m machines one job at a time.  Here the L
+// lanes of a node (L = 4 or 8, aligned) split the machines, lane q holding
 // machines [q*MQ, (q+1)*MQ), and the completion-time recurrence of the prefix
 // runs as a pipeline across them: at step s lane q takes job s - q, with the
 // completion time on the machine before its first one handed over by lane
 // q - 1 (a one-lane DPP shift), the only value that crosses lanes.
 //
-// The block's 64 prefix rows are staged in LDS, each in a slot row of at
-// least n + 16 words with four words of padding before it.  A first pass, with the
-// prefix split over the quad, checks every job's range, sets the scheduled
-// bits (LDS ORs; a repeated job shows at the end as fewer set bits than the
-// depth) and replaces each entry by the offset of the job's time row, or of
-// the zero row for an invalid job or an entry past the depth; the padding
-// holds the zero row too.  A step before a lane's first job or past the
-// prefix thus reads the zero row, which leaves the completion times
-// unchanged, because they never decrease along the machines.  Step s of lane
-// q reads entry s - q at a fixed distance from its own base: the offsets are
-// read four steps ahead, the time rows two steps ahead, and a step spends one
-// address add on them.  The tails split the jobs over the quad (job j to lane
-// j mod 4), with packed 16-bit minima combined across the quad.
+// The block's 256 / L prefix rows are staged in LDS, each in a slot row with
+// L words of padding before it and room after it for the pipeline's reads
+// past the deepest prefix.  A first pass, with the prefix split over the
+// node's lanes, checks every job's range, sets the scheduled bits (LDS ORs; a
+// repeated job shows at the end as fewer set bits than the depth) and
+// replaces each entry by the offset of the job's time row, or of the zero
+// row for an invalid job or an entry past the depth; the padding holds the
+// zero row too.  A step before a lane's first job or past the prefix thus
+// reads the zero row, which leaves the completion times unchanged, because
+// they never decrease along the machines.  Step s of lane q reads entry
+// s - q at a fixed distance from its own base: the offsets are read four
+// steps ahead, the time rows two steps ahead, and a step spends one address
+// add on them.  The tails split the jobs over the node's lanes (job j to
+// lane j mod L), with packed 16-bit minima combined across them.
 //
 // Writes the scan workspace in the layout of the one-lane decode (nodes in
 // pool order), and out_lb = 0 for every valid node so that a scan split over
 // several workgroups can combine by atomic max; FSP_LB_INVALID otherwise.
-// One block of 256 threads per 64 nodes; Npad is a multiple of 64; n <= 256
-// (the slot rows' LDS).
-constexpr int kLanesPad = 16;  // slot row: 4 words before the prefix, n entries, at least 12 after
+// One block of 256 threads per 256 / L nodes; Npad is a multiple of 128;
+// n <= 256 (the slot rows' LDS); MV is a multiple of L (machines past m have
+// zero times).
 
-// LDS bytes of decode16_lanes_kernel outside the slot rows.
-__host__ __device__ inline int lanes_lds_rest(int n, int MV)
+// LDS bytes of decode16_lanes_kernel outside the slot rows (L lanes per node,
+// 256 / L nodes per block).
+__host__ __device__ inline int lanes_lds_rest(int n, int MV, int L)
 {
-    return ((n + 1) * MV + n * (MV / 2) + 64 * ((n + 31) >> 5)) * 4;
+    return ((n + 1) * MV + n * (MV / 2) + (256 / L) * ((n + 31) >> 5)) * 4;
 }
 
-// Words per slot row: n + kLanesPad rounded up to 4, and one more 16-byte
-// unit when that makes the row an odd number of them, which puts the eight
-// nodes of a half-wave (read by their quads at four consecutive words) on
-// different LDS banks; but only while two blocks still fit a compute unit.
-__host__ __device__ inline int lanes_slot_row(int n, int MV)
+// Words per slot row: L words of padding before the prefix, the n entries,
+// and room for the pipeline's reads past the deepest prefix (L + 6 words),
+// rounded up to 4; one more 16-byte unit when that makes the row an odd
+// number of them, which puts the nodes of a half-wave (read by their lanes at
+// consecutive words) on different LDS banks, but only while two blocks still
+// fit a compute unit.
+__host__ __device__ inline int lanes_slot_row(int n, int MV, int L)
 {
-    const int r = (n + kLanesPad + 3) & ~3;
+    const int r = (L + n + L + 6 + 3) & ~3;
     const int rc = ((r >> 2) & 1) ? r : r + 4;
-    return 64 * rc * 4 + lanes_lds_rest(n, MV) <= 80 * 1024 ? rc : r;
+    return (256 / L) * rc * 4 + lanes_lds_rest(n, MV, L) <= 80 * 1024 ? rc : r;
 }
 
-template <int MV>
+template <int MV, int L>
 __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const int32_t *__restrict__ prefixes,
                                                              const int32_t *__restrict__ depths, int64_t N,
                                                              Workspace16 W, int32_t *__restrict__ out_lb)
 {
-    constexpr int MQ = MV / 4;  // machines per lane
-    constexpr int H = MV / 2;   // packed tail pairs per job
+    static_assert(L == 4 || L == 8, "four or eight lanes per node");
+    static_assert(MV % L == 0, "whole machines per lane");
+    constexpr int NB = 256 / L;  // nodes per block
+    constexpr int MQ = MV / L;   // machines per lane
+    constexpr int H = MV / 2;    // packed tail pairs per job
+    constexpr int PADB = L;      // slot words before the prefix
     extern __shared__ uint32_t sm[];
-    const int n = T.n, m = T.m, NW = (n + 31) >> 5, RS = lanes_slot_row(n, MV);
-    int32_t *slots = reinterpret_cast<int32_t *>(sm);  // 64 nodes x RS: padding, prefix entries, padding
-    int32_t *pl = slots + 64 * RS;                     // (n + 1) x MV times; row n is zero
+    const int n = T.n, m = T.m, NW = (n + 31) >> 5, RS = lanes_slot_row(n, MV, L);
+    int32_t *slots = reinterpret_cast<int32_t *>(sm);  // NB nodes x RS: padding, prefix entries, padding
+    int32_t *pl = slots + NB * RS;                     // (n + 1) x MV times; row n is zero
     uint32_t *tq = reinterpret_cast<uint32_t *>(pl + (n + 1) * MV);  // n x H packed tails
-    uint32_t *bits = tq + n * H;                       // 64 nodes x NW scheduled-job words
-    const int tid = threadIdx.x, q = tid & 3, nl = tid >> 2;
+    uint32_t *bits = tq + n * H;                       // NB nodes x NW scheduled-job words
+    const int tid = threadIdx.x, q = tid & (L - 1), nl = tid / L;
     const int zrow = n * MV;  // offset of the zero row in pl
-    const int64_t node0 = (int64_t)blockIdx.x * 64;
+    const int64_t node0 = (int64_t)blockIdx.x * NB;
     const int64_t node = node0 + nl;
     const bool live = node < N;
     int d;
     {
         // Every global load of the staging is issued before the first store:
         // the time rows (row n of p32 is zero), the packed tails, the depth
-        // and the block's 64 prefix rows, which are contiguous in the pool
+        // and the block's NB prefix rows, which are contiguous in the pool
         // (entry e of the copy is job e mod n of node e / n; the grid never
         // starts a block past the pool's end, so lim >= n).
         constexpr int PP = MV + 1, TP = H;  // (n + 1) * MV <= 256 * PP, n * H <= 256 * TP
@@ -434,13 +442,13 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
             tv[k] = T.tails16[(size_t)j * (kMaxMachines / 2) + (e - j * H)];
         }
         d = live ? depths[node] : 0;
-        const int lim = (int)max<int64_t>(0, min<int64_t>(64, N - node0)) * n;
+        const int lim = (int)max<int64_t>(0, min<int64_t>(NB, N - node0)) * n;
         const int32_t *src = prefixes + node0 * (int64_t)n;
         if (lim > 0 && (n & 3) == 0 && ((uintptr_t)src & 15) == 0) {
-            // 16-byte loads (16 n of them, at most 16 per thread) never cross
-            // a row; slot rows keep 16-byte alignment
+            // 16-byte loads (NB n / 4 of them, at most 16 per thread) never
+            // cross a row; slot rows keep 16-byte alignment
             const int4 *s4 = reinterpret_cast<const int4 *>(src);
-            const int lim4 = lim >> 2, c4 = 16 * n;
+            const int lim4 = lim >> 2, c4 = NB * n / 4;
             int4 rv[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) rv[k] = s4[min(k * 256 + tid, lim4 - 1)];
@@ -449,19 +457,20 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
                 const int e = k * 256 + tid;
                 if (e < c4) {
                     const int w = 4 * e, r = w / n;
-                    *reinterpret_cast<int4 *>(slots + r * RS + 4 + (w - r * n)) = e < lim4 ? rv[k] : int4{0, 0, 0, 0};
+                    *reinterpret_cast<int4 *>(slots + r * RS + PADB + (w - r * n)) =
+                        e < lim4 ? rv[k] : int4{0, 0, 0, 0};
                 }
             }
         } else if (lim > 0) {
             stage_lds_with<16, int32_t>(
-                64 * n,
+                NB * n,
                 [&](int e) {
                     const int32_t v = src[min(e, lim - 1)];
                     return e < lim ? v : 0;
                 },
                 [&](int e, int32_t v) {
                     const int r = e / n;
-                    slots[r * RS + 4 + (e - r * n)] = v;
+                    slots[r * RS + PADB + (e - r * n)] = v;
                 });
         }
 #pragma unroll
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
         for (int k = 0; k < TP; ++k)
             if (k * 256 + tid < ct) tq[k * 256 + tid] = tv[k];
     }
-    for (int e = tid; e < 64 * NW; e += 256) bits[e] = 0u;
+    for (int e = tid; e < NB * NW; e += 256) bits[e] = 0u;
     __syncthreads();
 
     bool ok = live && d >= 0 && d <= n;
@@ -480,24 +489,24 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     uint32_t *mybits = bits + nl * NW;
 
     // range checks, scheduled bits and time-row offsets, the prefix split
-    // over the quad; the padding takes the zero row
+    // over the node's lanes; the padding takes the zero row
     if (q == 0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) myslot[t] = zrow;
+        for (int t = 0; t < PADB; ++t) myslot[t] = zrow;
     }
-    for (int t = 4 + n + q; t < RS; t += 4) myslot[t] = zrow;
-    for (int t = q; t < n; t += 16) {
+    for (int t = PADB + n + q; t < RS; t += L) myslot[t] = zrow;
+    for (int t = q; t < n; t += 4 * L) {
         int32_t raw[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) raw[u] = myslot[4 + min(t + 4 * u, n - 1)];
+        for (int u = 0; u < 4; ++u) raw[u] = myslot[PADB + min(t + L * u, n - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int tt = t + 4 * u;
+            const int tt = t + L * u;
             if (tt < n) {
                 const bool in = tt < d, good = (unsigned)raw[u] < (unsigned)n;
                 if (in && good) atomicOr(&mybits[raw[u] >> 5], 1u << (raw[u] & 31));
                 if (in && !good) ok = false;
-                myslot[4 + tt] = in && good ? raw[u] * MV : zrow;
+                myslot[PADB + tt] = in && good ? raw[u] * MV : zrow;
             }
         }
     }
@@ -507,14 +516,14 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 #pragma unroll
     for (int kk = 0; kk < MQ; ++kk) { C[kk] = 0; S[kk] = 0; }
     // wave-uniform step count: the deepest prefix of the wave plus the pipeline fill
-    int smax = d + 3;
+    int smax = d + L - 1;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) smax = max(smax, __shfl_xor(smax, off));
 
     // step s of lane q takes entry s - q: base[s] (base[0] is padding for
     // q > 0).  Rings of four registers, indexed by the step modulo 4 in a loop
     // unrolled four times: offsets read four steps ahead, rows two steps ahead.
-    const int32_t *base = myslot + 4 - q;
+    const int32_t *base = myslot + PADB - q;
     const int lq = q * MQ;  // this lane's first machine in a time row
     int32_t xr[4][MQ], o[4];
 #pragma unroll
@@ -555,9 +564,10 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     int bad = !ok;
     bad |= __builtin_amdgcn_mov_dpp(bad, 0xb1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
     bad |= __builtin_amdgcn_mov_dpp(bad, 0x4e, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    if constexpr (L == 8) bad |= __shfl_xor(bad, 4);
     ok = !bad && live && nset == d;
 
-    // tails: lane q takes jobs j = 32w + q + 4i, packed 16-bit minima over (Q | off)
+    // tails: lane q takes jobs j = 32w + q + L i, packed 16-bit minima over (Q | off)
     uint32_t q2[H];
 #pragma unroll
     for (int c = 0; c < H; ++c) q2[c] = 0xffffffffu;
@@ -567,11 +577,11 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
         const uint32_t un = ~mybits[w] & valid;
         // four jobs per pass, their rows read before their minima; a job past
         // n reads row n - 1 with every half masked off
-        for (int b = q; b < 32 && lo + b < n; b += 16) {
+        for (int b = q; b < 32 && lo + b < n; b += 4 * L) {
             uint32_t off[4], r[4][H];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int bb = b + 4 * u;
+                const int bb = b + L * u;
                 const bool in = bb < 32 && lo + bb < n;
                 off[u] = in ? ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)un, bb, 1) : 0xffffffffu;
                 const uint32_t *tr = tq + min(lo + bb, n - 1) * H;
@@ -593,6 +603,8 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
         q2[c] = as32(__builtin_elementwise_min(as16(q2[c]),
                                                as16((uint32_t)__builtin_amdgcn_mov_dpp((int)q2[c], 0x4e, 0xf, 0xf,
                                                                                       false))));  // [2,3,0,1]
+        if constexpr (L == 8)
+            q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16((uint32_t)__shfl_xor((int)q2[c], 4))));
     }
 
     const bool empty = d == n;  // no unscheduled job: every tail is 0
@@ -610,7 +622,7 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
             d16[((G * 3 + 2) * m + k) * 128 + lane * 2 + half] = (uint16_t)(ok && !empty ? qk : 0u);
         }
     }
-    for (int w = q; w < NW; w += 4) {
+    for (int w = q; w < NW; w += L) {
         const int lo = w * 32;
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : ((1u << (n - lo)) - 1u);
         W.flg[(G * NW + w) * 128 + g] = ok ? (~mybits[w] & valid) : 0u;
@@ -625,9 +637,9 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 }
 
 // LDS bytes of decode16_lanes_kernel for n jobs and MV machine slots.
-inline size_t decode16_lanes_lds(int n, int MV)
+inline size_t decode16_lanes_lds(int n, int MV, int L)
 {
-    return (size_t)lanes_lds_rest(n, MV) + (size_t)64 * lanes_slot_row(n, MV) * 4;
+    return (size_t)lanes_lds_rest(n, MV, L) + (size_t)(256 / L) * lanes_slot_row(n, MV, L) * 4;
 }
 
 // How a pool is decoded and scanned.  Below one serial-decode wave per SIMD
@@ -637,9 +649,11 @@ inline size_t decode16_lanes_lds(int n, int MV)
 // over several workgroups (at least four pairs per split, about one per
 // wave), which needs the four-lane decode's zeroed bounds.
 struct PoolPlan {
-    bool lanes;  // four-lane decode
-    int splits;  // pair splits of the scan
+    bool lanes;          // several lanes per node in the decode
+    int splits;          // pair splits of the scan
+    int lanes_per_node;  // 4 or 8
 };
+
 
 constexpr int kLanesMaxJobs = 256;  // the four-lane decode stages 64 prefix rows in LDS
 
@@ -658,13 +672,18 @@ static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
     if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: the regular path only
     int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
     if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
-    if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1};
+    if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1, 4};
     int fill = 2, minp = 4;  // workgroups per compute unit; least pairs per split
     if (const char *e = getenv("FSPBB_SPLIT_FILL")) fill = std::max(1, atoi(e));
     if (const char *e = getenv("FSPBB_SPLIT_MIN_PAIRS")) minp = std::max(1, atoi(e));
     int sp = 1;
     while (sp < cap && G * sp < (int64_t)fill * cus && minp * 2 * sp <= I->P) sp *= 2;
-    return PoolPlan{true, sp};
+    // eight lanes per node while their blocks (32 nodes each) do not
+    // outnumber the compute units; four above (measured at 200x20: 24 against
+    // 30 us at 4,096 nodes, equal at 16,384, slower at 32,768)
+    int lpn = N <= (int64_t)32 * cus ? 8 : 4;
+    if (const char *e = getenv("FSPBB_LANES_PER_NODE")) lpn = atoi(e) == 8 ? 8 : 4;
+    return PoolPlan{true, sp, lpn};
 }
 
 // ---- batched bounding: many pools in one decode launch per machine-count
@@ -940,17 +959,22 @@ hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, co
     const int MV = (m + 3) & ~3;
     const PoolPlan plan = pool_plan(I, N, G);
     if (plan.lanes) {
-        // four lanes per node in pool order, then the pairs of each group,
-        // split over several workgroups when the groups are few
+        // L lanes per node in pool order, then the pairs of each group, split
+        // over several workgroups when the groups are few
         W.order = nullptr;
         if (marks) timing_mark(I, 0, s);
-        const dim3 lgrid((unsigned)(Npad / 64));
-        const size_t llds = decode16_lanes_lds(n, MV);
-#define FSP_LDECODE(MVV) \
-    case MVV: decode16_lanes_kernel<MVV><<<lgrid, 256, llds, s>>>(I->dt, prefixes, depths, N, W, out_lb); break;
-        switch (MV) {
-            FSP_LDECODE(4) FSP_LDECODE(8) FSP_LDECODE(12) FSP_LDECODE(16)
-            FSP_LDECODE(20) FSP_LDECODE(24) FSP_LDECODE(28) FSP_LDECODE(32)
+        const int L = plan.lanes_per_node, MVL = (m + L - 1) / L * L;
+        const dim3 lgrid((unsigned)(Npad / (256 / L)));
+        const size_t llds = decode16_lanes_lds(n, MVL, L);
+#define FSP_LDECODE(MVV, LL) \
+    case MVV: decode16_lanes_kernel<MVV, LL><<<lgrid, 256, llds, s>>>(I->dt, prefixes, depths, N, W, out_lb); break;
+        if (L == 8) {
+            switch (MVL) { FSP_LDECODE(8, 8) FSP_LDECODE(16, 8) FSP_LDECODE(24, 8) FSP_LDECODE(32, 8) }
+        } else {
+            switch (MVL) {
+                FSP_LDECODE(4, 4) FSP_LDECODE(8, 4) FSP_LDECODE(12, 4) FSP_LDECODE(16, 4)
+                FSP_LDECODE(20, 4) FSP_LDECODE(24, 4) FSP_LDECODE(28, 4) FSP_LDECODE(32, 4)
+            }
         }
 #undef FSP_LDECODE
         hipError_t e = hipGetLastError();

@@ -69,7 +69,9 @@ def test_small_pool_large_shapes_sampled(n, m, N):
     assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
 
 
-def test_small_pool_invalid_nodes_and_leaves():
+@pytest.mark.parametrize("lanes", ["4", "8"])
+def test_small_pool_invalid_nodes_and_leaves(lanes, monkeypatch):
+    monkeypatch.setenv("FSPBB_LANES_PER_NODE", lanes)
     torch = require_gpu()
     n, m, N = 30, 6, 300
     p = gen.processing_times(n, m, gen.make_seed(21, 0, gen.PURPOSE_TIMES))
@@ -147,3 +149,29 @@ def test_small_pool_split_shapes(fill, minp, ppw):
                 else:
                     os.environ[k] = v
     assert (got == want).all()
+
+
+@pytest.mark.parametrize("n,m", [(20, 5), (200, 20), (7, 32), (33, 3), (64, 17), (1, 2), (256, 32)])
+@pytest.mark.parametrize("N", [63, 1000, 4096])
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_small_pool_lanes_per_node(n, m, N, lanes):
+    """The small-pool decode with four or eight lanes per node (the machines
+    split over the node's lanes) gives the regular path's bounds."""
+    torch = require_gpu()
+    p = gen.processing_times(n, m, gen.make_seed(25, n * 100 + m, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(25, n * 100 + m + N, gen.PURPOSE_POOL), 0, n)
+    old = os.environ.get("FSPBB_LANES_PER_NODE")
+    with fspbb.create_instance(p) as inst:
+        want = _bounds(torch, inst, pre, dep, regular=True)
+        try:
+            os.environ["FSPBB_LANES_PER_NODE"] = str(lanes)
+            got = _bounds(torch, inst, pre, dep)
+            assert fspbb.pool_status(inst) == 0
+        finally:
+            if old is None:
+                os.environ.pop("FSPBB_LANES_PER_NODE", None)
+            else:
+                os.environ["FSPBB_LANES_PER_NODE"] = old
+    assert (got == want).all()
+    idx = np.arange(0, N, 11)
+    assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
