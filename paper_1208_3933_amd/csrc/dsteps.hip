@@ -28,21 +28,23 @@ namespace {
 
 constexpr int kSelThreads = kDevSelChunk;
 
-// Block-wide inclusive scan of one value per thread (1,024 threads).
+// Block-wide inclusive scan of one value per thread (1,024 threads: 16
+// waves): a scan within each wave by lane shuffles, then each wave adds the
+// totals of the waves before it.  sh: at least 16 words.
 __device__ int64_t block_scan_incl(int64_t v, int64_t *sh)
 {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kSelThreads; off <<= 1) {
-        const int64_t a = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += a;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t u = __shfl_up(v, off);
+        if (lane >= off) v += u;
     }
-    const int64_t r = sh[t];
+    if (lane == 63) sh[w] = v;
     __syncthreads();
-    return r;
+    int64_t before = 0;
+    for (int k = 0; k < w; ++k) before += sh[k];
+    __syncthreads();  // sh is free again when the call returns
+    return v + before;
 }
 
 // Children of stack entry i counted from the top (i = 0 is the top), or 0 past
