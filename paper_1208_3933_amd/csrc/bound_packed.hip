@@ -657,7 +657,7 @@ struct PoolPlan {
 
 constexpr int kLanesMaxJobs = 256;  // the four-lane decode stages 64 prefix rows in LDS
 
-static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
+static int device_cus()
 {
     static int cus = 0;
     if (cus == 0) {
@@ -668,16 +668,39 @@ static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
         else
             cus = 256;
     }
+    return cus;
+}
+
+// Pair splits of the scan for G groups: doubled while the workgroups stay
+// under two per compute unit and each split keeps at least four pairs.
+static int split_count(const fsp_instance_s *I, int64_t G)
+{
+    const int cus = device_cus();
     int cap = 16;
-    if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: the regular path only
-    int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
-    if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
-    if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1, 4};
+    if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: no splits
     int fill = 2, minp = 4;  // workgroups per compute unit; least pairs per split
     if (const char *e = getenv("FSPBB_SPLIT_FILL")) fill = std::max(1, atoi(e));
     if (const char *e = getenv("FSPBB_SPLIT_MIN_PAIRS")) minp = std::max(1, atoi(e));
     int sp = 1;
     while (sp < cap && G * sp < (int64_t)fill * cus && minp * 2 * sp <= I->P) sp *= 2;
+    return sp;
+}
+
+int scan_splits_for(const fsp_instance_s *I, int64_t N)
+{
+    if (N <= 0) return 1;
+    return split_count(I, (N + kGroup - 1) / kGroup);
+}
+
+static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
+{
+    const int cus = device_cus();
+    int cap = 16;
+    if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: the regular path only
+    int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
+    if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
+    if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1, 4};
+    const int sp = split_count(I, G);
     // eight lanes per node while their blocks (32 nodes each) do not
     // outnumber the compute units; four above (measured at 200x20: 24 against
     // 30 us at 4,096 nodes, equal at 16,384, slower at 32,768)

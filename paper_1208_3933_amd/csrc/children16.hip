@@ -298,6 +298,8 @@ __global__ __launch_bounds__(256) void kid_decode_kernel(const StepReq *__restri
     if (LIST && live && empty && mk < q->a.ub_in)
         atomicMin(q->w.best, ((unsigned long long)(uint32_t)mk << 32) | (unsigned long long)i);
     Wst[i] = live ? 1u : 0u;
+    // a scan split over several workgroups takes its bounds by atomic max
+    if (live && q->w.clb) q->w.clb[i] = 0;
 }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -74,4 +74,9 @@ hipError_t kids16_decode(const StepReq *dreqs, int R, int64_t maxK, int64_t maxC
 // children, bounds to clb (its w.clb).
 hipError_t kids16_bound(const StepReq *dreq, fsp_instance_s *I, Kids16 &k, int32_t *clb, hipStream_t s);
 
+// Pair splits for a scan of N children decoded by kids16_decode (which
+// zeroes each child's bound in the request's clb, so that the splits can
+// combine by atomic max): more than one when N fills too few workgroups.
+int scan_splits_for(const fsp_instance_s *I, int64_t N);
+
 }  // namespace fspbb

@@ -713,7 +713,7 @@ hipError_t tick(std::vector<Search *> &act, TickContext &ctx)
     // (decoded workspaces go straight to its scan)
     if (R == 1) {
         Search &S = *act[0];
-        e = kid_of[0] >= 0 ? launch_scan16(S.inst, kv[0].W, S.nch, S.B.w.clb, s)
+        e = kid_of[0] >= 0 ? launch_scan16(S.inst, kv[0].W, S.nch, S.B.w.clb, s, scan_splits_for(S.inst, S.nch))
                            : bound_rows(S.inst, S.B.w.crow, S.B.w.cdepth, S.nch, S.B.w.clb, s, false);
     } else {
         for (int r = 0; r < R && e == hipSuccess; ++r) {
@@ -860,6 +860,7 @@ hipError_t run_device_steps(Search &S, TickContext &ctx)
     // steps are large (at most about 2^20 children per synchronisation), so
     // that a search does not run many empty steps after its end
     const int chunk_max = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 20) / maxC));
+    const int splits = scan_splits_for(I, maxC);  // for the largest step
     int chunk = 1;
     while (e == hipSuccess && !st.done) {
         // the device pauses a search whose next step might not fit the stack
@@ -894,7 +895,7 @@ hipError_t run_device_steps(Search &S, TickContext &ctx)
         for (int k = 0; k < chunk && e == hipSuccess; ++k) {
             e = launch_device_step_select(dds, S.sdep, dsums, nchunks, dq, ds1, s);
             if (e == hipSuccess) e = kids16_decode(dq, 1, maxK, maxC, n, I->m, s, ds1);
-            if (e == hipSuccess) e = launch_scan16(I, kv[0].W, maxC, S.B.w.clb, s, 1, &dq->nchild);
+            if (e == hipSuccess) e = launch_scan16(I, kv[0].W, maxC, S.B.w.clb, s, splits, &dq->nchild);
             if (e == hipSuccess) e = mstep_finish(dq, 1, maxK, maxC, s, true);
             if (e == hipSuccess) e = launch_device_step_update(dds, dq, dlog, s);
         }
