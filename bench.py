@@ -402,8 +402,11 @@ def tables_leg(stream, reps: int) -> dict:
 
                 for fn in (device_only, with_transfers, device_only, with_transfers):
                     fn()
-                t_dev = _time_best(device_only, reps)
-                t_xfer = _time_best(with_transfers, reps)
+                # more calls per timing for smaller pools, so that the final
+                # synchronisation is a small share of each timing
+                r = reps * max(1, TABLE_POOLS[4] // N)
+                t_dev = _time_best(device_only, r)
+                t_xfer = _time_best(with_transfers, r)
                 row[str(N)] = {"device_nodes_per_s": N / t_dev, "with_transfers_nodes_per_s": N / t_xfer}
         out["%dx%d" % (n, m)] = row
     return out
