@@ -417,7 +417,16 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     uint32_t *bits = tq + n * H;                       // NB nodes x NW scheduled-job words
     const int tid = threadIdx.x, q = tid & (L - 1), nl = tid / L;
     const int zrow = n * MV;  // offset of the zero row in pl
-    const int64_t node0 = (int64_t)blockIdx.x * NB;
+    // Workgroups go to the chip's eight XCDs in turn (linear id mod 8), and
+    // the split scan's workgroups of group G land on XCD G mod 8 when the
+    // group count is a multiple of 8.  The blocks that decode group G are
+    // placed on that XCD too: block b is the (b / 8)-th of XCD b mod 8, so
+    // the scan finds the group's workspace in the same L2.
+    constexpr int BPG = kGroup / NB;  // blocks per 128-node group
+    const int64_t xb = blockIdx.x & 7, kb = blockIdx.x >> 3;
+    const int64_t grp = xb + 8 * (kb / BPG);
+    const int64_t node0 = grp * kGroup + (kb % BPG) * NB;
+    if (grp * kGroup >= N) return;  // a group past the pool (whole block)
     const int64_t node = node0 + nl;
     const bool live = node < N;
     int d;
@@ -987,7 +996,9 @@ hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, co
         W.order = nullptr;
         if (marks) timing_mark(I, 0, s);
         const int L = plan.lanes_per_node, MVL = (m + L - 1) / L * L;
-        const dim3 lgrid((unsigned)(Npad / (256 / L)));
+        // blocks for every group, rounded up to whole rounds of 8 XCDs
+        const int64_t bpg = kGroup / (256 / L), nblk = (G + 7) / 8 * 8 * bpg;
+        const dim3 lgrid((unsigned)nblk);
         const size_t llds = decode16_lanes_lds(n, MVL, L);
 #define FSP_LDECODE(MVV, LL) \
     case MVV: decode16_lanes_kernel<MVV, LL><<<lgrid, 256, llds, s>>>(I->dt, prefixes, depths, N, W, out_lb); break;
