@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const 
 // 256 / L nodes per block).
 __host__ __device__ inline int lanes_lds_rest(int n, int MV, int L)
 {
-    return ((n + 1) * MV + n * (MV / 2) + (256 / L) * ((n + 31) >> 5)) * 4;
+    return ((n + 1) * MV + n * (MV / 2) + (256 / L) * (((n + 31) >> 5) + 2)) * 4;
 }
 
 // Words per slot row: L words of padding before the prefix, the n entries,
@@ -415,6 +415,8 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     int32_t *pl = slots + NB * RS;                     // (n + 1) x MV times; row n is zero
     uint32_t *tq = reinterpret_cast<uint32_t *>(pl + (n + 1) * MV);  // n x H packed tails
     uint32_t *bits = tq + n * H;                       // NB nodes x NW scheduled-job words
+    int32_t *sdep = reinterpret_cast<int32_t *>(bits + NB * NW);  // NB depths (0 for an invalid node)
+    int32_t *sbad = sdep + NB;                                    // NB flags: a job out of range
     const int tid = threadIdx.x, q = tid & (L - 1), nl = tid / L;
     const int zrow = n * MV;  // offset of the zero row in pl
     // Workgroups go to the chip's eight XCDs in turn (linear id mod 8), and
@@ -430,6 +432,7 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     const int64_t node = node0 + nl;
     const bool live = node < N;
     int d;
+    bool fused = false;  // rows checked and converted during the staging
     {
         // Every global load of the staging is issued before the first store:
         // the time rows (row n of p32 is zero), the packed tails, the depth
@@ -453,21 +456,51 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
         d = live ? depths[node] : 0;
         const int lim = (int)max<int64_t>(0, min<int64_t>(NB, N - node0)) * n;
         const int32_t *src = prefixes + node0 * (int64_t)n;
-        if (lim > 0 && (n & 3) == 0 && ((uintptr_t)src & 15) == 0) {
+        fused = lim > 0 && (n & 3) == 0 && ((uintptr_t)src & 15) == 0;
+        if (fused) {
             // 16-byte loads (NB n / 4 of them, at most 16 per thread) never
-            // cross a row; slot rows keep 16-byte alignment
+            // cross a row.  The loaded jobs are checked and turned into
+            // time-row offsets right here, once every node's depth is in LDS.
             const int4 *s4 = reinterpret_cast<const int4 *>(src);
             const int lim4 = lim >> 2, c4 = NB * n / 4;
             int4 rv[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) rv[k] = s4[min(k * 256 + tid, lim4 - 1)];
 #pragma unroll
+            for (int k = 0; k < PP; ++k)
+                if (k * 256 + tid < cp) pl[k * 256 + tid] = pv[k];
+#pragma unroll
+            for (int k = 0; k < TP; ++k)
+                if (k * 256 + tid < ct) tq[k * 256 + tid] = tv[k];
+            for (int e = tid; e < NB * NW; e += 256) bits[e] = 0u;
+            if (q == 0) {
+                const bool dok = live && d >= 0 && d <= n;
+                sdep[nl] = dok ? d : 0;
+                sbad[nl] = dok ? 0 : 1;
+            }
+            __syncthreads();
+            // entry w of the block's rows is job w mod n of node w / n
+            // (w < 2^16, so the reciprocal product is exact)
+            const uint32_t magic = 0xffffffffu / (uint32_t)n + 1u;
+#pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int e = k * 256 + tid;
                 if (e < c4) {
-                    const int w = 4 * e, r = w / n;
-                    *reinterpret_cast<int4 *>(slots + r * RS + PADB + (w - r * n)) =
-                        e < lim4 ? rv[k] : int4{0, 0, 0, 0};
+                    const uint32_t w = 4u * (uint32_t)e;
+                    const int r = (int)__umulhi(w, magic), t = (int)w - r * n;
+                    const int dr = sdep[r];
+                    const int32_t jj[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+                    int32_t off[4];
+                    bool bad = false;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool in = e < lim4 && t + u < dr, good = (unsigned)jj[u] < (unsigned)n;
+                        if (in && good) atomicOr(&bits[r * NW + (jj[u] >> 5)], 1u << (jj[u] & 31));
+                        bad |= in && !good;
+                        off[u] = in && good ? jj[u] * MV : zrow;
+                    }
+                    if (bad) sbad[r] = 1;
+                    *reinterpret_cast<int4 *>(slots + r * RS + PADB + t) = int4{off[0], off[1], off[2], off[3]};
                 }
             }
         } else if (lim > 0) {
@@ -482,14 +515,16 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
                     slots[r * RS + PADB + (e - r * n)] = v;
                 });
         }
+        if (!fused) {
 #pragma unroll
-        for (int k = 0; k < PP; ++k)
-            if (k * 256 + tid < cp) pl[k * 256 + tid] = pv[k];
+            for (int k = 0; k < PP; ++k)
+                if (k * 256 + tid < cp) pl[k * 256 + tid] = pv[k];
 #pragma unroll
-        for (int k = 0; k < TP; ++k)
-            if (k * 256 + tid < ct) tq[k * 256 + tid] = tv[k];
+            for (int k = 0; k < TP; ++k)
+                if (k * 256 + tid < ct) tq[k * 256 + tid] = tv[k];
+            for (int e = tid; e < NB * NW; e += 256) bits[e] = 0u;
+        }
     }
-    for (int e = tid; e < NB * NW; e += 256) bits[e] = 0u;
     __syncthreads();
 
     bool ok = live && d >= 0 && d <= n;
@@ -497,25 +532,30 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     int32_t *myslot = slots + nl * RS;
     uint32_t *mybits = bits + nl * NW;
 
-    // range checks, scheduled bits and time-row offsets, the prefix split
-    // over the node's lanes; the padding takes the zero row
+    // the padding takes the zero row
     if (q == 0) {
 #pragma unroll
         for (int t = 0; t < PADB; ++t) myslot[t] = zrow;
     }
     for (int t = PADB + n + q; t < RS; t += L) myslot[t] = zrow;
-    for (int t = q; t < n; t += 4 * L) {
-        int32_t raw[4];
+    if (fused) {
+        ok = ok && !sbad[nl];
+    } else {
+        // range checks, scheduled bits and time-row offsets, the prefix
+        // split over the node's lanes
+        for (int t = q; t < n; t += 4 * L) {
+            int32_t raw[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) raw[u] = myslot[PADB + min(t + L * u, n - 1)];
+            for (int u = 0; u < 4; ++u) raw[u] = myslot[PADB + min(t + L * u, n - 1)];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int tt = t + L * u;
-            if (tt < n) {
-                const bool in = tt < d, good = (unsigned)raw[u] < (unsigned)n;
-                if (in && good) atomicOr(&mybits[raw[u] >> 5], 1u << (raw[u] & 31));
-                if (in && !good) ok = false;
-                myslot[PADB + tt] = in && good ? raw[u] * MV : zrow;
+            for (int u = 0; u < 4; ++u) {
+                const int tt = t + L * u;
+                if (tt < n) {
+                    const bool in = tt < d, good = (unsigned)raw[u] < (unsigned)n;
+                    if (in && good) atomicOr(&mybits[raw[u] >> 5], 1u << (raw[u] & 31));
+                    if (in && !good) ok = false;
+                    myslot[PADB + tt] = in && good ? raw[u] * MV : zrow;
+                }
             }
         }
     }
