@@ -18,6 +18,14 @@
 
 namespace fspbb {
 
+// Packed halves for tail minima (instances whose tails are at most
+// kTailsHalfMax): two tails as the bits of two half-precision numbers, which
+// order as the integers do.  kHalfNone (0x7bff twice) stands for a scheduled
+// job: above every tail.
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h16x2 as_h16(uint32_t x) { return __builtin_bit_cast(h16x2, x); }
+constexpr uint32_t kHalfNone = 0x7bff7bffu;
+
 // ---- counting sort of node indices by depth (bucket n+1 holds invalid depths)
 
 __device__ __forceinline__ int depth_bucket(int d, int n) { return (d >= 0 && d <= n) ? d : n + 1; }
@@ -153,8 +161,10 @@ void launch_depth_sort(const int32_t *depths, int64_t N, int n, int B, int64_t c
 //   - Each lane keeps its scheduled set as bits in LDS, set by OR writes that
 //     return nothing; a repeated job shows at the end as fewer set bits than
 //     the depth.
-//   - The tails are taken two machines at a time with packed 16-bit minima
-//     over a scalar-loaded table, four jobs per batch of scalar loads.
+//   - The tails are taken two machines at a time with packed minima over a
+//     scalar-loaded table, four jobs per batch of scalar loads: packed
+//     half-precision three-operand minima when every tail is at most
+//     kTailsHalfMax, packed 16-bit integer minima otherwise.
 // Decodes block `blk` (256 nodes) of one pool; every thread of the block calls it.
 // sm: dynamic LDS of decode16_lds_words(n, MV) words.
 template <int MV>
@@ -285,29 +295,70 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     }
     // tails, two machines per register: q = min over jobs of (Q | inactive mask)
     uint32_t q2[H];
+    if (T.tails16ok == 2) {
+        // every tail is at most kTailsHalfMax: minima as packed halves, two
+        // jobs per three-operand minimum; a scheduled job contributes 0x7bff
+        h16x2 qh[H];
 #pragma unroll
-    for (int c = 0; c < H; ++c) q2[c] = 0xffffffffu;
-    for (int w = 0; w < NW; ++w) {
-        const uint32_t aw = act[w];
-        const int jn = min(32, n - 32 * w);
-        cptr<uint32_t> qw = as_const(T.tails16 + (size_t)(32 * w) * (kMaxMachines / 2));
-        int b = 0;
-        for (; b + 4 <= jn; b += 4) {
+        for (int c = 0; c < H; ++c) qh[c] = as_h16(kHalfNone);
+        // the constant in a vector register, so that each select reads its
+        // scalar-loaded tail directly (one scalar operand per instruction)
+        uint32_t none;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(none) : "i"(kHalfNone));
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t aw = act[w];
+            const int jn = min(32, n - 32 * w);
+            cptr<uint32_t> qw = as_const(T.tails16 + (size_t)(32 * w) * (kMaxMachines / 2));
+            int b = 0;
+            for (; b + 4 <= jn; b += 4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b + u, 1);
-                cptr<uint32_t> qr = qw + (size_t)(b + u) * (kMaxMachines / 2);
+                for (int u = 0; u < 4; u += 2) {
+                    const uint32_t offa = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b + u, 1);
+                    const uint32_t offb = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b + u + 1, 1);
+                    cptr<uint32_t> qa = qw + (size_t)(b + u) * (kMaxMachines / 2);
+                    cptr<uint32_t> qb = qa + kMaxMachines / 2;
+#pragma unroll
+                    for (int c = 0; c < H; ++c)
+                        qh[c] = __builtin_elementwise_minimum(
+                            __builtin_elementwise_minimum(qh[c], as_h16((qa[c] & ~offa) | (none & offa))),
+                            as_h16((qb[c] & ~offb) | (none & offb)));
+                }
+            }
+            for (; b < jn; ++b) {
+                const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b, 1);
+                cptr<uint32_t> qr = qw + (size_t)b * (kMaxMachines / 2);
+#pragma unroll
+                for (int c = 0; c < H; ++c)
+                    qh[c] = __builtin_elementwise_minimum(qh[c], as_h16((qr[c] & ~off) | (none & off)));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < H; ++c) q2[c] = __builtin_bit_cast(uint32_t, qh[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < H; ++c) q2[c] = 0xffffffffu;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t aw = act[w];
+            const int jn = min(32, n - 32 * w);
+            cptr<uint32_t> qw = as_const(T.tails16 + (size_t)(32 * w) * (kMaxMachines / 2));
+            int b = 0;
+            for (; b + 4 <= jn; b += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b + u, 1);
+                    cptr<uint32_t> qr = qw + (size_t)(b + u) * (kMaxMachines / 2);
+#pragma unroll
+                    for (int c = 0; c < H; ++c)
+                        q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
+                }
+            }
+            for (; b < jn; ++b) {
+                const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b, 1);
+                cptr<uint32_t> qr = qw + (size_t)b * (kMaxMachines / 2);
 #pragma unroll
                 for (int c = 0; c < H; ++c)
                     q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
             }
-        }
-        for (; b < jn; ++b) {
-            const uint32_t off = ~(uint32_t)__builtin_amdgcn_sbfe((int32_t)aw, b, 1);
-            cptr<uint32_t> qr = qw + (size_t)b * (kMaxMachines / 2);
-#pragma unroll
-            for (int c = 0; c < H; ++c)
-                q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(qr[c] | off)));
         }
     }
 
@@ -616,10 +667,19 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
     if constexpr (L == 8) bad |= __shfl_xor(bad, 4);
     ok = !bad && live && nset == d;
 
-    // tails: lane q takes jobs j = 32w + q + L i, packed 16-bit minima over (Q | off)
+    // tails: lane q takes jobs j = 32w + q + L i, minima over (Q | off) as
+    // packed halves (three-operand, two jobs each) when every tail is at most
+    // kTailsHalfMax, else as packed 16-bit integers; the partial minima of a
+    // node's lanes are below 0x8000 in the first case, so the 16-bit
+    // reduction across lanes serves both
+    const bool halves = T.tails16ok == 2;
     uint32_t q2[H];
+    h16x2 qh[H];
 #pragma unroll
-    for (int c = 0; c < H; ++c) q2[c] = 0xffffffffu;
+    for (int c = 0; c < H; ++c) {
+        q2[c] = 0xffffffffu;
+        qh[c] = as_h16(kHalfNone);
+    }
     for (int w = 0; w < NW; ++w) {
         const int lo = w * 32;
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : ((1u << (n - lo)) - 1u);
@@ -637,12 +697,26 @@ __global__ __launch_bounds__(256) void decode16_lanes_kernel(DevTables T, const 
 #pragma unroll
                 for (int c = 0; c < H; ++c) r[u][c] = tr[c];
             }
+            if (halves) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 4; u += 2)
 #pragma unroll
-                for (int c = 0; c < H; ++c)
-                    q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(r[u][c] | off[u])));
+                    for (int c = 0; c < H; ++c)
+                        qh[c] = __builtin_elementwise_minimum(
+                            __builtin_elementwise_minimum(qh[c], as_h16((r[u][c] & ~off[u]) | (kHalfNone & off[u]))),
+                            as_h16((r[u + 1][c] & ~off[u + 1]) | (kHalfNone & off[u + 1])));
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < H; ++c)
+                        q2[c] = as32(__builtin_elementwise_min(as16(q2[c]), as16(r[u][c] | off[u])));
+            }
         }
+    }
+    if (halves) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) q2[c] = __builtin_bit_cast(uint32_t, qh[c]);
     }
 #pragma unroll
     for (int c = 0; c < H; ++c) {

@@ -42,12 +42,19 @@ struct RecW {
     int32_t E, C;
 };
 
+// Largest tail whose 16 bits, read as a half-precision number, are a finite
+// value below the largest finite half (0x7bff): non-negative finite halves
+// order like their bit patterns, so minima of such tails can be taken with
+// the packed half-precision minimum.
+constexpr int32_t kTailsHalfMax = 0x7bfe;
+
 // Kernel-side view of an instance (passed by value).
 struct DevTables {
     int32_t n, m, P;
     int32_t npad;             // slots per pair in rec16 (n rounded up to 4)
     int32_t heads;            // 1: releases are the earliest starts of unscheduled jobs
-    int32_t tails16ok;        // 1: every tail is below 65536, so tails16 is exact
+    int32_t tails16ok;        // 1: every tail is below 65536, so tails16 is exact; 2: also at most
+                              // kTailsHalfMax, so the tails order like their bits read as halves
     const int32_t *p32;       // (n+1) x 32, zero-padded; row n is zero (PTM)
     const int32_t *colsum32;  // 32: sum over all jobs of p[j][k], zero-padded
     const int32_t *tails32;   // n x 32: Q[j][l] = sum_{h>l} p[j][h], zero-padded

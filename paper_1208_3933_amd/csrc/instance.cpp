@@ -190,7 +190,10 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     I->flags = flags | (P < m * (m - 1) / 2 ? FSP_INSTANCE_PAIR_SUBSET : 0);
     I->dt.n = n; I->dt.m = m; I->dt.P = P; I->dt.npad = npad;
     I->dt.heads = (flags & FSP_INSTANCE_HEADS) ? 1 : 0;
-    I->dt.tails16ok = *std::max_element(tails.begin(), tails.end()) < 65536 ? 1 : 0;
+    {
+        const int32_t qmax = *std::max_element(tails.begin(), tails.end());
+        I->dt.tails16ok = qmax <= kTailsHalfMax ? 2 : qmax < 65536 ? 1 : 0;
+    }
     I->dt.p32 = (const int32_t *)(b + off_p);
     I->dt.colsum32 = (const int32_t *)(b + off_cs);
     I->dt.tails32 = (const int32_t *)(b + off_t);

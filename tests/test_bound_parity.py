@@ -215,3 +215,35 @@ def test_wide_values_full_pool(n, m, N):
     assert (got == got32).all()
     idx = np.unique(gen.splitmix64(gen.make_seed(18, n, 9), 1500) % np.uint64(N)).astype(np.int64)
     assert (got[idx] == oracle_bounds(p, pre[idx], dep[idx])).all()
+
+
+def _tail_edge_instance(last):
+    """4 jobs x 8 machines whose largest tail, job 0's after machine 0, is
+    30,000 + last; the other tails are at most 7 x 4,000."""
+    p = gen.processing_times(4, 8, gen.make_seed(19, 0, 0), 1, 4000)
+    p[0, 1:7] = 5000
+    p[0, 7] = last
+    return p
+
+
+@pytest.mark.parametrize("p_fn", [lambda: _tail_edge_instance(1742), lambda: _tail_edge_instance(1743),
+                                  lambda: gen.processing_times(3, 32, gen.make_seed(19, 1, 0), 1500, 1927),
+                                  lambda: gen.processing_times(6, 24, gen.make_seed(19, 2, 0), 1600, 2250)])
+@pytest.mark.parametrize("one_lane", [False, True])
+def test_tails_near_the_half_precision_range(p_fn, one_lane, monkeypatch):
+    """16-bit instances whose largest tail is 0x7bfe (the largest the packed
+    half-precision minima take), 0x7bff, or far above it: every bound against
+    the oracle, on the small-pool decode and on the one-lane decode."""
+    torch = require_gpu()
+    p = p_fn()
+    n, m = p.shape
+    qmax = int(np.cumsum(p[:, ::-1], axis=1)[:, -2].max())
+    assert qmax >= 0x7bfe
+    if one_lane:
+        monkeypatch.setenv("FSPBB_LANES_BELOW", "1")
+    pre, dep = gen.random_pool(n, 1000, gen.make_seed(19, n * 100 + m, 1), 0, n)
+    want = oracle_bounds(p, pre, dep)
+    with fspbb.create_instance(p) as inst:
+        assert inst.info()["packed16"] == 1
+        for v in (fspbb.VARIANT_AUTO, fspbb.VARIANT_PACKED16):
+            assert (gpu_bounds(torch, inst, pre, dep, v) == want).all()
