@@ -15,10 +15,10 @@ namespace fspbb {
 constexpr int kSortMaxBlocks = 64;
 
 // LDS words of the 16-bit decode for n jobs and MV machine slots: the
-// scheduled bits of 256 lanes (ceil(n / 32) words each) and the (n + 1) rows
+// scheduled bits of 256 lanes (floor(n / 32) + 1 words each: jobs 0..n) and the (n + 1) rows
 // of MV / 2 packed processing-time pairs.  Monotone in n, so a launch sized
 // for the largest n of several pools serves all of them.
-inline size_t decode16_lds_words(int n, int MV) { return (size_t)((n + 31) >> 5) * 256 + (size_t)(n + 1) * (MV / 2); }
+inline size_t decode16_lds_words(int n, int MV) { return (size_t)((n >> 5) + 1) * 256 + (size_t)(n + 1) * (MV / 2); }
 
 constexpr int kBatchWaves = 16;  // waves per workgroup of the persistent scan
 // LDS a workgroup may allocate on gfx950 (160 KB per compute unit).

@@ -175,8 +175,8 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
 {
     constexpr int H = MV / 2;  // packed pairs per job row
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
-    uint32_t *bits = sm;             // NW words x 256 lanes
-    uint32_t *p16 = sm + NW * 256;   // (n + 1) x H; row n is zero
+    uint32_t *bits = sm;                       // (n / 32 + 1) words x 256 lanes: job bits, job n's bit included
+    uint32_t *p16 = sm + ((n >> 5) + 1) * 256;  // (n + 1) x H; row n is zero
     const int tid = threadIdx.x;
     stage_lds<8>(p16, (n + 1) * H, [&](int e) {
         const int2 r = *reinterpret_cast<const int2 *>(T.p32 + (size_t)(e / H) * kMaxMachines + 2 * (e % H));
@@ -200,18 +200,18 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     for (int k = 0; k < MV; ++k) C[k] = 0;
 #pragma unroll
     for (int c = 0; c < H; ++c) S2[c] = u16x2{0, 0};
-    // Slots t..t+3 of the prefix, branch-free: a slot past the depth, or an
-    // out-of-range job, takes the zero row, which leaves the completion
-    // times unchanged (they never decrease along the machines) and sets no bit.
-    auto step4 = [&](int32_t j0, int32_t j1, int32_t j2, int32_t j3, int t) {
+    // Slots t..t+3 of the prefix, branch-free.  An out-of-range job becomes
+    // job n: the zero row, which leaves the completion times unchanged (they
+    // never decrease along the machines), and a bit outside the job mask, so
+    // that the node's count of scheduled jobs falls short of its depth.  With
+    // `tail`, slots past the depth take job n too.
+    auto step4 = [&](int32_t j0, int32_t j1, int32_t j2, int32_t j3, int t, bool tail) {
         const int32_t jj[4] = {j0, j1, j2, j3};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const bool in = t + c < d, good = (unsigned)jj[c] < (unsigned)n;
-            ok = ok && (good || !in);
-            const int j = in && good ? jj[c] : n;
-            const bool real = j < n;
-            atomicOr(&mybits[(real ? j >> 5 : 0) * 256], real ? 1u << (j & 31) : 0u);
+            int j = (int)min((uint32_t)jj[c], (uint32_t)n);
+            if (tail && t + c >= d) j = n;
+            atomicOr(&mybits[(j >> 5) * 256], 1u << (j & 31));
             const uint2 *pr = reinterpret_cast<const uint2 *>(p16 + __mul24(j, H));
             int32_t prev = 0;
 #pragma unroll
@@ -239,15 +239,21 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
         const int4 *r4 = reinterpret_cast<const int4 *>(row);
         const int last = max(0, (d - 1) >> 2);
         int4 a = d > 0 ? r4[0] : int4{0, 0, 0, 0};
-        for (int t = 0; t < d; t += 8) {
+        int t = 0;
+        for (; t + 8 <= d; t += 8) {
             const int4 b = r4[min((t >> 2) + 1, last)];
-            step4(a.x, a.y, a.z, a.w, t);
+            step4(a.x, a.y, a.z, a.w, t, false);
             a = r4[min((t >> 2) + 2, last)];
-            step4(b.x, b.y, b.z, b.w, t + 4);
+            step4(b.x, b.y, b.z, b.w, t + 4, false);
+        }
+        if (t < d) {  // the last 1 to 7 slots
+            const int4 b = r4[min((t >> 2) + 1, last)];
+            step4(a.x, a.y, a.z, a.w, t, true);
+            if (t + 4 < d) step4(b.x, b.y, b.z, b.w, t + 4, true);
         }
     } else {
         for (int t = 0; t < d; t += 4)
-            step4(row[t], row[min(t + 1, d - 1)], row[min(t + 2, d - 1)], row[min(t + 3, d - 1)], t);
+            step4(row[t], row[min(t + 1, d - 1)], row[min(t + 2, d - 1)], row[min(t + 3, d - 1)], t, true);
     }
 
     u32v<kMaskWords> act;
@@ -256,11 +262,11 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     for (int w = 0; w < kMaskWords; ++w) {
         const int lo = w * 32;
         const uint32_t valid = n >= lo + 32 ? 0xffffffffu : (n <= lo ? 0u : ((1u << (n - lo)) - 1u));
-        const uint32_t b = w < NW ? mybits[w * 256] : 0u;
+        const uint32_t b = (w < NW ? mybits[w * 256] : 0u) & valid;
         nset += __popc(b);
         act[w] = ~b & valid;
     }
-    ok = ok && nset == d;  // every job in range; fewer bits than jobs means a repeat
+    ok = ok && nset == d;  // fewer bits than slots: a job out of range or repeated
     if (!ok) {
 #pragma unroll
         for (int w = 0; w < kMaskWords; ++w) act[w] = 0u;

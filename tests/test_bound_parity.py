@@ -150,9 +150,16 @@ def test_large_values_use_the_32bit_kernel():
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_invalid_nodes(variant):
+@pytest.mark.parametrize("n", [20, 32])
+@pytest.mark.parametrize("one_lane", [False, True])
+def test_invalid_nodes(variant, n, one_lane, monkeypatch):
+    """Invalid depths, repeated and out-of-range jobs; n = 32 puts an
+    out-of-range job's bit past the last mask word.  one_lane forces the
+    one-lane decode on the 16-bit path."""
     torch = require_gpu()
-    n, m, N = 20, 5, 500
+    if one_lane:
+        monkeypatch.setenv("FSPBB_LANES_BELOW", "1")
+    m, N = 5, 500
     p, pre, dep = workload(16, n, m, N)
     pre = pre.copy()
     dep = dep.copy()
@@ -162,11 +169,13 @@ def test_invalid_nodes(variant):
     dep[6] = 3; pre[6, 1] = n                  # job out of range
     dep[7] = 2; pre[7, 0] = -3                 # negative job
     dep[8] = 2; pre[8, 2] = 999                # junk after the prefix is ignored
+    dep[9] = 8; pre[9, 7] = n                  # out of range in a full block of 8 slots
+    dep[10] = 16; pre[10, 12] = pre[10, 3]     # repeated within full blocks
     want = oracle_bounds(p, pre, dep)
-    assert (want[[3, 4, 5, 6, 7]] == oracle.INVALID).all() and want[8] != oracle.INVALID
+    assert (want[[3, 4, 5, 6, 7, 9, 10]] == oracle.INVALID).all() and want[8] != oracle.INVALID
     with fspbb.create_instance(p) as inst:
         got = gpu_bounds(torch, inst, pre, dep, variant)
-        assert fspbb.pool_status(inst) == 5
+        assert fspbb.pool_status(inst) == 7
         assert fspbb.pool_status(inst) == 0
     assert (got == want).all()
 
