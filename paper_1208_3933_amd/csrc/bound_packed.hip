@@ -171,7 +171,7 @@ template <int MV>
 __device__ inline void decode16_block(const DevTables &T, const int32_t *__restrict__ prefixes,
                                       const int32_t *__restrict__ depths, int64_t N, int64_t Npad,
                                       const Workspace16 &W, int32_t *__restrict__ out_lb, int64_t blk,
-                                      uint32_t *sm)
+                                      uint32_t *sm, bool zero_lb = false)
 {
     constexpr int H = MV / 2;  // packed pairs per job row
     const int n = T.n, m = T.m, NW = (n + 31) >> 5;
@@ -390,17 +390,21 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     if (live && !ok) {
         out_lb[node] = FSP_LB_INVALID;
         atomicAdd(T.bad, 1ull);
+    } else if (live && zero_lb) {
+        out_lb[node] = 0;  // the split scan takes the maximum over its workgroups into it
     }
 }
 
+// zero_lb: write 0 to each valid node's bound, for a scan split over
+// several workgroups per group.
 template <int MV>
 __global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const int32_t *__restrict__ prefixes,
                                                              const int32_t *__restrict__ depths, int64_t N,
                                                              int64_t Npad, Workspace16 W,
-                                                             int32_t *__restrict__ out_lb)
+                                                             int32_t *__restrict__ out_lb, int zero_lb)
 {
     extern __shared__ uint32_t sm[];
-    decode16_block<MV>(T, prefixes, depths, N, Npad, W, out_lb, blockIdx.x, sm);
+    decode16_block<MV>(T, prefixes, depths, N, Npad, W, out_lb, blockIdx.x, sm, zero_lb != 0);
 }
 
 // ---- decode with four or eight lanes per node, for pools too small to fill the chip
@@ -776,7 +780,8 @@ inline size_t decode16_lanes_lds(int n, int MV, int L)
 // decode (nodes in pool order, no depth sort); a pool of fewer
 // groups than two per compute unit also splits each group's machine pairs
 // over several workgroups (at least four pairs per split, about one per
-// wave), which needs the four-lane decode's zeroed bounds.
+// wave), which needs zeroed bounds from the decode.  Pools on the one-lane
+// decode split too, up to the workgroups that fit the LDS at once.
 struct PoolPlan {
     bool lanes;          // several lanes per node in the decode
     int splits;          // pair splits of the scan
@@ -800,15 +805,34 @@ static int device_cus()
     return cus;
 }
 
+static int64_t device_lds_per_cu()
+{
+    static int64_t bytes = 0;
+    if (bytes == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+            v > 0)
+            bytes = v;
+        else
+            bytes = 160 * 1024;
+    }
+    return bytes;
+}
+
 // Pair splits of the scan for G groups: doubled while the workgroups stay
-// under two per compute unit and each split keeps at least four pairs.
-static int split_count(const fsp_instance_s *I, int64_t G)
+// under `fill` per compute unit (default two) and each split keeps at least
+// four pairs.
+static int split_count(const fsp_instance_s *I, int64_t G, int fill = 0)
 {
     const int cus = device_cus();
     int cap = 16;
     if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: no splits
-    int fill = 2, minp = 4;  // workgroups per compute unit; least pairs per split
-    if (const char *e = getenv("FSPBB_SPLIT_FILL")) fill = std::max(1, atoi(e));
+    int minp = 4;  // least pairs per split
+    if (fill <= 0) {
+        fill = 2;
+        if (const char *e = getenv("FSPBB_SPLIT_FILL")) fill = std::max(1, atoi(e));
+    }
     if (const char *e = getenv("FSPBB_SPLIT_MIN_PAIRS")) minp = std::max(1, atoi(e));
     int sp = 1;
     while (sp < cap && G * sp < (int64_t)fill * cus && minp * 2 * sp <= I->P) sp *= 2;
@@ -828,7 +852,20 @@ static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
     if (const char *e = getenv("FSPBB_SMALL_SPLITS")) cap = atoi(e);  // 0 or 1: the regular path only
     int64_t lanes_below = (int64_t)cus * 4 * 64;                      // one one-lane wave per SIMD
     if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
-    if (I->dt.heads || cap <= 1 || N >= lanes_below || I->n > kLanesMaxJobs) return PoolPlan{false, 1, 4};
+    if (I->dt.heads || cap <= 1) return PoolPlan{false, 1, 4};
+    if (N >= lanes_below || I->n > kLanesMaxJobs) {
+        // the one-lane decode; its scan splits while the workgroups stay
+        // under as many per compute unit as fit its LDS (one group's mask
+        // rows, (n + 1) x 256 bytes), at most four.  Measured at 20
+        // machines: 500 jobs, 8,192 nodes, 187 us at four splits against
+        // about 295 unsplit; 200 and 100 jobs, 65,536 nodes, 2-3% faster
+        // at two; more workgroups than fit at once are slower (500 jobs,
+        // 32,768 nodes: 385 us at four splits against 334 unsplit).
+        const int64_t fit = device_lds_per_cu() / ((int64_t)(I->n + 1) * 256);
+        int fill1 = (int)std::min<int64_t>(4, std::max<int64_t>(1, fit));
+        if (const char *e = getenv("FSPBB_ONE_LANE_FILL")) fill1 = std::max(1, atoi(e));
+        return PoolPlan{false, split_count(I, G, fill1), 4};
+    }
     const int sp = split_count(I, G);
     // eight lanes per node while their blocks (32 nodes each) do not
     // outnumber the compute units; four above (measured at 200x20: 24 against
@@ -1142,11 +1179,14 @@ hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, co
     if (sort_depths) launch_depth_sort(depths, N, n, B, chunk, W.cnt, W.order, s);
 
     const size_t dlds = decode16_lds_words(n, MV) * 4;
+    const int zero_lb = plan.splits > 1 ? 1 : 0;
     // decode of sorted positions [0, Np) of a part whose workspace starts at W
     auto decode = [&](const Workspace16 &Wp, int64_t Np, int64_t Nppad, hipStream_t st) {
         const dim3 dgrid((unsigned)((Nppad + 255) / 256)), dblock(256);
 #define FSP_DECODE(MVV) \
-    case MVV: bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, st>>>(I->dt, prefixes, depths, Np, Nppad, Wp, out_lb); break;
+    case MVV: \
+        bound_decode16_kernel<MVV><<<dgrid, dblock, dlds, st>>>(I->dt, prefixes, depths, Np, Nppad, Wp, out_lb, zero_lb); \
+        break;
         switch (MV) {
             FSP_DECODE(4) FSP_DECODE(8) FSP_DECODE(12) FSP_DECODE(16)
             FSP_DECODE(20) FSP_DECODE(24) FSP_DECODE(28) FSP_DECODE(32)
@@ -1156,7 +1196,7 @@ hipError_t launch_bound_packed_ws(fsp_instance_s *I, const int32_t *prefixes, co
     };
     hipError_t e = decode(W, N, Npad, s);
     if (marks) timing_mark(I, 1, s);
-    if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s);
+    if (e == hipSuccess) e = launch_scan16(I, W, N, out_lb, s, plan.splits);
     if (marks) timing_mark(I, 2, s);
     return e;
 }
