@@ -854,17 +854,23 @@ static PoolPlan pool_plan(const fsp_instance_s *I, int64_t N, int64_t G)
     if (const char *e = getenv("FSPBB_LANES_BELOW")) lanes_below = atoll(e);
     if (I->dt.heads || cap <= 1) return PoolPlan{false, 1, 4};
     if (N >= lanes_below || I->n > kLanesMaxJobs) {
-        // the one-lane decode; its scan splits while the workgroups stay
-        // under as many per compute unit as fit its LDS (one group's mask
-        // rows, (n + 1) x 256 bytes), at most four.  Measured at 20
-        // machines: 500 jobs, 8,192 nodes, 187 us at four splits against
-        // about 295 unsplit; 200 and 100 jobs, 65,536 nodes, 2-3% faster
-        // at two; more workgroups than fit at once are slower (500 jobs,
-        // 32,768 nodes: 385 us at four splits against 334 unsplit).
+        // the one-lane decode.  When a group's scan is long (n·P of at
+        // least 9,000 job-pair slots), its pairs split while the workgroups
+        // stay under as many per compute unit as fit its LDS (one group's
+        // mask rows, (n + 1) x 256 bytes), at most three.  Measured:
+        //   - 500x20, 8,192 nodes: 187 us at four splits, about 295 unsplit;
+        //   - 200x20 and 200x10, 65,536 nodes: 3-6% faster at two;
+        //   - shorter scans (50x10, 100x10, 20x20, 20x5) are 2-9% slower
+        //     split, and so are more workgroups than fit at once (500x20,
+        //     32,768 nodes: 385 us at four splits against 334 unsplit).
         const int64_t fit = device_lds_per_cu() / ((int64_t)(I->n + 1) * 256);
-        int fill1 = (int)std::min<int64_t>(4, std::max<int64_t>(1, fit));
-        if (const char *e = getenv("FSPBB_ONE_LANE_FILL")) fill1 = std::max(1, atoi(e));
-        return PoolPlan{false, split_count(I, G, fill1), 4};
+        int fill1 = (int)std::min<int64_t>(3, std::max<int64_t>(1, fit));
+        bool split = (int64_t)I->n * I->P >= 9000;
+        if (const char *e = getenv("FSPBB_ONE_LANE_FILL")) {
+            fill1 = std::max(1, atoi(e));
+            split = true;
+        }
+        return PoolPlan{false, split ? split_count(I, G, fill1) : 1, 4};
     }
     const int sp = split_count(I, G);
     // eight lanes per node while their blocks (32 nodes each) do not

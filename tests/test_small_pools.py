@@ -180,12 +180,14 @@ def test_small_pool_lanes_per_node(n, m, N, lanes):
 @pytest.mark.parametrize("n,m,N", [(200, 20, 129), (200, 20, 3000), (100, 10, 1000), (500, 20, 1000), (33, 3, 64)])
 def test_one_lane_decode_with_split_scan(n, m, N, monkeypatch):
     """Small pools on the one-lane decode (forced here; the default for more
-    than 256 jobs) with the scan's pairs split over several workgroups: the
-    decode writes 0 to each valid node's bound and the splits take the
+    than 256 jobs) with the scan's pairs split over several workgroups (also
+    forced, for the shapes whose scans are too short to split by default):
+    the decode writes 0 to each valid node's bound and the splits take the
     maximum into it.  Invalid nodes and leaves included; every bound against
     the unsplit path, and against the oracle."""
     torch = require_gpu()
     monkeypatch.setenv("FSPBB_LANES_BELOW", "1")
+    monkeypatch.setenv("FSPBB_ONE_LANE_FILL", "3")
     p = gen.processing_times(n, m, gen.make_seed(22, n * 100 + m, gen.PURPOSE_TIMES))
     pre, dep = gen.random_pool(n, N, gen.make_seed(22, n * 100 + m + N, gen.PURPOSE_POOL), 0, n)
     dep[1] = n + 2
