@@ -570,7 +570,9 @@ def main() -> int:
 
     gpu_lb = out.cpu().numpy()
 
-    fspbb.timing_enable(inst, True)
+    # chained event timing: two event records per step (after the decode,
+    # after the scan), each step's decode measured from the previous scan's end
+    fspbb.timing_enable(inst, True, chained=True)
     fspbb.timing_read(inst)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

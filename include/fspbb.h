@@ -495,7 +495,10 @@ fsp_status fsp_server_destroy(fsp_server srv);
  * launch records HIP events on its stream around its decode and scan kernels.
  * fsp_timing_read() waits for the recorded events, returns the summed device
  * time of each kernel in milliseconds and the number of launches, and clears
- * the record.  Enabling costs two event records per kernel launch.
+ * the record.  on = 1 records three events per bound launch (start, after
+ * the decode, after the scan).  on = 2 records two: a launch's decode time
+ * runs from the previous launch's end, which suits back-to-back launches on
+ * one stream (the first launch after enabling or reading has its own start).
  */
 fsp_status fsp_timing_enable(fsp_instance inst, int32_t on);
 fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms, int64_t *launches);

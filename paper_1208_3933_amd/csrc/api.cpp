@@ -209,9 +209,13 @@ void timing_mark(fsp_instance_s *I, int which, hipStream_t s)
     if (!I->timing) return;
     if (!I->timing_log) I->timing_log = new std::vector<TimingRecord>();
     if (which == 0) {
-        TimingRecord r;
-        for (auto &e : r.ev) hipEventCreate(&e);
+        // chained timing: the launch starts where the previous one's scan
+        // ended (ev[0] stays null), one event record fewer per launch
+        const bool chain = I->timing == 2 && !I->timing_log->empty();
+        TimingRecord r{};
+        for (int k = chain ? 1 : 0; k < 3; ++k) hipEventCreate(&r.ev[k]);
         I->timing_log->push_back(r);
+        if (chain) return;
     }
     if (!I->timing_log->empty()) hipEventRecord(I->timing_log->back().ev[which], s);
 }
@@ -277,7 +281,7 @@ fsp_status fsp_pool_status(fsp_instance inst, void *stream, int64_t *n_bad)
 fsp_status fsp_timing_enable(fsp_instance inst, int32_t on)
 {
     if (!inst) return FSP_E_INVAL;
-    inst->timing = on ? 1 : 0;
+    inst->timing = on == 2 ? 2 : on ? 1 : 0;
     return FSP_OK;
 }
 
@@ -289,17 +293,23 @@ fsp_status fsp_timing_read(fsp_instance inst, double *decode_ms, double *scan_ms
     int64_t cnt = 0;
     hipError_t err = hipSuccess;
     if (inst->timing_log) {
-        for (auto &r : *inst->timing_log) {
+        std::vector<TimingRecord> &log = *inst->timing_log;
+        for (size_t i = 0; i < log.size(); ++i) {
+            const TimingRecord &r = log[i];
+            // a chained record starts at the previous record's end
+            hipEvent_t start = r.ev[0] ? r.ev[0] : (i > 0 ? log[i - 1].ev[2] : nullptr);
             float a = 0, b = 0;
-            hipError_t e = hipEventSynchronize(r.ev[2]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&a, r.ev[0], r.ev[1]);
+            hipError_t e = start ? hipEventSynchronize(r.ev[2]) : hipErrorInvalidValue;
+            if (e == hipSuccess) e = hipEventElapsedTime(&a, start, r.ev[1]);
             if (e == hipSuccess) e = hipEventElapsedTime(&b, r.ev[1], r.ev[2]);
             if (e != hipSuccess) err = e;
             dsum += a;
             ssum += b;
             ++cnt;
-            for (auto &ev : r.ev) hipEventDestroy(ev);
         }
+        for (auto &r : log)
+            for (auto &ev : r.ev)
+                if (ev) hipEventDestroy(ev);
         inst->timing_log->clear();
     }
     if (decode_ms) *decode_ms = dsum;

@@ -314,8 +314,11 @@ def pool_status(inst: Instance, stream=None) -> int:
     return int(n_bad.value)
 
 
-def timing_enable(inst: Instance, on: bool = True) -> None:
-    _check(lib().fsp_timing_enable(inst.handle, int(bool(on))), "fsp_timing_enable")
+def timing_enable(inst: Instance, on: bool = True, chained: bool = False) -> None:
+    """Event timing of each bound launch; chained: a launch's start is the
+    previous launch's end (back-to-back launches on one stream), one event
+    record fewer per launch."""
+    _check(lib().fsp_timing_enable(inst.handle, (2 if chained else 1) if on else 0), "fsp_timing_enable")
 
 
 def timing_read(inst: Instance):

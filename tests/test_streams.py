@@ -59,3 +59,37 @@ def test_searches_from_several_threads():
             assert (a["perm"] == r["perm"]).all()
     for inst in insts:
         inst.close()
+
+
+@pytest.mark.parametrize("chained", [False, True])
+def test_kernel_timing_records(chained):
+    """Event timing of bound launches, plain (three events per launch) and
+    chained (a launch starts at the previous one's end): every launch is
+    counted, both parts take time, their sum stays within the wall time of
+    the launches, and the bounds are those of an untimed launch."""
+    torch = require_gpu()
+    n, m, N = 200, 20, 70000
+    p = gen.processing_times(n, m, gen.make_seed(23, 0, gen.PURPOSE_TIMES))
+    pre, dep = gen.random_pool(n, N, gen.make_seed(23, 0, gen.PURPOSE_POOL))
+    with fspbb.create_instance(p) as inst:
+        pre_d, dep_d = to_dev(torch, pre, dep)
+        ref = torch.empty(N, dtype=torch.int32, device="cuda")
+        fspbb.bound_pool(inst, pre_d, dep_d, ref)
+        out = torch.empty(N, dtype=torch.int32, device="cuda")
+        fspbb.timing_enable(inst, True, chained=chained)
+        for rnd in range(2):  # the second round starts a new chain after the read
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                fspbb.bound_pool(inst, pre_d, dep_d, out)
+            e1.record()
+            torch.cuda.synchronize()
+            dec, scan, k = fspbb.timing_read(inst)
+            assert k == 5
+            assert dec > 0 and scan > 0
+            assert dec + scan <= e0.elapsed_time(e1) * 1.01 + 0.01
+        fspbb.timing_enable(inst, False)
+        assert fspbb.timing_read(inst)[2] == 0
+        assert torch.equal(out, ref)
