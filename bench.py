@@ -533,7 +533,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the bound path runs on "
-              "one device; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+              "one device; a pool would shard across GPUs by node ranges with no exchange, a search by sharing its incumbent)", file=sys.stderr)
         return 2
 
     import torch
