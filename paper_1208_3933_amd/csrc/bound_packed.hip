@@ -396,9 +396,12 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
 }
 
 // zero_lb: write 0 to each valid node's bound, for a scan split over
-// several workgroups per group.
+// several workgroups per group.  Up to 20 machines, five waves per SIMD (at
+// most 96 registers; at 20 machines one 8-byte spill outside the prefix
+// loop): the decode is latency-bound, and the fifth wave takes 1.7% off it
+// at 200x20.
 template <int MV>
-__global__ __launch_bounds__(256) void bound_decode16_kernel(DevTables T, const int32_t *__restrict__ prefixes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MV <= 20 ? 5 : 1))) void bound_decode16_kernel(DevTables T, const int32_t *__restrict__ prefixes,
                                                              const int32_t *__restrict__ depths, int64_t N,
                                                              int64_t Npad, Workspace16 W,
                                                              int32_t *__restrict__ out_lb, int zero_lb)
