@@ -864,10 +864,12 @@ hipError_t run_device_steps(Search &S, TickContext &ctx)
     int chunk = 1;
     while (e == hipSuccess && !st.done) {
         // the device pauses a search whose next step might not fit the stack
-        // (maxC more rows): grow it, doubling, and resume
-        if (st.paused || st.top + maxC > S.cap_stack) {
+        // (maxC more rows): grow it, doubling, until the coming chunk of
+        // steps fits whole (a pause idles the rest of its chunk), and resume
+        const int64_t need = st.top + (int64_t)chunk * maxC;
+        if (st.paused || need > S.cap_stack) {
             int64_t nc = S.cap_stack;
-            while (st.top + maxC > nc) nc *= 2;
+            while (need > nc) nc *= 2;
             if (nc > S.cap_stack) {
                 int32_t *r2 = nullptr, *d2 = nullptr;
                 e = stream_alloc((void **)&r2, (size_t)nc * n * 4, s);
