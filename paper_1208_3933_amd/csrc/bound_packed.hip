@@ -301,7 +301,33 @@ __device__ inline void decode16_block(const DevTables &T, const int32_t *__restr
     }
     // tails, two machines per register: q = min over jobs of (Q | inactive mask)
     uint32_t q2[H];
-    if (T.tails16ok == 2) {
+    if (__all(2 * d <= n)) {
+        // a wave of nodes at most half deep: each machine's tail is that of
+        // the first job, in increasing tail order on the machine, that the
+        // node has not scheduled; a few ranks usually reach it for every
+        // lane and machine, against a minimum over all n jobs
+        uint32_t qv[MV], need = 0;  // need: machines still without a tail
+#pragma unroll
+        for (int k = 0; k < MV; ++k) {
+            qv[k] = 0;
+            if (k < m) need |= 1u << k;
+        }
+        for (int r = 0; r < n; ++r) {
+            cptr<uint32_t> row = as_const(T.tord + (size_t)r * kMaxMachines);
+#pragma unroll
+            for (int k = 0; k < MV; ++k) {
+                if (k < m) {
+                    const uint32_t e = row[k], j = e >> 16;
+                    const bool take = ((need >> k) & 1u) && !((mybits[(j >> 5) * 256] >> (j & 31)) & 1u);
+                    qv[k] = take ? (e & 0xffffu) : qv[k];
+                    need = take ? need & ~(1u << k) : need;
+                }
+            }
+            if (__all(need == 0)) break;
+        }
+#pragma unroll
+        for (int c = 0; c < H; ++c) q2[c] = qv[2 * c] | (qv[2 * c + 1] << 16);
+    } else if (T.tails16ok == 2) {
         // every tail is at most kTailsHalfMax: minima as packed halves, two
         // jobs per three-operand minimum; a scheduled job contributes 0x7bff
         h16x2 qh[H];

@@ -59,6 +59,8 @@ struct DevTables {
     const int32_t *colsum32;  // 32: sum over all jobs of p[j][k], zero-padded
     const int32_t *tails32;   // n x 32: Q[j][l] = sum_{h>l} p[j][h], zero-padded
     const uint32_t *tails16;  // n x 16: (Q[j][2c], Q[j][2c+1]) as 16-bit halves (16-bit path)
+    const uint32_t *tord;     // n x 32: rank r, machine l: (job << 16) | low 16 bits of its tail, the
+                              // r-th job by increasing tail on machine l (ties by job)
     const int32_t *pairs;     // P x 2: (k, l), k < l, lexicographic (MM)
     const Rec32 *rec32;       // P x n
     const Rec32 *rec32sm;     // n x P: the same records slot-major (wave-per-node kernel)

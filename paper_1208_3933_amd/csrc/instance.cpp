@@ -120,6 +120,20 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
         for (int c = 0; c < S / 2; ++c)
             tails16[(size_t)j * (S / 2) + c] = ((uint32_t)tails[(size_t)j * S + 2 * c] & 0xffffu) |
                                                ((uint32_t)tails[(size_t)j * S + 2 * c + 1] << 16);
+    // tord: for rank r and machine l < m, the r-th job by increasing tail on
+    // machine l (ties by job) as (job << 16) | tail, the tail's low 16 bits
+    std::vector<uint32_t> tord((size_t)n * S, 0);
+    {
+        std::vector<int> idx(n);
+        for (int l = 0; l < m; ++l) {
+            for (int j = 0; j < n; ++j) idx[j] = j;
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+                return tails[(size_t)a * S + l] < tails[(size_t)c * S + l];
+            });
+            for (int r = 0; r < n; ++r)
+                tord[(size_t)r * S + l] = ((uint32_t)idx[r] << 16) | ((uint32_t)tails[(size_t)idx[r] * S + l] & 0xffffu);
+        }
+    }
     std::vector<int> order;
     std::vector<int32_t> lagv;
     for (int pr = 0; pr < P; ++pr) {
@@ -157,7 +171,8 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     size_t off_rsm = align(off_r32 + rec32.size() * sizeof(Rec32));
     size_t off_r16 = align(off_rsm + rec32sm.size() * sizeof(Rec32));
     size_t off_rw = align(off_r16 + rec16.size() * sizeof(Rec16));
-    size_t off_bad = align(off_rw + recw.size() * sizeof(RecW));
+    size_t off_to = align(off_rw + recw.size() * sizeof(RecW));
+    size_t off_bad = align(off_to + tord.size() * 4);
     size_t total = align(off_bad + sizeof(unsigned long long));
     std::vector<unsigned char> blob(total, 0);
     std::memcpy(blob.data() + off_p, hp.data(), hp.size() * 4);
@@ -169,6 +184,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     std::memcpy(blob.data() + off_rsm, rec32sm.data(), rec32sm.size() * sizeof(Rec32));
     std::memcpy(blob.data() + off_r16, rec16.data(), rec16.size() * sizeof(Rec16));
     std::memcpy(blob.data() + off_rw, recw.data(), recw.size() * sizeof(RecW));
+    std::memcpy(blob.data() + off_to, tord.data(), tord.size() * 4);
 
     void *d = nullptr;
     e = hipMalloc(&d, total);
@@ -203,6 +219,7 @@ fsp_status create_instance(const int32_t *p, int32_t n, int32_t m, int32_t flags
     I->dt.rec32sm = (const Rec32 *)(b + off_rsm);
     I->dt.rec16 = (const Rec16 *)(b + off_r16);
     I->dt.recw = (const RecW *)(b + off_rw);
+    I->dt.tord = (const uint32_t *)(b + off_to);
     I->dt.bad = (unsigned long long *)(b + off_bad);
     *out = I;
     return FSP_OK;
